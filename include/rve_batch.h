@@ -1,0 +1,213 @@
+/*
+ * rve_batch.h - C ABI of the MI355X batched fiber-network RVE solver.
+ *
+ * The library is the microscale side of an FE^2 computation (paper:
+ * Section 3, "batched" microscale routines that take a set of deformation
+ * states and return stresses and material stiffnesses for the whole set at
+ * once; Section 4.2, one independent sub-problem per RVE).  Each RVE is a
+ * truss network in the unit cube; its boundary nodes follow the affine map
+ * x = F Xm (Section 2, affine boundary condition), its free nodes are
+ * relaxed to static equilibrium by damped explicit dynamic relaxation
+ * (Section 3.2, Algorithm "Dynamic Relaxation"), and the homogenized Cauchy
+ * stress is the boundary-traction integral sigma_ij = 1/V sum_b f_b,i x_b,j
+ * (Section 2, stress as the surface integral of traction times position).
+ *
+ * Conventions shared by every entry point
+ *  - Return value: RVE_OK (0) on success, a negative RVE_E* code otherwise.
+ *    No entry point throws, aborts or exits; rve_last_error() returns a
+ *    thread-local message for the last failure on the calling thread.
+ *  - Matrices are row-major doubles: F[r][i][j] = F_ij of RVE r, sigma the
+ *    same, dsdF[r][3i+j][3k+l] = d sigma_ij / d F_kl.
+ *  - ptr_kind says whether the caller's output/input arrays live in host
+ *    memory (RVE_PTR_HOST: the call is synchronous) or device memory
+ *    (RVE_PTR_DEVICE: the call is stream-ordered on opts.stream and returns
+ *    before the work finishes).
+ *  - A batch object is not thread-safe: one call at a time per object.
+ *    Distinct objects may be used from distinct threads.
+ *  - Per-RVE outcomes are written to status[r] (RVE_ST_*); the outputs of an
+ *    RVE that did not converge hold the last state's values (MAXITER) or NaN
+ *    (NONFINITE, BAD_F).
+ */
+#ifndef RVE_BATCH_H
+#define RVE_BATCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RVE_API_VERSION 1
+
+/* return codes */
+#define RVE_OK 0
+#define RVE_EINVAL (-22)       /* malformed argument, topology or option */
+#define RVE_ENOMEM (-12)       /* host or device allocation failed */
+#define RVE_EDEVICE (-5)       /* HIP runtime error or no usable gfx950 device */
+#define RVE_ESTATE (-3)        /* call order: e.g. tangent before any solve */
+
+/* per-RVE status codes */
+#define RVE_ST_CONVERGED 0     /* R <= tol and damping-force norm <= tol */
+#define RVE_ST_MAXITER 1       /* n_max iterations reached first */
+#define RVE_ST_NONFINITE 2     /* the relaxation produced Inf/NaN */
+#define RVE_ST_BAD_F 3         /* F non-finite or det F <= 0: RVE skipped */
+#define RVE_ST_NO_STATE 4      /* tangent: RVE has no converged state */
+#define RVE_ST_CG_MAXITER 5    /* tangent: CG stopped at its iteration cap */
+#define RVE_ST_CG_INDEFINITE 6 /* tangent: K_ff not positive (unstable state) */
+
+/* options */
+#define RVE_FP64 0             /* all arithmetic in double */
+#define RVE_MIXED 1            /* fibers and state in float; residual, damping
+                                  test, time-step scalar and stress in double */
+#define RVE_LAW_LINEAR 0       /* T = EA eps */
+#define RVE_LAW_EXP 1          /* T = EA (exp(B eps) - 1)/B, eps >= 0; EA eps below */
+#define RVE_MASS_LUMPED 0      /* M_a = rhoA/2 sum L0 over fibers at a */
+#define RVE_MASS_SCALED 1      /* M_a = G_a(x0)/4, Gershgorin sum at the start */
+#define RVE_INIT_AFFINE 0      /* free nodes start at F Xm */
+#define RVE_INIT_WARM 2        /* free nodes start at F Xm + h, h = fluctuation
+                                  left by the previous solve of this batch */
+#define RVE_ENGINE_AUTO 0      /* register-resident persistent kernel where an
+                                  RVE fits, streamed persistent kernel otherwise */
+#define RVE_ENGINE_STREAMED 1  /* persistent kernel, state in global memory */
+#define RVE_ENGINE_NAIVE 2     /* one RVE at a time, one launch per step of
+                                  every iteration, atomics, FP64 only */
+#define RVE_PTR_HOST 0
+#define RVE_PTR_DEVICE 1
+
+typedef struct rve_batch rve_batch;
+
+/*
+ * Network description: a ragged batch in row-offset + value layout.
+ * All pointers are host pointers; create() copies what it needs and the
+ * caller keeps ownership.
+ *   node_off[n_rve+1], fib_off[n_rve+1]: offsets of each RVE's nodes/fibers.
+ *   X[node_off[n_rve]][3]: reference coordinates in the unit cube [0,1]^3
+ *     (the RVE centre 0.5,0.5,0.5 is the macroscale material point).
+ *   is_bnd[node_off[n_rve]]: 1 for a boundary node (prescribed x = F Xm).
+ *   fib[fib_off[n_rve]][2]: fiber end nodes as ids local to the RVE.
+ *   V0[n_rve]: reference RVE volume (NULL: 1, the unit cube).
+ * Rest lengths are the reference lengths |X_j - X_i|.
+ * Rejected with RVE_EINVAL: ids out of range, a fiber joining a node to
+ * itself, a zero-length fiber, an RVE without a boundary node, an RVE with
+ * 65535 nodes or more, non-finite coordinates.
+ */
+typedef struct {
+    int64_t n_rve;
+    const int64_t* node_off;
+    const int64_t* fib_off;
+    const double* X;
+    const uint8_t* is_bnd;
+    const int32_t* fib;
+    const double* V0;
+} rve_net_desc;
+
+/*
+ * Solver options (copied at create; change later with rve_batch_set_opts).
+ *   EA, B: fiber law constants.  rhoA: lumped-mass density (RVE_MASS_LUMPED).
+ *   alpha: time-step safety factor, dt = alpha * 2 / sqrt(max_a G_a / M_a)
+ *     with G_a = 2 sum_{fibers at a} max(k_t/L0, |T|/l).
+ *   c: mass-proportional damping constant (c_per_rve, if non-NULL, is a host
+ *     array of n_rve values that overrides it; copied).
+ *   Convergence: R = |f_free|_2 <= tol and c |M v|_2 <= tol with
+ *     tol = max(tol_abs, tol_rel |f_bnd|_2), tested every check_every
+ *     iterations (>= 1); n_max caps the iterations.
+ *   engine: RVE_ENGINE_*.  threads_per_rve: 0 = autotune, else 256/512/1024.
+ *   cg_tol, cg_max_iter: conjugate-gradient controls of rve_batch_tangent and
+ *     rve_batch_vjp.
+ *   stream: hipStream_t for every launch and copy (NULL: the null stream).
+ */
+typedef struct {
+    int32_t precision;
+    int32_t law;
+    int32_t mass;
+    int32_t init;
+    double EA, B, rhoA;
+    double alpha;
+    double c;
+    const double* c_per_rve;
+    double tol_abs, tol_rel;
+    int64_t n_max;
+    int32_t check_every;
+    int32_t engine;
+    int32_t threads_per_rve;
+    double cg_tol;          /* tangent/vjp CG: stop at |r_k| <= cg_tol |b_k| */
+    int64_t cg_max_iter;    /* tangent/vjp CG iteration cap (0: 20 x free DOFs) */
+    void* stream;
+} rve_opts;
+
+/* Optional per-RVE diagnostics of a solve (each pointer may be NULL; same
+ * ptr_kind as the solve call). */
+typedef struct {
+    int64_t* iters;   /* iterations taken */
+    double* R;        /* final |f_free|_2 */
+    double* D;        /* final damping-force norm c |M v|_2 */
+    double* Fb;       /* final |f_bnd|_2 (reaction scale of tol_rel) */
+} rve_stats;
+
+int rve_version(void);
+const char* rve_last_error(void);
+
+/* Fill *o with defaults: FP64, linear law, EA 1, B 10, rhoA 1, alpha 0.9,
+ * c 2, tol_abs 1e-10, tol_rel 0, n_max 1e6, check_every 1, auto engine,
+ * cg_tol 1e-6, cg_max_iter 0. */
+void rve_default_opts(rve_opts* o);
+
+/*
+ * Build a batch: validate and copy the networks, reorder each RVE's nodes
+ * (free nodes first in a locality order, boundary nodes last), compute rest
+ * lengths and lumped masses, build node->fiber incidence, pick a kernel
+ * variant per RVE, and upload everything to the current HIP device
+ * (Algorithm "Dynamic Relaxation": connectivity and mass prepared on the
+ * host once and transferred to the device).  *out is NULL on failure.
+ */
+int rve_batch_create(const rve_net_desc* net, const rve_opts* opts, rve_batch** out);
+
+/* Replace the options of an existing batch (same validation as create). */
+int rve_batch_set_opts(rve_batch* b, const rve_opts* opts);
+
+/* Replace only the stream of the batch (hipStream_t; NULL = null stream). */
+int rve_batch_set_stream(rve_batch* b, void* stream);
+
+/* Number of RVEs, nodes and fibers of the batch. */
+int rve_batch_sizes(const rve_batch* b, int64_t* n_rve, int64_t* n_nodes, int64_t* n_fib);
+
+/*
+ * Relax every RVE under its F and return the homogenized Cauchy stress.
+ *   F[n_rve][3][3] (input), sigma[n_rve][3][3] (output), status[n_rve].
+ *   sigma_ij = 1/(det F V0) sum_b f_b,i x_b,j, f_b the internal force at
+ *   boundary node b (its reaction), x_b = F Xm_b.
+ * The converged fluctuation state stays on the device for rve_batch_tangent,
+ * rve_batch_vjp, rve_batch_positions and warm starts.
+ */
+int rve_batch_solve(rve_batch* b, const double* F, double* sigma, int32_t* status,
+                    rve_stats* stats, int32_t ptr_kind);
+
+/*
+ * Material tangent dsigma/dF at the state left by the last solve, by an
+ * adjoint: for each of the 9 directions E = e_k e_l the free nodes follow
+ * K_ff dx_f = -K_fb (E Xm)_b (matrix-free Hessian-vector conjugate
+ * gradients, 9 right-hand sides at once), the reactions change by
+ * df_b = (K dx)_b, and dsigma = (sum_b df_b x_b^T + f_b (E Xm_b)^T)/(J V0)
+ * - sigma (F^-1)_lk.  dsdF[n_rve][9][9]; status per RVE.
+ */
+int rve_batch_tangent(rve_batch* b, double* dsdF, int32_t* status, int32_t ptr_kind);
+
+/*
+ * Vector-Jacobian product of the last solve: gF_kl = sum_ij g_ij dsigma_ij/dF_kl
+ * with one adjoint CG per RVE.  gsigma[n_rve][9] in, gF[n_rve][9] out.
+ */
+int rve_batch_vjp(rve_batch* b, const double* gsigma, double* gF, int32_t* status, int32_t ptr_kind);
+
+/* Positions x[n_nodes_r][3] of RVE r after the last solve, in the caller's
+ * original node order (host pointer; synchronous). */
+int rve_batch_positions(rve_batch* b, int64_t r, double* x);
+
+/* Free every host and device resource of the batch (NULL is a no-op). */
+void rve_batch_destroy(rve_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RVE_BATCH_H */

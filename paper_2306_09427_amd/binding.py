@@ -1,0 +1,224 @@
+"""ctypes binding of librvebatch.so (argument marshalling only).
+
+Every step of the relaxation, the stress and the tangent runs in the HIP
+library; this module converts numpy arrays / torch tensors to pointers and
+option structs.  Importing it does not touch the GPU; creating a Batch does.
+If the library is missing, loading fails with an error (there is no CPU
+fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librvebatch.so")
+
+FP64, MIXED = 0, 1
+LAW_LINEAR, LAW_EXP = 0, 1
+MASS_LUMPED, MASS_SCALED = 0, 1
+INIT_AFFINE, INIT_WARM = 0, 2
+ENGINE_AUTO, ENGINE_STREAMED, ENGINE_NAIVE = 0, 1, 2
+PTR_HOST, PTR_DEVICE = 0, 1
+ST_CONVERGED, ST_MAXITER, ST_NONFINITE, ST_BAD_F, ST_NO_STATE, ST_CG_MAXITER, ST_CG_INDEFINITE = range(7)
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE = 0, -22, -12, -5, -3
+
+EXPORTS = ["rve_version", "rve_last_error", "rve_default_opts", "rve_batch_create", "rve_batch_set_opts",
+           "rve_batch_set_stream", "rve_batch_sizes", "rve_batch_solve", "rve_batch_tangent", "rve_batch_vjp",
+           "rve_batch_positions", "rve_batch_destroy"]
+
+
+class NetDesc(C.Structure):
+    _fields_ = [("n_rve", C.c_int64), ("node_off", C.c_void_p), ("fib_off", C.c_void_p), ("X", C.c_void_p),
+                ("is_bnd", C.c_void_p), ("fib", C.c_void_p), ("V0", C.c_void_p)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("law", C.c_int32), ("mass", C.c_int32), ("init", C.c_int32),
+                ("EA", C.c_double), ("B", C.c_double), ("rhoA", C.c_double), ("alpha", C.c_double),
+                ("c", C.c_double), ("c_per_rve", C.c_void_p), ("tol_abs", C.c_double), ("tol_rel", C.c_double),
+                ("n_max", C.c_int64), ("check_every", C.c_int32), ("engine", C.c_int32),
+                ("threads_per_rve", C.c_int32), ("cg_tol", C.c_double), ("cg_max_iter", C.c_int64),
+                ("stream", C.c_void_p)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("iters", C.c_void_p), ("R", C.c_void_p), ("D", C.c_void_p), ("Fb", C.c_void_p)]
+
+
+class RVEError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"rvebatch error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load librvebatch.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(hipcc --offload-arch=gfx950); there is no CPU fallback")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.rve_version.restype = C.c_int
+        L.rve_last_error.restype = C.c_char_p
+        L.rve_default_opts.argtypes = [C.POINTER(Opts)]
+        L.rve_batch_create.argtypes = [C.POINTER(NetDesc), C.POINTER(Opts), C.POINTER(P)]
+        L.rve_batch_set_opts.argtypes = [P, C.POINTER(Opts)]
+        L.rve_batch_set_stream.argtypes = [P, P]
+        L.rve_batch_sizes.argtypes = [P, P, P, P]
+        L.rve_batch_solve.argtypes = [P, P, P, P, C.POINTER(Stats), C.c_int32]
+        L.rve_batch_tangent.argtypes = [P, P, P, C.c_int32]
+        L.rve_batch_vjp.argtypes = [P, P, P, P, C.c_int32]
+        L.rve_batch_positions.argtypes = [P, C.c_int64, P]
+        L.rve_batch_destroy.argtypes = [P]
+        L.rve_batch_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().rve_last_error().decode()
+
+
+def _check(rc):
+    if rc != OK:
+        raise RVEError(rc, last_error())
+
+
+def make_opts(precision=FP64, law=LAW_EXP, mass=MASS_LUMPED, init=INIT_AFFINE, EA=1.0, B=10.0, rhoA=1.0,
+              alpha=0.9, c=2.0, tol_abs=1e-10, tol_rel=0.0, n_max=1_000_000, check_every=1,
+              engine=ENGINE_AUTO, threads_per_rve=0, cg_tol=1e-6, cg_max_iter=0) -> Opts:
+    o = Opts()
+    lib().rve_default_opts(C.byref(o))
+    o.precision, o.law, o.mass, o.init = int(precision), int(law), int(mass), int(init)
+    o.EA, o.B, o.rhoA, o.alpha, o.c = float(EA), float(B), float(rhoA), float(alpha), float(c)
+    o.tol_abs, o.tol_rel, o.n_max, o.check_every = float(tol_abs), float(tol_rel), int(n_max), int(check_every)
+    o.engine, o.threads_per_rve = int(engine), int(threads_per_rve)
+    o.cg_tol, o.cg_max_iter = float(cg_tol), int(cg_max_iter)
+    return o
+
+
+def _ptr(a):
+    """Pointer and kind of a numpy array (host) or torch tensor (host or device)."""
+    if a is None:
+        return None, PTR_HOST
+    if hasattr(a, "data_ptr"):
+        return a.data_ptr(), (PTR_DEVICE if a.is_cuda else PTR_HOST)
+    return a.ctypes.data, PTR_HOST
+
+
+class Batch:
+    """A packed batch of RVE networks resident on the current HIP device."""
+
+    def __init__(self, nets, opts: Opts | None = None, c_per_rve=None, V0=None, **kw):
+        self._keep = {}
+        node_off = np.ascontiguousarray(nets.node_off, np.int64)
+        fib_off = np.ascontiguousarray(nets.fib_off, np.int64)
+        X = np.ascontiguousarray(nets.X, np.float64)
+        ib = np.ascontiguousarray(nets.is_bnd, np.uint8)
+        fib = np.ascontiguousarray(nets.fib, np.int32)
+        self.n_rve = int(len(node_off) - 1)
+        V0a = None if V0 is None else np.ascontiguousarray(np.broadcast_to(V0, (self.n_rve,)), np.float64)
+        d = NetDesc(self.n_rve, node_off.ctypes.data, fib_off.ctypes.data, X.ctypes.data, ib.ctypes.data,
+                    fib.ctypes.data, None if V0a is None else V0a.ctypes.data)
+        self.opts = opts if opts is not None else make_opts(**kw)
+        cpr = None
+        if c_per_rve is not None:
+            cpr = np.ascontiguousarray(np.broadcast_to(c_per_rve, (self.n_rve,)), np.float64)
+            self.opts.c_per_rve = cpr.ctypes.data
+        h = C.c_void_p()
+        _check(lib().rve_batch_create(C.byref(d), C.byref(self.opts), C.byref(h)))
+        self.opts.c_per_rve = None
+        self._h = h
+        self.node_off = node_off
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().rve_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_opts(self, opts: Opts | None = None, c_per_rve=None, **kw):
+        o = opts if opts is not None else make_opts(**kw)
+        cpr = None
+        if c_per_rve is not None:
+            cpr = np.ascontiguousarray(np.broadcast_to(c_per_rve, (self.n_rve,)), np.float64)
+            o.c_per_rve = cpr.ctypes.data
+        _check(lib().rve_batch_set_opts(self._h, C.byref(o)))
+        o.c_per_rve = None
+        self.opts = o
+
+    def set_stream(self, stream_handle):
+        _check(lib().rve_batch_set_stream(self._h, stream_handle))
+
+    def sizes(self):
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().rve_batch_sizes(self._h, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
+    def _outs(self, F, shape_tail, dtype):
+        """Allocate outputs like F (numpy on host, torch on F's device)."""
+        if hasattr(F, "data_ptr"):
+            import torch
+            tdt = {np.float64: torch.float64, np.int32: torch.int32, np.int64: torch.int64}[dtype]
+            return torch.empty((self.n_rve, *shape_tail), dtype=tdt, device=F.device)
+        return np.empty((self.n_rve, *shape_tail), dtype=dtype)
+
+    def solve(self, F, stats=False):
+        """Relax all RVEs under F[R,3,3]; returns sigma[R,3,3], status[R] (and stats)."""
+        if hasattr(F, "data_ptr"):
+            F = F.contiguous()
+            if F.is_cuda:
+                import torch
+                self.set_stream(C.c_void_p(torch.cuda.current_stream(F.device).cuda_stream))
+        else:
+            F = np.ascontiguousarray(F, np.float64).reshape(self.n_rve, 3, 3)
+        sig = self._outs(F, (3, 3), np.float64)
+        st = self._outs(F, (), np.int32)
+        fp, kind = _ptr(F)
+        S = None
+        out = {}
+        if stats:
+            out = {"iters": self._outs(F, (), np.int64), "R": self._outs(F, (), np.float64),
+                   "D": self._outs(F, (), np.float64), "Fb": self._outs(F, (), np.float64)}
+            S = Stats(_ptr(out["iters"])[0], _ptr(out["R"])[0], _ptr(out["D"])[0], _ptr(out["Fb"])[0])
+        _check(lib().rve_batch_solve(self._h, fp, _ptr(sig)[0], _ptr(st)[0], C.byref(S) if S else None, kind))
+        return (sig, st, out) if stats else (sig, st)
+
+    def tangent(self, like=None):
+        """dsigma/dF [R,9,9] at the last solve's state, and status [R]."""
+        ref = like if like is not None else np.empty(0)
+        ds = self._outs(ref, (9, 9), np.float64)
+        st = self._outs(ref, (), np.int32)
+        _check(lib().rve_batch_tangent(self._h, _ptr(ds)[0], _ptr(st)[0], _ptr(ds)[1]))
+        return ds, st
+
+    def vjp(self, gsigma):
+        """g_F[R,3,3] = sum_ij g_ij dsigma_ij/dF at the last solve's state."""
+        if hasattr(gsigma, "data_ptr"):
+            gsigma = gsigma.contiguous()
+        else:
+            gsigma = np.ascontiguousarray(gsigma, np.float64)
+        gF = self._outs(gsigma, (3, 3), np.float64)
+        st = self._outs(gsigma, (), np.int32)
+        gp, kind = _ptr(gsigma)
+        _check(lib().rve_batch_vjp(self._h, gp, _ptr(gF)[0], _ptr(st)[0], kind))
+        return gF, st
+
+    def positions(self, r):
+        nn = int(self.node_off[r + 1] - self.node_off[r])
+        x = np.empty((nn, 3))
+        _check(lib().rve_batch_positions(self._h, int(r), x.ctypes.data))
+        return x

@@ -1,0 +1,777 @@
+// Host runtime and C ABI of the batched RVE solver (the "RVE batch manager"
+// of Section 4.2: data marshalling on the CPU, solver selection, launches).
+//
+// rve_batch_create validates the networks on the host before touching the
+// device, so malformed input is rejected (RVE_EINVAL) even where no GPU is
+// present.  Packing per RVE: free nodes first in breadth-first locality
+// order, boundary nodes last; fibers sorted by their lower end; reference
+// fiber vectors, rest lengths and lumped masses in FP64; CSR node->fiber
+// incidence with the end sign.  All RVEs of a batch share one device
+// allocation in row-offset + value layout (the packed-view layout of
+// Section 4.2).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/rve_batch.h"
+#include "rve_internal.h"
+
+using namespace rve;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(RVE_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+struct DeviceArena {
+    char* base = nullptr;
+    size_t used = 0, cap = 0;
+    size_t reserve(size_t bytes)
+    {
+        size_t off = (used + 255) & ~size_t(255);
+        used = off + bytes;
+        return off;
+    }
+};
+
+}  // namespace
+
+struct rve_batch {
+    int64_t R = 0, NN = 0, NF = 0, NFREE = 0, NBND = 0;
+    std::vector<int64_t> node_off, fib_off, free_off, bnd_off;
+    std::vector<int32_t> newid;        // [NN] original node -> reordered local id
+    std::vector<double> Xm;            // [NN][3] centred reference coordinates (original order)
+    std::vector<int64_t> nf_of, nfib_of;
+    std::vector<int32_t> maxdeg_of;
+    rve_opts opts{};
+    std::vector<double> c_host;
+    int device = 0, n_cu = 0;
+    // device memory
+    char* dmem = nullptr;
+    DevNet net{};
+    double *dF = nullptr, *dc = nullptr, *dsigma = nullptr, *dR = nullptr, *dD = nullptr, *dB = nullptr;
+    double *dh = nullptr, *dV0 = nullptr;
+    int32_t *dstatus = nullptr, *dqueue = nullptr, *dlist = nullptr;
+    int64_t* diters = nullptr;
+    void *ws_fib = nullptr, *ws_node = nullptr;
+    size_t ws_fib_bytes = 0, ws_node_bytes = 0;
+    // engine assignment: RVE ids per launch group, in longest-first order
+    std::vector<int32_t> group_variant;        // resident variant per group, -1 = streamed
+    std::vector<std::vector<int32_t>> groups;  // RVE ids
+    std::vector<int32_t> group_first;          // offset of each group's ids in dlist
+    std::vector<size_t> group_lds;
+    bool have_state = false;
+    bool variant_spills[2][kNumResident] = {};   // [fp64][variant]: the variant uses private memory
+    // tangent / vjp workspace
+    void* t_par = nullptr;
+    float* t_vec = nullptr;
+    double* t_out = nullptr;
+    double* t_in = nullptr;
+    int32_t* t_status = nullptr;
+    size_t t_par_bytes = 0, t_vec_bytes = 0;
+};
+
+// ------------------------------------------------------------------ helpers
+static int validate_opts(const rve_opts* o, int64_t R)
+{
+    if (!o) return fail(RVE_EINVAL, "opts is NULL");
+    if (o->precision != RVE_FP64 && o->precision != RVE_MIXED) return fail(RVE_EINVAL, "bad precision");
+    if (o->law != RVE_LAW_LINEAR && o->law != RVE_LAW_EXP) return fail(RVE_EINVAL, "bad law");
+    if (o->mass != RVE_MASS_LUMPED && o->mass != RVE_MASS_SCALED) return fail(RVE_EINVAL, "bad mass mode");
+    if (o->init != RVE_INIT_AFFINE && o->init != RVE_INIT_WARM) return fail(RVE_EINVAL, "bad init");
+    if (!(o->EA > 0) || !std::isfinite(o->EA)) return fail(RVE_EINVAL, "EA must be positive");
+    if (o->law == RVE_LAW_EXP && (!(o->B > 0) || !std::isfinite(o->B))) return fail(RVE_EINVAL, "B must be positive");
+    if (!(o->rhoA > 0) || !std::isfinite(o->rhoA)) return fail(RVE_EINVAL, "rhoA must be positive");
+    if (!(o->alpha > 0) || !(o->alpha <= 1.0)) return fail(RVE_EINVAL, "alpha must be in (0, 1]");
+    if (!o->c_per_rve && (!(o->c >= 0) || !std::isfinite(o->c))) return fail(RVE_EINVAL, "c must be >= 0");
+    if (o->c_per_rve)
+        for (int64_t r = 0; r < R; ++r)
+            if (!(o->c_per_rve[r] >= 0) || !std::isfinite(o->c_per_rve[r]))
+                return fail(RVE_EINVAL, "c_per_rve[" + std::to_string(r) + "] must be >= 0");
+    if (!(o->tol_abs >= 0) || !(o->tol_rel >= 0)) return fail(RVE_EINVAL, "tolerances must be >= 0");
+    if (o->n_max < 0) return fail(RVE_EINVAL, "n_max must be >= 0");
+    if (o->check_every < 1) return fail(RVE_EINVAL, "check_every must be >= 1");
+    if (o->engine != RVE_ENGINE_AUTO && o->engine != RVE_ENGINE_STREAMED && o->engine != RVE_ENGINE_NAIVE)
+        return fail(RVE_EINVAL, "bad engine");
+    if (o->engine == RVE_ENGINE_NAIVE && o->precision != RVE_FP64)
+        return fail(RVE_EINVAL, "the naive engine is FP64 only");
+    if (!(o->cg_tol > 0) || o->cg_max_iter < 0) return fail(RVE_EINVAL, "cg_tol must be > 0, cg_max_iter >= 0");
+    if (o->threads_per_rve != 0 && o->threads_per_rve != 256 && o->threads_per_rve != 512 &&
+        o->threads_per_rve != 1024)
+        return fail(RVE_EINVAL, "threads_per_rve must be 0, 256, 512 or 1024");
+    return RVE_OK;
+}
+
+static int validate_net(const rve_net_desc* d)
+{
+    if (!d) return fail(RVE_EINVAL, "net is NULL");
+    if (d->n_rve < 0) return fail(RVE_EINVAL, "n_rve < 0");
+    if (d->n_rve == 0) return RVE_OK;
+    if (!d->node_off || !d->fib_off || !d->X || !d->is_bnd || !d->fib)
+        return fail(RVE_EINVAL, "NULL array in net");
+    if (d->node_off[0] != 0 || d->fib_off[0] != 0) return fail(RVE_EINVAL, "offsets must start at 0");
+    for (int64_t r = 0; r < d->n_rve; ++r) {
+        int64_t n0 = d->node_off[r], n1 = d->node_off[r + 1], f0 = d->fib_off[r], f1 = d->fib_off[r + 1];
+        std::string rs = "RVE " + std::to_string(r) + ": ";
+        if (n1 < n0 || f1 < f0) return fail(RVE_EINVAL, rs + "offsets decrease");
+        int64_t nn = n1 - n0;
+        if (nn >= 65535) return fail(RVE_EINVAL, rs + "65535 or more nodes");
+        bool anyb = false;
+        for (int64_t p = n0; p < n1; ++p) {
+            if (d->is_bnd[p] > 1) return fail(RVE_EINVAL, rs + "is_bnd must be 0 or 1");
+            anyb |= d->is_bnd[p] != 0;
+            for (int k = 0; k < 3; ++k)
+                if (!std::isfinite(d->X[3 * p + k])) return fail(RVE_EINVAL, rs + "non-finite coordinate");
+        }
+        if (!anyb) return fail(RVE_EINVAL, rs + "no boundary node");
+        for (int64_t k = f0; k < f1; ++k) {
+            int32_t i = d->fib[2 * k], j = d->fib[2 * k + 1];
+            if (i < 0 || j < 0 || i >= nn || j >= nn)
+                return fail(RVE_EINVAL, rs + "fiber " + std::to_string(k - f0) + " has a node id out of range");
+            if (i == j) return fail(RVE_EINVAL, rs + "fiber " + std::to_string(k - f0) + " joins a node to itself");
+            const double* a = d->X + 3 * (n0 + i);
+            const double* b = d->X + 3 * (n0 + j);
+            double L = std::sqrt((b[0] - a[0]) * (b[0] - a[0]) + (b[1] - a[1]) * (b[1] - a[1]) +
+                                 (b[2] - a[2]) * (b[2] - a[2]));
+            if (!(L > 0)) return fail(RVE_EINVAL, rs + "fiber " + std::to_string(k - f0) + " has zero length");
+        }
+        if (d->V0 && !(d->V0[r] > 0)) return fail(RVE_EINVAL, rs + "V0 must be positive");
+    }
+    return RVE_OK;
+}
+
+// Host packing of one batch (everything except the upload).
+struct HostPack {
+    std::vector<int64_t> fib_off, free_off, bnd_off;
+    std::vector<double> d0, L0, mass, Xb;
+    std::vector<uint32_t> ends, inc, binc;
+    std::vector<int64_t> inc_off, binc_off;
+    std::vector<int32_t> newid;
+    std::vector<int64_t> nf, nfib;
+    std::vector<int32_t> maxdeg;
+};
+
+static void pack_batch(const rve_net_desc* d, HostPack& P)
+{
+    const int64_t R = d->n_rve;
+    P.fib_off.assign(R + 1, 0);
+    P.free_off.assign(R + 1, 0);
+    P.bnd_off.assign(R + 1, 0);
+    const int64_t NN = R ? d->node_off[R] : 0, NF = R ? d->fib_off[R] : 0;
+    P.newid.assign(NN, -1);
+    P.d0.resize(3 * NF);
+    P.L0.resize(NF);
+    P.ends.resize(NF);
+    P.nf.assign(R, 0);
+    P.nfib.assign(R, 0);
+    P.maxdeg.assign(R, 0);
+    P.inc_off.push_back(0);
+    P.binc_off.push_back(0);
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> adj;
+    for (int64_t r = 0; r < R; ++r) {
+        const int64_t n0 = d->node_off[r], nn = d->node_off[r + 1] - n0;
+        const int64_t f0 = d->fib_off[r], nfib = d->fib_off[r + 1] - f0;
+        const uint8_t* ib = d->is_bnd + n0;
+        const int32_t* fb = d->fib + 2 * f0;
+        adj.assign(nn, {});
+        for (int64_t k = 0; k < nfib; ++k) {
+            adj[fb[2 * k]].push_back({fb[2 * k + 1], (int32_t)k});
+            adj[fb[2 * k + 1]].push_back({fb[2 * k], (int32_t)k});
+        }
+        // breadth-first order of the free nodes (locality), seeded at the
+        // lowest-degree unvisited free node of each component
+        std::vector<int32_t> order;
+        order.reserve(nn);
+        std::vector<char> seen(nn, 0);
+        std::vector<int32_t> seeds;
+        for (int32_t p = 0; p < nn; ++p)
+            if (!ib[p]) seeds.push_back(p);
+        std::stable_sort(seeds.begin(), seeds.end(),
+                         [&](int32_t a, int32_t b) { return adj[a].size() < adj[b].size(); });
+        for (int32_t s : seeds) {
+            if (seen[s]) continue;
+            size_t head = order.size();
+            order.push_back(s);
+            seen[s] = 1;
+            while (head < order.size()) {
+                int32_t u = order[head++];
+                for (auto& e : adj[u])
+                    if (!ib[e.first] && !seen[e.first]) {
+                        seen[e.first] = 1;
+                        order.push_back(e.first);
+                    }
+            }
+        }
+        const int64_t nf = (int64_t)order.size();
+        for (int32_t p = 0; p < nn; ++p)
+            if (ib[p]) order.push_back(p);
+        std::vector<int32_t> nid(nn);
+        for (int64_t q = 0; q < nn; ++q) nid[order[q]] = (int32_t)q;
+        for (int64_t q = 0; q < nn; ++q) P.newid[n0 + q] = nid[q];
+        P.nf[r] = nf;
+        P.nfib[r] = nfib;
+        P.fib_off[r + 1] = P.fib_off[r] + nfib;
+        P.free_off[r + 1] = P.free_off[r] + nf;
+        P.bnd_off[r + 1] = P.bnd_off[r] + (nn - nf);
+        // fibers sorted by their lower reordered end
+        std::vector<int32_t> fo(nfib);
+        for (int64_t k = 0; k < nfib; ++k) fo[k] = (int32_t)k;
+        std::stable_sort(fo.begin(), fo.end(), [&](int32_t a, int32_t b) {
+            int32_t la = std::min(nid[fb[2 * a]], nid[fb[2 * a + 1]]), lb = std::min(nid[fb[2 * b]], nid[fb[2 * b + 1]]);
+            if (la != lb) return la < lb;
+            return std::max(nid[fb[2 * a]], nid[fb[2 * a + 1]]) < std::max(nid[fb[2 * b]], nid[fb[2 * b + 1]]);
+        });
+        std::vector<int32_t> fpos(nfib);
+        std::vector<std::vector<uint32_t>> inc_of(nn);
+        for (int64_t q = 0; q < nfib; ++q) {
+            int32_t k = fo[q];
+            fpos[k] = (int32_t)q;
+            int32_t i = fb[2 * k], j = fb[2 * k + 1];
+            const double* Xi = d->X + 3 * (n0 + i);
+            const double* Xj = d->X + 3 * (n0 + j);
+            int64_t g = P.fib_off[r] + q;
+            double dx = Xj[0] - Xi[0], dy = Xj[1] - Xi[1], dz = Xj[2] - Xi[2];
+            P.d0[3 * g] = dx;
+            P.d0[3 * g + 1] = dy;
+            P.d0[3 * g + 2] = dz;
+            P.L0[g] = std::sqrt(dx * dx + dy * dy + dz * dz);
+            P.ends[g] = (uint32_t)nid[i] | ((uint32_t)nid[j] << 16);
+            inc_of[nid[i]].push_back((uint32_t)q | (1u << 31));
+            inc_of[nid[j]].push_back((uint32_t)q);
+        }
+        for (int64_t q = 0; q < nn; ++q)
+            std::sort(inc_of[q].begin(), inc_of[q].end(),
+                      [](uint32_t a, uint32_t b) { return (a & 0x7fffffffu) < (b & 0x7fffffffu); });
+        int32_t md = 0;
+        for (int64_t q = 0; q < nf; ++q) {
+            double m = 0.0;
+            for (uint32_t w : inc_of[q]) {
+                m += 0.5 * P.L0[P.fib_off[r] + (w & 0x7fffffffu)];
+                P.inc.push_back(w);
+            }
+            P.mass.push_back(m);
+            P.inc_off.push_back((int64_t)P.inc.size());
+            md = std::max<int32_t>(md, (int32_t)inc_of[q].size());
+        }
+        P.maxdeg[r] = md;
+        for (int64_t q = nf; q < nn; ++q) {
+            for (uint32_t w : inc_of[q]) P.binc.push_back(w);
+            P.binc_off.push_back((int64_t)P.binc.size());
+            const double* X = d->X + 3 * (n0 + order[q]);
+            P.Xb.push_back(X[0] - 0.5);
+            P.Xb.push_back(X[1] - 0.5);
+            P.Xb.push_back(X[2] - 0.5);
+        }
+    }
+}
+
+template <typename T>
+static T* carve(char* base, size_t off)
+{
+    return reinterpret_cast<T*>(base + off);
+}
+
+// Assign every RVE to an engine/variant group, longest-first inside a group.
+static void assign_groups(rve_batch* b)
+{
+    b->groups.clear();
+    b->group_variant.clear();
+    b->group_lds.clear();
+    const bool fp64 = b->opts.precision == RVE_FP64;
+    const int T = b->opts.threads_per_rve;
+    std::vector<std::vector<int32_t>> per(kNumResident + 1);
+    size_t lds_cap = 160 * 1024 - 4096;   // static shared of the kernel (reduction slots) stays below 4 KB
+    for (int64_t r = 0; r < b->R; ++r) {
+        int chosen = -1;
+        if (b->opts.engine == RVE_ENGINE_AUTO && b->maxdeg_of[r] <= kMaxResidentDegree && b->nfib_of[r] < 32767) {
+            size_t lds = resident_lds_bytes(fp64, b->nf_of[r], b->nfib_of[r], 0);
+            if (lds <= lds_cap) {
+                int64_t best_cap = -1;
+                for (int v = 0; v < kNumResident; ++v) {
+                    const ResidentVariant& rv = kResident[v];
+                    if (T && rv.threads != T) continue;
+                    if (b->variant_spills[fp64 ? 1 : 0][v] && !T) continue;
+                    int64_t capf = (int64_t)rv.threads * rv.sf, capn = (int64_t)rv.threads * rv.sn;
+                    if (b->nfib_of[r] > capf || b->nf_of[r] > capn) continue;
+                    // smallest register footprint first, then more threads
+                    int64_t key = (int64_t)(rv.sf * 5 + rv.sn * 12) * 4096 - rv.threads;
+                    if (chosen < 0 || key < best_cap) {
+                        chosen = v;
+                        best_cap = key;
+                    }
+                }
+            }
+        }
+        per[chosen < 0 ? kNumResident : chosen].push_back((int32_t)r);
+    }
+    for (int v = 0; v <= kNumResident; ++v) {
+        if (per[v].empty()) continue;
+        std::stable_sort(per[v].begin(), per[v].end(),
+                         [&](int32_t a, int32_t c) { return b->nfib_of[a] > b->nfib_of[c]; });
+        size_t lds = 0;
+        if (v < kNumResident)
+            for (int32_t r : per[v]) lds = std::max(lds, resident_lds_bytes(fp64, b->nf_of[r], b->nfib_of[r], 0));
+        b->groups.push_back(per[v]);
+        b->group_variant.push_back(v < kNumResident ? v : -1);
+        b->group_lds.push_back(lds);
+    }
+}
+
+static int upload_groups(rve_batch* b)
+{
+    std::vector<int32_t> flat;
+    b->group_first.clear();
+    for (auto& g : b->groups) {
+        b->group_first.push_back((int32_t)flat.size());
+        flat.insert(flat.end(), g.begin(), g.end());
+    }
+    if (!flat.empty()) HIP_TRY(hipMemcpy(b->dlist, flat.data(), flat.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    return RVE_OK;
+}
+
+static int ensure_workspace(rve_batch* b)
+{
+    bool need = false;
+    for (int v : b->group_variant) need |= (v < 0);
+    if (!need) return RVE_OK;
+    const size_t r4 = b->opts.precision == RVE_FP64 ? 32 : 16;
+    size_t fb = r4 * 2 * (size_t)(b->NF + b->R);
+    size_t nb = r4 * (2 * (size_t)(b->NFREE + b->R) + 2 * (size_t)b->NFREE + 1);
+    if (fb > b->ws_fib_bytes) {
+        if (b->ws_fib) (void)hipFree(b->ws_fib);
+        b->ws_fib = nullptr;
+        b->ws_fib_bytes = 0;
+        if (hipMalloc(&b->ws_fib, fb) != hipSuccess) return fail(RVE_ENOMEM, "workspace allocation failed");
+        b->ws_fib_bytes = fb;
+    }
+    if (nb > b->ws_node_bytes) {
+        if (b->ws_node) (void)hipFree(b->ws_node);
+        b->ws_node = nullptr;
+        b->ws_node_bytes = 0;
+        if (hipMalloc(&b->ws_node, nb) != hipSuccess) return fail(RVE_ENOMEM, "workspace allocation failed");
+        b->ws_node_bytes = nb;
+    }
+    return RVE_OK;
+}
+
+int rve_naive_run(const SolveArgs& A, const std::vector<int64_t>& fib_off, const std::vector<int64_t>& free_off,
+                  const std::vector<int64_t>& bnd_off, const std::vector<double>& F, const std::vector<double>& c,
+                  hipStream_t s, std::string* err);
+
+// ------------------------------------------------------------------ ABI
+extern "C" {
+
+int rve_version(void) { return RVE_API_VERSION; }
+
+const char* rve_last_error(void) { return g_last_error.c_str(); }
+
+void rve_default_opts(rve_opts* o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->precision = RVE_FP64;
+    o->law = RVE_LAW_LINEAR;
+    o->mass = RVE_MASS_LUMPED;
+    o->init = RVE_INIT_AFFINE;
+    o->EA = 1.0;
+    o->B = 10.0;
+    o->rhoA = 1.0;
+    o->alpha = 0.9;
+    o->c = 2.0;
+    o->tol_abs = 1e-10;
+    o->tol_rel = 0.0;
+    o->n_max = 1000000;
+    o->check_every = 1;
+    o->engine = RVE_ENGINE_AUTO;
+    o->cg_tol = 1e-6;
+    o->cg_max_iter = 0;
+}
+
+int rve_batch_create(const rve_net_desc* net, const rve_opts* opts, rve_batch** out)
+{
+    if (!out) return fail(RVE_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate_net(net);
+    if (rc) return rc;
+    rc = validate_opts(opts, net->n_rve);
+    if (rc) return rc;
+
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(RVE_EDEVICE, "no HIP device");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(RVE_EDEVICE, std::string("device is ") + prop.gcnArchName + ", the kernels are built for gfx950");
+
+    rve_batch* b = new (std::nothrow) rve_batch();
+    if (!b) return fail(RVE_ENOMEM, "host allocation failed");
+    b->device = dev;
+    b->n_cu = prop.multiProcessorCount;
+    for (int p = 0; p < 2; ++p)
+        for (int v = 0; v < kNumResident; ++v) {
+            size_t sb = 0;
+            if (resident_scratch_bytes(v, p == 1, &sb) == hipSuccess) b->variant_spills[p][v] = sb > 0;
+        }
+    b->R = net->n_rve;
+    b->opts = *opts;
+    b->c_host.assign(b->R, opts->c);
+    if (opts->c_per_rve) std::copy(opts->c_per_rve, opts->c_per_rve + b->R, b->c_host.begin());
+    b->opts.c_per_rve = nullptr;
+
+    HostPack P;
+    try {
+        pack_batch(net, P);
+    } catch (const std::bad_alloc&) {
+        delete b;
+        return fail(RVE_ENOMEM, "host allocation failed while packing");
+    }
+    const int64_t R = b->R;
+    b->NN = R ? net->node_off[R] : 0;
+    b->NF = R ? net->fib_off[R] : 0;
+    b->NFREE = P.free_off[R];
+    b->NBND = P.bnd_off[R];
+    b->node_off.assign(net->node_off, net->node_off + R + 1);
+    b->fib_off = P.fib_off;
+    b->free_off = P.free_off;
+    b->bnd_off = P.bnd_off;
+    b->newid = P.newid;
+    b->nf_of = P.nf;
+    b->nfib_of = P.nfib;
+    b->maxdeg_of = P.maxdeg;
+    b->Xm.resize(3 * b->NN);
+    for (int64_t p = 0; p < 3 * b->NN; ++p) b->Xm[p] = net->X[p] - 0.5;
+
+    // one device allocation for the network, per-RVE inputs/outputs and state
+    DeviceArena A;
+    size_t o_fib_off = A.reserve(8 * (R + 1)), o_free_off = A.reserve(8 * (R + 1)), o_bnd_off = A.reserve(8 * (R + 1));
+    size_t o_d0 = A.reserve(24 * b->NF), o_L0 = A.reserve(8 * b->NF), o_ends = A.reserve(4 * b->NF);
+    size_t o_mass = A.reserve(8 * b->NFREE), o_inc_off = A.reserve(8 * (b->NFREE + 1)),
+           o_inc = A.reserve(4 * P.inc.size() + 4);
+    size_t o_binc_off = A.reserve(8 * (b->NBND + 1)), o_binc = A.reserve(4 * P.binc.size() + 4);
+    size_t o_Xb = A.reserve(24 * b->NBND), o_V0 = A.reserve(8 * R);
+    size_t o_F = A.reserve(72 * R), o_c = A.reserve(8 * R), o_sig = A.reserve(72 * R), o_R = A.reserve(8 * R),
+           o_D = A.reserve(8 * R), o_B = A.reserve(8 * R), o_h = A.reserve(24 * b->NFREE + 8),
+           o_st = A.reserve(4 * R), o_it = A.reserve(8 * R), o_q = A.reserve(256), o_list = A.reserve(4 * R + 4);
+    if (hipMalloc(&b->dmem, A.used + 256) != hipSuccess) {
+        delete b;
+        return fail(RVE_ENOMEM, "device allocation of " + std::to_string(A.used) + " bytes failed");
+    }
+    char* m = b->dmem;
+    auto up = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
+        if (!bytes) return hipSuccess;
+        return hipMemcpy(m + off, src, bytes, hipMemcpyHostToDevice);
+    };
+    std::vector<double> V0(R, 1.0);
+    if (net->V0) std::copy(net->V0, net->V0 + R, V0.begin());
+    hipError_t e = hipSuccess;
+    e = e ? e : up(o_fib_off, P.fib_off.data(), 8 * (R + 1));
+    e = e ? e : up(o_free_off, P.free_off.data(), 8 * (R + 1));
+    e = e ? e : up(o_bnd_off, P.bnd_off.data(), 8 * (R + 1));
+    e = e ? e : up(o_d0, P.d0.data(), 24 * b->NF);
+    e = e ? e : up(o_L0, P.L0.data(), 8 * b->NF);
+    e = e ? e : up(o_ends, P.ends.data(), 4 * b->NF);
+    e = e ? e : up(o_mass, P.mass.data(), 8 * b->NFREE);
+    e = e ? e : up(o_inc_off, P.inc_off.data(), 8 * (b->NFREE + 1));
+    e = e ? e : up(o_inc, P.inc.data(), 4 * P.inc.size());
+    e = e ? e : up(o_binc_off, P.binc_off.data(), 8 * (b->NBND + 1));
+    e = e ? e : up(o_binc, P.binc.data(), 4 * P.binc.size());
+    e = e ? e : up(o_Xb, P.Xb.data(), 24 * b->NBND);
+    e = e ? e : up(o_V0, V0.data(), 8 * R);
+    e = e ? e : up(o_c, b->c_host.data(), 8 * R);
+    e = e ? e : hipMemset(m + o_h, 0, 24 * b->NFREE + 8);
+    if (e != hipSuccess) {
+        (void)hipFree(b->dmem);
+        delete b;
+        return fail(RVE_EDEVICE, std::string("upload failed: ") + hipGetErrorString(e));
+    }
+    DevNet& n = b->net;
+    n.n_rve = R;
+    n.fib_off = carve<int64_t>(m, o_fib_off);
+    n.free_off = carve<int64_t>(m, o_free_off);
+    n.bnd_off = carve<int64_t>(m, o_bnd_off);
+    n.d0 = carve<double>(m, o_d0);
+    n.L0 = carve<double>(m, o_L0);
+    n.ends = carve<uint32_t>(m, o_ends);
+    n.mass = carve<double>(m, o_mass);
+    n.inc_off = carve<int64_t>(m, o_inc_off);
+    n.inc = carve<uint32_t>(m, o_inc);
+    n.binc_off = carve<int64_t>(m, o_binc_off);
+    n.binc = carve<uint32_t>(m, o_binc);
+    n.Xb = carve<double>(m, o_Xb);
+    n.V0 = carve<double>(m, o_V0);
+    b->dV0 = carve<double>(m, o_V0);
+    b->dF = carve<double>(m, o_F);
+    b->dc = carve<double>(m, o_c);
+    b->dsigma = carve<double>(m, o_sig);
+    b->dR = carve<double>(m, o_R);
+    b->dD = carve<double>(m, o_D);
+    b->dB = carve<double>(m, o_B);
+    b->dh = carve<double>(m, o_h);
+    b->dstatus = carve<int32_t>(m, o_st);
+    b->diters = carve<int64_t>(m, o_it);
+    b->dqueue = carve<int32_t>(m, o_q);
+    b->dlist = carve<int32_t>(m, o_list);
+
+    assign_groups(b);
+    rc = upload_groups(b);
+    if (rc) {
+        rve_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return RVE_OK;
+}
+
+int rve_batch_set_opts(rve_batch* b, const rve_opts* opts)
+{
+    if (!b) return fail(RVE_EINVAL, "batch is NULL");
+    int rc = validate_opts(opts, b->R);
+    if (rc) return rc;
+    b->opts = *opts;
+    b->c_host.assign(b->R, opts->c);
+    if (opts->c_per_rve) std::copy(opts->c_per_rve, opts->c_per_rve + b->R, b->c_host.begin());
+    b->opts.c_per_rve = nullptr;
+    if (b->R) HIP_TRY(hipMemcpy(b->dc, b->c_host.data(), 8 * b->R, hipMemcpyHostToDevice));
+    assign_groups(b);
+    return upload_groups(b);
+}
+
+int rve_batch_set_stream(rve_batch* b, void* stream)
+{
+    if (!b) return fail(RVE_EINVAL, "batch is NULL");
+    b->opts.stream = stream;
+    return RVE_OK;
+}
+
+int rve_batch_sizes(const rve_batch* b, int64_t* n_rve, int64_t* n_nodes, int64_t* n_fib)
+{
+    if (!b) return fail(RVE_EINVAL, "batch is NULL");
+    if (n_rve) *n_rve = b->R;
+    if (n_nodes) *n_nodes = b->NN;
+    if (n_fib) *n_fib = b->NF;
+    return RVE_OK;
+}
+
+
+int rve_batch_solve(rve_batch* b, const double* F, double* sigma, int32_t* status, rve_stats* stats,
+                    int32_t ptr_kind)
+{
+    if (!b) return fail(RVE_EINVAL, "batch is NULL");
+    if (ptr_kind != RVE_PTR_HOST && ptr_kind != RVE_PTR_DEVICE) return fail(RVE_EINVAL, "bad ptr_kind");
+    if (b->R == 0) return RVE_OK;
+    if (!F || !sigma || !status) return fail(RVE_EINVAL, "F, sigma and status are required");
+    if (b->opts.init == RVE_INIT_WARM && !b->have_state)
+        return fail(RVE_ESTATE, "warm start requested before any solve");
+    hipStream_t s = (hipStream_t)b->opts.stream;
+    const hipMemcpyKind in_kind = ptr_kind == RVE_PTR_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    const hipMemcpyKind out_kind = ptr_kind == RVE_PTR_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    HIP_TRY(hipMemcpyAsync(b->dF, F, 72 * b->R, in_kind, s));
+    int rc = ensure_workspace(b);
+    if (rc) return rc;
+
+    SolveArgs a{};
+    a.net = b->net;
+    a.F = b->dF;
+    a.c = b->dc;
+    a.queue = b->dqueue;
+    a.law = b->opts.law;
+    a.mass_mode = b->opts.mass;
+    a.init = b->opts.init;
+    a.check_every = b->opts.check_every;
+    a.EA = b->opts.EA;
+    a.B = b->opts.B;
+    a.rhoA = b->opts.rhoA;
+    a.alpha = b->opts.alpha;
+    a.tol_abs = b->opts.tol_abs;
+    a.tol_rel = b->opts.tol_rel;
+    a.n_max = b->opts.n_max;
+    a.sigma = b->dsigma;
+    a.status = b->dstatus;
+    a.iters = b->diters;
+    a.Rres = b->dR;
+    a.Dres = b->dD;
+    a.Bres = b->dB;
+    a.h_state = b->dh;
+    a.ws_fib = b->ws_fib;
+    a.ws_node = b->ws_node;
+
+    if (b->opts.engine == RVE_ENGINE_NAIVE) {
+        std::vector<double> Fh(9 * b->R);
+        HIP_TRY(hipMemcpyAsync(Fh.data(), b->dF, 72 * b->R, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        std::string err;
+        rc = rve_naive_run(a, b->fib_off, b->free_off, b->bnd_off, Fh, b->c_host, s, &err);
+        if (rc) return fail(rc, err);
+    } else {
+        const bool fp64 = b->opts.precision == RVE_FP64;
+        for (size_t g = 0; g < b->groups.size(); ++g) {
+            a.list = b->dlist + b->group_first[g];
+            a.n_list = (int32_t)b->groups[g].size();
+            a.queue = b->dqueue + 2 * g;
+            HIP_TRY(hipMemsetAsync(a.queue, 0, sizeof(int32_t), s));
+            const int v = b->group_variant[g];
+            if (v >= 0) {
+                int per_cu = 1;
+                HIP_TRY(max_resident_blocks(v, fp64, b->group_lds[g], &per_cu));
+                if (per_cu < 1) return fail(RVE_EDEVICE, "resident kernel variant does not fit a CU");
+                int grid = std::min<int64_t>((int64_t)per_cu * b->n_cu, a.n_list);
+                HIP_TRY(launch_resident(v, fp64, a, b->group_lds[g], grid, s));
+            } else {
+                int threads = b->opts.threads_per_rve == 256 ? 256 : 1024;
+                int grid = std::min<int64_t>((int64_t)b->n_cu * (threads == 256 ? 4 : 2), a.n_list);
+                HIP_TRY(launch_streamed(fp64, a, grid, threads, s));
+            }
+        }
+        HIP_TRY(launch_stress(a, (int)b->R, s));
+    }
+    HIP_TRY(hipMemcpyAsync(sigma, b->dsigma, 72 * b->R, out_kind, s));
+    HIP_TRY(hipMemcpyAsync(status, b->dstatus, 4 * b->R, out_kind, s));
+    if (stats) {
+        if (stats->iters) HIP_TRY(hipMemcpyAsync(stats->iters, b->diters, 8 * b->R, out_kind, s));
+        if (stats->R) HIP_TRY(hipMemcpyAsync(stats->R, b->dR, 8 * b->R, out_kind, s));
+        if (stats->D) HIP_TRY(hipMemcpyAsync(stats->D, b->dD, 8 * b->R, out_kind, s));
+        if (stats->Fb) HIP_TRY(hipMemcpyAsync(stats->Fb, b->dB, 8 * b->R, out_kind, s));
+    }
+    if (ptr_kind == RVE_PTR_HOST) HIP_TRY(hipStreamSynchronize(s));
+    b->have_state = true;
+    return RVE_OK;
+}
+
+int rve_batch_positions(rve_batch* b, int64_t r, double* x)
+{
+    if (!b || !x) return fail(RVE_EINVAL, "NULL argument");
+    if (r < 0 || r >= b->R) return fail(RVE_EINVAL, "RVE index out of range");
+    if (!b->have_state) return fail(RVE_ESTATE, "no solve yet");
+    hipStream_t s = (hipStream_t)b->opts.stream;
+    HIP_TRY(hipStreamSynchronize(s));
+    const int64_t nf = b->nf_of[r], a0 = b->free_off[r];
+    std::vector<double> h(3 * nf), F(9);
+    if (nf) HIP_TRY(hipMemcpy(h.data(), b->dh + 3 * a0, 24 * nf, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(F.data(), b->dF + 9 * r, 72, hipMemcpyDeviceToHost));
+    const int64_t n0 = b->node_off[r], nn = b->node_off[r + 1] - n0;
+    for (int64_t p = 0; p < nn; ++p) {
+        const double* X = &b->Xm[3 * (n0 + p)];
+        int32_t q = b->newid[n0 + p];
+        for (int i = 0; i < 3; ++i) {
+            double v = F[3 * i] * X[0] + F[3 * i + 1] * X[1] + F[3 * i + 2] * X[2];
+            if (q < nf) v += h[3 * q + i];
+            x[3 * p + i] = v;
+        }
+    }
+    return RVE_OK;
+}
+
+static int ensure_tangent_ws(rve_batch* b, int W)
+{
+    size_t pb = 32 * (size_t)(b->NF + b->R);
+    size_t vb = 4 * sizeof(float) * (size_t)W * (size_t)(b->NFREE + b->R);
+    if (pb > b->t_par_bytes) {
+        if (b->t_par) (void)hipFree(b->t_par);
+        b->t_par = nullptr;
+        b->t_par_bytes = 0;
+        if (hipMalloc(&b->t_par, pb) != hipSuccess) return fail(RVE_ENOMEM, "tangent workspace allocation failed");
+        b->t_par_bytes = pb;
+    }
+    if (vb > b->t_vec_bytes) {
+        if (b->t_vec) (void)hipFree(b->t_vec);
+        b->t_vec = nullptr;
+        b->t_vec_bytes = 0;
+        if (hipMalloc(&b->t_vec, vb) != hipSuccess) return fail(RVE_ENOMEM, "tangent workspace allocation failed");
+        b->t_vec_bytes = vb;
+    }
+    if (!b->t_out) {
+        if (hipMalloc(&b->t_out, 8 * 81 * (size_t)b->R + 8) != hipSuccess ||
+            hipMalloc(&b->t_in, 8 * 9 * (size_t)b->R + 8) != hipSuccess ||
+            hipMalloc(&b->t_status, 4 * (size_t)b->R + 4) != hipSuccess)
+            return fail(RVE_ENOMEM, "tangent output allocation failed");
+    }
+    return RVE_OK;
+}
+
+static int run_cg(rve_batch* b, int mode, const double* gsigma, double* out, int32_t* status, int32_t ptr_kind)
+{
+    if (!b) return fail(RVE_EINVAL, "batch is NULL");
+    if (ptr_kind != RVE_PTR_HOST && ptr_kind != RVE_PTR_DEVICE) return fail(RVE_EINVAL, "bad ptr_kind");
+    if (b->R == 0) return RVE_OK;
+    if (!out || !status || (mode == 1 && !gsigma)) return fail(RVE_EINVAL, "NULL output or input");
+    if (!b->have_state) return fail(RVE_ESTATE, "no solve yet");
+    int rc = ensure_tangent_ws(b, mode == 0 ? 27 : 3);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)b->opts.stream;
+    const hipMemcpyKind in_kind = ptr_kind == RVE_PTR_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    const hipMemcpyKind out_kind = ptr_kind == RVE_PTR_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    if (mode == 1) HIP_TRY(hipMemcpyAsync(b->t_in, gsigma, 72 * b->R, in_kind, s));
+    TangentArgs a{};
+    a.net = b->net;
+    a.F = b->dF;
+    a.sigma = b->dsigma;
+    a.solve_status = b->dstatus;
+    a.h_state = b->dh;
+    a.gsigma = b->t_in;
+    a.out = b->t_out;
+    a.status = b->t_status;
+    a.queue = b->dqueue + 60;
+    a.mode = mode;
+    a.law = b->opts.law;
+    a.EA = b->opts.EA;
+    a.B = b->opts.B;
+    a.cg_tol = b->opts.cg_tol;
+    a.cg_max = b->opts.cg_max_iter;
+    a.n_free_total = b->NFREE;
+    a.n_rve = b->R;
+    a.ws_par = b->t_par;
+    a.ws_vec = b->t_vec;
+    HIP_TRY(hipMemsetAsync(a.queue, 0, sizeof(int32_t), s));
+    int grid = (int)std::min<int64_t>((int64_t)b->n_cu * 4, b->R);
+    HIP_TRY(launch_tangent(a, grid, s));
+    HIP_TRY(hipMemcpyAsync(out, b->t_out, (mode == 0 ? 648 : 72) * b->R, out_kind, s));
+    HIP_TRY(hipMemcpyAsync(status, b->t_status, 4 * b->R, out_kind, s));
+    if (ptr_kind == RVE_PTR_HOST) HIP_TRY(hipStreamSynchronize(s));
+    return RVE_OK;
+}
+
+int rve_batch_tangent(rve_batch* b, double* dsdF, int32_t* status, int32_t ptr_kind)
+{
+    return run_cg(b, 0, nullptr, dsdF, status, ptr_kind);
+}
+
+int rve_batch_vjp(rve_batch* b, const double* gsigma, double* gF, int32_t* status, int32_t ptr_kind)
+{
+    return run_cg(b, 1, gsigma, gF, status, ptr_kind);
+}
+
+void rve_batch_destroy(rve_batch* b)
+{
+    if (!b) return;
+    if (b->t_par) (void)hipFree(b->t_par);
+    if (b->t_vec) (void)hipFree(b->t_vec);
+    if (b->t_out) (void)hipFree(b->t_out);
+    if (b->t_in) (void)hipFree(b->t_in);
+    if (b->t_status) (void)hipFree(b->t_status);
+    if (b->dmem) (void)hipFree(b->dmem);
+    if (b->ws_fib) (void)hipFree(b->ws_fib);
+    if (b->ws_node) (void)hipFree(b->ws_node);
+    delete b;
+}
+
+}  // extern "C"

@@ -1,0 +1,97 @@
+// Internal layout shared by the host runtime (rve_host.hip) and the kernels
+// (rve_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rve {
+
+// Packed, reordered batch on the device.  Within an RVE the nodes are
+// renumbered free-first (ids 0..nf-1, locality ordered) and boundary-last
+// (ids nf..nn-1), so an operation over the free DOFs is a contiguous range
+// and boundary nodes never need their positions recomputed inside the loop
+// (the grouping of free and fixed DOFs of Section 3.2).
+struct DevNet {
+    int64_t n_rve;
+    const int64_t* fib_off;   // [R+1] fibers of RVE r: fib_off[r] .. fib_off[r+1]
+    const int64_t* free_off;  // [R+1] free nodes
+    const int64_t* bnd_off;   // [R+1] boundary nodes
+    const double* d0;         // [NF][3] reference fiber vector Xm_j - Xm_i
+    const double* L0;         // [NF] rest length |d0|
+    const uint32_t* ends;     // [NF] local ids i | (j << 16), free-first numbering
+    const double* mass;       // [NFREE] lumped mass rhoA/2 sum L0
+    const int64_t* inc_off;   // [NFREE+1] CSR node -> fiber incidence of free nodes
+    const uint32_t* inc;      // local fiber id | (1u << 31 if the node is end i)
+    const int64_t* binc_off;  // [NBND+1] same for boundary nodes
+    const uint32_t* binc;
+    const double* Xb;         // [NBND][3] centred reference coordinates of boundary nodes
+    const double* V0;         // [R] reference volume
+};
+
+struct SolveArgs {
+    DevNet net;
+    const double* F;          // [R][9]
+    const double* c;          // [R] damping
+    const int32_t* list;      // RVE ids handled by this launch, in work order
+    int32_t n_list;
+    int32_t* queue;           // work counter, zero at launch
+    int32_t law, mass_mode, init, check_every;
+    double EA, B, rhoA, alpha, tol_abs, tol_rel;
+    int64_t n_max;
+    double* sigma;            // [R][9]
+    int32_t* status;          // [R]
+    int64_t* iters;           // [R]
+    double* Rres;             // [R]
+    double* Dres;             // [R]
+    double* Bres;             // [R]
+    double* h_state;          // [NFREE][3] fluctuation h (warm-start input, output)
+    // workspace of the streamed engine (indexed with fib_off / free_off + r)
+    void* ws_fib;             // [NF + R] Real4 (D0, q0) then [NF + R] Real4 (fv, b)
+    void* ws_node;            // [NFREE + R] Real4 h, [NFREE] Real4 v, [NFREE] Real inv mass
+};
+
+struct TangentArgs {
+    DevNet net;
+    const double* F;             // [R][9]
+    const double* sigma;         // [R][9] stress of the last solve
+    const int32_t* solve_status; // [R]
+    const double* h_state;       // [NFREE][3]
+    const double* gsigma;        // [R][9] (vjp)
+    double* out;                 // [R][81] (tangent) or [R][9] (vjp)
+    int32_t* status;             // [R]
+    int32_t* queue;
+    int32_t mode;                // 0 tangent, 1 vjp
+    int32_t law;
+    double EA, B, cg_tol;
+    int64_t cg_max;
+    int64_t n_free_total;
+    int64_t n_rve;
+    void* ws_par;                // [NF + R][2] float4 fiber operators
+    float* ws_vec;               // 4 vectors of [NFREE + R][3 NR] floats
+};
+
+// Which register-resident variants exist (threads per RVE, fiber slots per
+// thread, free-node slots per thread).
+struct ResidentVariant {
+    int threads, sf, sn;
+};
+
+constexpr int kMaxResidentDegree = 8;   // incidence kept in registers
+constexpr int kNumResident = 6;
+extern const ResidentVariant kResident[kNumResident];
+
+// LDS bytes a resident variant needs for an RVE of nf free nodes and nfib fibers.
+size_t resident_lds_bytes(bool fp64, int64_t nf, int64_t nfib, int threads);
+
+hipError_t launch_resident(int variant, bool fp64, const SolveArgs& a, size_t lds_bytes, int grid,
+                           hipStream_t s);
+hipError_t launch_streamed(bool fp64, const SolveArgs& a, int grid, int threads, hipStream_t s);
+hipError_t launch_stress(const SolveArgs& a, int n_rve, hipStream_t s);
+hipError_t launch_tangent(const TangentArgs& a, int grid, hipStream_t s);
+hipError_t max_resident_blocks(int variant, bool fp64, size_t lds_bytes, int* blocks_per_cu);
+// Private (spill) bytes per lane of a resident variant; > 0 means it spills.
+hipError_t resident_scratch_bytes(int variant, bool fp64, size_t* bytes);
+
+
+}  // namespace rve

@@ -1,0 +1,1023 @@
+// Persistent batched dynamic-relaxation kernels for gfx950 (MI355X).
+//
+// One workgroup relaxes one RVE at a time and pulls the next RVE id from a
+// device work counter (longest-first order), so thousands of uneven RVEs go
+// through one launch (the whole relaxation loop inside a single kernel,
+// Section 4.2).  Per iteration (Algorithm "Dynamic Relaxation"):
+//
+//   fiber pass   every fiber: d = F d0 + h_j - h_i, strain, axial force T,
+//                force vector fv = T d / l and Gershgorin term
+//                b = max(k_t/L0, |T|/l)                       -> LDS
+//   node pass    every free node gathers +-fv of its fibers (no atomics:
+//                a fixed incidence list, so results are bitwise repeatable),
+//                forms the damped acceleration and the velocity update,
+//                G = 2 sum b, and partial reductions
+//   reduction    max G/M (time step) every iteration; |f_free|^2,
+//                |c M v|^2 and |f_bnd|^2 in FP64 on test iterations
+//   update       half-step velocity and position of the free nodes -> LDS
+//
+// The state is the fluctuation h of the free nodes (x = F Xm + h, Section 2,
+// Taylor expansion of the micro coordinates); boundary nodes have h = 0 by
+// the affine boundary condition, so they read a zero slot.  With
+// l^2 - L0^2 = q0 + 2 D0.dh + dh.dh, q0 = |F d0|^2 - L0^2 formed once per
+// solve in FP64, the strain carries no cancellation in FP32.
+//
+// Resident variant: the RVE's fibers and free nodes are dealt round-robin to
+// the threads and kept in VGPRs for the whole solve (the register file of a
+// CU is 512 KB, three times its LDS); LDS only holds the two exchange arrays
+// (positions and fiber forces).  Streamed variant: the same loop with every
+// array in global memory, for RVEs too large for one CU's LDS.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "rve_internal.h"
+
+namespace rve {
+
+const ResidentVariant kResident[kNumResident] = {
+    {256, 4, 2},  {512, 4, 2}, {1024, 4, 2}, {512, 8, 4}, {1024, 6, 3}, {256, 16, 8},
+};
+
+constexpr int kLawLinear = 0;
+constexpr int kMassScaled = 1;
+constexpr int kInitWarm = 2;
+
+constexpr int ST_CONVERGED = 0, ST_MAXITER = 1, ST_NONFINITE = 2, ST_BAD_F = 3;
+
+// ------------------------------------------------------------------ helpers
+template <typename Real>
+struct Vec4;
+template <>
+struct Vec4<float> {
+    using T = float4;
+};
+template <>
+struct Vec4<double> {
+    using T = double4;
+};
+
+__device__ inline float dev_sqrt(float x) { return __builtin_sqrtf(x); }
+__device__ inline double dev_sqrt(double x) { return sqrt(x); }
+__device__ inline float dev_expm1(float x) { return expm1f(x); }
+__device__ inline double dev_expm1(double x) { return expm1(x); }
+
+// Axial force T(eps) and k_t = dT/deps (truss law).
+template <typename Real>
+__device__ inline void fiber_law(int law, Real EA, Real B, Real eps, Real& T, Real& kt)
+{
+    if (law != kLawLinear && eps >= Real(0)) {
+        Real em1 = dev_expm1(B * eps);
+        T = EA * em1 / B;
+        kt = EA * (em1 + Real(1));
+    } else {
+        T = EA * eps;
+        kt = EA;
+    }
+}
+
+template <typename Real>
+struct FiberOut {
+    Real fx, fy, fz, b;
+};
+
+// Force vector on end j (= -force on end i) and Gershgorin term of one fiber.
+// iL0 = 1/L0.  FP32 uses the hardware reciprocal square root and reciprocal
+// (about 1 ulp); FP64 uses correctly rounded sqrt and division.
+__device__ inline float dev_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ inline float dev_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double dev_rsqrt(double x) { return 1.0 / sqrt(x); }
+__device__ inline double dev_rcp(double x) { return 1.0 / x; }
+
+template <typename Real>
+__device__ __forceinline__ FiberOut<Real> fiber_eval(int law, Real EA, Real B, Real D0x, Real D0y, Real D0z,
+                                                     Real q0, Real L0, Real iL0, Real dhx, Real dhy, Real dhz)
+{
+    Real dx = D0x + dhx, dy = D0y + dhy, dz = D0z + dhz;
+    // l^2 - L0^2 without cancellation
+    Real q = q0 + (Real(2) * (D0x * dhx + D0y * dhy + D0z * dhz) + (dhx * dhx + dhy * dhy + dhz * dhz));
+    Real l2 = L0 * L0 + q;
+    Real il = dev_rsqrt(l2);
+    Real l = l2 * il;
+    Real eps = q * iL0 * dev_rcp(l + L0);
+    Real T, kt;
+    fiber_law<Real>(law, EA, B, eps, T, kt);
+    Real g = T * il;
+    FiberOut<Real> o;
+    o.fx = g * dx;
+    o.fy = g * dy;
+    o.fz = g * dz;
+    o.b = fmax(kt * iL0, fabs(g));
+    return o;
+}
+
+// Exact-arithmetic fiber evaluation in FP64 (stress recompute).
+__device__ __forceinline__ FiberOut<double> fiber_eval_exact(int law, double EA, double B, double D0x, double D0y,
+                                                             double D0z, double q0, double L0, double dhx, double dhy,
+                                                             double dhz)
+{
+    double dx = D0x + dhx, dy = D0y + dhy, dz = D0z + dhz;
+    double q = q0 + (2.0 * (D0x * dhx + D0y * dhy + D0z * dhz) + (dhx * dhx + dhy * dhy + dhz * dhz));
+    double l = sqrt(L0 * L0 + q);
+    double eps = q / (L0 * (l + L0));
+    double T, kt;
+    fiber_law<double>(law, EA, B, eps, T, kt);
+    double g = T / l;
+    FiberOut<double> o;
+    o.fx = g * dx;
+    o.fy = g * dy;
+    o.fz = g * dz;
+    o.b = fmax(kt / L0, fabs(g));
+    return o;
+}
+
+// Broadcast helpers: values every lane holds identically (read back from LDS
+// after a barrier) are moved to scalar registers.
+__device__ __forceinline__ double uniform(double x)
+{
+    int lo = __builtin_amdgcn_readfirstlane(__double2loint(x));
+    int hi = __builtin_amdgcn_readfirstlane(__double2hiint(x));
+    return __hiloint2double(hi, lo);
+}
+
+template <typename T>
+__device__ inline T wave_sum(T v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+__device__ inline double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Neumaier-compensated accumulation (sum, compensation).
+__device__ inline void neumaier_add(double& s, double& c, double x)
+{
+    double t = s + x;
+    if (fabs(s) >= fabs(x))
+        c += (s - t) + x;
+    else
+        c += (x - t) + s;
+    s = t;
+}
+
+__device__ inline double det3(const double* F)
+{
+    return F[0] * (F[4] * F[8] - F[5] * F[7]) - F[1] * (F[3] * F[8] - F[5] * F[6]) +
+           F[2] * (F[3] * F[7] - F[4] * F[6]);
+}
+
+// ------------------------------------------------------------------ LDS layouts
+// FP32: positions and fiber forces as float4 (one 16-byte LDS access each).
+// FP64: structure-of-arrays doubles, fiber Gershgorin term as float, so an
+// RVE of ~1900 free nodes and ~4000 fibers still fits one CU's 160 KB.
+template <typename Real>
+struct Lds;
+
+template <>
+struct Lds<float> {
+    float4* h;
+    float4* fv;
+    static __host__ __device__ size_t bytes(int64_t nf, int64_t nfib)
+    {
+        return 16 * (size_t)(nf + 1) + 16 * (size_t)(nfib + 1);
+    }
+    __device__ void init(char* base, int64_t nf, int64_t nfib)
+    {
+        h = reinterpret_cast<float4*>(base);
+        fv = h + (nf + 1);
+    }
+    __device__ void put_h(int a, float x, float y, float z) { h[a] = make_float4(x, y, z, 0.f); }
+    __device__ void get_h(int a, float& x, float& y, float& z) const
+    {
+        float4 q = h[a];
+        x = q.x; y = q.y; z = q.z;
+    }
+    __device__ void put_fv(int k, const FiberOut<float>& o) { fv[k] = make_float4(o.fx, o.fy, o.fz, o.b); }
+    __device__ void get_fv(int k, float& x, float& y, float& z, float& b) const
+    {
+        float4 q = fv[k];
+        x = q.x; y = q.y; z = q.z; b = q.w;
+    }
+};
+
+template <>
+struct Lds<double> {
+    double *hx, *hy, *hz, *fx, *fy, *fz;
+    float* fb;
+    static __host__ __device__ size_t bytes(int64_t nf, int64_t nfib)
+    {
+        return 24 * (size_t)(nf + 1) + 24 * (size_t)(nfib + 1) + 4 * (size_t)(nfib + 1) + 16;
+    }
+    __device__ void init(char* base, int64_t nf, int64_t nfib)
+    {
+        hx = reinterpret_cast<double*>(base);
+        hy = hx + (nf + 1);
+        hz = hy + (nf + 1);
+        fx = hz + (nf + 1);
+        fy = fx + (nfib + 1);
+        fz = fy + (nfib + 1);
+        fb = reinterpret_cast<float*>(fz + (nfib + 1));
+    }
+    __device__ void put_h(int a, double x, double y, double z)
+    {
+        hx[a] = x; hy[a] = y; hz[a] = z;
+    }
+    __device__ void get_h(int a, double& x, double& y, double& z) const
+    {
+        x = hx[a]; y = hy[a]; z = hz[a];
+    }
+    __device__ void put_fv(int k, const FiberOut<double>& o)
+    {
+        fx[k] = o.fx; fy[k] = o.fy; fz[k] = o.fz; fb[k] = (float)o.b;
+    }
+    __device__ void get_fv(int k, double& x, double& y, double& z, double& b) const
+    {
+        x = fx[k]; y = fy[k]; z = fz[k]; b = (double)fb[k];
+    }
+};
+
+size_t resident_lds_bytes(bool fp64, int64_t nf, int64_t nfib, int /*threads*/)
+{
+    return fp64 ? Lds<double>::bytes(nf, nfib) : Lds<float>::bytes(nf, nfib);
+}
+
+// Per-wave reduction slots: [0] max G/M, [1] |f_free|^2, [2] |cMv|^2, [3] |f_bnd|^2.
+struct RedSlots {
+    double v[4][16];
+};
+
+// Block-wide reduction of up to four values.  Every thread returns the same
+// totals (fixed summation order: bitwise repeatable).  Ends with a barrier
+// after the LDS slots were read, so they may be reused immediately.
+template <int NW>
+__device__ __forceinline__ void block_reduce4(RedSlots& red, double gmax, double r2, double d2, double b2, bool full,
+                                     double& gmax_o, double& r2_o, double& d2_o, double& b2_o)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    gmax = wave_max(gmax);
+    if (full) {
+        r2 = wave_sum(r2);
+        d2 = wave_sum(d2);
+        b2 = wave_sum(b2);
+    }
+    if (lane == 0) {
+        red.v[0][wave] = gmax;
+        if (full) {
+            red.v[1][wave] = r2;
+            red.v[2][wave] = d2;
+            red.v[3][wave] = b2;
+        }
+    }
+    __syncthreads();
+    double g = 0.0;
+    double a = 0.0, b = 0.0, c = 0.0;
+#pragma unroll 2
+    for (int w = 0; w < NW; ++w) {
+        g = fmax(g, red.v[0][w]);
+        if (full) {
+            a += red.v[1][w];
+            b += red.v[2][w];
+            c += red.v[3][w];
+        }
+    }
+    gmax_o = uniform(g);
+    r2_o = uniform(a);
+    d2_o = uniform(b);
+    b2_o = uniform(c);
+    __syncthreads();
+}
+
+// Boundary reaction norm^2 partial of this thread (test iterations only).
+template <typename Real, int T>
+__device__ __forceinline__ double boundary_norm2_partial(const DevNet& net, const Lds<Real>& L, int64_t b0, int64_t nb)
+{
+    double acc = 0.0;
+#pragma unroll 1
+    for (int64_t q = threadIdx.x; q < nb; q += T) {
+        double x = 0, y = 0, z = 0;
+#pragma unroll 1
+        for (int64_t e = net.binc_off[b0 + q]; e < net.binc_off[b0 + q + 1]; ++e) {
+            uint32_t w = net.binc[e];
+            int k = (int)(w & 0x7fffffffu);
+            Real fx, fy, fz, bb;
+            L.get_fv(k, fx, fy, fz, bb);
+            double s = (w >> 31) ? -1.0 : 1.0;
+            x += s * (double)fx; y += s * (double)fy; z += s * (double)fz;
+        }
+        acc += x * x + y * y + z * z;
+    }
+    return acc;
+}
+
+// Block-reduce the 9 per-thread stress sums and write sigma = tau / (J V0):
+// pairwise (tree) sums inside each wave, then Neumaier-compensated
+// accumulation of the per-wave partials in a fixed order.
+template <int NW>
+__device__ __forceinline__ void stress_finish(double* s, double J, double V0, double* out)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __shared__ double xs[9][16];
+#pragma unroll
+    for (int p = 0; p < 9; ++p) {
+        double a = wave_sum(s[p]);
+        if (lane == 0) xs[p][wave] = a;
+    }
+    __syncthreads();
+    if (threadIdx.x < 9) {
+        const int p = threadIdx.x;
+        double a = 0.0, ca = 0.0;
+        for (int w = 0; w < NW; ++w) neumaier_add(a, ca, xs[p][w]);
+        out[p] = (a + ca) / (J * V0);
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------------ resident kernel
+template <typename Real, int T, int SF, int SN>
+__device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* smem, RedSlots& red)
+{
+    constexpr int NW = T / 64;
+    const int tid = threadIdx.x;
+    const DevNet& net = A.net;
+    const int64_t f0 = net.fib_off[r], nfib = net.fib_off[r + 1] - f0;
+    const int64_t a0 = net.free_off[r], nf = net.free_off[r + 1] - a0;
+    const int64_t b0 = net.bnd_off[r], nb = net.bnd_off[r + 1] - b0;
+
+    double F[9];
+    bool finite = true;
+    for (int k = 0; k < 9; ++k) {
+        F[k] = A.F[9 * r + k];
+        finite = finite && isfinite(F[k]);
+    }
+    const double J = det3(F);
+    if (!finite || !(J > 0.0)) {
+        if (tid == 0) {
+            A.status[r] = ST_BAD_F;
+            A.iters[r] = 0;
+            A.Rres[r] = NAN; A.Dres[r] = NAN; A.Bres[r] = NAN;
+            for (int k = 0; k < 9; ++k) A.sigma[9 * r + k] = NAN;
+        }
+        return;
+    }
+    const Real EA = (Real)A.EA, Bc = (Real)A.B;
+    const double cd = A.c[r];
+    const Real c = (Real)cd;
+
+    Lds<Real> L;
+    L.init(smem, nf, nfib);
+
+    // ---- fibers into registers: D0 = F d0, q0 = |D0|^2 - L0^2 (FP64 then rounded)
+    Real D0x[SF], D0y[SF], D0z[SF], Q0[SF], L0r[SF], iL0r[SF];
+    uint32_t E[SF];
+#pragma unroll
+    for (int s = 0; s < SF; ++s) {
+        int k = s * T + tid;
+        D0x[s] = D0y[s] = D0z[s] = Q0[s] = Real(0);
+        L0r[s] = iL0r[s] = Real(1);
+        E[s] = 0;
+        if (k < nfib) {
+            const double* d0 = net.d0 + 3 * (f0 + k);
+            double L0 = net.L0[f0 + k];
+            double Dx = F[0] * d0[0] + F[1] * d0[1] + F[2] * d0[2];
+            double Dy = F[3] * d0[0] + F[4] * d0[1] + F[5] * d0[2];
+            double Dz = F[6] * d0[0] + F[7] * d0[1] + F[8] * d0[2];
+            D0x[s] = (Real)Dx; D0y[s] = (Real)Dy; D0z[s] = (Real)Dz;
+            Q0[s] = (Real)((Dx * Dx + Dy * Dy + Dz * Dz) - L0 * L0);
+            L0r[s] = (Real)L0;
+            iL0r[s] = (Real)(1.0 / L0);
+            uint32_t e = net.ends[f0 + k];
+            uint32_t i = e & 0xffffu, j = e >> 16;
+            // boundary ends read the zero slot nf
+            i = i < (uint32_t)nf ? i : (uint32_t)nf;
+            j = j < (uint32_t)nf ? j : (uint32_t)nf;
+            E[s] = i | (j << 16);
+        }
+    }
+    // ---- free nodes into registers
+    Real hx[SN], hy[SN], hz[SN], vx[SN], vy[SN], vz[SN], iM[SN];
+    uint32_t inc[SN][kMaxResidentDegree / 2];
+    int deg[SN];
+#pragma unroll
+    for (int s = 0; s < SN; ++s) {
+        int a = s * T + tid;
+        hx[s] = hy[s] = hz[s] = vx[s] = vy[s] = vz[s] = Real(0);
+        iM[s] = Real(0);
+        deg[s] = 0;
+#pragma unroll
+        for (int q = 0; q < kMaxResidentDegree / 2; ++q) inc[s][q] = (uint32_t)nfib | ((uint32_t)nfib << 16);
+        if (a < nf) {
+            iM[s] = (Real)(1.0 / (net.mass[a0 + a] * A.rhoA));
+            int64_t e0 = net.inc_off[a0 + a], e1 = net.inc_off[a0 + a + 1];
+            deg[s] = (int)(e1 - e0);
+#pragma unroll
+            for (int q = 0; q < kMaxResidentDegree; ++q) {
+                if (q < deg[s]) {
+                    uint32_t w = net.inc[e0 + q];
+                    uint32_t code = (w & 0x7fffu) | ((w >> 31) << 15);
+                    if (q & 1)
+                        inc[s][q >> 1] = (inc[s][q >> 1] & 0xffffu) | (code << 16);
+                    else
+                        inc[s][q >> 1] = (inc[s][q >> 1] & 0xffff0000u) | code;
+                }
+            }
+            if (A.init == kInitWarm) {
+                const double* h = A.h_state + 3 * (a0 + a);
+                hx[s] = (Real)h[0]; hy[s] = (Real)h[1]; hz[s] = (Real)h[2];
+            }
+            L.put_h(a, hx[s], hy[s], hz[s]);
+        }
+    }
+    if (tid == 0) {
+        L.put_h((int)nf, Real(0), Real(0), Real(0));
+        FiberOut<Real> z{Real(0), Real(0), Real(0), Real(0)};
+        L.put_fv((int)nfib, z);
+    }
+    __syncthreads();
+
+    auto fiber_pass = [&]() __attribute__((always_inline)) {
+#pragma unroll
+        for (int s = 0; s < SF; ++s) {
+            int k = s * T + tid;
+            if (k < nfib) {
+                int i = E[s] & 0xffff, j = E[s] >> 16;
+                Real ix, iy, iz, jx, jy, jz;
+                L.get_h(i, ix, iy, iz);
+                L.get_h(j, jx, jy, jz);
+                FiberOut<Real> o = fiber_eval<Real>(A.law, EA, Bc, D0x[s], D0y[s], D0z[s], Q0[s], L0r[s], iL0r[s],
+                                                    jx - ix, jy - iy, jz - iz);
+                L.put_fv(k, o);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+    // gather forces and Gershgorin sums of node slot s
+    auto gather = [&](int s, Real& fx, Real& fy, Real& fz, Real& G) __attribute__((always_inline)) {
+        fx = fy = fz = G = Real(0);
+#pragma unroll
+        for (int q = 0; q < kMaxResidentDegree; ++q) {
+            if (q >= deg[s]) continue;
+            uint32_t code = (q & 1) ? (inc[s][q >> 1] >> 16) : (inc[s][q >> 1] & 0xffffu);
+            int k = (int)(code & 0x7fffu);
+            Real x, y, z, b;
+            L.get_fv(k, x, y, z, b);
+            if (code & 0x8000u) {
+                x = -x; y = -y; z = -z;
+            }
+            fx += x; fy += y; fz += z; G += b;
+        }
+        G *= Real(2);
+    };
+
+    // ---- initial force, residual and (optionally) stiffness-scaled mass
+    fiber_pass();
+    __syncthreads();
+    Real ax[SN], ay[SN], az[SN];
+    double gpart = 0.0;
+    double r2p = 0.0, b2p = 0.0;
+#pragma unroll
+    for (int s = 0; s < SN; ++s) {
+        int a = s * T + tid;
+        ax[s] = ay[s] = az[s] = Real(0);
+        if (a < nf) {
+            Real fx, fy, fz, G;
+            gather(s, fx, fy, fz, G);
+            if (A.mass_mode == kMassScaled) iM[s] = G > Real(0) ? Real(4) / G : Real(1);
+            ax[s] = -fx * iM[s];
+            ay[s] = -fy * iM[s];
+            az[s] = -fz * iM[s];
+            gpart = fmax(gpart, (double)(G * iM[s]));
+            r2p += (double)fx * fx + (double)fy * fy + (double)fz * fz;
+        }
+    }
+    b2p = boundary_norm2_partial<Real, T>(net, L, b0, nb);
+    double gmax;
+    double R2, D2, B2;
+    block_reduce4<NW>(red, gpart, r2p, 0.0, b2p, true, gmax, R2, D2, B2);
+
+    int64_t n = 0;
+    int status = ST_CONVERGED;
+    const int ce = A.check_every > 0 ? A.check_every : 1;
+    double tol = fmax(A.tol_abs, A.tol_rel * sqrt(B2));
+    bool done = (sqrt(R2) <= tol);   // v = 0: damping norm is 0
+    double Rlast = sqrt(R2), Dlast = 0.0, Blast = sqrt(B2);
+    if (!isfinite(R2)) {
+        status = ST_NONFINITE;
+        done = true;
+    }
+    if (!done && n >= A.n_max) {
+        status = ST_MAXITER;
+        done = true;
+    }
+    double dt = A.alpha * 2.0 / sqrt(gmax);
+
+    while (!done) {
+        // Keep the packed fiber ends and incidence lists packed: without this the
+        // compiler hoists their unpacked addresses and sign masks out of the loop,
+        // which multiplies the registers they occupy.
+#pragma unroll
+        for (int s = 0; s < SF; ++s) {
+            asm volatile("" : "+v"(E[s]));
+            asm volatile("" : "+v"(D0x[s]), "+v"(D0y[s]), "+v"(D0z[s]), "+v"(Q0[s]), "+v"(L0r[s]), "+v"(iL0r[s]));
+        }
+#pragma unroll
+        for (int s = 0; s < SN; ++s) {
+            asm volatile("" : "+v"(deg[s]), "+v"(iM[s]));
+#pragma unroll
+            for (int q = 0; q < kMaxResidentDegree / 2; ++q) asm volatile("" : "+v"(inc[s][q]));
+        }
+        // half-step velocity and position update with the time step of this state
+        const Real hdt = (Real)(0.5 * dt), rdt = (Real)dt;
+#pragma unroll
+        for (int s = 0; s < SN; ++s) {
+            int a = s * T + tid;
+            if (a < nf) {
+                vx[s] += hdt * ax[s]; vy[s] += hdt * ay[s]; vz[s] += hdt * az[s];
+                hx[s] += rdt * vx[s]; hy[s] += rdt * vy[s]; hz[s] += rdt * vz[s];
+                L.put_h(a, hx[s], hy[s], hz[s]);
+            }
+        }
+        __syncthreads();
+        fiber_pass();
+        __syncthreads();
+        ++n;
+        const bool check = (n % ce) == 0;
+        gpart = 0.0;
+        r2p = 0.0;
+        double d2p = 0.0;
+#pragma unroll
+        for (int s = 0; s < SN; ++s) {
+            int a = s * T + tid;
+            if (a < nf) {
+                Real fx, fy, fz, G;
+                gather(s, fx, fy, fz, G);
+                // damped acceleration with the half-step velocity, then second half step
+                ax[s] = -fx * iM[s] - c * vx[s];
+                ay[s] = -fy * iM[s] - c * vy[s];
+                az[s] = -fz * iM[s] - c * vz[s];
+                vx[s] += hdt * ax[s]; vy[s] += hdt * ay[s]; vz[s] += hdt * az[s];
+                gpart = fmax(gpart, (double)(G * iM[s]));
+                if (check) {
+                    r2p += (double)fx * fx + (double)fy * fy + (double)fz * fz;
+                    double m = cd / (double)iM[s];
+                    double px = m * (double)vx[s], py = m * (double)vy[s], pz = m * (double)vz[s];
+                    d2p += px * px + py * py + pz * pz;
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (check) b2p = boundary_norm2_partial<Real, T>(net, L, b0, nb);
+        block_reduce4<NW>(red, gpart, r2p, d2p, b2p, check, gmax, R2, D2, B2);
+        if (check) {
+            Rlast = sqrt(R2);
+            Dlast = sqrt(D2);
+            Blast = sqrt(B2);
+            tol = fmax(A.tol_abs, A.tol_rel * Blast);
+            if (!isfinite(R2) || !isfinite(D2)) {
+                status = ST_NONFINITE;
+                break;
+            }
+            if (Rlast <= tol && Dlast <= tol) break;
+        }
+        if (!(gmax > 0.0) || !isfinite(gmax)) {
+            status = ST_NONFINITE;
+            break;
+        }
+        if (n >= A.n_max) {
+            status = ST_MAXITER;
+            break;
+        }
+        dt = A.alpha * 2.0 / sqrt(gmax);
+    }
+
+    // ---- fluctuation state for warm starts, positions and the tangent
+#pragma unroll
+    for (int s = 0; s < SN; ++s) {
+        int a = s * T + tid;
+        if (a < nf) {
+            double* h = A.h_state + 3 * (a0 + a);
+            h[0] = (double)hx[s]; h[1] = (double)hy[s]; h[2] = (double)hz[s];
+        }
+    }
+    if (tid == 0) {
+        A.status[r] = status;
+        A.iters[r] = n;
+        A.Rres[r] = Rlast;
+        A.Dres[r] = Dlast;
+        A.Bres[r] = Blast;
+    }
+    __syncthreads();
+}
+
+template <typename Real, int T, int SF, int SN>
+__global__ __launch_bounds__(T) void dr_resident_kernel(SolveArgs A)
+{
+    extern __shared__ char smem[];
+    __shared__ RedSlots red;
+    __shared__ int task;
+    for (;;) {
+        if (threadIdx.x == 0) task = atomicAdd(A.queue, 1);
+        __syncthreads();
+        // the task id is the same for every lane: keep everything derived from it in SGPRs
+        const int t = __builtin_amdgcn_readfirstlane(task);
+        __syncthreads();
+        if (t >= A.n_list) break;
+        resident_solve<Real, T, SF, SN>(A, __builtin_amdgcn_readfirstlane(A.list[t]), smem, red);
+    }
+}
+
+// ------------------------------------------------------------------ streamed kernel
+// Same iteration with fibers, state and exchange arrays in global memory
+// (per-RVE regions of the workspace).  One workgroup per RVE; every loop is
+// strided over the workgroup.
+template <typename Real, int T>
+__device__ __forceinline__ void streamed_solve(const SolveArgs& A, int r, RedSlots& red)
+{
+    using R4 = typename Vec4<Real>::T;
+    constexpr int NW = T / 64;
+    const int tid = threadIdx.x;
+    const DevNet& net = A.net;
+    const int64_t f0 = net.fib_off[r], nfib = net.fib_off[r + 1] - f0;
+    const int64_t a0 = net.free_off[r], nf = net.free_off[r + 1] - a0;
+    const int64_t b0 = net.bnd_off[r], nb = net.bnd_off[r + 1] - b0;
+    const int64_t NF = net.fib_off[net.n_rve], NFREE = net.free_off[net.n_rve];
+
+    R4* wsD = reinterpret_cast<R4*>(A.ws_fib) + (f0 + r);             // [nfib+1] (D0, q0)
+    R4* wsFv = reinterpret_cast<R4*>(A.ws_fib) + (NF + net.n_rve) + (f0 + r);   // [nfib+1]
+    R4* wsH = reinterpret_cast<R4*>(A.ws_node) + (a0 + r);            // [nf+1]
+    R4* wsV = reinterpret_cast<R4*>(A.ws_node) + (NFREE + net.n_rve) + a0;     // [nf]
+    Real* wsM = reinterpret_cast<Real*>(reinterpret_cast<R4*>(A.ws_node) + (NFREE + net.n_rve) + NFREE) + a0;
+    R4* wsA = reinterpret_cast<R4*>(A.ws_node) + 2 * (NFREE + net.n_rve) + NFREE + a0;   // [nf] accel
+
+    double F[9];
+    bool finite = true;
+    for (int k = 0; k < 9; ++k) {
+        F[k] = A.F[9 * r + k];
+        finite = finite && isfinite(F[k]);
+    }
+    const double J = det3(F);
+    if (!finite || !(J > 0.0)) {
+        if (tid == 0) {
+            A.status[r] = ST_BAD_F;
+            A.iters[r] = 0;
+            A.Rres[r] = NAN; A.Dres[r] = NAN; A.Bres[r] = NAN;
+            for (int k = 0; k < 9; ++k) A.sigma[9 * r + k] = NAN;
+        }
+        return;
+    }
+    const Real EA = (Real)A.EA, Bc = (Real)A.B;
+    const double cd = A.c[r];
+    const Real c = (Real)cd;
+
+#pragma unroll 1
+    for (int64_t k = tid; k < nfib; k += T) {
+        const double* d0 = net.d0 + 3 * (f0 + k);
+        double L0 = net.L0[f0 + k];
+        double Dx = F[0] * d0[0] + F[1] * d0[1] + F[2] * d0[2];
+        double Dy = F[3] * d0[0] + F[4] * d0[1] + F[5] * d0[2];
+        double Dz = F[6] * d0[0] + F[7] * d0[1] + F[8] * d0[2];
+        R4 q;
+        q.x = (Real)Dx; q.y = (Real)Dy; q.z = (Real)Dz;
+        q.w = (Real)((Dx * Dx + Dy * Dy + Dz * Dz) - L0 * L0);
+        wsD[k] = q;
+    }
+#pragma unroll 1
+    for (int64_t a = tid; a < nf; a += T) {
+        R4 h;
+        h.x = h.y = h.z = h.w = Real(0);
+        if (A.init == kInitWarm) {
+            const double* hs = A.h_state + 3 * (a0 + a);
+            h.x = (Real)hs[0]; h.y = (Real)hs[1]; h.z = (Real)hs[2];
+        }
+        wsH[a] = h;
+        R4 z;
+        z.x = z.y = z.z = z.w = Real(0);
+        wsV[a] = z;
+        wsM[a] = (Real)(net.mass[a0 + a] * A.rhoA);
+    }
+    if (tid == 0) {
+        R4 z;
+        z.x = z.y = z.z = z.w = Real(0);
+        wsH[nf] = z;
+        wsFv[nfib] = z;
+    }
+    __syncthreads();
+
+    auto fiber_pass = [&]() __attribute__((always_inline)) {
+        #pragma unroll 1
+        for (int64_t k = tid; k < nfib; k += T) {
+            R4 D = wsD[k];
+            uint32_t e = net.ends[f0 + k];
+            uint32_t i = e & 0xffffu, j = e >> 16;
+            i = i < (uint32_t)nf ? i : (uint32_t)nf;
+            j = j < (uint32_t)nf ? j : (uint32_t)nf;
+            R4 hi = wsH[i], hj = wsH[j];
+            double L0d = net.L0[f0 + k];
+            FiberOut<Real> o = fiber_eval<Real>(A.law, EA, Bc, D.x, D.y, D.z, D.w, (Real)L0d, (Real)(1.0 / L0d),
+                                                hj.x - hi.x, hj.y - hi.y, hj.z - hi.z);
+            R4 w;
+            w.x = o.fx; w.y = o.fy; w.z = o.fz; w.w = o.b;
+            wsFv[k] = w;
+        }
+    };
+    auto gather = [&](int64_t a, Real& fx, Real& fy, Real& fz, Real& G) __attribute__((always_inline)) {
+        fx = fy = fz = G = Real(0);
+#pragma unroll 1
+        for (int64_t e = net.inc_off[a0 + a]; e < net.inc_off[a0 + a + 1]; ++e) {
+            uint32_t w = net.inc[e];
+            R4 q = wsFv[w & 0x7fffffffu];
+            if (w >> 31) {
+                q.x = -q.x; q.y = -q.y; q.z = -q.z;
+            }
+            fx += q.x; fy += q.y; fz += q.z; G += q.w;
+        }
+        G *= Real(2);
+    };
+    auto bnorm2 = [&]() __attribute__((always_inline)) {
+        double acc = 0.0;
+#pragma unroll 1
+        for (int64_t q = tid; q < nb; q += T) {
+            double x = 0, y = 0, z = 0;
+#pragma unroll 1
+            for (int64_t e = net.binc_off[b0 + q]; e < net.binc_off[b0 + q + 1]; ++e) {
+                uint32_t w = net.binc[e];
+                R4 f = wsFv[w & 0x7fffffffu];
+                double s = (w >> 31) ? -1.0 : 1.0;
+                x += s * (double)f.x; y += s * (double)f.y; z += s * (double)f.z;
+            }
+            acc += x * x + y * y + z * z;
+        }
+        return acc;
+    };
+
+    fiber_pass();
+    __syncthreads();
+    double gpart = 0.0;
+    double r2p = 0.0;
+#pragma unroll 1
+    for (int64_t a = tid; a < nf; a += T) {
+        Real fx, fy, fz, G;
+        gather(a, fx, fy, fz, G);
+        Real m = wsM[a];
+        if (A.mass_mode == kMassScaled) {
+            m = G > Real(0) ? G / Real(4) : Real(1);
+            wsM[a] = m;
+        }
+        Real im = Real(1) / m;
+        R4 acc;
+        acc.x = -fx * im; acc.y = -fy * im; acc.z = -fz * im; acc.w = Real(0);
+        wsA[a] = acc;
+        gpart = fmax(gpart, (double)(G * im));
+        r2p += (double)fx * fx + (double)fy * fy + (double)fz * fz;
+    }
+    double b2p = bnorm2();
+    double gmax;
+    double R2, D2, B2;
+    block_reduce4<NW>(red, gpart, r2p, 0.0, b2p, true, gmax, R2, D2, B2);
+
+    int64_t n = 0;
+    int status = ST_CONVERGED;
+    const int ce = A.check_every > 0 ? A.check_every : 1;
+    double tol = fmax(A.tol_abs, A.tol_rel * sqrt(B2));
+    bool done = (sqrt(R2) <= tol);
+    double Rlast = sqrt(R2), Dlast = 0.0, Blast = sqrt(B2);
+    if (!isfinite(R2)) {
+        status = ST_NONFINITE;
+        done = true;
+    }
+    if (!done && n >= A.n_max) {
+        status = ST_MAXITER;
+        done = true;
+    }
+    double dt = A.alpha * 2.0 / sqrt(gmax);
+    while (!done) {
+        const Real hdt = (Real)(0.5 * dt), rdt = (Real)dt;
+#pragma unroll 1
+        for (int64_t a = tid; a < nf; a += T) {
+            R4 v = wsV[a], h = wsH[a], acc = wsA[a];
+            v.x += hdt * acc.x; v.y += hdt * acc.y; v.z += hdt * acc.z;
+            h.x += rdt * v.x; h.y += rdt * v.y; h.z += rdt * v.z;
+            wsV[a] = v;
+            wsH[a] = h;
+        }
+        __syncthreads();
+        fiber_pass();
+        __syncthreads();
+        ++n;
+        const bool check = (n % ce) == 0;
+        gpart = 0.0;
+        r2p = 0.0;
+        double d2p = 0.0;
+#pragma unroll 1
+        for (int64_t a = tid; a < nf; a += T) {
+            Real fx, fy, fz, G;
+            gather(a, fx, fy, fz, G);
+            Real m = wsM[a], im = Real(1) / m;
+            R4 v = wsV[a], acc;
+            acc.x = -fx * im - c * v.x;
+            acc.y = -fy * im - c * v.y;
+            acc.z = -fz * im - c * v.z;
+            acc.w = Real(0);
+            v.x += hdt * acc.x; v.y += hdt * acc.y; v.z += hdt * acc.z;
+            wsV[a] = v;
+            wsA[a] = acc;
+            gpart = fmax(gpart, (double)(G * im));
+            if (check) {
+                r2p += (double)fx * fx + (double)fy * fy + (double)fz * fz;
+                double md = (double)m * cd;
+                double px = md * (double)v.x, py = md * (double)v.y, pz = md * (double)v.z;
+                d2p += px * px + py * py + pz * pz;
+            }
+        }
+        if (check) b2p = bnorm2();
+        block_reduce4<NW>(red, gpart, r2p, d2p, b2p, check, gmax, R2, D2, B2);
+        if (check) {
+            Rlast = sqrt(R2);
+            Dlast = sqrt(D2);
+            Blast = sqrt(B2);
+            tol = fmax(A.tol_abs, A.tol_rel * Blast);
+            if (!isfinite(R2) || !isfinite(D2)) {
+                status = ST_NONFINITE;
+                break;
+            }
+            if (Rlast <= tol && Dlast <= tol) break;
+        }
+        if (!(gmax > 0.0) || !isfinite(gmax)) {
+            status = ST_NONFINITE;
+            break;
+        }
+        if (n >= A.n_max) {
+            status = ST_MAXITER;
+            break;
+        }
+        dt = A.alpha * 2.0 / sqrt(gmax);
+    }
+
+#pragma unroll 1
+    for (int64_t a = tid; a < nf; a += T) {
+        R4 h = wsH[a];
+        double* hs = A.h_state + 3 * (a0 + a);
+        hs[0] = (double)h.x; hs[1] = (double)h.y; hs[2] = (double)h.z;
+    }
+    if (tid == 0) {
+        A.status[r] = status;
+        A.iters[r] = n;
+        A.Rres[r] = Rlast;
+        A.Dres[r] = Dlast;
+        A.Bres[r] = Blast;
+    }
+    __syncthreads();
+}
+
+template <typename Real, int T>
+__global__ __launch_bounds__(T) void dr_streamed_kernel(SolveArgs A)
+{
+    __shared__ RedSlots red;
+    __shared__ int task;
+    for (;;) {
+        if (threadIdx.x == 0) task = atomicAdd(A.queue, 1);
+        __syncthreads();
+        const int t = __builtin_amdgcn_readfirstlane(task);
+        __syncthreads();
+        if (t >= A.n_list) break;
+        streamed_solve<Real, T>(A, __builtin_amdgcn_readfirstlane(A.list[t]), red);
+    }
+}
+
+// ------------------------------------------------------------------ stress kernel
+// Homogenized stress of every RVE from its final fluctuation state, one
+// workgroup per RVE: each fiber with a boundary end is re-evaluated in FP64
+// and f_b (x) x_b is accumulated at that end (x_b = F Xm_b); per-thread sums,
+// pairwise wave sums and a compensated sum over waves, then / (det F V0).
+// RVEs whose status is NONFINITE or BAD_F get NaN.
+constexpr int kStressThreads = 256;
+
+__global__ __launch_bounds__(kStressThreads) void stress_kernel(SolveArgs A)
+{
+    const int r = blockIdx.x;
+    const DevNet& net = A.net;
+    const int st = A.status[r];
+    if (st == ST_NONFINITE || st == ST_BAD_F) {
+        if (threadIdx.x < 9) A.sigma[9 * r + threadIdx.x] = NAN;
+        return;
+    }
+    const int64_t f0 = net.fib_off[r], nfib = net.fib_off[r + 1] - f0;
+    const int64_t a0 = net.free_off[r], nf = net.free_off[r + 1] - a0;
+    const int64_t b0 = net.bnd_off[r];
+    double F[9];
+    for (int k = 0; k < 9; ++k) F[k] = A.F[9 * r + k];
+    const double J = det3(F);
+    double s9[9];
+#pragma unroll
+    for (int p = 0; p < 9; ++p) s9[p] = 0.0;
+#pragma unroll 1
+    for (int64_t k = threadIdx.x; k < nfib; k += kStressThreads) {
+        uint32_t e = net.ends[f0 + k];
+        int i = e & 0xffff, j = e >> 16;
+        if (i < nf && j < nf) continue;
+        const double* d0 = net.d0 + 3 * (f0 + k);
+        double L0 = net.L0[f0 + k];
+        double Dx = F[0] * d0[0] + F[1] * d0[1] + F[2] * d0[2];
+        double Dy = F[3] * d0[0] + F[4] * d0[1] + F[5] * d0[2];
+        double Dz = F[6] * d0[0] + F[7] * d0[1] + F[8] * d0[2];
+        double q0 = (Dx * Dx + Dy * Dy + Dz * Dz) - L0 * L0;
+        double dh[3] = {0.0, 0.0, 0.0};
+        for (int c = 0; c < 3; ++c) {
+            if (j < nf) dh[c] += A.h_state[3 * (a0 + j) + c];
+            if (i < nf) dh[c] -= A.h_state[3 * (a0 + i) + c];
+        }
+        FiberOut<double> o = fiber_eval_exact(A.law, A.EA, A.B, Dx, Dy, Dz, q0, L0, dh[0], dh[1], dh[2]);
+        const double fvv[3] = {o.fx, o.fy, o.fz};
+        for (int end = 0; end < 2; ++end) {
+            int node = end ? j : i;
+            if (node < nf) continue;
+            const double* Xm = net.Xb + 3 * (b0 + (node - nf));
+            double xb[3] = {F[0] * Xm[0] + F[1] * Xm[1] + F[2] * Xm[2], F[3] * Xm[0] + F[4] * Xm[1] + F[5] * Xm[2],
+                            F[6] * Xm[0] + F[7] * Xm[1] + F[8] * Xm[2]};
+            double sg = end ? 1.0 : -1.0;
+            for (int p = 0; p < 3; ++p)
+                for (int q = 0; q < 3; ++q) s9[3 * p + q] += sg * fvv[p] * xb[q];
+        }
+    }
+    stress_finish<kStressThreads / 64>(s9, J, net.V0[r], A.sigma + 9 * r);
+}
+
+hipError_t launch_stress(const SolveArgs& a, int n_rve, hipStream_t s)
+{
+    if (n_rve <= 0) return hipSuccess;
+    hipLaunchKernelGGL(stress_kernel, dim3(n_rve), dim3(kStressThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ launch helpers
+template <typename Real, int T, int SF, int SN>
+static hipError_t launch_res(const SolveArgs& a, size_t lds, int grid, hipStream_t s)
+{
+    auto k = dr_resident_kernel<Real, T, SF, SN>;
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3(grid), dim3(T), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename Real, int T, int SF, int SN>
+static hipError_t spill_res(size_t* bytes)
+{
+    hipFuncAttributes at;
+    hipError_t e = hipFuncGetAttributes(&at, (const void*)dr_resident_kernel<Real, T, SF, SN>);
+    *bytes = at.localSizeBytes;
+    return e;
+}
+
+template <typename Real, int T, int SF, int SN>
+static hipError_t occ_res(size_t lds, int* blocks)
+{
+    auto k = dr_resident_kernel<Real, T, SF, SN>;
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, (const void*)k, T, lds);
+}
+
+#define RVE_RES_DISPATCH(FN, ...)                                                                     \
+    switch (variant) {                                                                                \
+    case 0: return fp64 ? FN<double, 256, 4, 2>(__VA_ARGS__) : FN<float, 256, 4, 2>(__VA_ARGS__);     \
+    case 1: return fp64 ? FN<double, 512, 4, 2>(__VA_ARGS__) : FN<float, 512, 4, 2>(__VA_ARGS__);     \
+    case 2: return fp64 ? FN<double, 1024, 4, 2>(__VA_ARGS__) : FN<float, 1024, 4, 2>(__VA_ARGS__);   \
+    case 3: return fp64 ? FN<double, 512, 8, 4>(__VA_ARGS__) : FN<float, 512, 8, 4>(__VA_ARGS__);     \
+    case 4: return fp64 ? FN<double, 1024, 6, 3>(__VA_ARGS__) : FN<float, 1024, 6, 3>(__VA_ARGS__);   \
+    case 5: return fp64 ? FN<double, 256, 16, 8>(__VA_ARGS__) : FN<float, 256, 16, 8>(__VA_ARGS__);   \
+    default: return hipErrorInvalidValue;                                                             \
+    }
+
+hipError_t launch_resident(int variant, bool fp64, const SolveArgs& a, size_t lds, int grid, hipStream_t s)
+{
+    RVE_RES_DISPATCH(launch_res, a, lds, grid, s)
+}
+
+hipError_t max_resident_blocks(int variant, bool fp64, size_t lds, int* blocks)
+{
+    RVE_RES_DISPATCH(occ_res, lds, blocks)
+}
+
+hipError_t resident_scratch_bytes(int variant, bool fp64, size_t* bytes)
+{
+    RVE_RES_DISPATCH(spill_res, bytes)
+}
+
+hipError_t launch_streamed(bool fp64, const SolveArgs& a, int grid, int threads, hipStream_t s)
+{
+    if (threads == 256) {
+        if (fp64) hipLaunchKernelGGL((dr_streamed_kernel<double, 256>), dim3(grid), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((dr_streamed_kernel<float, 256>), dim3(grid), dim3(256), 0, s, a);
+    } else {
+        if (fp64) hipLaunchKernelGGL((dr_streamed_kernel<double, 1024>), dim3(grid), dim3(1024), 0, s, a);
+        else hipLaunchKernelGGL((dr_streamed_kernel<float, 1024>), dim3(grid), dim3(1024), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace rve
