@@ -1,0 +1,211 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched RVE relaxation on one MI355X.
+
+Workload: 4096 Voronoi fiber-network RVEs of uneven size (200-400 uniform
+seeds each), exponential-stiffening fibers (EA = 1, B = 10, linear in
+compression), per-RVE F = I + 0.1 G with G symmetric (upper entries N(0,1)
+clipped to [-1, 1]), affine boundary condition, damped dynamic relaxation to
+|f_free| <= tol_rel |f_bnd|, homogenized Cauchy stress from the boundary
+reactions.  One step = one rve_batch_solve of the whole batch from the affine
+start, inputs resident in HBM (device pointers).
+
+Also measured: the same batch in FP64 (batched persistent kernel), the plain
+FP64 one-RVE-at-a-time engine on a few RVEs (extrapolated), and the CPU oracle
+on a bounded sample (cpu_baseline), whose stresses also check the GPU result.
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM = 8.0e12          # B/s, MI355X HBM3E
+PEAK_FP32_VALU = 157.3e12  # FLOP/s, MI355X FP32 vector (packed)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n-rve", type=int, default=4096)
+    ap.add_argument("--alpha", type=float, default=0.5)
+    ap.add_argument("--c", type=float, default=2.0)
+    ap.add_argument("--mass", type=int, default=0)
+    ap.add_argument("--tol-rel", type=float, default=1e-6)
+    ap.add_argument("--n-max", type=int, default=100000)
+    ap.add_argument("--check-every", type=int, default=8)
+    ap.add_argument("--naive-sample", type=int, default=4)
+    ap.add_argument("--cpu-sample", type=int, default=16)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-naive", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: RVEs are independent, so a multi-GPU run is the same kernel on a "
+              "shard per GPU; only --gpus 1 is supported here.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2306_09427_amd import binding as rb
+    from paper_2306_09427_amd import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    t0 = time.time()
+    batch, F = synth.make_config_batch(2, n_rve=args.n_rve)
+    nfib = np.diff(batch.fib_off)
+    nfree = np.array([int((batch.is_bnd[batch.node_off[r]:batch.node_off[r + 1]] == 0).sum())
+                      for r in range(batch.n_rve)])
+    log(f"generated {batch.n_rve} RVEs in {time.time() - t0:.1f}s: fibers {nfib.sum()} (mean {nfib.mean():.0f}), "
+        f"free nodes {nfree.sum()}")
+    common = dict(law=rb.LAW_EXP, mass=args.mass, alpha=args.alpha, c=args.c, tol_abs=0.0, tol_rel=args.tol_rel,
+                  n_max=args.n_max, check_every=args.check_every)
+    Fd = torch.tensor(F, device=dev)
+
+    # ---------------- mixed precision, timed
+    b = rb.Batch(batch, precision=rb.MIXED, **common)
+    b.profile(True)
+    for _ in range(args.warmup):
+        b.solve(Fd)
+    torch.cuda.synchronize()
+    kms = []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        sig, st, stats = b.solve(Fd, stats=True)
+        kms.append(b.kernel_ms())
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    ms_per_step = 1e3 * t_total / args.steps
+    sig = sig.cpu().numpy()
+    st = st.cpu().numpy()
+    iters = stats["iters"].cpu().numpy()
+    relax_ms = float(np.mean([k[0] for k in kms]))
+    stress_ms = float(np.mean([k[1] for k in kms]))
+    elem_updates = float((iters * nfib).sum())
+    value = batch.n_rve / (ms_per_step / 1e3)
+    log(f"mixed: {ms_per_step:.1f} ms/step, relax kernel {relax_ms:.1f} ms, stress {stress_ms:.2f} ms, "
+        f"status {np.bincount(st, minlength=4).tolist()}, iters median {np.median(iters):.0f} max {iters.max()}")
+
+    # algorithmic bytes (one relaxation iteration reads the fibers and reads/writes the state):
+    # mixed 20 B per fiber + 52 B per free node
+    alg_bytes = float((iters * (20 * nfib + 52 * nfree)).sum())
+    alg_flops = float((iters * (53 * nfib + 40 * nfree)).sum())
+    hbm_achieved = alg_bytes / (relax_ms / 1e3)
+    flop_achieved = alg_flops / (relax_ms / 1e3)
+
+    out = {
+        "metric": "RVE solves/sec (sigma rel-err <= 1e-4) mixed vs FP64 plain; fraction of HBM peak",
+        "value": value,
+        "unit": "RVE solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 fibers/state, f64 reductions and stress",
+        "data": "synthetic",
+        "config": {"workload": "4096 Voronoi RVEs, 200-400 seeds, exp fibers B=10, F=I+0.1G, mixed precision",
+                   "n_rve": int(batch.n_rve), "fibers": int(nfib.sum()), "free_nodes": int(nfree.sum()),
+                   "alpha": args.alpha, "c": args.c, "mass": ["lumped", "scaled"][args.mass],
+                   "tol_rel": args.tol_rel, "n_max": args.n_max, "check_every": args.check_every},
+        "converged": int((st == 0).sum()),
+        "status_counts": np.bincount(st, minlength=4).tolist(),
+        "iters_median": float(np.median(iters)),
+        "element_updates_per_s": elem_updates / (ms_per_step / 1e3),
+        "relax_kernel_ms": relax_ms,
+        "stress_kernel_ms": stress_ms,
+    }
+    b.close()
+
+    # ---------------- FP64 batched (same batch, tol scaled to FP64)
+    if not args.no_fp64:
+        b64 = rb.Batch(batch, precision=rb.FP64, **common)
+        b64.profile(True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s64, st64 = b64.solve(Fd)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t1
+        st64 = st64.cpu().numpy()
+        s64 = s64.cpu().numpy()
+        both = (st64 == 0) & (st == 0)
+        scale = np.maximum(np.abs(s64).reshape(len(s64), -1).max(1), 1e-300)
+        err = np.abs(sig - s64).reshape(len(s64), -1).max(1) / scale
+        out["fp64_batched_solves_per_s"] = batch.n_rve / t64
+        out["mixed_vs_fp64_batched_speedup"] = value / (batch.n_rve / t64)
+        out["mixed_vs_fp64_sigma_relerr_frac_le_1e-4"] = float(np.mean(err[both] <= 1e-4)) if both.any() else None
+        log(f"fp64 batched: {t64:.2f}s; mixed-vs-fp64 sigma: {np.mean(err[both] <= 1e-4):.3f} of {both.sum()} <= 1e-4")
+        b64.close()
+
+    # ---------------- naive FP64, one RVE at a time (a few RVEs, extrapolated)
+    if not args.no_naive and args.naive_sample > 0:
+        idx = np.arange(args.naive_sample)
+        sub = batch.subset(idx)
+        bn = rb.Batch(sub, precision=rb.FP64, engine=rb.ENGINE_NAIVE, **common)
+        t1 = time.perf_counter()
+        sn, stn, sts = bn.solve(F[idx], stats=True)
+        tn = time.perf_counter() - t1
+        # extrapolate by element-updates: naive time per element-update x the batch's element-updates
+        eu_sub = float((sts["iters"] * nfib[idx]).sum())
+        naive_per_eu = tn / max(eu_sub, 1.0)
+        naive_batch_s = naive_per_eu * elem_updates
+        out["naive_fp64_solves_per_s_extrapolated"] = batch.n_rve / naive_batch_s
+        out["speedup_vs_naive_fp64"] = value / (batch.n_rve / naive_batch_s)
+        out["naive_sample"] = f"{args.naive_sample} RVEs, {tn:.1f}s, extrapolated per element-update"
+        log(f"naive: {tn:.1f}s for {args.naive_sample} RVEs -> speedup {out['speedup_vs_naive_fp64']:.0f}x")
+        bn.close()
+
+    # ---------------- roofline of the dominant kernel (relaxation)
+    out["roofline"] = {
+        "bound": "alu",
+        "achieved": flop_achieved / 1e12,
+        "peak": PEAK_FP32_VALU / 1e12,
+        "unit": "TFLOP/s",
+        "frac": flop_achieved / PEAK_FP32_VALU,
+        "traffic": None,
+        "kernel": "dr_resident_kernel<float>",
+        "hbm_algorithmic": {"achieved_GBps": hbm_achieved / 1e9, "peak_GBps": PEAK_HBM / 1e9,
+                            "frac": hbm_achieved / PEAK_HBM, "bytes_per_launch": alg_bytes},
+    }
+
+    # ---------------- CPU oracle on a bounded sample
+    if not args.no_cpu and args.cpu_sample > 0:
+        import oracle
+        idx = np.arange(args.cpu_sample)
+        sub = batch.subset(idx)
+        threads = min(os.cpu_count() or 1, 16)
+        o = oracle.make_opts(law=oracle.EXP, alpha=args.alpha, tol_abs=0.0, tol_rel=args.tol_rel,
+                             n_max=args.n_max, mass=args.mass)
+        t1 = time.perf_counter()
+        ref = oracle.solve_batch(sub, F[idx], args.c, o, threads=threads)
+        tc = time.perf_counter() - t1
+        both = (ref["status"] == 0) & (st[idx] == 0)
+        scale = np.maximum(np.abs(ref["sigma"]).reshape(len(idx), -1).max(1), 1e-300)
+        err = np.abs(sig[idx] - ref["sigma"]).reshape(len(idx), -1).max(1) / scale
+        out["cpu_baseline"] = {"value": args.cpu_sample / tc, "unit": "RVE solves/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"first {args.cpu_sample} RVEs of the batch, same options, {tc:.1f}s"}
+        out["sigma_relerr_vs_oracle_sample"] = {"converged_both": int(both.sum()),
+                                                "max": float(err[both].max()) if both.any() else None}
+        log(f"oracle: {tc:.1f}s on {threads} threads; max rel err {err[both].max() if both.any() else float('nan'):.2e}")
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -169,6 +169,16 @@ int rve_batch_set_opts(rve_batch* b, const rve_opts* opts);
 /* Replace only the stream of the batch (hipStream_t; NULL = null stream). */
 int rve_batch_set_stream(rve_batch* b, void* stream);
 
+/*
+ * Kernel timing: after rve_batch_profile(b, 1), every solve records HIP
+ * events around each relaxation launch and the stress launch on the batch's
+ * stream.  rve_batch_kernel_ms then returns, for the last solve, the summed
+ * duration of the relaxation kernels (*relax_ms) and of the stress kernel
+ * (*stress_ms) in milliseconds (it synchronises the stream).
+ */
+int rve_batch_profile(rve_batch* b, int enable);
+int rve_batch_kernel_ms(rve_batch* b, double* relax_ms, double* stress_ms);
+
 /* Number of RVEs, nodes and fibers of the batch. */
 int rve_batch_sizes(const rve_batch* b, int64_t* n_rve, int64_t* n_nodes, int64_t* n_fib);
 

@@ -27,7 +27,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ESTATE = 0, -22, -12, -5, -3
 
 EXPORTS = ["rve_version", "rve_last_error", "rve_default_opts", "rve_batch_create", "rve_batch_set_opts",
            "rve_batch_set_stream", "rve_batch_sizes", "rve_batch_solve", "rve_batch_tangent", "rve_batch_vjp",
-           "rve_batch_positions", "rve_batch_destroy"]
+           "rve_batch_positions", "rve_batch_destroy", "rve_batch_profile", "rve_batch_kernel_ms"]
 
 
 class NetDesc(C.Structure):
@@ -77,6 +77,8 @@ def lib():
         L.rve_batch_tangent.argtypes = [P, P, P, C.c_int32]
         L.rve_batch_vjp.argtypes = [P, P, P, P, C.c_int32]
         L.rve_batch_positions.argtypes = [P, C.c_int64, P]
+        L.rve_batch_profile.argtypes = [P, C.c_int]
+        L.rve_batch_kernel_ms.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.rve_batch_destroy.argtypes = [P]
         L.rve_batch_destroy.restype = None
         _lib = L
@@ -216,6 +218,15 @@ class Batch:
         gp, kind = _ptr(gsigma)
         _check(lib().rve_batch_vjp(self._h, gp, _ptr(gF)[0], _ptr(st)[0], kind))
         return gF, st
+
+    def profile(self, enable=True):
+        _check(lib().rve_batch_profile(self._h, 1 if enable else 0))
+
+    def kernel_ms(self):
+        """(relaxation ms, stress ms) of the last profiled solve (HIP events)."""
+        a, b = C.c_double(), C.c_double()
+        _check(lib().rve_batch_kernel_ms(self._h, C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     def positions(self, r):
         nn = int(self.node_off[r + 1] - self.node_off[r])

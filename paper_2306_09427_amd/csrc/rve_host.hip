@@ -82,12 +82,28 @@ struct rve_batch {
     bool variant_spills[2][kNumResident] = {};   // [fp64][variant]: the variant uses private memory
     // tangent / vjp workspace
     void* t_par = nullptr;
+    double* t_par64 = nullptr;
     float* t_vec = nullptr;
+    double* t_vec64 = nullptr;
     double* t_out = nullptr;
     double* t_in = nullptr;
     int32_t* t_status = nullptr;
     size_t t_par_bytes = 0, t_vec_bytes = 0;
+    // profiling events: [group][start, stop], then the stress kernel
+    bool profile = false;
+    std::vector<hipEvent_t> ev;
+    int ev_used = 0;
 };
+
+static int ensure_events(rve_batch* b, int n)
+{
+    while ((int)b->ev.size() < n) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        b->ev.push_back(e);
+    }
+    return RVE_OK;
+}
 
 // ------------------------------------------------------------------ helpers
 static int validate_opts(const rve_opts* o, int64_t R)
@@ -563,6 +579,31 @@ int rve_batch_set_stream(rve_batch* b, void* stream)
     return RVE_OK;
 }
 
+int rve_batch_profile(rve_batch* b, int enable)
+{
+    if (!b) return fail(RVE_EINVAL, "batch is NULL");
+    b->profile = enable != 0;
+    return RVE_OK;
+}
+
+int rve_batch_kernel_ms(rve_batch* b, double* relax_ms, double* stress_ms)
+{
+    if (!b || !relax_ms || !stress_ms) return fail(RVE_EINVAL, "NULL argument");
+    if (b->ev_used < 2) return fail(RVE_ESTATE, "no profiled solve");
+    HIP_TRY(hipEventSynchronize(b->ev[b->ev_used - 1]));
+    double relax = 0.0;
+    for (int g = 0; g + 2 < b->ev_used; g += 2) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, b->ev[g], b->ev[g + 1]));
+        relax += ms;
+    }
+    float st = 0.f;
+    HIP_TRY(hipEventElapsedTime(&st, b->ev[b->ev_used - 2], b->ev[b->ev_used - 1]));
+    *relax_ms = relax;
+    *stress_ms = st;
+    return RVE_OK;
+}
+
 int rve_batch_sizes(const rve_batch* b, int64_t* n_rve, int64_t* n_nodes, int64_t* n_fib)
 {
     if (!b) return fail(RVE_EINVAL, "batch is NULL");
@@ -624,12 +665,18 @@ int rve_batch_solve(rve_batch* b, const double* F, double* sigma, int32_t* statu
         if (rc) return fail(rc, err);
     } else {
         const bool fp64 = b->opts.precision == RVE_FP64;
+        b->ev_used = 0;
+        if (b->profile) {
+            rc = ensure_events(b, 2 * (int)b->groups.size() + 2);
+            if (rc) return rc;
+        }
         for (size_t g = 0; g < b->groups.size(); ++g) {
             a.list = b->dlist + b->group_first[g];
             a.n_list = (int32_t)b->groups[g].size();
             a.queue = b->dqueue + 2 * g;
             HIP_TRY(hipMemsetAsync(a.queue, 0, sizeof(int32_t), s));
             const int v = b->group_variant[g];
+            if (b->profile) HIP_TRY(hipEventRecord(b->ev[2 * g], s));
             if (v >= 0) {
                 int per_cu = 1;
                 HIP_TRY(max_resident_blocks(v, fp64, b->group_lds[g], &per_cu));
@@ -641,8 +688,15 @@ int rve_batch_solve(rve_batch* b, const double* F, double* sigma, int32_t* statu
                 int grid = std::min<int64_t>((int64_t)b->n_cu * (threads == 256 ? 4 : 2), a.n_list);
                 HIP_TRY(launch_streamed(fp64, a, grid, threads, s));
             }
+            if (b->profile) HIP_TRY(hipEventRecord(b->ev[2 * g + 1], s));
         }
+        const size_t gs = b->groups.size();
+        if (b->profile) HIP_TRY(hipEventRecord(b->ev[2 * gs], s));
         HIP_TRY(launch_stress(a, (int)b->R, s));
+        if (b->profile) {
+            HIP_TRY(hipEventRecord(b->ev[2 * gs + 1], s));
+            b->ev_used = 2 * (int)gs + 2;
+        }
     }
     HIP_TRY(hipMemcpyAsync(sigma, b->dsigma, 72 * b->R, out_kind, s));
     HIP_TRY(hipMemcpyAsync(status, b->dstatus, 4 * b->R, out_kind, s));
@@ -687,16 +741,22 @@ static int ensure_tangent_ws(rve_batch* b, int W)
     size_t vb = 4 * sizeof(float) * (size_t)W * (size_t)(b->NFREE + b->R);
     if (pb > b->t_par_bytes) {
         if (b->t_par) (void)hipFree(b->t_par);
+        if (b->t_par64) (void)hipFree(b->t_par64);
         b->t_par = nullptr;
+        b->t_par64 = nullptr;
         b->t_par_bytes = 0;
-        if (hipMalloc(&b->t_par, pb) != hipSuccess) return fail(RVE_ENOMEM, "tangent workspace allocation failed");
+        if (hipMalloc(&b->t_par, pb) != hipSuccess || hipMalloc((void**)&b->t_par64, 40 * (size_t)(b->NF + b->R)) != hipSuccess)
+            return fail(RVE_ENOMEM, "tangent workspace allocation failed");
         b->t_par_bytes = pb;
     }
     if (vb > b->t_vec_bytes) {
         if (b->t_vec) (void)hipFree(b->t_vec);
+        if (b->t_vec64) (void)hipFree(b->t_vec64);
         b->t_vec = nullptr;
+        b->t_vec64 = nullptr;
         b->t_vec_bytes = 0;
-        if (hipMalloc(&b->t_vec, vb) != hipSuccess) return fail(RVE_ENOMEM, "tangent workspace allocation failed");
+        if (hipMalloc((void**)&b->t_vec, vb) != hipSuccess || hipMalloc((void**)&b->t_vec64, vb) != hipSuccess)
+            return fail(RVE_ENOMEM, "tangent workspace allocation failed");
         b->t_vec_bytes = vb;
     }
     if (!b->t_out) {
@@ -740,7 +800,9 @@ static int run_cg(rve_batch* b, int mode, const double* gsigma, double* out, int
     a.n_free_total = b->NFREE;
     a.n_rve = b->R;
     a.ws_par = b->t_par;
+    a.ws_par64 = b->t_par64;
     a.ws_vec = b->t_vec;
+    a.ws_vec64 = b->t_vec64;
     HIP_TRY(hipMemsetAsync(a.queue, 0, sizeof(int32_t), s));
     int grid = (int)std::min<int64_t>((int64_t)b->n_cu * 4, b->R);
     HIP_TRY(launch_tangent(a, grid, s));
@@ -763,8 +825,11 @@ int rve_batch_vjp(rve_batch* b, const double* gsigma, double* gF, int32_t* statu
 void rve_batch_destroy(rve_batch* b)
 {
     if (!b) return;
+    for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
     if (b->t_par) (void)hipFree(b->t_par);
     if (b->t_vec) (void)hipFree(b->t_vec);
+    if (b->t_par64) (void)hipFree(b->t_par64);
+    if (b->t_vec64) (void)hipFree(b->t_vec64);
     if (b->t_out) (void)hipFree(b->t_out);
     if (b->t_in) (void)hipFree(b->t_in);
     if (b->t_status) (void)hipFree(b->t_status);

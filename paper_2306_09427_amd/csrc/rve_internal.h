@@ -68,7 +68,9 @@ struct TangentArgs {
     int64_t n_free_total;
     int64_t n_rve;
     void* ws_par;                // [NF + R][2] float4 fiber operators
+    double* ws_par64;            // [NF + R][5] FP64 fiber operators
     float* ws_vec;               // 4 vectors of [NFREE + R][3 NR] floats
+    double* ws_vec64;            // 2 vectors of [NFREE + R][3 NR] doubles
 };
 
 // Which register-resident variants exist (threads per RVE, fiber slots per

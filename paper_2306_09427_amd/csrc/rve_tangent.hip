@@ -16,9 +16,14 @@
 // and u = [0; y], solve K_ff lambda = (K u)_f, then z_b = (K [-lambda; y])_b
 // and dL/dF_kl = sum_b (z_b + G^T f_b)_k Xm_b,l / (J V0) - (G:sigma) F^-T_kl.
 //
-// Products are FP32 (fiber operators and vectors), dot products and the
-// residual norms FP64, the final assembly FP64 from an FP64 re-evaluation of
-// the boundary fibers.  One workgroup per RVE, persistent over a work queue.
+// Precision: iterative refinement.  The outer loop keeps the solution, the
+// right-hand side and the residual r = b - K x in FP64 (FP64 fiber operators);
+// each inner solve K d = r is conjugate gradients with FP32 products and FP64
+// dot products, stopped after a 1e-6 reduction of its residual; x += d.
+// Plain FP32 CG stalls near eps_32 cond(K_ff), about 1e-3 on these networks,
+// which refinement removes.  The final assembly is FP64 from an FP64
+// re-evaluation of the boundary fibers.  One workgroup per RVE, persistent
+// over a work queue.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -139,53 +144,61 @@ __device__ void cg_one(const TangentArgs& A, int r, double (*sh)[NT / 64])
     if (NR == 1)
         for (int k = 0; k < 9; ++k) G[k] = A.gsigma[9 * r + k];
     const double J = det3(F);
+    const int64_t NV = (A.n_free_total + A.n_rve) * (int64_t)W;   // length of one vector over the batch
+    // fiber operators: FP32 copy for the inner solves, FP64 copy for residuals
     float4* par = reinterpret_cast<float4*>(A.ws_par) + 2 * (f0 + r);   // [nfib][2]: (n, a), (g, -, -, -)
-    float* vx = A.ws_vec + (a0 + r) * (int64_t)W;                       // x
-    float* vr = vx + (A.n_free_total + A.n_rve) * (int64_t)W;            // r
-    float* vp = vr + (A.n_free_total + A.n_rve) * (int64_t)W;            // p (entry nf = 0)
-    float* vq = vp + (A.n_free_total + A.n_rve) * (int64_t)W;            // Ap
+    double* par64 = A.ws_par64 + 5 * (f0 + r);                          // [nfib][5]: n, a, g
+    float* vx = A.ws_vec + (a0 + r) * (int64_t)W;     // inner solution d
+    float* vr = vx + NV;                              // inner residual
+    float* vp = vr + NV;                              // search direction (entry nf = 0)
+    float* vq = vp + NV;                              // K p
+    double* xb = A.ws_vec64 + (a0 + r) * (int64_t)W;  // FP64 solution (entry nf = 0)
+    double* bb64 = xb + NV;                           // FP64 right-hand side
 
-    // fiber operators
 #pragma unroll 1
     for (int64_t k = tid; k < nfib; k += NT) {
         FiberOp o = fiber_op(A, F, f0, a0, nf, k);
         par[2 * k] = make_float4((float)o.nx, (float)o.ny, (float)o.nz, (float)o.a);
         par[2 * k + 1] = make_float4((float)o.g, 0.f, 0.f, 0.f);
+        double* q = par64 + 5 * k;
+        q[0] = o.nx; q[1] = o.ny; q[2] = o.nz; q[3] = o.a; q[4] = o.g;
     }
-    if (tid < W) vp[nf * W + tid] = 0.f;
+    if (tid < W) {
+        vp[nf * W + tid] = 0.f;
+        xb[nf * W + tid] = 0.0;
+    }
     __syncthreads();
 
-    // right-hand sides
-    double rr[NR];
+    // right-hand sides (FP64)
+    double bnorm2[NR];
 #pragma unroll
-    for (int k = 0; k < NR; ++k) rr[k] = 0.0;
+    for (int k = 0; k < NR; ++k) bnorm2[k] = 0.0;
 #pragma unroll 1
     for (int64_t a = tid; a < nf; a += NT) {
-        float b[W];
+        double b[W];
 #pragma unroll
-        for (int k = 0; k < W; ++k) b[k] = 0.f;
+        for (int k = 0; k < W; ++k) b[k] = 0.0;
 #pragma unroll 1
         for (int64_t e = net.inc_off[a0 + a]; e < net.inc_off[a0 + a + 1]; ++e) {
             uint32_t w = net.inc[e];
             int64_t k = w & 0x7fffffffu;
-            float sgn = (w >> 31) ? -1.f : 1.f;     // end i: -1, end j: +1
-            float4 nA = par[2 * k];
-            float g = par[2 * k + 1].x;
+            double sgn = (w >> 31) ? -1.0 : 1.0;     // end i: -1, end j: +1
+            const double* q = par64 + 5 * k;
             if (NR == 9) {
                 // -s B_f (e_kk d0_l) for direction (kk, l)
                 const double* d0 = net.d0 + 3 * (f0 + k);
 #pragma unroll
                 for (int kk = 0; kk < 3; ++kk) {
-                    float ex = kk == 0, ey = kk == 1, ez = kk == 2;
-                    float wx, wy, wz;
-                    apply_B(nA, g, ex, ey, ez, wx, wy, wz);
+                    double n_k = q[kk], c = (q[3] - q[4]) * n_k;
+                    double wv[3] = {c * q[0], c * q[1], c * q[2]};
+                    wv[kk] += q[4];
 #pragma unroll
                     for (int l = 0; l < 3; ++l) {
-                        float s = -sgn * (float)d0[l];
+                        double s = -sgn * d0[l];
                         int col = 3 * kk + l;
-                        b[3 * col] += s * wx;
-                        b[3 * col + 1] += s * wy;
-                        b[3 * col + 2] += s * wz;
+                        b[3 * col] += s * wv[0];
+                        b[3 * col + 1] += s * wv[1];
+                        b[3 * col + 2] += s * wv[2];
                     }
                 }
             } else {
@@ -196,143 +209,208 @@ __device__ void cg_one(const TangentArgs& A, int r, double (*sh)[NT / 64])
                     const double* Xm = net.Xb + 3 * (b0 + (o - nf));
                     double x[3], y[3];
                     for (int p = 0; p < 3; ++p) x[p] = F[3 * p] * Xm[0] + F[3 * p + 1] * Xm[1] + F[3 * p + 2] * Xm[2];
-                    for (int p = 0; p < 3; ++p) y[p] = G[3 * p] * x[0] + G[3 * p + 1] * x[1] + G[3 * p + 2] * x[2];
-                    float wx, wy, wz;
-                    apply_B(nA, g, (float)-y[0], (float)-y[1], (float)-y[2], wx, wy, wz);
-                    b[0] += wx;
-                    b[1] += wy;
-                    b[2] += wz;
+                    for (int p = 0; p < 3; ++p) y[p] = -(G[3 * p] * x[0] + G[3 * p + 1] * x[1] + G[3 * p + 2] * x[2]);
+                    double dn = q[0] * y[0] + q[1] * y[1] + q[2] * y[2];
+                    double c = (q[3] - q[4]) * dn;
+                    for (int p = 0; p < 3; ++p) b[p] += q[4] * y[p] + c * q[p];
                 }
             }
         }
-        float* X = vx + a * W;
-        float* R = vr + a * W;
-        float* P = vp + a * W;
 #pragma unroll
         for (int k = 0; k < W; ++k) {
-            X[k] = 0.f;
-            R[k] = b[k];
-            P[k] = b[k];
+            bb64[a * W + k] = b[k];
+            xb[a * W + k] = 0.0;
         }
 #pragma unroll
-        for (int k = 0; k < NR; ++k)
-            rr[k] += (double)b[3 * k] * b[3 * k] + (double)b[3 * k + 1] * b[3 * k + 1] + (double)b[3 * k + 2] * b[3 * k + 2];
+        for (int k = 0; k < NR; ++k) bnorm2[k] += b[3 * k] * b[3 * k] + b[3 * k + 1] * b[3 * k + 1] + b[3 * k + 2] * b[3 * k + 2];
     }
-    block_sum<NR, NT>(rr, sh);
-    double bb[NR];
-    bool active[NR];
+    block_sum<NR, NT>(bnorm2, sh);
+
     int status = ST_CONVERGED;
     const double tol2 = A.cg_tol * A.cg_tol;
-#pragma unroll
-    for (int k = 0; k < NR; ++k) {
-        bb[k] = rr[k];
-        active[k] = rr[k] > 0.0;
-    }
     const int64_t maxit = A.cg_max > 0 ? A.cg_max : 6 * nf + 100;
-    int64_t it = 0;
-    for (;;) {
+    int64_t it_total = 0;
+    bool done[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) done[k] = !(bnorm2[k] > 0.0);
+
+    // Outer loop: FP64 residual r = b - K x of the FP64 solution, inner CG with
+    // FP32 products on K d = r, x += d (iterative refinement).
+    for (int outer = 0; outer < 8; ++outer) {
+        double rr[NR];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) rr[k] = 0.0;
+#pragma unroll 1
+        for (int64_t a = tid; a < nf; a += NT) {
+            double ra[W];
+#pragma unroll
+            for (int k = 0; k < W; ++k) ra[k] = bb64[a * W + k];
+            if (outer > 0) {
+                double xa[W];
+#pragma unroll
+                for (int k = 0; k < W; ++k) xa[k] = xb[a * W + k];
+#pragma unroll 1
+                for (int64_t e = net.inc_off[a0 + a]; e < net.inc_off[a0 + a + 1]; ++e) {
+                    uint32_t w = net.inc[e];
+                    int64_t k = w & 0x7fffffffu;
+                    uint32_t en = net.ends[f0 + k];
+                    int o = (w >> 31) ? (int)(en >> 16) : (int)(en & 0xffff);
+                    const double* xo = xb + (o < nf ? o : nf) * (int64_t)W;
+                    const double* q = par64 + 5 * k;
+#pragma unroll
+                    for (int c = 0; c < NR; ++c) {
+                        double dx = xa[3 * c] - xo[3 * c], dy = xa[3 * c + 1] - xo[3 * c + 1],
+                               dz = xa[3 * c + 2] - xo[3 * c + 2];
+                        double dn = q[0] * dx + q[1] * dy + q[2] * dz;
+                        double cc = (q[3] - q[4]) * dn;
+                        ra[3 * c] -= q[4] * dx + cc * q[0];
+                        ra[3 * c + 1] -= q[4] * dy + cc * q[1];
+                        ra[3 * c + 2] -= q[4] * dz + cc * q[2];
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                vr[a * W + k] = (float)ra[k];
+                vp[a * W + k] = (float)ra[k];
+                vx[a * W + k] = 0.f;
+            }
+#pragma unroll
+            for (int c = 0; c < NR; ++c)
+                rr[c] += ra[3 * c] * ra[3 * c] + ra[3 * c + 1] * ra[3 * c + 1] + ra[3 * c + 2] * ra[3 * c + 2];
+        }
+        block_sum<NR, NT>(rr, sh);
+        bool active[NR];
         bool any = false;
 #pragma unroll
-        for (int k = 0; k < NR; ++k) any = any || active[k];
+        for (int k = 0; k < NR; ++k) {
+            if (!done[k] && rr[k] <= tol2 * bnorm2[k]) done[k] = true;
+            active[k] = !done[k];
+            any = any || active[k];
+        }
         if (!any) break;
-        if (it >= maxit) {
+        if (it_total >= maxit) {
             status = ST_CG_MAXITER;
             break;
         }
-        ++it;
-        // q = K p and p.q
-        double pq[NR];
+        // inner CG: reduce the FP32 residual by 1e-3 (or to the final tolerance)
+        double rr0[NR];
 #pragma unroll
-        for (int k = 0; k < NR; ++k) pq[k] = 0.0;
+        for (int k = 0; k < NR; ++k) rr0[k] = rr[k];
+        for (;;) {
+            bool anyi = false;
+#pragma unroll
+            for (int k = 0; k < NR; ++k) anyi = anyi || active[k];
+            if (!anyi) break;
+            if (it_total >= maxit) break;
+            ++it_total;
+            double pq[NR];
+#pragma unroll
+            for (int k = 0; k < NR; ++k) pq[k] = 0.0;
 #pragma unroll 1
-        for (int64_t a = tid; a < nf; a += NT) {
-            const float* Pa = vp + a * W;
-            float pa[W], q[W];
+            for (int64_t a = tid; a < nf; a += NT) {
+                const float* Pa = vp + a * W;
+                float pa[W], q[W];
 #pragma unroll
-            for (int k = 0; k < W; ++k) {
-                pa[k] = Pa[k];
-                q[k] = 0.f;
+                for (int k = 0; k < W; ++k) {
+                    pa[k] = Pa[k];
+                    q[k] = 0.f;
+                }
+#pragma unroll 1
+                for (int64_t e = net.inc_off[a0 + a]; e < net.inc_off[a0 + a + 1]; ++e) {
+                    uint32_t w = net.inc[e];
+                    int64_t k = w & 0x7fffffffu;
+                    uint32_t en = net.ends[f0 + k];
+                    int o = (w >> 31) ? (int)(en >> 16) : (int)(en & 0xffff);
+                    const float* Po = vp + (o < nf ? o : nf) * (int64_t)W;
+                    float4 nA = par[2 * k];
+                    float g = par[2 * k + 1].x;
+#pragma unroll
+                    for (int c = 0; c < NR; ++c) {
+                        float wx, wy, wz;
+                        apply_B(nA, g, pa[3 * c] - Po[3 * c], pa[3 * c + 1] - Po[3 * c + 1],
+                                pa[3 * c + 2] - Po[3 * c + 2], wx, wy, wz);
+                        q[3 * c] += wx;
+                        q[3 * c + 1] += wy;
+                        q[3 * c + 2] += wz;
+                    }
+                }
+                float* Q = vq + a * W;
+#pragma unroll
+                for (int k = 0; k < W; ++k) Q[k] = q[k];
+#pragma unroll
+                for (int c = 0; c < NR; ++c)
+                    pq[c] += (double)pa[3 * c] * q[3 * c] + (double)pa[3 * c + 1] * q[3 * c + 1] +
+                             (double)pa[3 * c + 2] * q[3 * c + 2];
             }
-#pragma unroll 1
-            for (int64_t e = net.inc_off[a0 + a]; e < net.inc_off[a0 + a + 1]; ++e) {
-                uint32_t w = net.inc[e];
-                int64_t k = w & 0x7fffffffu;
-                uint32_t en = net.ends[f0 + k];
-                int o = (w >> 31) ? (int)(en >> 16) : (int)(en & 0xffff);
-                const float* Po = vp + (o < nf ? o : nf) * (int64_t)W;
-                float4 nA = par[2 * k];
-                float g = par[2 * k + 1].x;
+            block_sum<NR, NT>(pq, sh);
+            float alpha[NR];
 #pragma unroll
-                for (int c = 0; c < NR; ++c) {
-                    float wx, wy, wz;
-                    apply_B(nA, g, pa[3 * c] - Po[3 * c], pa[3 * c + 1] - Po[3 * c + 1], pa[3 * c + 2] - Po[3 * c + 2],
-                            wx, wy, wz);
-                    q[3 * c] += wx;
-                    q[3 * c + 1] += wy;
-                    q[3 * c + 2] += wz;
+            for (int k = 0; k < NR; ++k) {
+                alpha[k] = 0.f;
+                if (active[k]) {
+                    if (!(pq[k] > 0.0)) {
+                        active[k] = false;
+                        done[k] = true;
+                        status = ST_CG_INDEFINITE;
+                    } else {
+                        alpha[k] = (float)(rr[k] / pq[k]);
+                    }
                 }
             }
-            float* Q = vq + a * W;
+            double rn[NR];
 #pragma unroll
-            for (int k = 0; k < W; ++k) Q[k] = q[k];
+            for (int k = 0; k < NR; ++k) rn[k] = 0.0;
+#pragma unroll 1
+            for (int64_t a = tid; a < nf; a += NT) {
+                float* X = vx + a * W;
+                float* R = vr + a * W;
+                const float* P = vp + a * W;
+                const float* Q = vq + a * W;
 #pragma unroll
-            for (int c = 0; c < NR; ++c)
-                pq[c] += (double)pa[3 * c] * q[3 * c] + (double)pa[3 * c + 1] * q[3 * c + 1] + (double)pa[3 * c + 2] * q[3 * c + 2];
-        }
-        block_sum<NR, NT>(pq, sh);
-        float alpha[NR];
+                for (int c = 0; c < NR; ++c)
 #pragma unroll
-        for (int k = 0; k < NR; ++k) {
-            alpha[k] = 0.f;
-            if (active[k]) {
-                if (!(pq[k] > 0.0)) {
-                    active[k] = false;
-                    status = ST_CG_INDEFINITE;
-                } else {
-                    alpha[k] = (float)(rr[k] / pq[k]);
+                    for (int p = 0; p < 3; ++p) {
+                        int k = 3 * c + p;
+                        X[k] += alpha[c] * P[k];
+                        float rk = R[k] - alpha[c] * Q[k];
+                        R[k] = rk;
+                        rn[c] += (double)rk * rk;
+                    }
+            }
+            block_sum<NR, NT>(rn, sh);
+            float beta[NR];
+#pragma unroll
+            for (int k = 0; k < NR; ++k) {
+                beta[k] = active[k] ? (float)(rn[k] / rr[k]) : 0.f;
+                if (active[k]) {
+                    rr[k] = rn[k];
+                    if (rn[k] <= 1e-6 * rr0[k] || rn[k] <= 0.25 * tol2 * bnorm2[k]) active[k] = false;
                 }
             }
-        }
-        double rn[NR];
-#pragma unroll
-        for (int k = 0; k < NR; ++k) rn[k] = 0.0;
 #pragma unroll 1
-        for (int64_t a = tid; a < nf; a += NT) {
-            float* X = vx + a * W;
-            float* R = vr + a * W;
-            const float* P = vp + a * W;
-            const float* Q = vq + a * W;
+            for (int64_t a = tid; a < nf; a += NT) {
+                float* P = vp + a * W;
+                const float* R = vr + a * W;
 #pragma unroll
-            for (int c = 0; c < NR; ++c)
+                for (int c = 0; c < NR; ++c)
 #pragma unroll
-                for (int p = 0; p < 3; ++p) {
-                    int k = 3 * c + p;
-                    X[k] += alpha[c] * P[k];
-                    float rk = R[k] - alpha[c] * Q[k];
-                    R[k] = rk;
-                    rn[c] += (double)rk * rk;
-                }
-        }
-        block_sum<NR, NT>(rn, sh);
-        float beta[NR];
-#pragma unroll
-        for (int k = 0; k < NR; ++k) {
-            beta[k] = active[k] ? (float)(rn[k] / rr[k]) : 0.f;
-            if (active[k]) {
-                rr[k] = rn[k];
-                if (rn[k] <= tol2 * bb[k]) active[k] = false;
+                    for (int p = 0; p < 3; ++p) P[3 * c + p] = R[3 * c + p] + beta[c] * P[3 * c + p];
             }
+            __syncthreads();
         }
+        // x += d
 #pragma unroll 1
-        for (int64_t a = tid; a < nf; a += NT) {
-            float* P = vp + a * W;
-            const float* R = vr + a * W;
+        for (int64_t a = tid; a < nf; a += NT)
 #pragma unroll
-            for (int c = 0; c < NR; ++c)
-#pragma unroll
-                for (int p = 0; p < 3; ++p) P[3 * c + p] = R[3 * c + p] + beta[c] * P[3 * c + p];
-        }
+            for (int k = 0; k < W; ++k) xb[a * W + k] += (double)vx[a * W + k];
         __syncthreads();
+        if (outer == 7) {
+            bool left = false;
+#pragma unroll
+            for (int k = 0; k < NR; ++k) left = left || !done[k];
+            if (left && status == ST_CONVERGED) status = ST_CG_MAXITER;
+        }
     }
 
     // assembly over fibers with a boundary end (FP64 operators)
@@ -368,8 +446,8 @@ __device__ void cg_one(const TangentArgs& A, int r, double (*sh)[NT / 64])
                 double u[3] = {0, 0, 0};
                 u[kk] = d0[l];
                 for (int p = 0; p < 3; ++p) {
-                    if (j < nf) u[p] += vx[j * W + 3 * col + p];
-                    if (i < nf) u[p] -= vx[i * W + 3 * col + p];
+                    if (j < nf) u[p] += xb[j * W + 3 * col + p];
+                    if (i < nf) u[p] -= xb[i * W + 3 * col + p];
                 }
                 double dn = o.nx * u[0] + o.ny * u[1] + o.nz * u[2];
                 double cc = (o.a - o.g) * dn;
@@ -410,7 +488,7 @@ __device__ void cg_one(const TangentArgs& A, int r, double (*sh)[NT / 64])
                 int node = end ? j : i;
                 double* u = end ? uj : ui;
                 if (node < nf) {
-                    for (int p = 0; p < 3; ++p) u[p] = -(double)vx[node * W + p];
+                    for (int p = 0; p < 3; ++p) u[p] = -xb[node * W + p];
                 } else {
                     const double* Xm = net.Xb + 3 * (b0 + (node - nf));
                     double x[3];
