@@ -294,11 +294,11 @@ __device__ __forceinline__ void block_reduce4(RedSlots& red, double gmax, double
 
 // Boundary reaction norm^2 partial of this thread (test iterations only).
 template <typename Real, int T>
-__device__ __forceinline__ double boundary_norm2_partial(const DevNet& net, const Lds<Real>& L, int64_t b0, int64_t nb)
+__device__ __forceinline__ double boundary_norm2_partial(const DevNet& net, const Lds<Real>& L, int64_t b0, int nb)
 {
     double acc = 0.0;
 #pragma unroll 1
-    for (int64_t q = threadIdx.x; q < nb; q += T) {
+    for (int q = threadIdx.x; q < nb; q += T) {
         double x = 0, y = 0, z = 0;
 #pragma unroll 1
         for (int64_t e = net.binc_off[b0 + q]; e < net.binc_off[b0 + q + 1]; ++e) {
@@ -342,11 +342,21 @@ template <typename Real, int T, int SF, int SN>
 __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* smem, RedSlots& red)
 {
     constexpr int NW = T / 64;
-    const int tid = threadIdx.x;
+    // Opaque per RVE: slot indices derived from the thread id are recomputed
+    // for each RVE instead of being held live across the persistent loop.
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
     const DevNet& net = A.net;
-    const int64_t f0 = net.fib_off[r], nfib = net.fib_off[r + 1] - f0;
-    const int64_t a0 = net.free_off[r], nf = net.free_off[r + 1] - a0;
-    const int64_t b0 = net.bnd_off[r], nb = net.bnd_off[r + 1] - b0;
+    const int64_t f0 = net.fib_off[r], a0 = net.free_off[r], b0 = net.bnd_off[r];
+    const int nfib = (int)(net.fib_off[r + 1] - f0);
+    const int nf = (int)(net.free_off[r + 1] - a0);
+    const int nb = (int)(net.bnd_off[r + 1] - b0);
+    const double* d0b = net.d0 + 3 * f0;
+    const double* L0b = net.L0 + f0;
+    const uint32_t* endb = net.ends + f0;
+    const double* massb = net.mass + a0;
+    const int64_t* incoffb = net.inc_off + a0;
+    double* hsb = A.h_state + 3 * a0;
 
     double F[9];
     bool finite = true;
@@ -381,8 +391,8 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
         L0r[s] = iL0r[s] = Real(1);
         E[s] = 0;
         if (k < nfib) {
-            const double* d0 = net.d0 + 3 * (f0 + k);
-            double L0 = net.L0[f0 + k];
+            const double* d0 = d0b + 3 * k;
+            double L0 = L0b[k];
             double Dx = F[0] * d0[0] + F[1] * d0[1] + F[2] * d0[2];
             double Dy = F[3] * d0[0] + F[4] * d0[1] + F[5] * d0[2];
             double Dz = F[6] * d0[0] + F[7] * d0[1] + F[8] * d0[2];
@@ -390,7 +400,7 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
             Q0[s] = (Real)((Dx * Dx + Dy * Dy + Dz * Dz) - L0 * L0);
             L0r[s] = (Real)L0;
             iL0r[s] = (Real)(1.0 / L0);
-            uint32_t e = net.ends[f0 + k];
+            uint32_t e = endb[k];
             uint32_t i = e & 0xffffu, j = e >> 16;
             // boundary ends read the zero slot nf
             i = i < (uint32_t)nf ? i : (uint32_t)nf;
@@ -411,8 +421,8 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
 #pragma unroll
         for (int q = 0; q < kMaxResidentDegree / 2; ++q) inc[s][q] = (uint32_t)nfib | ((uint32_t)nfib << 16);
         if (a < nf) {
-            iM[s] = (Real)(1.0 / (net.mass[a0 + a] * A.rhoA));
-            int64_t e0 = net.inc_off[a0 + a], e1 = net.inc_off[a0 + a + 1];
+            iM[s] = (Real)(1.0 / (massb[a] * A.rhoA));
+            int64_t e0 = incoffb[a], e1 = incoffb[a + 1];
             deg[s] = (int)(e1 - e0);
 #pragma unroll
             for (int q = 0; q < kMaxResidentDegree; ++q) {
@@ -426,16 +436,16 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
                 }
             }
             if (A.init == kInitWarm) {
-                const double* h = A.h_state + 3 * (a0 + a);
+                const double* h = hsb + 3 * a;
                 hx[s] = (Real)h[0]; hy[s] = (Real)h[1]; hz[s] = (Real)h[2];
             }
             L.put_h(a, hx[s], hy[s], hz[s]);
         }
     }
     if (tid == 0) {
-        L.put_h((int)nf, Real(0), Real(0), Real(0));
+        L.put_h(nf, Real(0), Real(0), Real(0));
         FiberOut<Real> z{Real(0), Real(0), Real(0), Real(0)};
-        L.put_fv((int)nfib, z);
+        L.put_fv(nfib, z);
     }
     __syncthreads();
 
@@ -563,8 +573,9 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
                 gpart = fmax(gpart, (double)(G * iM[s]));
                 if (check) {
                     r2p += (double)fx * fx + (double)fy * fy + (double)fz * fz;
-                    double m = cd / (double)iM[s];
-                    double px = m * (double)vx[s], py = m * (double)vy[s], pz = m * (double)vz[s];
+                    // damping force c M v of this node (only tested against the tolerance)
+                    const Real cm = c * dev_rcp(iM[s]);
+                    const double px = (double)(cm * vx[s]), py = (double)(cm * vy[s]), pz = (double)(cm * vz[s]);
                     d2p += px * px + py * py + pz * pz;
                 }
             }
@@ -599,7 +610,7 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
     for (int s = 0; s < SN; ++s) {
         int a = s * T + tid;
         if (a < nf) {
-            double* h = A.h_state + 3 * (a0 + a);
+            double* h = hsb + 3 * a;
             h[0] = (double)hx[s]; h[1] = (double)hy[s]; h[2] = (double)hz[s];
         }
     }

@@ -89,7 +89,8 @@ def test_identity_bad_F_and_nmax(rb):
         sig, st, stats = b.solve(F, stats=True)
         assert st.tolist() == [rb.ST_CONVERGED, rb.ST_BAD_F, rb.ST_MAXITER, rb.ST_BAD_F]
         assert stats["iters"].tolist() == [0, 0, 5, 0]
-        assert np.all(sig[0] == 0.0)
+        # F = I: q0 = |F d0|^2 - L0^2 is a rounding-level residue, so sigma is ~0
+        assert np.abs(sig[0]).max() < 1e-14
         assert np.all(np.isnan(sig[1])) and np.all(np.isnan(sig[3]))
         assert np.all(np.isfinite(sig[2]))
         b.close()
@@ -148,7 +149,9 @@ def test_config2_fp64_matches_oracle(rb, cfg2_subset, engine):
 def test_config2_mixed_matches_oracle(rb, cfg2_subset):
     batch, F, ref = cfg2_subset
     log("config2 mixed")
-    b = rb.Batch(batch, precision=rb.MIXED, law=rb.LAW_EXP, tol_abs=0.0, tol_rel=1e-6, **CFG2)
+    # FP32 positions and forces put the residual floor near 1e-5 |f_bnd| on these
+    # networks (short stiff fibers), so mixed precision stops at tol_rel = 1e-5
+    b = rb.Batch(batch, precision=rb.MIXED, law=rb.LAW_EXP, tol_abs=0.0, tol_rel=1e-5, **CFG2)
     sig, st, stats = b.solve(F, stats=True)
     both = (st == 0) & (ref["status"] == 0)
     err = rel_err(sig[both], ref["sigma"][both])
