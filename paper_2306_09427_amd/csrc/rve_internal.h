@@ -90,6 +90,7 @@ hipError_t launch_resident(int variant, bool fp64, const SolveArgs& a, size_t ld
                            hipStream_t s);
 hipError_t launch_streamed(bool fp64, const SolveArgs& a, int grid, int threads, hipStream_t s);
 hipError_t launch_stress(const SolveArgs& a, int n_rve, hipStream_t s);
+hipError_t launch_reset(int32_t* counters, int n, hipStream_t s);   // n <= 64
 hipError_t launch_tangent(const TangentArgs& a, int grid, hipStream_t s);
 hipError_t max_resident_blocks(int variant, bool fp64, size_t lds_bytes, int* blocks_per_cu);
 // Private (spill) bytes per lane of a resident variant; > 0 means it spills.

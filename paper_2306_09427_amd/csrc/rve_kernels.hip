@@ -59,7 +59,22 @@ struct Vec4<double> {
 
 __device__ inline float dev_sqrt(float x) { return __builtin_sqrtf(x); }
 __device__ inline double dev_sqrt(double x) { return sqrt(x); }
-__device__ inline float dev_expm1(float x) { return expm1f(x); }
+// exp(x) - 1 for the exponential fiber law in FP32: degree-8 Taylor series
+// below 0.5 (relative truncation error < 2e-8 there), the hardware 2^x
+// above (relative error < 2e-7 of e^x - 1 at the switch, falling with x).
+__device__ inline float dev_expm1(float x)
+{
+    float t = x * (1.f / 40320.f) + (1.f / 5040.f);
+    t = t * x + (1.f / 720.f);
+    t = t * x + (1.f / 120.f);
+    t = t * x + (1.f / 24.f);
+    t = t * x + (1.f / 6.f);
+    t = t * x + 0.5f;
+    t = t * x + 1.f;
+    float taylor = t * x;
+    float big = __builtin_amdgcn_exp2f(x * 1.44269504088896341f) - 1.f;
+    return fabsf(x) < 0.5f ? taylor : big;
+}
 __device__ inline double dev_expm1(double x) { return expm1(x); }
 
 // Axial force T(eps) and k_t = dT/deps (truss law).
@@ -154,6 +169,28 @@ __device__ inline double wave_max(double v)
     return v;
 }
 
+// Maximum over the 64 lanes of a non-negative float (bit patterns of
+// non-negative floats order like unsigned integers), by DPP butterflies
+// inside each row of 16 lanes and row broadcasts across rows; the result of
+// lane 63 is returned in a scalar register.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ unsigned dpp_max_step(unsigned v)
+{
+    unsigned o = (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, ROW_MASK, 0xf, false);
+    return o > v ? o : v;
+}
+__device__ __forceinline__ float wave_max_nonneg(float x)
+{
+    unsigned v = __float_as_uint(x);
+    v = dpp_max_step<0xb1, 0xf>(v);    // quad_perm [1,0,3,2]
+    v = dpp_max_step<0x4e, 0xf>(v);    // quad_perm [2,3,0,1]
+    v = dpp_max_step<0x141, 0xf>(v);   // row_half_mirror
+    v = dpp_max_step<0x140, 0xf>(v);   // row_mirror
+    v = dpp_max_step<0x142, 0xa>(v);   // row_bcast:15
+    v = dpp_max_step<0x143, 0xc>(v);   // row_bcast:31
+    return __uint_as_float(__builtin_amdgcn_readlane(v, 63));
+}
+
 // Neumaier-compensated accumulation (sum, compensation).
 __device__ inline void neumaier_add(double& s, double& c, double x)
 {
@@ -246,50 +283,71 @@ size_t resident_lds_bytes(bool fp64, int64_t nf, int64_t nfib, int /*threads*/)
     return fp64 ? Lds<double>::bytes(nf, nfib) : Lds<float>::bytes(nf, nfib);
 }
 
-// Per-wave reduction slots: [0] max G/M, [1] |f_free|^2, [2] |cMv|^2, [3] |f_bnd|^2.
+// Reduction slots of a workgroup: per-wave partial sums of |f_free|^2,
+// |c M v|^2 and |f_bnd|^2, and two alternating slots for the time-step
+// maximum (LDS atomic max on the bit pattern of a non-negative number).
 struct RedSlots {
-    double v[4][16];
+    double v[3][16];
+    unsigned long long g64[2];
+    unsigned g32[2];
 };
 
-// Block-wide reduction of up to four values.  Every thread returns the same
-// totals (fixed summation order: bitwise repeatable).  Ends with a barrier
-// after the LDS slots were read, so they may be reused immediately.
-template <int NW>
-__device__ __forceinline__ void block_reduce4(RedSlots& red, double gmax, double r2, double d2, double b2, bool full,
-                                     double& gmax_o, double& r2_o, double& d2_o, double& b2_o)
+__device__ __forceinline__ void reset_gslots(RedSlots& red)
+{
+    if (threadIdx.x < 2) {
+        red.g64[threadIdx.x] = 0ull;
+        red.g32[threadIdx.x] = 0u;
+    }
+}
+
+// Workgroup reduction: max of gpart (>= 0) every call, and the three sums
+// when `full`.  Every thread returns the same (scalar) totals in a fixed
+// summation order.  One barrier; the max slot alternates with `parity`, the
+// other slot is cleared for the next call (at least two barriers separate a
+// clear from the next atomic on that slot).
+template <typename Real, int NW>
+__device__ __forceinline__ void block_reduce(RedSlots& red, int parity, Real gpart, double r2, double d2, double b2,
+                                             bool full, double& gmax_o, double& r2_o, double& d2_o, double& b2_o)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    gmax = wave_max(gmax);
+    if constexpr (sizeof(Real) == 4) {
+        float g = wave_max_nonneg((float)gpart);
+        if (lane == 0) atomicMax(&red.g32[parity], __float_as_uint(g));
+    } else {
+        double g = wave_max((double)gpart);
+        if (lane == 0) atomicMax(&red.g64[parity], (unsigned long long)__double_as_longlong(g));
+    }
     if (full) {
         r2 = wave_sum(r2);
         d2 = wave_sum(d2);
         b2 = wave_sum(b2);
-    }
-    if (lane == 0) {
-        red.v[0][wave] = gmax;
-        if (full) {
-            red.v[1][wave] = r2;
-            red.v[2][wave] = d2;
-            red.v[3][wave] = b2;
+        if (lane == 0) {
+            red.v[0][wave] = r2;
+            red.v[1][wave] = d2;
+            red.v[2][wave] = b2;
         }
     }
     __syncthreads();
-    double g = 0.0;
-    double a = 0.0, b = 0.0, c = 0.0;
-#pragma unroll 2
-    for (int w = 0; w < NW; ++w) {
-        g = fmax(g, red.v[0][w]);
-        if (full) {
-            a += red.v[1][w];
-            b += red.v[2][w];
-            c += red.v[3][w];
-        }
+    if constexpr (sizeof(Real) == 4)
+        gmax_o = (double)__uint_as_float(__builtin_amdgcn_readfirstlane(red.g32[parity]));
+    else
+        gmax_o = uniform(__longlong_as_double((long long)red.g64[parity]));
+    if (threadIdx.x == 0) {
+        red.g32[parity ^ 1] = 0u;
+        red.g64[parity ^ 1] = 0ull;
     }
-    gmax_o = uniform(g);
-    r2_o = uniform(a);
-    d2_o = uniform(b);
-    b2_o = uniform(c);
-    __syncthreads();
+    if (full) {
+        double a = 0.0, b = 0.0, c = 0.0;
+#pragma unroll 4
+        for (int w = 0; w < NW; ++w) {
+            a += red.v[0][w];
+            b += red.v[1][w];
+            c += red.v[2][w];
+        }
+        r2_o = uniform(a);
+        d2_o = uniform(b);
+        b2_o = uniform(c);
+    }
 }
 
 // Boundary reaction norm^2 partial of this thread (test iterations only).
@@ -411,22 +469,22 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
     // ---- free nodes into registers
     Real hx[SN], hy[SN], hz[SN], vx[SN], vy[SN], vz[SN], iM[SN];
     uint32_t inc[SN][kMaxResidentDegree / 2];
-    int deg[SN];
+    int degw[SN];   // largest degree in this wave's node slot (scalar)
 #pragma unroll
     for (int s = 0; s < SN; ++s) {
         int a = s * T + tid;
         hx[s] = hy[s] = hz[s] = vx[s] = vy[s] = vz[s] = Real(0);
         iM[s] = Real(0);
-        deg[s] = 0;
+        int deg = 0;
 #pragma unroll
         for (int q = 0; q < kMaxResidentDegree / 2; ++q) inc[s][q] = (uint32_t)nfib | ((uint32_t)nfib << 16);
         if (a < nf) {
             iM[s] = (Real)(1.0 / (massb[a] * A.rhoA));
             int64_t e0 = incoffb[a], e1 = incoffb[a + 1];
-            deg[s] = (int)(e1 - e0);
+            deg = (int)(e1 - e0);
 #pragma unroll
             for (int q = 0; q < kMaxResidentDegree; ++q) {
-                if (q < deg[s]) {
+                if (q < deg) {
                     uint32_t w = net.inc[e0 + q];
                     uint32_t code = (w & 0x7fffu) | ((w >> 31) << 15);
                     if (q & 1)
@@ -441,7 +499,10 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
             }
             L.put_h(a, hx[s], hy[s], hz[s]);
         }
+        degw[s] = (int)__builtin_amdgcn_readfirstlane(
+            __float_as_uint(wave_max_nonneg(__uint_as_float((unsigned)deg))));
     }
+    reset_gslots(red);
     if (tid == 0) {
         L.put_h(nf, Real(0), Real(0), Real(0));
         FiberOut<Real> z{Real(0), Real(0), Real(0), Real(0)};
@@ -465,12 +526,13 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
             __builtin_amdgcn_sched_barrier(0);
         }
     };
-    // gather forces and Gershgorin sums of node slot s
+    // gather forces and Gershgorin sums of node slot s; lanes whose node has
+    // fewer incidences than the wave's largest read the zero slot
     auto gather = [&](int s, Real& fx, Real& fy, Real& fz, Real& G) __attribute__((always_inline)) {
         fx = fy = fz = G = Real(0);
 #pragma unroll
         for (int q = 0; q < kMaxResidentDegree; ++q) {
-            if (q >= deg[s]) continue;
+            if (q >= degw[s]) break;
             uint32_t code = (q & 1) ? (inc[s][q >> 1] >> 16) : (inc[s][q >> 1] & 0xffffu);
             int k = (int)(code & 0x7fffu);
             Real x, y, z, b;
@@ -480,6 +542,23 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
             }
             fx += x; fy += y; fz += z; G += b;
         }
+        if (degw[s] > kMaxResidentDegree) {
+            // rare high-degree nodes: remaining incidences from the CSR in HBM
+            const int a = s * T + tid;
+            if (a < nf) {
+                const int64_t e1 = incoffb[a + 1];
+#pragma unroll 1
+                for (int64_t e = incoffb[a] + kMaxResidentDegree; e < e1; ++e) {
+                    uint32_t w = net.inc[e];
+                    Real x, y, z, b;
+                    L.get_fv((int)(w & 0x7fffffffu), x, y, z, b);
+                    if (w >> 31) {
+                        x = -x; y = -y; z = -z;
+                    }
+                    fx += x; fy += y; fz += z; G += b;
+                }
+            }
+        }
         G *= Real(2);
     };
 
@@ -487,7 +566,7 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
     fiber_pass();
     __syncthreads();
     Real ax[SN], ay[SN], az[SN];
-    double gpart = 0.0;
+    Real gpart = Real(0);
     double r2p = 0.0, b2p = 0.0;
 #pragma unroll
     for (int s = 0; s < SN; ++s) {
@@ -500,14 +579,15 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
             ax[s] = -fx * iM[s];
             ay[s] = -fy * iM[s];
             az[s] = -fz * iM[s];
-            gpart = fmax(gpart, (double)(G * iM[s]));
+            gpart = fmax(gpart, G * iM[s]);
             r2p += (double)fx * fx + (double)fy * fy + (double)fz * fz;
         }
     }
     b2p = boundary_norm2_partial<Real, T>(net, L, b0, nb);
     double gmax;
-    double R2, D2, B2;
-    block_reduce4<NW>(red, gpart, r2p, 0.0, b2p, true, gmax, R2, D2, B2);
+    double R2 = 0.0, D2 = 0.0, B2 = 0.0;
+    int parity = 0;
+    block_reduce<Real, NW>(red, parity, gpart, r2p, 0.0, b2p, true, gmax, R2, D2, B2);
 
     int64_t n = 0;
     int status = ST_CONVERGED;
@@ -536,7 +616,7 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
         }
 #pragma unroll
         for (int s = 0; s < SN; ++s) {
-            asm volatile("" : "+v"(deg[s]), "+v"(iM[s]));
+            asm volatile("" : "+v"(iM[s]));
 #pragma unroll
             for (int q = 0; q < kMaxResidentDegree / 2; ++q) asm volatile("" : "+v"(inc[s][q]));
         }
@@ -556,7 +636,7 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
         __syncthreads();
         ++n;
         const bool check = (n % ce) == 0;
-        gpart = 0.0;
+        gpart = Real(0);
         r2p = 0.0;
         double d2p = 0.0;
 #pragma unroll
@@ -570,7 +650,7 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
                 ay[s] = -fy * iM[s] - c * vy[s];
                 az[s] = -fz * iM[s] - c * vz[s];
                 vx[s] += hdt * ax[s]; vy[s] += hdt * ay[s]; vz[s] += hdt * az[s];
-                gpart = fmax(gpart, (double)(G * iM[s]));
+                gpart = fmax(gpart, G * iM[s]);
                 if (check) {
                     r2p += (double)fx * fx + (double)fy * fy + (double)fz * fz;
                     // damping force c M v of this node (only tested against the tolerance)
@@ -582,7 +662,8 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
             __builtin_amdgcn_sched_barrier(0);
         }
         if (check) b2p = boundary_norm2_partial<Real, T>(net, L, b0, nb);
-        block_reduce4<NW>(red, gpart, r2p, d2p, b2p, check, gmax, R2, D2, B2);
+        parity ^= 1;
+        block_reduce<Real, NW>(red, parity, gpart, r2p, d2p, b2p, check, gmax, R2, D2, B2);
         if (check) {
             Rlast = sqrt(R2);
             Dlast = sqrt(D2);
@@ -765,9 +846,10 @@ __device__ __forceinline__ void streamed_solve(const SolveArgs& A, int r, RedSlo
         return acc;
     };
 
+    reset_gslots(red);
     fiber_pass();
     __syncthreads();
-    double gpart = 0.0;
+    Real gpart = Real(0);
     double r2p = 0.0;
 #pragma unroll 1
     for (int64_t a = tid; a < nf; a += T) {
@@ -782,13 +864,14 @@ __device__ __forceinline__ void streamed_solve(const SolveArgs& A, int r, RedSlo
         R4 acc;
         acc.x = -fx * im; acc.y = -fy * im; acc.z = -fz * im; acc.w = Real(0);
         wsA[a] = acc;
-        gpart = fmax(gpart, (double)(G * im));
+        gpart = fmax(gpart, G * im);
         r2p += (double)fx * fx + (double)fy * fy + (double)fz * fz;
     }
     double b2p = bnorm2();
     double gmax;
-    double R2, D2, B2;
-    block_reduce4<NW>(red, gpart, r2p, 0.0, b2p, true, gmax, R2, D2, B2);
+    double R2 = 0.0, D2 = 0.0, B2 = 0.0;
+    int parity = 0;
+    block_reduce<Real, NW>(red, parity, gpart, r2p, 0.0, b2p, true, gmax, R2, D2, B2);
 
     int64_t n = 0;
     int status = ST_CONVERGED;
@@ -820,7 +903,7 @@ __device__ __forceinline__ void streamed_solve(const SolveArgs& A, int r, RedSlo
         __syncthreads();
         ++n;
         const bool check = (n % ce) == 0;
-        gpart = 0.0;
+        gpart = Real(0);
         r2p = 0.0;
         double d2p = 0.0;
 #pragma unroll 1
@@ -836,7 +919,7 @@ __device__ __forceinline__ void streamed_solve(const SolveArgs& A, int r, RedSlo
             v.x += hdt * acc.x; v.y += hdt * acc.y; v.z += hdt * acc.z;
             wsV[a] = v;
             wsA[a] = acc;
-            gpart = fmax(gpart, (double)(G * im));
+            gpart = fmax(gpart, G * im);
             if (check) {
                 r2p += (double)fx * fx + (double)fy * fy + (double)fz * fz;
                 double md = (double)m * cd;
@@ -845,7 +928,8 @@ __device__ __forceinline__ void streamed_solve(const SolveArgs& A, int r, RedSlo
             }
         }
         if (check) b2p = bnorm2();
-        block_reduce4<NW>(red, gpart, r2p, d2p, b2p, check, gmax, R2, D2, B2);
+        parity ^= 1;
+        block_reduce<Real, NW>(red, parity, gpart, r2p, d2p, b2p, check, gmax, R2, D2, B2);
         if (check) {
             Rlast = sqrt(R2);
             Dlast = sqrt(D2);
@@ -955,6 +1039,19 @@ __global__ __launch_bounds__(kStressThreads) void stress_kernel(SolveArgs A)
         }
     }
     stress_finish<kStressThreads / 64>(s9, J, net.V0[r], A.sigma + 9 * r);
+}
+
+// Zero n work counters (a kernel rather than a memset node, so that a
+// solve can be captured in a HIP graph and replayed).
+__global__ void reset_counters(int32_t* c, int n)
+{
+    if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
+}
+
+hipError_t launch_reset(int32_t* counters, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, s, counters, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_stress(const SolveArgs& a, int n_rve, hipStream_t s)
