@@ -179,6 +179,22 @@ int rve_batch_set_stream(rve_batch* b, void* stream);
 int rve_batch_profile(rve_batch* b, int enable);
 int rve_batch_kernel_ms(rve_batch* b, double* relax_ms, double* stress_ms);
 
+/*
+ * Autotuner: for every size tier of the batch (RVEs grouped by the smallest
+ * register-resident variant that holds them), run each eligible kernel
+ * variant (threads per RVE x fiber/node slots per thread, and the streamed
+ * kernel) on a sample of that tier's largest RVEs for n_iter relaxation
+ * iterations under F (host or device pointer per ptr_kind), time it with HIP
+ * events, and keep the fastest per fiber evaluation for the batch's current
+ * precision.  Later solves use the choice.  The trial runs overwrite the
+ * state of the last solve.
+ */
+int rve_batch_autotune(rve_batch* b, const double* F, int32_t ptr_kind, int32_t n_iter);
+
+/* Describe the kernel groups of the next solve ("variant:count;...") into
+ * buf (NUL-terminated, truncated to n bytes). */
+int rve_batch_describe(const rve_batch* b, char* buf, size_t n);
+
 /* Number of RVEs, nodes and fibers of the batch. */
 int rve_batch_sizes(const rve_batch* b, int64_t* n_rve, int64_t* n_nodes, int64_t* n_fib);
 

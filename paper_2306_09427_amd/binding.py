@@ -27,7 +27,8 @@ OK, EINVAL, ENOMEM, EDEVICE, ESTATE = 0, -22, -12, -5, -3
 
 EXPORTS = ["rve_version", "rve_last_error", "rve_default_opts", "rve_batch_create", "rve_batch_set_opts",
            "rve_batch_set_stream", "rve_batch_sizes", "rve_batch_solve", "rve_batch_tangent", "rve_batch_vjp",
-           "rve_batch_positions", "rve_batch_destroy", "rve_batch_profile", "rve_batch_kernel_ms"]
+           "rve_batch_positions", "rve_batch_destroy", "rve_batch_profile", "rve_batch_kernel_ms",
+           "rve_batch_autotune", "rve_batch_describe"]
 
 
 class NetDesc(C.Structure):
@@ -79,6 +80,8 @@ def lib():
         L.rve_batch_positions.argtypes = [P, C.c_int64, P]
         L.rve_batch_profile.argtypes = [P, C.c_int]
         L.rve_batch_kernel_ms.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.rve_batch_autotune.argtypes = [P, P, C.c_int32, C.c_int32]
+        L.rve_batch_describe.argtypes = [P, C.c_char_p, C.c_size_t]
         L.rve_batch_destroy.argtypes = [P]
         L.rve_batch_destroy.restype = None
         _lib = L
@@ -218,6 +221,20 @@ class Batch:
         gp, kind = _ptr(gsigma)
         _check(lib().rve_batch_vjp(self._h, gp, _ptr(gF)[0], _ptr(st)[0], kind))
         return gF, st
+
+    def autotune(self, F, n_iter=200):
+        """Time every eligible kernel variant per size tier and keep the fastest."""
+        if hasattr(F, "data_ptr"):
+            F = F.contiguous()
+        else:
+            F = np.ascontiguousarray(F, np.float64).reshape(self.n_rve, 3, 3)
+        p, kind = _ptr(F)
+        _check(lib().rve_batch_autotune(self._h, p, kind, int(n_iter)))
+
+    def describe(self):
+        buf = C.create_string_buffer(1024)
+        _check(lib().rve_batch_describe(self._h, buf, 1024))
+        return buf.value.decode()
 
     def profile(self, enable=True):
         _check(lib().rve_batch_profile(self._h, 1 if enable else 0))

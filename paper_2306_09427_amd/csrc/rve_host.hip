@@ -93,7 +93,39 @@ struct rve_batch {
     bool profile = false;
     std::vector<hipEvent_t> ev;
     int ev_used = 0;
+    // autotuner choice per [fp64][tier]: -2 untuned, -1 streamed, else a resident variant
+    int tuned[2][8] = {{-2, -2, -2, -2, -2, -2, -2, -2}, {-2, -2, -2, -2, -2, -2, -2, -2}};
+    int32_t* dtune_list = nullptr;
 };
+
+// Size tiers: distinct (fiber, node) capacities of the resident variants, ascending.
+static std::vector<std::pair<int64_t, int64_t>> tier_caps()
+{
+    std::vector<std::pair<int64_t, int64_t>> caps;
+    for (int v = 0; v < kNumResident; ++v)
+        caps.push_back({(int64_t)kResident[v].threads * kResident[v].sf, (int64_t)kResident[v].threads * kResident[v].sn});
+    std::sort(caps.begin(), caps.end());
+    caps.erase(std::unique(caps.begin(), caps.end()), caps.end());
+    return caps;
+}
+
+// Tier of an RVE (index into tier_caps) or -1 when only the streamed kernel can take it.
+static int tier_of(const rve_batch* b, int64_t r, bool fp64)
+{
+    size_t lds_cap = 160 * 1024 - 4096;
+    if (b->nfib_of[r] >= 32767 || resident_lds_bytes(fp64, b->nf_of[r], b->nfib_of[r], 0) > lds_cap) return -1;
+    auto caps = tier_caps();
+    for (size_t t = 0; t < caps.size(); ++t)
+        if (b->nfib_of[r] <= caps[t].first && b->nf_of[r] <= caps[t].second) return (int)t;
+    return -1;
+}
+
+static bool variant_fits_tier(int v, int tier)
+{
+    auto caps = tier_caps();
+    return (int64_t)kResident[v].threads * kResident[v].sf >= caps[tier].first &&
+           (int64_t)kResident[v].threads * kResident[v].sn >= caps[tier].second;
+}
 
 static int ensure_events(rve_batch* b, int n)
 {
@@ -310,34 +342,42 @@ static T* carve(char* base, size_t off)
 }
 
 // Assign every RVE to an engine/variant group, longest-first inside a group.
+// Resident variants are chosen per size tier: the autotuner's choice if one
+// exists, else the variant with the smallest register footprint that holds
+// the tier and does not spill inside the loop (more threads on ties).
+static int default_variant(const rve_batch* b, int tier, bool fp64)
+{
+    const int T = b->opts.threads_per_rve;
+    int chosen = -1;
+    int64_t best = 0;
+    for (int v = 0; v < kNumResident; ++v) {
+        const ResidentVariant& rv = kResident[v];
+        if (T && rv.threads != T) continue;
+        if (b->variant_spills[fp64 ? 1 : 0][v] && !T) continue;
+        if (!variant_fits_tier(v, tier)) continue;
+        int64_t key = (int64_t)(rv.sf * 5 + rv.sn * 12) * 4096 - rv.threads;
+        if (chosen < 0 || key < best) {
+            chosen = v;
+            best = key;
+        }
+    }
+    return chosen;
+}
+
 static void assign_groups(rve_batch* b)
 {
     b->groups.clear();
     b->group_variant.clear();
     b->group_lds.clear();
     const bool fp64 = b->opts.precision == RVE_FP64;
-    const int T = b->opts.threads_per_rve;
     std::vector<std::vector<int32_t>> per(kNumResident + 1);
-    size_t lds_cap = 160 * 1024 - 4096;   // static shared of the kernel (reduction slots) stays below 4 KB
     for (int64_t r = 0; r < b->R; ++r) {
         int chosen = -1;
-        if (b->opts.engine == RVE_ENGINE_AUTO && b->nfib_of[r] < 32767) {
-            size_t lds = resident_lds_bytes(fp64, b->nf_of[r], b->nfib_of[r], 0);
-            if (lds <= lds_cap) {
-                int64_t best_cap = -1;
-                for (int v = 0; v < kNumResident; ++v) {
-                    const ResidentVariant& rv = kResident[v];
-                    if (T && rv.threads != T) continue;
-                    if (b->variant_spills[fp64 ? 1 : 0][v] && !T) continue;
-                    int64_t capf = (int64_t)rv.threads * rv.sf, capn = (int64_t)rv.threads * rv.sn;
-                    if (b->nfib_of[r] > capf || b->nf_of[r] > capn) continue;
-                    // smallest register footprint first, then more threads
-                    int64_t key = (int64_t)(rv.sf * 5 + rv.sn * 12) * 4096 - rv.threads;
-                    if (chosen < 0 || key < best_cap) {
-                        chosen = v;
-                        best_cap = key;
-                    }
-                }
+        if (b->opts.engine == RVE_ENGINE_AUTO) {
+            int t = tier_of(b, r, fp64);
+            if (t >= 0) {
+                int tv = b->tuned[fp64 ? 1 : 0][t];
+                chosen = (tv != -2 && !b->opts.threads_per_rve) ? tv : default_variant(b, t, fp64);
             }
         }
         per[chosen < 0 ? kNumResident : chosen].push_back((int32_t)r);
@@ -717,6 +757,131 @@ int rve_batch_solve(rve_batch* b, const double* F, double* sigma, int32_t* statu
     return RVE_OK;
 }
 
+static void fill_solve_args(rve_batch* b, SolveArgs& a)
+{
+    a = SolveArgs{};
+    a.net = b->net;
+    a.F = b->dF;
+    a.c = b->dc;
+    a.law = b->opts.law;
+    a.mass_mode = b->opts.mass;
+    a.init = RVE_INIT_AFFINE;
+    a.check_every = b->opts.check_every;
+    a.EA = b->opts.EA;
+    a.B = b->opts.B;
+    a.rhoA = b->opts.rhoA;
+    a.alpha = b->opts.alpha;
+    a.tol_abs = b->opts.tol_abs;
+    a.tol_rel = b->opts.tol_rel;
+    a.n_max = b->opts.n_max;
+    a.sigma = b->dsigma;
+    a.status = b->dstatus;
+    a.iters = b->diters;
+    a.Rres = b->dR;
+    a.Dres = b->dD;
+    a.Bres = b->dB;
+    a.h_state = b->dh;
+    a.ws_fib = b->ws_fib;
+    a.ws_node = b->ws_node;
+}
+
+int rve_batch_autotune(rve_batch* b, const double* F, int32_t ptr_kind, int32_t n_iter)
+{
+    if (!b || !F) return fail(RVE_EINVAL, "NULL argument");
+    if (ptr_kind != RVE_PTR_HOST && ptr_kind != RVE_PTR_DEVICE) return fail(RVE_EINVAL, "bad ptr_kind");
+    if (n_iter < 1) return fail(RVE_EINVAL, "n_iter must be >= 1");
+    if (b->R == 0 || b->opts.engine != RVE_ENGINE_AUTO) return RVE_OK;
+    hipStream_t s = (hipStream_t)b->opts.stream;
+    const bool fp64 = b->opts.precision == RVE_FP64;
+    HIP_TRY(hipMemcpyAsync(b->dF, F, 72 * b->R, ptr_kind == RVE_PTR_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s));
+    if (!b->dtune_list && hipMalloc((void**)&b->dtune_list, 4 * (size_t)b->R + 4) != hipSuccess)
+        return fail(RVE_ENOMEM, "autotune list allocation failed");
+    // the streamed candidate needs its workspace
+    std::vector<int> saved_variant = b->group_variant;
+    b->group_variant.assign(1, -1);
+    int rc = ensure_workspace(b);
+    b->group_variant = saved_variant;
+    if (rc) return rc;
+    int rc_ev = ensure_events(b, 2);
+    if (rc_ev) return rc_ev;
+    auto caps = tier_caps();
+    for (size_t t = 0; t < caps.size(); ++t) {
+        std::vector<int32_t> members;
+        for (int64_t r = 0; r < b->R; ++r)
+            if (tier_of(b, r, fp64) == (int)t) members.push_back((int32_t)r);
+        if (members.empty()) continue;
+        std::stable_sort(members.begin(), members.end(),
+                         [&](int32_t x, int32_t y) { return b->nfib_of[x] > b->nfib_of[y]; });
+        members.resize(std::min<size_t>(members.size(), (size_t)b->n_cu * 2));
+        double fibs = 0.0;
+        size_t lds = 0;
+        for (int32_t r : members) {
+            fibs += (double)b->nfib_of[r];
+            lds = std::max(lds, resident_lds_bytes(fp64, b->nf_of[r], b->nfib_of[r], 0));
+        }
+        HIP_TRY(hipMemcpy(b->dtune_list, members.data(), 4 * members.size(), hipMemcpyHostToDevice));
+        SolveArgs a;
+        fill_solve_args(b, a);
+        a.n_max = n_iter;
+        a.tol_abs = 0.0;
+        a.tol_rel = 0.0;
+        a.list = b->dtune_list;
+        a.n_list = (int32_t)members.size();
+        a.queue = b->dqueue + 62;
+        double best = 1e300;
+        int best_v = -1;
+        for (int v = -1; v < kNumResident; ++v) {
+            if (v >= 0 && (!variant_fits_tier(v, (int)t) || b->variant_spills[fp64 ? 1 : 0][v])) continue;
+            int grid = 0;
+            if (v >= 0) {
+                int per_cu = 0;
+                if (max_resident_blocks(v, fp64, lds, &per_cu) != hipSuccess || per_cu < 1) continue;
+                grid = (int)std::min<int64_t>((int64_t)per_cu * b->n_cu, a.n_list);
+            } else {
+                grid = (int)std::min<int64_t>((int64_t)b->n_cu * 2, a.n_list);
+            }
+            for (int rep = 0; rep < 2; ++rep) {   // first run warms up
+                HIP_TRY(launch_reset(a.queue, 1, s));
+                HIP_TRY(hipEventRecord(b->ev[0], s));
+                if (v >= 0)
+                    HIP_TRY(launch_resident(v, fp64, a, lds, grid, s));
+                else
+                    HIP_TRY(launch_streamed(fp64, a, grid, 1024, s));
+                HIP_TRY(hipEventRecord(b->ev[1], s));
+            }
+            HIP_TRY(hipEventSynchronize(b->ev[1]));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, b->ev[0], b->ev[1]));
+            double per = ms / (fibs * n_iter);
+            if (per < best) {
+                best = per;
+                best_v = v;
+            }
+        }
+        b->tuned[fp64 ? 1 : 0][t] = best_v;
+    }
+    b->have_state = false;
+    assign_groups(b);
+    return upload_groups(b);
+}
+
+int rve_batch_describe(const rve_batch* b, char* buf, size_t n)
+{
+    if (!b || !buf || n == 0) return fail(RVE_EINVAL, "NULL argument");
+    std::string d;
+    for (size_t g = 0; g < b->groups.size(); ++g) {
+        int v = b->group_variant[g];
+        if (v >= 0)
+            d += "resident(" + std::to_string(kResident[v].threads) + "," + std::to_string(kResident[v].sf) + "," +
+                 std::to_string(kResident[v].sn) + ")";
+        else
+            d += "streamed";
+        d += ":" + std::to_string(b->groups[g].size()) + ";";
+    }
+    std::snprintf(buf, n, "%s", d.c_str());
+    return RVE_OK;
+}
+
 int rve_batch_positions(rve_batch* b, int64_t r, double* x)
 {
     if (!b || !x) return fail(RVE_EINVAL, "NULL argument");
@@ -839,6 +1004,7 @@ void rve_batch_destroy(rve_batch* b)
     if (b->t_out) (void)hipFree(b->t_out);
     if (b->t_in) (void)hipFree(b->t_in);
     if (b->t_status) (void)hipFree(b->t_status);
+    if (b->dtune_list) (void)hipFree(b->dtune_list);
     if (b->dmem) (void)hipFree(b->dmem);
     if (b->ws_fib) (void)hipFree(b->ws_fib);
     if (b->ws_node) (void)hipFree(b->ws_node);
