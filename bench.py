@@ -88,6 +88,9 @@ def main():
 
     # ---------------- mixed precision, timed
     b = rb.Batch(batch, precision=rb.MIXED, **common)
+    b.autotune(Fd, 300)
+    groups = b.describe()
+    log(f"mixed kernel groups: {groups}")
     b.profile(True)
     for _ in range(args.warmup):
         b.solve(Fd)
@@ -143,6 +146,7 @@ def main():
         "iters_median": float(np.median(iters)),
         "element_updates_per_s": elem_updates / (ms_per_step / 1e3),
         "relax_kernel_ms": relax_ms,
+        "kernel_groups": groups,
         "stress_kernel_ms": stress_ms,
     }
     b.close()
@@ -150,6 +154,8 @@ def main():
     # ---------------- FP64 batched (same batch, tol scaled to FP64)
     if not args.no_fp64:
         b64 = rb.Batch(batch, precision=rb.FP64, **common)
+        b64.autotune(Fd, 300)
+        log(f"fp64 kernel groups: {b64.describe()}")
         b64.profile(True)
         torch.cuda.synchronize()
         t1 = time.perf_counter()

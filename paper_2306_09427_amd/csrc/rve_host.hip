@@ -831,7 +831,8 @@ int rve_batch_autotune(rve_batch* b, const double* F, int32_t ptr_kind, int32_t 
         double best = 1e300;
         int best_v = -1;
         for (int v = -1; v < kNumResident; ++v) {
-            if (v >= 0 && (!variant_fits_tier(v, (int)t) || b->variant_spills[fp64 ? 1 : 0][v])) continue;
+            // spilling variants are timed too: for FP64 the register file is the limit
+            if (v >= 0 && !variant_fits_tier(v, (int)t)) continue;
             int grid = 0;
             if (v >= 0) {
                 int per_cu = 0;
