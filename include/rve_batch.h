@@ -180,6 +180,16 @@ int rve_batch_profile(rve_batch* b, int enable);
 int rve_batch_kernel_ms(rve_batch* b, double* relax_ms, double* stress_ms);
 
 /*
+ * Kernel groups of the last solve: group_of_rve[R] receives the launch group
+ * of every RVE, variant[g] its resident variant index (-1 streamed) and, if
+ * the solve was profiled, ms[g] the duration of that group's relaxation
+ * launch (NaN otherwise).  Arrays are host memory of max_groups entries;
+ * *n_groups receives the number of groups.
+ */
+int rve_batch_groups(rve_batch* b, int32_t* group_of_rve, int32_t* variant, double* ms, int32_t max_groups,
+                     int32_t* n_groups);
+
+/*
  * Autotuner: for every size tier of the batch (RVEs grouped by the smallest
  * register-resident variant that holds them), run each eligible kernel
  * variant (threads per RVE x fiber/node slots per thread, and the streamed

@@ -28,7 +28,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ESTATE = 0, -22, -12, -5, -3
 EXPORTS = ["rve_version", "rve_last_error", "rve_default_opts", "rve_batch_create", "rve_batch_set_opts",
            "rve_batch_set_stream", "rve_batch_sizes", "rve_batch_solve", "rve_batch_tangent", "rve_batch_vjp",
            "rve_batch_positions", "rve_batch_destroy", "rve_batch_profile", "rve_batch_kernel_ms",
-           "rve_batch_autotune", "rve_batch_describe"]
+           "rve_batch_autotune", "rve_batch_describe", "rve_batch_groups"]
 
 
 class NetDesc(C.Structure):
@@ -82,6 +82,7 @@ def lib():
         L.rve_batch_kernel_ms.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.rve_batch_autotune.argtypes = [P, P, C.c_int32, C.c_int32]
         L.rve_batch_describe.argtypes = [P, C.c_char_p, C.c_size_t]
+        L.rve_batch_groups.argtypes = [P, P, P, P, C.c_int32, P]
         L.rve_batch_destroy.argtypes = [P]
         L.rve_batch_destroy.restype = None
         _lib = L
@@ -235,6 +236,15 @@ class Batch:
         buf = C.create_string_buffer(1024)
         _check(lib().rve_batch_describe(self._h, buf, 1024))
         return buf.value.decode()
+
+    def groups(self):
+        """(group index per RVE, resident variant per group (-1 streamed), ms per group of the last profiled solve)."""
+        g = np.empty(self.n_rve, np.int32)
+        var = np.empty(16, np.int32)
+        ms = np.empty(16)
+        n = C.c_int32()
+        _check(lib().rve_batch_groups(self._h, g.ctypes.data, var.ctypes.data, ms.ctypes.data, 16, C.byref(n)))
+        return g, var[:n.value], ms[:n.value]
 
     def profile(self, enable=True):
         _check(lib().rve_batch_profile(self._h, 1 if enable else 0))

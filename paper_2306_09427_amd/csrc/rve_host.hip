@@ -650,6 +650,30 @@ int rve_batch_kernel_ms(rve_batch* b, double* relax_ms, double* stress_ms)
     return RVE_OK;
 }
 
+int rve_batch_groups(rve_batch* b, int32_t* group_of_rve, int32_t* variant, double* ms, int32_t max_groups,
+                     int32_t* n_groups)
+{
+    if (!b || !n_groups) return fail(RVE_EINVAL, "NULL argument");
+    const int G = (int)b->groups.size();
+    *n_groups = G;
+    if (group_of_rve)
+        for (int g = 0; g < G; ++g)
+            for (int32_t r : b->groups[g]) group_of_rve[r] = g;
+    const bool timed = b->ev_used == 2 * G + 2;
+    for (int g = 0; g < G && g < max_groups; ++g) {
+        if (variant) variant[g] = b->group_variant[g];
+        if (ms) {
+            float t = NAN;
+            if (timed) {
+                HIP_TRY(hipEventSynchronize(b->ev[2 * g + 1]));
+                HIP_TRY(hipEventElapsedTime(&t, b->ev[2 * g], b->ev[2 * g + 1]));
+            }
+            ms[g] = t;
+        }
+    }
+    return RVE_OK;
+}
+
 int rve_batch_sizes(const rve_batch* b, int64_t* n_rve, int64_t* n_nodes, int64_t* n_fib)
 {
     if (!b) return fail(RVE_EINVAL, "batch is NULL");
