@@ -36,6 +36,22 @@ def rb_variant_name(v):
     return "%d,%d,%d" % VARIANTS[v]
 
 
+def measured_traffic(kernel_name):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of this
+    kernel, or None when the kernel source changed since it was taken."""
+    import hashlib
+    if kernel_name != "dr_resident_kernel<float,1024,4,2>":
+        return None
+    path = os.path.join(ROOT, "profiles", "dr_resident_kernel_4096rve_200-400seeds_mixed.md")
+    src = os.path.join(ROOT, "paper_2306_09427_amd", "csrc", "rve_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    fields = dict(line.split(": ", 1) for line in open(path).read().splitlines() if ": " in line and " " not in line.split(": ", 1)[0])
+    if fields.get("kernel_source_sha256", "").strip() != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -226,13 +242,14 @@ def main():
     # The resident kernel keeps the network and state in VGPRs/LDS, so the
     # algorithmic rate is an HBM-equivalent rate; measured HBM traffic (rocprof
     # FETCH_SIZE/WRITE_SIZE, see profiles/) is far below it.
+    traffic = measured_traffic(dom_name)
     out["roofline"] = {
         "bound": "hbm",
         "achieved": hbm_achieved / 1e9,
         "peak": PEAK_HBM / 1e9,
         "unit": "GB/s",
         "frac": hbm_achieved / PEAK_HBM,
-        "traffic": None,
+        "traffic": traffic,
         "kernel": dom_name,
         "kernel_ms": dom_ms,
         "rves_in_kernel": int(in_dom.sum()),

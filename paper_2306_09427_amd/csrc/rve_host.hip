@@ -19,7 +19,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/rve_batch.h"
+#include "rve_batch.h"
 #include "rve_internal.h"
 
 using namespace rve;

@@ -17,7 +17,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/rve_batch.h"
+#include "rve_batch.h"
 #include "rve_internal.h"
 
 namespace rve {
