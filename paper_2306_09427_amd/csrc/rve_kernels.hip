@@ -77,13 +77,13 @@ __device__ inline float dev_expm1(float x)
 }
 __device__ inline double dev_expm1(double x) { return expm1(x); }
 
-// Axial force T(eps) and k_t = dT/deps (truss law).
+// Axial force T(eps) and k_t = dT/deps (truss law); EAoB = EA / B.
 template <typename Real>
-__device__ inline void fiber_law(int law, Real EA, Real B, Real eps, Real& T, Real& kt)
+__device__ inline void fiber_law(int law, Real EA, Real B, Real EAoB, Real eps, Real& T, Real& kt)
 {
     if (law != kLawLinear && eps >= Real(0)) {
         Real em1 = dev_expm1(B * eps);
-        T = EA * em1 / B;
+        T = EAoB * em1;
         kt = EA * (em1 + Real(1));
     } else {
         T = EA * eps;
@@ -105,8 +105,9 @@ __device__ inline double dev_rsqrt(double x) { return 1.0 / sqrt(x); }
 __device__ inline double dev_rcp(double x) { return 1.0 / x; }
 
 template <typename Real>
-__device__ __forceinline__ FiberOut<Real> fiber_eval(int law, Real EA, Real B, Real D0x, Real D0y, Real D0z,
-                                                     Real q0, Real L0, Real iL0, Real dhx, Real dhy, Real dhz)
+__device__ __forceinline__ FiberOut<Real> fiber_eval(int law, Real EA, Real B, Real EAoB, Real D0x, Real D0y,
+                                                     Real D0z, Real q0, Real L0, Real iL0, Real dhx, Real dhy,
+                                                     Real dhz)
 {
     Real dx = D0x + dhx, dy = D0y + dhy, dz = D0z + dhz;
     // l^2 - L0^2 without cancellation
@@ -116,7 +117,7 @@ __device__ __forceinline__ FiberOut<Real> fiber_eval(int law, Real EA, Real B, R
     Real l = l2 * il;
     Real eps = q * iL0 * dev_rcp(l + L0);
     Real T, kt;
-    fiber_law<Real>(law, EA, B, eps, T, kt);
+    fiber_law<Real>(law, EA, B, EAoB, eps, T, kt);
     Real g = T * il;
     FiberOut<Real> o;
     o.fx = g * dx;
@@ -136,7 +137,14 @@ __device__ __forceinline__ FiberOut<double> fiber_eval_exact(int law, double EA,
     double l = sqrt(L0 * L0 + q);
     double eps = q / (L0 * (l + L0));
     double T, kt;
-    fiber_law<double>(law, EA, B, eps, T, kt);
+    if (law != kLawLinear && eps >= 0.0) {
+        double em1 = expm1(B * eps);
+        T = EA * em1 / B;
+        kt = EA * (em1 + 1.0);
+    } else {
+        T = EA * eps;
+        kt = EA;
+    }
     double g = T / l;
     FiberOut<double> o;
     o.fx = g * dx;
@@ -432,7 +440,7 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
         }
         return;
     }
-    const Real EA = (Real)A.EA, Bc = (Real)A.B;
+    const Real EA = (Real)A.EA, Bc = (Real)A.B, EAoB = (Real)(A.EA / A.B);
     const double cd = A.c[r];
     const Real c = (Real)cd;
 
@@ -519,8 +527,8 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
                 Real ix, iy, iz, jx, jy, jz;
                 L.get_h(i, ix, iy, iz);
                 L.get_h(j, jx, jy, jz);
-                FiberOut<Real> o = fiber_eval<Real>(A.law, EA, Bc, D0x[s], D0y[s], D0z[s], Q0[s], L0r[s], iL0r[s],
-                                                    jx - ix, jy - iy, jz - iz);
+                FiberOut<Real> o = fiber_eval<Real>(A.law, EA, Bc, EAoB, D0x[s], D0y[s], D0z[s], Q0[s], L0r[s],
+                                                    iL0r[s], jx - ix, jy - iy, jz - iz);
                 L.put_fv(k, o);
             }
             __builtin_amdgcn_sched_barrier(0);
@@ -537,10 +545,8 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
             int k = (int)(code & 0x7fffu);
             Real x, y, z, b;
             L.get_fv(k, x, y, z, b);
-            if (code & 0x8000u) {
-                x = -x; y = -y; z = -z;
-            }
-            fx += x; fy += y; fz += z; G += b;
+            const Real sg = (code & 0x8000u) ? Real(-1) : Real(1);
+            fx = fma(sg, x, fx); fy = fma(sg, y, fy); fz = fma(sg, z, fz); G += b;
         }
         if (degw[s] > kMaxResidentDegree) {
             // rare high-degree nodes: remaining incidences from the CSR in HBM
@@ -603,7 +609,15 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
         status = ST_MAXITER;
         done = true;
     }
-    double dt = A.alpha * 2.0 / sqrt(gmax);
+    // time step: FP64 in FP64 mode; FP32 (hardware rsqrt) in mixed mode, where
+    // the state it advances is FP32 anyway
+    auto time_step = [&](double g) __attribute__((always_inline)) -> double {
+        if constexpr (sizeof(Real) == 4)
+            return (double)((float)(2.0 * A.alpha) * __builtin_amdgcn_rsqf((float)g));
+        else
+            return A.alpha * 2.0 / sqrt(g);
+    };
+    double dt = time_step(gmax);
 
     while (!done) {
         // Keep the packed fiber ends and incidence lists packed: without this the
@@ -683,7 +697,7 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
             status = ST_MAXITER;
             break;
         }
-        dt = A.alpha * 2.0 / sqrt(gmax);
+        dt = time_step(gmax);
     }
 
     // ---- fluctuation state for warm starts, positions and the tangent
@@ -761,7 +775,7 @@ __device__ __forceinline__ void streamed_solve(const SolveArgs& A, int r, RedSlo
         }
         return;
     }
-    const Real EA = (Real)A.EA, Bc = (Real)A.B;
+    const Real EA = (Real)A.EA, Bc = (Real)A.B, EAoB = (Real)(A.EA / A.B);
     const double cd = A.c[r];
     const Real c = (Real)cd;
 
@@ -809,8 +823,8 @@ __device__ __forceinline__ void streamed_solve(const SolveArgs& A, int r, RedSlo
             j = j < (uint32_t)nf ? j : (uint32_t)nf;
             R4 hi = wsH[i], hj = wsH[j];
             double L0d = net.L0[f0 + k];
-            FiberOut<Real> o = fiber_eval<Real>(A.law, EA, Bc, D.x, D.y, D.z, D.w, (Real)L0d, (Real)(1.0 / L0d),
-                                                hj.x - hi.x, hj.y - hi.y, hj.z - hi.z);
+            FiberOut<Real> o = fiber_eval<Real>(A.law, EA, Bc, EAoB, D.x, D.y, D.z, D.w, (Real)L0d,
+                                                (Real)(1.0 / L0d), hj.x - hi.x, hj.y - hi.y, hj.z - hi.z);
             R4 w;
             w.x = o.fx; w.y = o.fy; w.z = o.fz; w.w = o.b;
             wsFv[k] = w;
