@@ -132,7 +132,7 @@ typedef struct {
     int32_t engine;
     int32_t threads_per_rve;
     double cg_tol;          /* tangent/vjp CG: stop at |r_k| <= cg_tol |b_k| */
-    int64_t cg_max_iter;    /* tangent/vjp CG iteration cap (0: 20 x free DOFs) */
+    int64_t cg_max_iter;    /* tangent/vjp CG iteration cap per right-hand side (0: 2 x free DOFs + 100) */
     void* stream;
 } rve_opts;
 
@@ -221,11 +221,20 @@ int rve_batch_solve(rve_batch* b, const double* F, double* sigma, int32_t* statu
 
 /*
  * Material tangent dsigma/dF at the state left by the last solve, by an
- * adjoint: for each of the 9 directions E = e_k e_l the free nodes follow
- * K_ff dx_f = -K_fb (E Xm)_b (matrix-free Hessian-vector conjugate
- * gradients, 9 right-hand sides at once), the reactions change by
+ * adjoint (the paper obtains the same linearisation by finite differences of
+ * extra relaxations, Section 3.2): for each of the 9 directions E = e_k e_l
+ * the free nodes follow K_ff dx_f = -K_fb (E Xm)_b, the reactions change by
  * df_b = (K dx)_b, and dsigma = (sum_b df_b x_b^T + f_b (E Xm_b)^T)/(J V0)
- * - sigma (F^-1)_lk.  dsdF[n_rve][9][9]; status per RVE.
+ * - sigma (F^-1)_lk.  K_ff is applied matrix-free (per-fiber Hessian
+ * blocks); each right-hand side is an independent block-Jacobi
+ * preconditioned CG with FP32 products inside FP64 iterative refinement,
+ * stopped at |r| <= cg_tol |b| (FP64 residual).
+ * dsdF[n_rve][9][9] (row 3i+j = sigma_ij, column 3k+l = F_kl); status per
+ * RVE: 0, RVE_ST_NO_STATE if the solve did not converge (outputs NaN),
+ * RVE_ST_CG_MAXITER, RVE_ST_CG_INDEFINITE (p.Kp <= 0 met: K_ff not
+ * positive definite at this state).  The first tangent or VJP call on a
+ * batch allocates its workspace, so it cannot be captured in a graph; later
+ * calls allocate only when the task grid grows.
  */
 int rve_batch_tangent(rve_batch* b, double* dsdF, int32_t* status, int32_t ptr_kind);
 
@@ -234,6 +243,13 @@ int rve_batch_tangent(rve_batch* b, double* dsdF, int32_t* status, int32_t ptr_k
  * with one adjoint CG per RVE.  gsigma[n_rve][9] in, gF[n_rve][9] out.
  */
 int rve_batch_vjp(rve_batch* b, const double* gsigma, double* gF, int32_t* status, int32_t ptr_kind);
+
+/*
+ * Inner CG iterations of the last rve_batch_tangent or rve_batch_vjp call,
+ * summed over each RVE's right-hand sides: iters[n_rve].  RVE_ESTATE before
+ * the first such call.
+ */
+int rve_batch_tangent_iters(rve_batch* b, int64_t* iters, int32_t ptr_kind);
 
 /* Positions x[n_nodes_r][3] of RVE r after the last solve, in the caller's
  * original node order (host pointer; synchronous). */

@@ -28,7 +28,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ESTATE = 0, -22, -12, -5, -3
 EXPORTS = ["rve_version", "rve_last_error", "rve_default_opts", "rve_batch_create", "rve_batch_set_opts",
            "rve_batch_set_stream", "rve_batch_sizes", "rve_batch_solve", "rve_batch_tangent", "rve_batch_vjp",
            "rve_batch_positions", "rve_batch_destroy", "rve_batch_profile", "rve_batch_kernel_ms",
-           "rve_batch_autotune", "rve_batch_describe", "rve_batch_groups"]
+           "rve_batch_autotune", "rve_batch_describe", "rve_batch_groups", "rve_batch_tangent_iters"]
 
 
 class NetDesc(C.Structure):
@@ -83,6 +83,7 @@ def lib():
         L.rve_batch_autotune.argtypes = [P, P, C.c_int32, C.c_int32]
         L.rve_batch_describe.argtypes = [P, C.c_char_p, C.c_size_t]
         L.rve_batch_groups.argtypes = [P, P, P, P, C.c_int32, P]
+        L.rve_batch_tangent_iters.argtypes = [P, P, C.c_int32]
         L.rve_batch_destroy.argtypes = [P]
         L.rve_batch_destroy.restype = None
         _lib = L
@@ -222,6 +223,12 @@ class Batch:
         gp, kind = _ptr(gsigma)
         _check(lib().rve_batch_vjp(self._h, gp, _ptr(gF)[0], _ptr(st)[0], kind))
         return gF, st
+
+    def tangent_iters(self):
+        """Inner CG iterations of the last tangent/vjp call, summed per RVE (host int64 [R])."""
+        it = np.zeros(self.n_rve, np.int64)
+        _check(lib().rve_batch_tangent_iters(self._h, _ptr(it)[0], 0))
+        return it
 
     def autotune(self, F, n_iter=200):
         """Time every eligible kernel variant per size tier and keep the fastest."""

@@ -61,6 +61,10 @@ struct rve_batch {
     std::vector<double> Xm;            // [NN][3] centred reference coordinates (original order)
     std::vector<int64_t> nf_of, nfib_of;
     std::vector<int32_t> maxdeg_of;
+    // tangent incidence in ELL chunks of 64 free nodes: first chunk of each
+    // RVE, and the first record of each chunk (width = records / 64, a
+    // multiple of 4)
+    std::vector<int64_t> chunk_first, chunk_rec;
     rve_opts opts{};
     std::vector<double> c_host;
     int device = 0, n_cu = 0;
@@ -81,14 +85,22 @@ struct rve_batch {
     bool have_state = false;
     bool variant_spills[2][kNumResident] = {};   // [fp64][variant]: the variant uses private memory
     // tangent / vjp workspace
-    void* t_par = nullptr;
+    char* t_mem = nullptr;             // operators, records, preconditioner, chunk tables, I/O
+    bool t_static_built = false;       // records' (fiber, other end) filled
     double* t_par64 = nullptr;
-    float* t_vec = nullptr;
-    double* t_vec64 = nullptr;
+    int2 *t_rec_static = nullptr, *t_recB = nullptr;
+    float4 *t_recA = nullptr, *t_precond = nullptr;
+    int64_t *t_chunk_first = nullptr, *t_chunk_rec = nullptr;
     double* t_out = nullptr;
     double* t_in = nullptr;
     int32_t* t_status = nullptr;
-    size_t t_par_bytes = 0, t_vec_bytes = 0;
+    int64_t* t_iters = nullptr;
+    int32_t* t_order = nullptr;
+    std::vector<int64_t> t_group_first;   // [kNumTanRes + 2] offsets of the task groups in t_order
+    std::vector<int32_t> t_order_host;    // host copy of t_order
+    std::vector<int64_t> t_max_nf;        // per launch of the last call: largest free-node count
+    char* t_slots = nullptr;           // per-wavefront solver vectors
+    size_t t_slot_bytes = 0;
     // profiling events: [group][start, stop], then the stress kernel
     bool profile = false;
     std::vector<hipEvent_t> ev;
@@ -520,6 +532,19 @@ int rve_batch_create(const rve_net_desc* net, const rve_opts* opts, rve_batch** 
     b->nf_of = P.nf;
     b->nfib_of = P.nfib;
     b->maxdeg_of = P.maxdeg;
+    b->chunk_first.assign(1, 0);
+    b->chunk_rec.assign(1, 0);
+    for (int64_t r = 0; r < R; ++r) {
+        const int64_t a0 = P.free_off[r], nf = P.free_off[r + 1] - a0;
+        for (int64_t c0 = 0; c0 < nf; c0 += 64) {
+            int64_t w = 0;
+            for (int64_t a = c0; a < std::min<int64_t>(c0 + 64, nf); ++a)
+                w = std::max<int64_t>(w, P.inc_off[a0 + a + 1] - P.inc_off[a0 + a]);
+            w = (w + 3) & ~int64_t(3);   // whole groups of 4 records per lane
+            b->chunk_rec.push_back(b->chunk_rec.back() + 64 * w);
+        }
+        b->chunk_first.push_back((int64_t)b->chunk_rec.size() - 1);
+    }
     b->Xm.resize(3 * b->NN);
     for (int64_t p = 0; p < 3 * b->NN; ++p) b->Xm[p] = net->X[p] - 0.5;
 
@@ -931,35 +956,80 @@ int rve_batch_positions(rve_batch* b, int64_t r, double* x)
     return RVE_OK;
 }
 
-static int ensure_tangent_ws(rve_batch* b, int W)
+// Tangent workspace: fiber operators, ELL records, preconditioner, chunk
+// tables and task groups for the whole batch (allocated once), and the
+// per-workgroup solver slots (`slot_bytes`, grown on demand).
+static int ensure_tangent_ws(rve_batch* b, size_t slot_bytes)
 {
-    size_t pb = 32 * (size_t)(b->NF + b->R);
-    size_t vb = 4 * sizeof(float) * (size_t)W * (size_t)(b->NFREE + b->R);
-    if (pb > b->t_par_bytes) {
-        if (b->t_par) (void)hipFree(b->t_par);
-        if (b->t_par64) (void)hipFree(b->t_par64);
-        b->t_par = nullptr;
-        b->t_par64 = nullptr;
-        b->t_par_bytes = 0;
-        if (hipMalloc(&b->t_par, pb) != hipSuccess || hipMalloc((void**)&b->t_par64, 40 * (size_t)(b->NF + b->R)) != hipSuccess)
+    if (!b->t_mem) {
+        const int64_t nch = (int64_t)b->chunk_rec.size() - 1, nrec = b->chunk_rec.back();
+        DeviceArena A;
+        size_t o_par = A.reserve(48 * (size_t)b->NF), o_rs = A.reserve(8 * (size_t)nrec), o_ra = A.reserve(16 * (size_t)nrec),
+               o_rb = A.reserve(8 * (size_t)nrec), o_pc = A.reserve(32 * (size_t)b->NFREE),
+               o_cf = A.reserve(8 * (size_t)(b->R + 1)), o_cr = A.reserve(8 * (size_t)(nch + 1)),
+               o_out = A.reserve(8 * 81 * (size_t)b->R), o_in = A.reserve(8 * 9 * (size_t)b->R),
+               o_st = A.reserve(4 * (size_t)b->R), o_it = A.reserve(8 * (size_t)b->R),
+               o_ord = A.reserve(4 * (size_t)b->R);
+        if (hipMalloc((void**)&b->t_mem, A.used + 256) != hipSuccess) {
+            b->t_mem = nullptr;
             return fail(RVE_ENOMEM, "tangent workspace allocation failed");
-        b->t_par_bytes = pb;
+        }
+        char* m = b->t_mem;
+        b->t_par64 = carve<double>(m, o_par);
+        b->t_rec_static = carve<int2>(m, o_rs);
+        b->t_recA = carve<float4>(m, o_ra);
+        b->t_recB = carve<int2>(m, o_rb);
+        b->t_precond = carve<float4>(m, o_pc);
+        b->t_chunk_first = carve<int64_t>(m, o_cf);
+        b->t_chunk_rec = carve<int64_t>(m, o_cr);
+        b->t_out = carve<double>(m, o_out);
+        b->t_in = carve<double>(m, o_in);
+        b->t_status = carve<int32_t>(m, o_st);
+        b->t_iters = carve<int64_t>(m, o_it);
+        b->t_order = carve<int32_t>(m, o_ord);
+        // task groups: RVEs for each resident variant (smallest that holds the
+        // RVE), then the rest for the wavefront kernel; longest first in each
+        std::vector<int32_t> lpt(b->R);
+        for (int64_t r = 0; r < b->R; ++r) lpt[r] = (int32_t)r;
+        std::stable_sort(lpt.begin(), lpt.end(), [&](int32_t x, int32_t y) { return b->nf_of[x] > b->nf_of[y]; });
+        std::vector<int32_t> order;
+        order.reserve(b->R);
+        b->t_group_first.assign(kNumTanRes + 2, 0);
+        for (int v = 0; v <= kNumTanRes; ++v) {
+            b->t_group_first[v] = (int64_t)order.size();
+            for (int32_t r : lpt) {
+                int g = kNumTanRes;
+                for (int u = 0; u < kNumTanRes; ++u)
+                    if (b->nf_of[r] <= (int64_t)kTanRes[u].threads * kTanRes[u].sn) {
+                        g = u;
+                        break;
+                    }
+                if (g == v) order.push_back(r);
+            }
+        }
+        b->t_group_first[kNumTanRes + 1] = (int64_t)order.size();
+        b->t_order_host = order;
+        hipError_t e = hipMemcpy(b->t_order, order.data(), 4 * (size_t)b->R, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(b->t_chunk_first, b->chunk_first.data(), 8 * (size_t)(b->R + 1), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(b->t_chunk_rec, b->chunk_rec.data(), 8 * (size_t)(nch + 1), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(b->t_mem);
+            b->t_mem = nullptr;
+            return fail(RVE_EDEVICE, std::string("tangent table upload: ") + hipGetErrorString(e));
+        }
+        b->t_static_built = false;
     }
-    if (vb > b->t_vec_bytes) {
-        if (b->t_vec) (void)hipFree(b->t_vec);
-        if (b->t_vec64) (void)hipFree(b->t_vec64);
-        b->t_vec = nullptr;
-        b->t_vec64 = nullptr;
-        b->t_vec_bytes = 0;
-        if (hipMalloc((void**)&b->t_vec, vb) != hipSuccess || hipMalloc((void**)&b->t_vec64, vb) != hipSuccess)
+    if (slot_bytes > b->t_slot_bytes) {
+        if (b->t_slots) (void)hipFree(b->t_slots);
+        b->t_slots = nullptr;
+        b->t_slot_bytes = 0;
+        if (hipMalloc((void**)&b->t_slots, slot_bytes) != hipSuccess) {
+            b->t_slots = nullptr;
             return fail(RVE_ENOMEM, "tangent workspace allocation failed");
-        b->t_vec_bytes = vb;
-    }
-    if (!b->t_out) {
-        if (hipMalloc(&b->t_out, 8 * 81 * (size_t)b->R + 8) != hipSuccess ||
-            hipMalloc(&b->t_in, 8 * 9 * (size_t)b->R + 8) != hipSuccess ||
-            hipMalloc(&b->t_status, 4 * (size_t)b->R + 4) != hipSuccess)
-            return fail(RVE_ENOMEM, "tangent output allocation failed");
+        }
+        b->t_slot_bytes = slot_bytes;
     }
     return RVE_OK;
 }
@@ -971,7 +1041,44 @@ static int run_cg(rve_batch* b, int mode, const double* gsigma, double* out, int
     if (b->R == 0) return RVE_OK;
     if (!out || !status || (mode == 1 && !gsigma)) return fail(RVE_EINVAL, "NULL output or input");
     if (!b->have_state) return fail(RVE_ESTATE, "no solve yet");
-    int rc = ensure_tangent_ws(b, mode == 0 ? 27 : 3);
+    // allocate the batch tables first (task groups), then size the slots
+    int rc = ensure_tangent_ws(b, 0);
+    if (rc) return rc;
+    const int per = mode == 0 ? 9 : 1;
+    // task ranges in t_order: one per resident variant, then the wavefront
+    // kernel; engines other than AUTO run every task on the wavefront kernel
+    std::vector<int64_t> gf = b->t_group_first;
+    if (b->opts.engine != RVE_ENGINE_AUTO) {
+        for (int v = 0; v <= kNumTanRes; ++v) gf[v] = 0;
+        gf[kNumTanRes + 1] = b->R;
+    }
+    // largest free-node count of each launch's RVEs
+    b->t_max_nf.assign(kNumTanRes + 1, 0);
+    for (int v = 0; v <= kNumTanRes; ++v)
+        for (int64_t q = gf[v]; q < gf[v + 1]; ++q)
+            b->t_max_nf[v] = std::max<int64_t>(b->t_max_nf[v], b->nf_of[b->t_order_host[q]]);
+    int grid[kNumTanRes + 1];
+    int64_t S[kNumTanRes + 1];
+    size_t slot_bytes = 0;
+    for (int v = 0; v <= kNumTanRes; ++v) {
+        const int64_t tasks = (gf[v + 1] - gf[v]) * per;
+        grid[v] = 0;
+        S[v] = 1;
+        if (tasks == 0) continue;
+        if (v < kNumTanRes) {
+            int bpc = 0;
+            HIP_TRY(tangent_res_blocks(v, mode != 0, &bpc));
+            if (bpc < 1) return fail(RVE_EDEVICE, "tangent kernel does not fit a compute unit");
+            grid[v] = (int)std::min<int64_t>((int64_t)bpc * b->n_cu, tasks);
+            S[v] = (int64_t)kTanRes[v].threads * kTanRes[v].sn + 1;
+            slot_bytes = std::max(slot_bytes, 48 * (size_t)S[v] * (size_t)grid[v]);
+        } else {
+            grid[v] = (int)std::min<int64_t>((int64_t)b->n_cu * 8, tasks);
+            for (int64_t r = 0; r < b->R; ++r) S[v] = std::max<int64_t>(S[v], b->nf_of[r] + 1);
+            slot_bytes = std::max(slot_bytes, 128 * (size_t)S[v] * (size_t)grid[v]);
+        }
+    }
+    rc = ensure_tangent_ws(b, slot_bytes);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)b->opts.stream;
     const hipMemcpyKind in_kind = ptr_kind == RVE_PTR_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
@@ -986,6 +1093,7 @@ static int run_cg(rve_batch* b, int mode, const double* gsigma, double* out, int
     a.gsigma = b->t_in;
     a.out = b->t_out;
     a.status = b->t_status;
+    a.iters = reinterpret_cast<unsigned long long*>(b->t_iters);
     a.queue = b->dqueue + 60;
     a.mode = mode;
     a.law = b->opts.law;
@@ -995,13 +1103,33 @@ static int run_cg(rve_batch* b, int mode, const double* gsigma, double* out, int
     a.cg_max = b->opts.cg_max_iter;
     a.n_free_total = b->NFREE;
     a.n_rve = b->R;
-    a.ws_par = b->t_par;
-    a.ws_par64 = b->t_par64;
-    a.ws_vec = b->t_vec;
-    a.ws_vec64 = b->t_vec64;
-    HIP_TRY(launch_reset(a.queue, 1, s));
-    int grid = (int)std::min<int64_t>((int64_t)b->n_cu * 4, b->R);
-    HIP_TRY(launch_tangent(a, grid, s));
+    a.chunk_first = b->t_chunk_first;
+    a.chunk_rec = b->t_chunk_rec;
+    a.rec_static = b->t_rec_static;
+    a.recA = b->t_recA;
+    a.recB = b->t_recB;
+    a.precond = b->t_precond;
+    a.par64 = b->t_par64;
+    a.slot_ws64 = reinterpret_cast<double*>(b->t_slots);
+    a.build_static = b->t_static_built ? 0 : 1;
+    HIP_TRY(launch_tangent_prep(a, s));
+    b->t_static_built = true;
+    for (int v = 0; v <= kNumTanRes; ++v) {
+        if (grid[v] == 0) continue;
+        // every RVE of the launch must fit its slot (and, resident, its LDS)
+        const size_t need = (v < kNumTanRes ? 48 : 128) * (size_t)S[v] * (size_t)grid[v];
+        if (need > b->t_slot_bytes || b->t_max_nf[v] >= S[v])
+            return fail(RVE_EINVAL, "internal: tangent slot smaller than an RVE of its group");
+        a.order = b->t_order + gf[v];
+        a.n_order = gf[v + 1] - gf[v];
+        a.slot_nodes = S[v];
+        a.slot_ws32 = reinterpret_cast<float4*>(b->t_slots + 48 * (size_t)S[v] * (size_t)grid[v]);
+        HIP_TRY(launch_reset(a.queue, 1, s));
+        if (v < kNumTanRes)
+            HIP_TRY(launch_tangent_res(v, a, grid[v], s));
+        else
+            HIP_TRY(launch_tangent_wave(a, grid[v], s));
+    }
     HIP_TRY(hipMemcpyAsync(out, b->t_out, (mode == 0 ? 648 : 72) * b->R, out_kind, s));
     HIP_TRY(hipMemcpyAsync(status, b->t_status, 4 * b->R, out_kind, s));
     if (ptr_kind == RVE_PTR_HOST) HIP_TRY(hipStreamSynchronize(s));
@@ -1018,17 +1146,26 @@ int rve_batch_vjp(rve_batch* b, const double* gsigma, double* gF, int32_t* statu
     return run_cg(b, 1, gsigma, gF, status, ptr_kind);
 }
 
+int rve_batch_tangent_iters(rve_batch* b, int64_t* iters, int32_t ptr_kind)
+{
+    if (!b) return fail(RVE_EINVAL, "batch is NULL");
+    if (ptr_kind != RVE_PTR_HOST && ptr_kind != RVE_PTR_DEVICE) return fail(RVE_EINVAL, "bad ptr_kind");
+    if (b->R == 0) return RVE_OK;
+    if (!iters) return fail(RVE_EINVAL, "iters is NULL");
+    if (!b->t_iters || !b->t_static_built) return fail(RVE_ESTATE, "no tangent or vjp call yet");
+    hipStream_t s = (hipStream_t)b->opts.stream;
+    HIP_TRY(hipMemcpyAsync(iters, b->t_iters, 8 * b->R,
+                           ptr_kind == RVE_PTR_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s));
+    if (ptr_kind == RVE_PTR_HOST) HIP_TRY(hipStreamSynchronize(s));
+    return RVE_OK;
+}
+
 void rve_batch_destroy(rve_batch* b)
 {
     if (!b) return;
     for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
-    if (b->t_par) (void)hipFree(b->t_par);
-    if (b->t_vec) (void)hipFree(b->t_vec);
-    if (b->t_par64) (void)hipFree(b->t_par64);
-    if (b->t_vec64) (void)hipFree(b->t_vec64);
-    if (b->t_out) (void)hipFree(b->t_out);
-    if (b->t_in) (void)hipFree(b->t_in);
-    if (b->t_status) (void)hipFree(b->t_status);
+    if (b->t_mem) (void)hipFree(b->t_mem);
+    if (b->t_slots) (void)hipFree(b->t_slots);
     if (b->dtune_list) (void)hipFree(b->dtune_list);
     if (b->dmem) (void)hipFree(b->dmem);
     if (b->ws_fib) (void)hipFree(b->ws_fib);

@@ -60,17 +60,28 @@ struct TangentArgs {
     const double* gsigma;        // [R][9] (vjp)
     double* out;                 // [R][81] (tangent) or [R][9] (vjp)
     int32_t* status;             // [R]
-    int32_t* queue;
+    unsigned long long* iters;   // [R] inner CG iterations summed over the RVE's right-hand sides
+    int32_t* queue;              // work counter of the launch
+    const int32_t* order;        // RVE ids of the launch, most free nodes first
+    int64_t n_order;
     int32_t mode;                // 0 tangent, 1 vjp
     int32_t law;
     double EA, B, cg_tol;
     int64_t cg_max;
     int64_t n_free_total;
     int64_t n_rve;
-    void* ws_par;                // [NF + R][2] float4 fiber operators
-    double* ws_par64;            // [NF + R][5] FP64 fiber operators
-    float* ws_vec;               // 4 vectors of [NFREE + R][3 NR] floats
-    double* ws_vec64;            // 2 vectors of [NFREE + R][3 NR] doubles
+    // free-node incidence in ELL chunks of 64 nodes (records s*64 + lane)
+    const int64_t* chunk_first;  // [R+1] first chunk of each RVE
+    const int64_t* chunk_rec;    // [NCH+1] first record of each chunk; width = records / 64
+    int2* rec_static;            // [NREC] (local fiber id or -1, other end; nf if fixed or padding)
+    float4* recA;                // [NREC] FP32 operator of the record's fiber: (n, k_t/L0)
+    int2* recB;                  // [NREC] (other end, bits of FP32 T/l)
+    float4* precond;             // [NFREE][2] inverse 3x3 diagonal block: (00, 01, 02, 11), (12, 22, -, -)
+    double* par64;               // [NF][6] FP64 fiber operators: n, k_t/L0, T/l, T
+    double* slot_ws64;           // [grid][2][3 slot_nodes] per-workgroup FP64 x and b
+    float4* slot_ws32;           // [grid][5][slot_nodes] per-wavefront FP32 p, q, r, d, z (wave kernel)
+    int64_t slot_nodes;          // free-node capacity of a slot + 1
+    int32_t build_static;        // 1: fill rec_static from the incidence first
 };
 
 // Which register-resident variants exist (threads per RVE, fiber slots per
@@ -91,7 +102,19 @@ hipError_t launch_resident(int variant, bool fp64, const SolveArgs& a, size_t ld
 hipError_t launch_streamed(bool fp64, const SolveArgs& a, int grid, int threads, hipStream_t s);
 hipError_t launch_stress(const SolveArgs& a, int n_rve, hipStream_t s);
 hipError_t launch_reset(int32_t* counters, int n, hipStream_t s);   // n <= 64
-hipError_t launch_tangent(const TangentArgs& a, int grid, hipStream_t s);
+// Tangent / VJP.  prep: statuses, ELL records (first call), fiber operators
+// and preconditioner for every RVE.  Then the tasks of the RVEs in a.order:
+// register/LDS-resident workgroups (variant v, RVEs with fewer than
+// threads * slots free nodes) or one wavefront per task (any size).
+struct TangentVariant {
+    int threads, sn;
+};
+constexpr int kNumTanRes = 3;
+extern const TangentVariant kTanRes[kNumTanRes];
+hipError_t launch_tangent_prep(const TangentArgs& a, hipStream_t s);
+hipError_t launch_tangent_res(int variant, const TangentArgs& a, int grid, hipStream_t s);
+hipError_t launch_tangent_wave(const TangentArgs& a, int grid, hipStream_t s);
+hipError_t tangent_res_blocks(int variant, bool vjp, int* blocks_per_cu);
 hipError_t max_resident_blocks(int variant, bool fp64, size_t lds_bytes, int* blocks_per_cu);
 // Private (spill) bytes per lane of a resident variant; > 0 means it spills.
 hipError_t resident_scratch_bytes(int variant, bool fp64, size_t* bytes);

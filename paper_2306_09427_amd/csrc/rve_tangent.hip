@@ -7,23 +7,32 @@
 // Per fiber, K contributes B_f = a n n^T + g (I - n n^T) with n = d/l,
 // a = k_t/L0, g = T/l, so (K u)_a = sum_{fibers at a} B_f (u_a - u_other).
 //
-// Tangent (9 right-hand sides, one per F_kl): the boundary moves by E Xm_b,
+// Tangent (one right-hand side per F_kl): the boundary moves by E Xm_b,
 // E = e_k e_l, so K_ff dx = -[K (E Xm)]_f with [K (E Xm)]_a =
 // sum s_af B_f (E d0_f); then df_b = sum s_bf B_f (E d0_f + dx_j - dx_i) and
 // dsigma = (sum_b df_b x_b^T + f_b (E Xm_b)^T) / (J V0) - sigma (F^-1)_lk.
 //
-// VJP (1 right-hand side): with y_b = G x_b on boundary nodes (G = dL/dsigma)
+// VJP (one right-hand side): with y_b = G x_b on boundary nodes (G = dL/dsigma)
 // and u = [0; y], solve K_ff lambda = (K u)_f, then z_b = (K [-lambda; y])_b
 // and dL/dF_kl = sum_b (z_b + G^T f_b)_k Xm_b,l / (J V0) - (G:sigma) F^-T_kl.
 //
+// Work decomposition: one wavefront per (RVE, right-hand side) task, pulled
+// from a work counter in longest-first order of the RVEs, so the nine solves
+// of one RVE's tangent run as nine independent wavefronts with no workgroup
+// synchronisation.  A first kernel
+// forms, once per call, the fiber operators (FP64 per fiber, FP32 per
+// incidence record) and the block-Jacobi preconditioner.  The incidence of
+// the free nodes is stored in ELL chunks of 64 nodes (record s of the chunk's
+// lane-th node at s*64 + lane), so the lanes of a wavefront read their
+// records with unit stride.
+//
 // Precision: iterative refinement.  The outer loop keeps the solution, the
-// right-hand side and the residual r = b - K x in FP64 (FP64 fiber operators);
-// each inner solve K d = r is conjugate gradients with FP32 products and FP64
-// dot products, stopped after a 1e-6 reduction of its residual; x += d.
-// Plain FP32 CG stalls near eps_32 cond(K_ff), about 1e-3 on these networks,
-// which refinement removes.  The final assembly is FP64 from an FP64
-// re-evaluation of the boundary fibers.  One workgroup per RVE, persistent
-// over a work queue.
+// right-hand side and the residual r = b - K x in FP64 (FP64 fiber
+// operators); each inner solve K d = r is conjugate gradients preconditioned
+// by the inverse 3x3 diagonal blocks of K_ff, with FP32 products and FP64 dot
+// products, stopped after a 1e-6 reduction of its residual; x += d.  Plain
+// FP32 CG stalls near eps_32 cond(K_ff), about 1e-3 on these networks, which
+// refinement removes.  The final assembly is FP64.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -35,6 +44,7 @@ namespace rve {
 namespace {
 
 constexpr int ST_CONVERGED = 0, ST_NO_STATE = 4, ST_CG_MAXITER = 5, ST_CG_INDEFINITE = 6;
+constexpr int kOpsThreads = 256;
 
 __device__ inline double det3(const double* F)
 {
@@ -42,510 +52,931 @@ __device__ inline double det3(const double* F)
            F[2] * (F[3] * F[7] - F[4] * F[6]);
 }
 
-// FP64 fiber state: unit vector n, a = k_t/L0, g = T/l, axial force T.
-struct FiberOp {
-    double nx, ny, nz, a, g, T;
-};
-
-__device__ inline FiberOp fiber_op(const TangentArgs& A, const double* F, int64_t f0, int64_t a0, int64_t nf,
-                                   int64_t k)
+// ------------------------------------------------------------------ static records
+// Fills (fiber, other end) of every ELL record of RVE blockIdx.x from the CSR
+// incidence; padding records are (-1, nf).
+__global__ __launch_bounds__(kOpsThreads) void ell_build_kernel(TangentArgs A)
 {
+    const int r = blockIdx.x;
     const DevNet& net = A.net;
-    const double* d0 = net.d0 + 3 * (f0 + k);
-    const double L0 = net.L0[f0 + k];
-    uint32_t e = net.ends[f0 + k];
-    int i = e & 0xffff, j = e >> 16;
-    double D[3];
-    for (int p = 0; p < 3; ++p) D[p] = F[3 * p] * d0[0] + F[3 * p + 1] * d0[1] + F[3 * p + 2] * d0[2];
-    double q0 = (D[0] * D[0] + D[1] * D[1] + D[2] * D[2]) - L0 * L0;
-    double dh[3] = {0, 0, 0};
-    for (int p = 0; p < 3; ++p) {
-        if (j < nf) dh[p] += A.h_state[3 * (a0 + j) + p];
-        if (i < nf) dh[p] -= A.h_state[3 * (a0 + i) + p];
+    const int64_t f0 = net.fib_off[r];
+    const int64_t a0 = net.free_off[r], nf = net.free_off[r + 1] - a0;
+    const int64_t cf = A.chunk_first[r], nch = A.chunk_first[r + 1] - cf;
+#pragma unroll 1
+    for (int64_t a = threadIdx.x; a < 64 * nch; a += kOpsThreads) {
+        const int64_t c = cf + (a >> 6);
+        const int64_t base = A.chunk_rec[c] + (a & 63), w = (A.chunk_rec[c + 1] - A.chunk_rec[c]) >> 6;
+        const int64_t e0 = a < nf ? net.inc_off[a0 + a] : 0, deg = a < nf ? net.inc_off[a0 + a + 1] - e0 : 0;
+#pragma unroll 1
+        for (int64_t s = 0; s < w; ++s) {
+            int2 v = make_int2(-1, (int)nf);
+            if (s < deg) {
+                const uint32_t e = net.inc[e0 + s];
+                const int64_t k = e & 0x7fffffffu;
+                const uint32_t en = net.ends[f0 + k];
+                const int64_t o = (e >> 31) ? (int64_t)(en >> 16) : (int64_t)(en & 0xffff);
+                v = make_int2((int)k, (int)(o < nf ? o : nf));
+            }
+            A.rec_static[base + 64 * s] = v;
+        }
     }
-    double d[3] = {D[0] + dh[0], D[1] + dh[1], D[2] + dh[2]};
-    double q = q0 + (2.0 * (D[0] * dh[0] + D[1] * dh[1] + D[2] * dh[2]) + (dh[0] * dh[0] + dh[1] * dh[1] + dh[2] * dh[2]));
-    double l = sqrt(L0 * L0 + q);
-    double eps = q / (L0 * (l + L0));
-    double T, kt;
-    if (A.law != 0 && eps >= 0.0) {
-        double em1 = expm1(A.B * eps);
-        T = A.EA * em1 / A.B;
-        kt = A.EA * (em1 + 1.0);
-    } else {
-        T = A.EA * eps;
-        kt = A.EA;
-    }
-    FiberOp o;
-    o.nx = d[0] / l;
-    o.ny = d[1] / l;
-    o.nz = d[2] / l;
-    o.a = kt / L0;
-    o.g = T / l;
-    o.T = T;
-    return o;
 }
 
+// ------------------------------------------------------------------ fiber operators
+// One workgroup per RVE: n, a = k_t/L0, g = T/l and T of every fiber at the
+// last solve's state (FP64), then the FP32 record operators and the inverse
+// diagonal blocks of K_ff.
+__global__ __launch_bounds__(kOpsThreads) void fiber_ops_kernel(TangentArgs A)
+{
+    const int r = blockIdx.x;
+    if (A.solve_status[r] != 0) return;
+    const DevNet& net = A.net;
+    const int64_t f0 = net.fib_off[r], nfib = net.fib_off[r + 1] - f0;
+    const int64_t a0 = net.free_off[r], nf = net.free_off[r + 1] - a0;
+    double F[9];
+    for (int k = 0; k < 9; ++k) F[k] = A.F[9 * r + k];
+#pragma unroll 1
+    for (int64_t k = threadIdx.x; k < nfib; k += kOpsThreads) {
+        const double* d0 = net.d0 + 3 * (f0 + k);
+        const double L0 = net.L0[f0 + k];
+        uint32_t e = net.ends[f0 + k];
+        int i = e & 0xffff, j = e >> 16;
+        double D[3], dh[3] = {0, 0, 0};
+        for (int p = 0; p < 3; ++p) D[p] = F[3 * p] * d0[0] + F[3 * p + 1] * d0[1] + F[3 * p + 2] * d0[2];
+        for (int p = 0; p < 3; ++p) {
+            if (j < nf) dh[p] += A.h_state[3 * (a0 + j) + p];
+            if (i < nf) dh[p] -= A.h_state[3 * (a0 + i) + p];
+        }
+        double q0 = (D[0] * D[0] + D[1] * D[1] + D[2] * D[2]) - L0 * L0;
+        double q = q0 + (2.0 * (D[0] * dh[0] + D[1] * dh[1] + D[2] * dh[2]) + (dh[0] * dh[0] + dh[1] * dh[1] + dh[2] * dh[2]));
+        double l = sqrt(L0 * L0 + q);
+        double eps = q / (L0 * (l + L0));
+        double T, kt;
+        if (A.law != 0 && eps >= 0.0) {
+            double em1 = expm1(A.B * eps);
+            T = A.EA * em1 / A.B;
+            kt = A.EA * (em1 + 1.0);
+        } else {
+            T = A.EA * eps;
+            kt = A.EA;
+        }
+        double* q64 = A.par64 + 6 * (f0 + k);
+        q64[0] = (D[0] + dh[0]) / l;
+        q64[1] = (D[1] + dh[1]) / l;
+        q64[2] = (D[2] + dh[2]) / l;
+        q64[3] = kt / L0;
+        q64[4] = T / l;
+        q64[5] = T;
+    }
+    __syncthreads();
+    const double* par64 = A.par64 + 6 * f0;
+    const int64_t cf = A.chunk_first[r], nch = A.chunk_first[r + 1] - cf;
+#pragma unroll 1
+    for (int64_t a = threadIdx.x; a < 64 * nch; a += kOpsThreads) {
+        const int64_t c = cf + (a >> 6);
+        const int64_t base = A.chunk_rec[c] + (a & 63), w = (A.chunk_rec[c + 1] - A.chunk_rec[c]) >> 6;
+        double Dg[6] = {0, 0, 0, 0, 0, 0};   // 00 01 02 11 12 22
+#pragma unroll 1
+        for (int64_t s = 0; s < w; ++s) {
+            const int2 st = A.rec_static[base + 64 * s];
+            float4 ra = make_float4(0.f, 0.f, 0.f, 0.f);
+            int2 rb = make_int2(st.y, 0);
+            if (st.x >= 0) {
+                const double* q = par64 + 6 * st.x;
+                ra = make_float4((float)q[0], (float)q[1], (float)q[2], (float)q[3]);
+                rb.y = __float_as_int((float)q[4]);
+                const double c2 = q[3] - q[4];
+                Dg[0] += q[4] + c2 * q[0] * q[0];
+                Dg[1] += c2 * q[0] * q[1];
+                Dg[2] += c2 * q[0] * q[2];
+                Dg[3] += q[4] + c2 * q[1] * q[1];
+                Dg[4] += c2 * q[1] * q[2];
+                Dg[5] += q[4] + c2 * q[2] * q[2];
+            }
+            A.recA[base + 64 * s] = ra;
+            A.recB[base + 64 * s] = rb;
+        }
+        if (a < nf) {
+            // inverse by cofactors when the block is positive definite
+            // (leading minors), else a scalar 1/max diagonal
+            const double m1 = Dg[0], m2 = Dg[0] * Dg[3] - Dg[1] * Dg[1];
+            const double c00 = Dg[3] * Dg[5] - Dg[4] * Dg[4], c01 = Dg[2] * Dg[4] - Dg[1] * Dg[5],
+                         c02 = Dg[1] * Dg[4] - Dg[2] * Dg[3], c11 = Dg[0] * Dg[5] - Dg[2] * Dg[2],
+                         c12 = Dg[1] * Dg[2] - Dg[0] * Dg[4], c22 = m2;
+            const double det = Dg[0] * c00 + Dg[1] * c01 + Dg[2] * c02;
+            const double tr = Dg[0] + Dg[3] + Dg[5];
+            float4 p0, p1;
+            if (m1 > 0.0 && m2 > 0.0 && det > 1e-9 * tr * tr * tr) {
+                const double id = 1.0 / det;
+                p0 = make_float4((float)(c00 * id), (float)(c01 * id), (float)(c02 * id), (float)(c11 * id));
+                p1 = make_float4((float)(c12 * id), (float)(c22 * id), 0.f, 0.f);
+            } else {
+                const double dm = fmax(fmax(fabs(Dg[0]), fabs(Dg[3])), fabs(Dg[5]));
+                const float s = dm > 0.0 ? (float)(1.0 / dm) : 1.f;
+                p0 = make_float4(s, 0.f, 0.f, s);
+                p1 = make_float4(0.f, s, 0.f, 0.f);
+            }
+            A.precond[2 * (a0 + a)] = p0;
+            A.precond[2 * (a0 + a) + 1] = p1;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ wave helpers
 template <typename T>
-__device__ inline T wsum(T v)
+__device__ __forceinline__ T wsum(T v)
 {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
 }
 
-// Sum NR doubles over the workgroup; every thread gets the totals.
-template <int NR, int NT>
-__device__ inline void block_sum(double* v, double (*sh)[NT / 64])
+// Values the whole wavefront shares (loaded through vector memory) moved to
+// scalar registers.
+__device__ __forceinline__ int64_t uni64(int64_t x)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < NR; ++k) {
-        double s = wsum(v[k]);
-        if (lane == 0) sh[k][wave] = s;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < NR; ++k) {
-        double s = 0.0;
-        for (int w = 0; w < NT / 64; ++w) s += sh[k][w];
-        v[k] = s;
-    }
-    __syncthreads();
+    int lo = __builtin_amdgcn_readfirstlane((int)(x & 0xffffffff));
+    int hi = __builtin_amdgcn_readfirstlane((int)(x >> 32));
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
-// Apply B_f (FP32 parameters) to a vector.
-__device__ inline void apply_B(const float4 nA, float g, float dx, float dy, float dz, float& wx, float& wy, float& wz)
+__device__ __forceinline__ double uniformd(double x)
 {
-    float dn = nA.x * dx + nA.y * dy + nA.z * dz;
-    float c = (nA.w - g) * dn;
-    wx = g * dx + c * nA.x;
-    wy = g * dy + c * nA.y;
-    wz = g * dz + c * nA.z;
+    int lo = __builtin_amdgcn_readfirstlane(__double2loint(x));
+    int hi = __builtin_amdgcn_readfirstlane(__double2hiint(x));
+    return __hiloint2double(hi, lo);
 }
 
-template <int NR, int NT>
-__device__ void cg_one(const TangentArgs& A, int r, double (*sh)[NT / 64])
+__device__ __forceinline__ void apply_B64(const double* q, double dx, double dy, double dz, double& wx, double& wy,
+                                          double& wz)
+{
+    double dn = q[0] * dx + q[1] * dy + q[2] * dz;
+    double c = (q[3] - q[4]) * dn;
+    wx = q[4] * dx + c * q[0];
+    wy = q[4] * dy + c * q[1];
+    wz = q[4] * dz + c * q[2];
+}
+
+// z = P v with P the symmetric inverse block (00, 01, 02, 11), (12, 22, -, -)
+__device__ __forceinline__ float4 precond_apply(const float4* P, float4 v)
+{
+    const float4 p0 = P[0], p1 = P[1];
+    return make_float4(p0.x * v.x + p0.y * v.y + p0.z * v.z, p0.y * v.x + p0.w * v.y + p1.x * v.z,
+                       p0.z * v.x + p1.x * v.y + p1.y * v.z, 0.f);
+}
+
+__device__ __forceinline__ double dot3(float4 a, float4 b)
+{
+    return (double)a.x * b.x + (double)a.y * b.y + (double)a.z * b.z;
+}
+
+// ------------------------------------------------------------------ per-RVE context
+struct Ctx {
+    int64_t f0, nfib, a0, nf, b0;
+    const double* par64;
+    const int64_t* incoff;
+    const uint32_t* ends;
+};
+
+__device__ __forceinline__ Ctx make_ctx(const TangentArgs& A, int r)
 {
     const DevNet& net = A.net;
-    const int tid = threadIdx.x;
-    const int64_t f0 = net.fib_off[r], nfib = net.fib_off[r + 1] - f0;
-    const int64_t a0 = net.free_off[r], nf = net.free_off[r + 1] - a0;
-    const int64_t b0 = net.bnd_off[r];
-    constexpr int W = NR * 3;
-    double* out = A.out + (int64_t)r * (NR == 9 ? 81 : 9);
-    if (A.solve_status[r] != 0) {
-        if (tid == 0) A.status[r] = ST_NO_STATE;
-        for (int k = tid; k < (NR == 9 ? 81 : 9); k += NT) out[k] = NAN;
-        return;
+    Ctx c;
+    c.f0 = uni64(net.fib_off[r]);
+    c.nfib = uni64(net.fib_off[r + 1]) - c.f0;
+    c.a0 = uni64(net.free_off[r]);
+    c.nf = uni64(net.free_off[r + 1]) - c.a0;
+    c.b0 = uni64(net.bnd_off[r]);
+    c.par64 = A.par64 + 6 * c.f0;
+    c.incoff = net.inc_off + c.a0;
+    c.ends = net.ends + c.f0;
+    return c;
+}
+
+// Outputs of a task whose RVE has no converged state.
+template <bool TAN>
+__device__ void no_state(const TangentArgs& A, int r, int col)
+{
+    if (threadIdx.x == 0) atomicMax(&A.status[r], ST_NO_STATE);
+    if (threadIdx.x < 9) {
+        if (TAN)
+            A.out[(int64_t)r * 81 + 9 * threadIdx.x + col] = NAN;
+        else
+            A.out[(int64_t)r * 9 + threadIdx.x] = NAN;
     }
+}
+
+// Right-hand side at free node a (FP64).  Tangent: -sum s B_f (e_k d0_l),
+// s = +1 at end j, -1 at end i.  VJP: (K u)_a with u = -G x_b on fixed ends.
+template <bool TAN>
+__device__ __forceinline__ void rhs_node(const TangentArgs& A, const Ctx& c, int64_t a, int kk, int ll,
+                                         const double* F, const double* G, double* b)
+{
+    const DevNet& net = A.net;
+    b[0] = b[1] = b[2] = 0.0;
+#pragma unroll 1
+    for (int64_t e = c.incoff[a]; e < c.incoff[a + 1]; ++e) {
+        const uint32_t w = net.inc[e];
+        const int64_t k = w & 0x7fffffffu;
+        const double* q = c.par64 + 6 * k;
+        if (TAN) {
+            const double s = ((w >> 31) ? 1.0 : -1.0) * net.d0[3 * (c.f0 + k) + ll];
+            const double nk = kk == 0 ? q[0] : (kk == 1 ? q[1] : q[2]);
+            const double cc = (q[3] - q[4]) * nk;
+            for (int p = 0; p < 3; ++p) b[p] += s * (cc * q[p] + (p == kk ? q[4] : 0.0));
+        } else {
+            const uint32_t en = c.ends[k];
+            const int64_t o = (w >> 31) ? (int64_t)(en >> 16) : (int64_t)(en & 0xffff);
+            if (o >= c.nf) {
+                const double* Xm = net.Xb + 3 * (c.b0 + (o - c.nf));
+                double x[3], y[3];
+                for (int p = 0; p < 3; ++p) x[p] = F[3 * p] * Xm[0] + F[3 * p + 1] * Xm[1] + F[3 * p + 2] * Xm[2];
+                for (int p = 0; p < 3; ++p) y[p] = -(G[3 * p] * x[0] + G[3 * p + 1] * x[1] + G[3 * p + 2] * x[2]);
+                double w3[3];
+                apply_B64(q, y[0], y[1], y[2], w3[0], w3[1], w3[2]);
+                for (int p = 0; p < 3; ++p) b[p] += w3[p];
+            }
+        }
+    }
+}
+
+// FP64 residual b - K x at free node a; x64 holds the solution (entry nf = 0).
+__device__ __forceinline__ void residual_node(const TangentArgs& A, const Ctx& c, int64_t a, const double* x64,
+                                              const double* b64, bool first, double* ra)
+{
+    for (int p = 0; p < 3; ++p) ra[p] = b64[3 * a + p];
+    if (first) return;
+    const double xa[3] = {x64[3 * a], x64[3 * a + 1], x64[3 * a + 2]};
+#pragma unroll 1
+    for (int64_t e = c.incoff[a]; e < c.incoff[a + 1]; ++e) {
+        const uint32_t w = A.net.inc[e];
+        const uint32_t en = c.ends[w & 0x7fffffffu];
+        int64_t o = (w >> 31) ? (int64_t)(en >> 16) : (int64_t)(en & 0xffff);
+        o = o < c.nf ? o : c.nf;
+        const double* xo = x64 + 3 * o;
+        double w3[3];
+        apply_B64(c.par64 + 6 * (w & 0x7fffffffu), xa[0] - xo[0], xa[1] - xo[1], xa[2] - xo[2], w3[0], w3[1], w3[2]);
+        for (int p = 0; p < 3; ++p) ra[p] -= w3[p];
+    }
+}
+
+// Partial sums of the assembly over fibers k0, k0 + stride, ... that have a
+// fixed end (FP64).  acc[3p + c] collects sum_b df_b,p x_b,c + f_b,p (E Xm_b)_c
+// (tangent) or sum_b (z_b + G^T f_b)_p Xm_b,c (VJP).
+template <bool TAN>
+__device__ __forceinline__ void assembly_partial(const TangentArgs& A, const Ctx& c, int r, int kk, int ll,
+                                                 const double* x64, int64_t k0, int stride, double* acc)
+{
+    const DevNet& net = A.net;
     double F[9], G[9];
     for (int k = 0; k < 9; ++k) F[k] = A.F[9 * r + k];
-    if (NR == 1)
+    if (!TAN)
         for (int k = 0; k < 9; ++k) G[k] = A.gsigma[9 * r + k];
-    const double J = det3(F);
-    const int64_t NV = (A.n_free_total + A.n_rve) * (int64_t)W;   // length of one vector over the batch
-    // fiber operators: FP32 copy for the inner solves, FP64 copy for residuals
-    float4* par = reinterpret_cast<float4*>(A.ws_par) + 2 * (f0 + r);   // [nfib][2]: (n, a), (g, -, -, -)
-    double* par64 = A.ws_par64 + 5 * (f0 + r);                          // [nfib][5]: n, a, g
-    float* vx = A.ws_vec + (a0 + r) * (int64_t)W;     // inner solution d
-    float* vr = vx + NV;                              // inner residual
-    float* vp = vr + NV;                              // search direction (entry nf = 0)
-    float* vq = vp + NV;                              // K p
-    double* xb = A.ws_vec64 + (a0 + r) * (int64_t)W;  // FP64 solution (entry nf = 0)
-    double* bb64 = xb + NV;                           // FP64 right-hand side
-
+#pragma unroll
+    for (int p = 0; p < 9; ++p) acc[p] = 0.0;
 #pragma unroll 1
-    for (int64_t k = tid; k < nfib; k += NT) {
-        FiberOp o = fiber_op(A, F, f0, a0, nf, k);
-        par[2 * k] = make_float4((float)o.nx, (float)o.ny, (float)o.nz, (float)o.a);
-        par[2 * k + 1] = make_float4((float)o.g, 0.f, 0.f, 0.f);
-        double* q = par64 + 5 * k;
-        q[0] = o.nx; q[1] = o.ny; q[2] = o.nz; q[3] = o.a; q[4] = o.g;
-    }
-    if (tid < W) {
-        vp[nf * W + tid] = 0.f;
-        xb[nf * W + tid] = 0.0;
-    }
-    __syncthreads();
-
-    // right-hand sides (FP64)
-    double bnorm2[NR];
-#pragma unroll
-    for (int k = 0; k < NR; ++k) bnorm2[k] = 0.0;
-#pragma unroll 1
-    for (int64_t a = tid; a < nf; a += NT) {
-        double b[W];
-#pragma unroll
-        for (int k = 0; k < W; ++k) b[k] = 0.0;
-#pragma unroll 1
-        for (int64_t e = net.inc_off[a0 + a]; e < net.inc_off[a0 + a + 1]; ++e) {
-            uint32_t w = net.inc[e];
-            int64_t k = w & 0x7fffffffu;
-            double sgn = (w >> 31) ? -1.0 : 1.0;     // end i: -1, end j: +1
-            const double* q = par64 + 5 * k;
-            if (NR == 9) {
-                // -s B_f (e_kk d0_l) for direction (kk, l)
-                const double* d0 = net.d0 + 3 * (f0 + k);
-#pragma unroll
-                for (int kk = 0; kk < 3; ++kk) {
-                    double n_k = q[kk], c = (q[3] - q[4]) * n_k;
-                    double wv[3] = {c * q[0], c * q[1], c * q[2]};
-                    wv[kk] += q[4];
-#pragma unroll
-                    for (int l = 0; l < 3; ++l) {
-                        double s = -sgn * d0[l];
-                        int col = 3 * kk + l;
-                        b[3 * col] += s * wv[0];
-                        b[3 * col + 1] += s * wv[1];
-                        b[3 * col + 2] += s * wv[2];
-                    }
-                }
-            } else {
-                // (K u)_a with u = y on boundary ends: B_f (0 - y_other)
-                uint32_t en = net.ends[f0 + k];
-                int o = (w >> 31) ? (int)(en >> 16) : (int)(en & 0xffff);
-                if (o >= nf) {
-                    const double* Xm = net.Xb + 3 * (b0 + (o - nf));
-                    double x[3], y[3];
+    for (int64_t k = k0; k < c.nfib; k += stride) {
+        const uint32_t en = c.ends[k];
+        const int64_t i = en & 0xffff, j = en >> 16;
+        if (i < c.nf && j < c.nf) continue;
+        const double* q = c.par64 + 6 * k;
+        double u[3] = {0.0, 0.0, 0.0};
+        if (TAN) {
+            const double d0l = net.d0[3 * (c.f0 + k) + ll];
+            for (int p = 0; p < 3; ++p) {
+                u[p] = p == kk ? d0l : 0.0;
+                if (j < c.nf) u[p] += x64[3 * j + p];
+                if (i < c.nf) u[p] -= x64[3 * i + p];
+            }
+        } else {
+            // u = [-lambda; y] at the two ends, difference j - i
+            for (int end = 0; end < 2; ++end) {
+                const int64_t node = end ? j : i;
+                const double s = end ? 1.0 : -1.0;
+                if (node < c.nf) {
+                    for (int p = 0; p < 3; ++p) u[p] -= s * x64[3 * node + p];
+                } else {
+                    const double* Xm = net.Xb + 3 * (c.b0 + (node - c.nf));
+                    double x[3];
                     for (int p = 0; p < 3; ++p) x[p] = F[3 * p] * Xm[0] + F[3 * p + 1] * Xm[1] + F[3 * p + 2] * Xm[2];
-                    for (int p = 0; p < 3; ++p) y[p] = -(G[3 * p] * x[0] + G[3 * p + 1] * x[1] + G[3 * p + 2] * x[2]);
-                    double dn = q[0] * y[0] + q[1] * y[1] + q[2] * y[2];
-                    double c = (q[3] - q[4]) * dn;
-                    for (int p = 0; p < 3; ++p) b[p] += q[4] * y[p] + c * q[p];
+                    for (int p = 0; p < 3; ++p) u[p] += s * (G[3 * p] * x[0] + G[3 * p + 1] * x[1] + G[3 * p + 2] * x[2]);
                 }
             }
         }
-#pragma unroll
-        for (int k = 0; k < W; ++k) {
-            bb64[a * W + k] = b[k];
-            xb[a * W + k] = 0.0;
+        double w[3];
+        apply_B64(q, u[0], u[1], u[2], w[0], w[1], w[2]);
+        const double fv[3] = {q[5] * q[0], q[5] * q[1], q[5] * q[2]};
+        for (int end = 0; end < 2; ++end) {
+            const int64_t node = end ? j : i;
+            if (node < c.nf) continue;
+            const double s = end ? 1.0 : -1.0;
+            const double* Xm = net.Xb + 3 * (c.b0 + (node - c.nf));
+            if (TAN) {
+                double x[3];
+                for (int p = 0; p < 3; ++p) x[p] = F[3 * p] * Xm[0] + F[3 * p + 1] * Xm[1] + F[3 * p + 2] * Xm[2];
+                const double xl = ll == 0 ? Xm[0] : (ll == 1 ? Xm[1] : Xm[2]);
+                for (int p = 0; p < 3; ++p)
+                    for (int cc = 0; cc < 3; ++cc) acc[3 * p + cc] += s * (w[p] * x[cc] + (cc == kk ? fv[p] * xl : 0.0));
+            } else {
+                double gtf[3];
+                for (int p = 0; p < 3; ++p) gtf[p] = G[p] * fv[0] + G[3 + p] * fv[1] + G[6 + p] * fv[2];
+                for (int p = 0; p < 3; ++p)
+                    for (int cc = 0; cc < 3; ++cc) acc[3 * p + cc] += s * (w[p] + gtf[p]) * Xm[cc];
+            }
         }
-#pragma unroll
-        for (int k = 0; k < NR; ++k) bnorm2[k] += b[3 * k] * b[3 * k] + b[3 * k + 1] * b[3 * k + 1] + b[3 * k + 2] * b[3 * k + 2];
     }
-    block_sum<NR, NT>(bnorm2, sh);
+}
+
+// Final outputs of a task from the summed assembly (one thread).
+template <bool TAN>
+__device__ void assembly_write(const TangentArgs& A, int r, int col, const double* acc, int status, int64_t iters)
+{
+    double F[9];
+    for (int k = 0; k < 9; ++k) F[k] = A.F[9 * r + k];
+    const double J = det3(F);
+    const double V0 = A.net.V0[r];
+    const double id = 1.0 / J;
+    // F^-1 by cofactors
+    const double Fi[9] = {(F[4] * F[8] - F[5] * F[7]) * id, (F[2] * F[7] - F[1] * F[8]) * id,
+                          (F[1] * F[5] - F[2] * F[4]) * id, (F[5] * F[6] - F[3] * F[8]) * id,
+                          (F[0] * F[8] - F[2] * F[6]) * id, (F[2] * F[3] - F[0] * F[5]) * id,
+                          (F[3] * F[7] - F[4] * F[6]) * id, (F[1] * F[6] - F[0] * F[7]) * id,
+                          (F[0] * F[4] - F[1] * F[3]) * id};
+    if (TAN) {
+        const int kk = col / 3, ll = col % 3;
+        double fi = 0.0;   // (F^-1)_{l k}
+        for (int m = 0; m < 9; ++m) fi = m == 3 * ll + kk ? Fi[m] : fi;
+        for (int p = 0; p < 9; ++p)
+            A.out[(int64_t)r * 81 + 9 * p + col] = acc[p] / (J * V0) - A.sigma[9 * r + p] * fi;
+    } else {
+        double gs = 0.0;
+        for (int p = 0; p < 9; ++p) gs += A.gsigma[9 * r + p] * A.sigma[9 * r + p];
+        for (int p = 0; p < 9; ++p) {
+            const int k2 = p / 3, l2 = p % 3;
+            A.out[(int64_t)r * 9 + p] = acc[p] / (J * V0) - gs * Fi[3 * l2 + k2];
+        }
+    }
+    if (status != ST_CONVERGED) atomicMax(&A.status[r], status);
+    atomicAdd(&A.iters[r], (unsigned long long)iters);
+}
+
+// ------------------------------------------------------------------ wavefront tasks
+// A task is (RVE r, right-hand side col): col = 3k + l for the tangent, 0 for
+// the VJP.  One wavefront; lane = node within a chunk of 64.  Solver vectors
+// live in a per-wavefront global slot (any RVE size).
+template <bool TAN>
+__device__ void cg_wave_task(const TangentArgs& A, int r, int col)
+{
+    const int lane = threadIdx.x;
+    if (__builtin_amdgcn_readfirstlane(A.solve_status[r]) != 0) {
+        no_state<TAN>(A, r, col);
+        return;
+    }
+    const Ctx c = make_ctx(A, r);
+    const int64_t nf = c.nf;
+    const int kk = col / 3, ll = col % 3;
+    const float4* Pc = A.precond + 2 * c.a0;
+    const int64_t cf = uni64(A.chunk_first[r]), nch = uni64(A.chunk_first[r + 1]) - cf;
+    const float4* recA = A.recA;
+    const int2* recB = A.recB;
+
+    // slot workspace: FP64 x and b (3 per node), FP32 p, q, r, d, z (float4
+    // per node); entry nf of p and x is the zero vector of fixed ends
+    const int64_t S = A.slot_nodes;
+    double* x64 = A.slot_ws64 + (int64_t)blockIdx.x * 6 * S;
+    double* b64 = x64 + 3 * S;
+    float4* vp = A.slot_ws32 + (int64_t)blockIdx.x * 5 * S;
+    float4* vq = vp + S;
+    float4* vr = vq + S;
+    float4* vd = vr + S;
+    float4* vz = vd + S;
+    if (lane == 0) vp[nf] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (lane < 3) x64[3 * nf + lane] = 0.0;
+
+    double bb = 0.0;
+    {
+        double F[9], G[9];
+        for (int k = 0; k < 9; ++k) F[k] = A.F[9 * r + k];
+        if (!TAN)
+            for (int k = 0; k < 9; ++k) G[k] = A.gsigma[9 * r + k];
+#pragma unroll 1
+        for (int64_t a = lane; a < nf; a += 64) {
+            double b[3];
+            rhs_node<TAN>(A, c, a, kk, ll, F, G, b);
+            for (int p = 0; p < 3; ++p) {
+                b64[3 * a + p] = b[p];
+                x64[3 * a + p] = 0.0;
+            }
+            bb += b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+        }
+    }
+    bb = uniformd(wsum(bb));
+    __syncthreads();
 
     int status = ST_CONVERGED;
     const double tol2 = A.cg_tol * A.cg_tol;
     const int64_t maxit = A.cg_max > 0 ? A.cg_max : 6 * nf + 100;
     int64_t it_total = 0;
-    bool done[NR];
-#pragma unroll
-    for (int k = 0; k < NR; ++k) done[k] = !(bnorm2[k] > 0.0);
-
-    // Outer loop: FP64 residual r = b - K x of the FP64 solution, inner CG with
-    // FP32 products on K d = r, x += d (iterative refinement).
-    for (int outer = 0; outer < 8; ++outer) {
-        double rr[NR];
-#pragma unroll
-        for (int k = 0; k < NR; ++k) rr[k] = 0.0;
+    bool done = !(bb > 0.0);
+    for (int outer = 0; outer < 8 && !done; ++outer) {
+        // FP64 residual r = b - K x of the FP64 solution; z = P r, p = z
+        double rr = 0.0, rz = 0.0;
 #pragma unroll 1
-        for (int64_t a = tid; a < nf; a += NT) {
-            double ra[W];
-#pragma unroll
-            for (int k = 0; k < W; ++k) ra[k] = bb64[a * W + k];
-            if (outer > 0) {
-                double xa[W];
-#pragma unroll
-                for (int k = 0; k < W; ++k) xa[k] = xb[a * W + k];
-#pragma unroll 1
-                for (int64_t e = net.inc_off[a0 + a]; e < net.inc_off[a0 + a + 1]; ++e) {
-                    uint32_t w = net.inc[e];
-                    int64_t k = w & 0x7fffffffu;
-                    uint32_t en = net.ends[f0 + k];
-                    int o = (w >> 31) ? (int)(en >> 16) : (int)(en & 0xffff);
-                    const double* xo = xb + (o < nf ? o : nf) * (int64_t)W;
-                    const double* q = par64 + 5 * k;
-#pragma unroll
-                    for (int c = 0; c < NR; ++c) {
-                        double dx = xa[3 * c] - xo[3 * c], dy = xa[3 * c + 1] - xo[3 * c + 1],
-                               dz = xa[3 * c + 2] - xo[3 * c + 2];
-                        double dn = q[0] * dx + q[1] * dy + q[2] * dz;
-                        double cc = (q[3] - q[4]) * dn;
-                        ra[3 * c] -= q[4] * dx + cc * q[0];
-                        ra[3 * c + 1] -= q[4] * dy + cc * q[1];
-                        ra[3 * c + 2] -= q[4] * dz + cc * q[2];
-                    }
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < W; ++k) {
-                vr[a * W + k] = (float)ra[k];
-                vp[a * W + k] = (float)ra[k];
-                vx[a * W + k] = 0.f;
-            }
-#pragma unroll
-            for (int c = 0; c < NR; ++c)
-                rr[c] += ra[3 * c] * ra[3 * c] + ra[3 * c + 1] * ra[3 * c + 1] + ra[3 * c + 2] * ra[3 * c + 2];
+        for (int64_t a = lane; a < nf; a += 64) {
+            double ra[3];
+            residual_node(A, c, a, x64, b64, outer == 0, ra);
+            const float4 r4 = make_float4((float)ra[0], (float)ra[1], (float)ra[2], 0.f);
+            const float4 z4 = precond_apply(Pc + 2 * a, r4);
+            vr[a] = r4;
+            vz[a] = z4;
+            vp[a] = z4;
+            vd[a] = make_float4(0.f, 0.f, 0.f, 0.f);
+            rr += ra[0] * ra[0] + ra[1] * ra[1] + ra[2] * ra[2];
+            rz += dot3(r4, z4);
         }
-        block_sum<NR, NT>(rr, sh);
-        bool active[NR];
-        bool any = false;
-#pragma unroll
-        for (int k = 0; k < NR; ++k) {
-            if (!done[k] && rr[k] <= tol2 * bnorm2[k]) done[k] = true;
-            active[k] = !done[k];
-            any = any || active[k];
+        rr = uniformd(wsum(rr));
+        rz = uniformd(wsum(rz));
+        __syncthreads();
+        if (rr <= tol2 * bb) {
+            done = true;
+            break;
         }
-        if (!any) break;
         if (it_total >= maxit) {
             status = ST_CG_MAXITER;
             break;
         }
-        // inner CG: reduce the FP32 residual by 1e-3 (or to the final tolerance)
-        double rr0[NR];
-#pragma unroll
-        for (int k = 0; k < NR; ++k) rr0[k] = rr[k];
+        // inner preconditioned CG with FP32 products
+        const double rr0 = rr;
         for (;;) {
-            bool anyi = false;
-#pragma unroll
-            for (int k = 0; k < NR; ++k) anyi = anyi || active[k];
-            if (!anyi) break;
             if (it_total >= maxit) break;
             ++it_total;
-            double pq[NR];
-#pragma unroll
-            for (int k = 0; k < NR; ++k) pq[k] = 0.0;
+            // q = K p over the ELL records of each chunk
+            double pq = 0.0;
 #pragma unroll 1
-            for (int64_t a = tid; a < nf; a += NT) {
-                const float* Pa = vp + a * W;
-                float pa[W], q[W];
-#pragma unroll
-                for (int k = 0; k < W; ++k) {
-                    pa[k] = Pa[k];
-                    q[k] = 0.f;
-                }
+            for (int64_t ch = 0; ch < nch; ++ch) {
+                const int64_t a = 64 * ch + lane;
+                const int64_t c0 = uni64(A.chunk_rec[cf + ch]), w = (uni64(A.chunk_rec[cf + ch + 1]) - c0) >> 6;
+                const int64_t rb = c0 + lane;
+                if (a < nf) {
+                    const float4 pa = vp[a];
+                    float qx = 0.f, qy = 0.f, qz = 0.f;
+                    // w is a multiple of 4: issue 4 records' loads, then their gathers
 #pragma unroll 1
-                for (int64_t e = net.inc_off[a0 + a]; e < net.inc_off[a0 + a + 1]; ++e) {
-                    uint32_t w = net.inc[e];
-                    int64_t k = w & 0x7fffffffu;
-                    uint32_t en = net.ends[f0 + k];
-                    int o = (w >> 31) ? (int)(en >> 16) : (int)(en & 0xffff);
-                    const float* Po = vp + (o < nf ? o : nf) * (int64_t)W;
-                    float4 nA = par[2 * k];
-                    float g = par[2 * k + 1].x;
+                    for (int64_t s0 = 0; s0 < w; s0 += 4) {
+                        float4 nA[4];
+                        int2 ob[4];
+                        float4 po[4];
 #pragma unroll
-                    for (int c = 0; c < NR; ++c) {
-                        float wx, wy, wz;
-                        apply_B(nA, g, pa[3 * c] - Po[3 * c], pa[3 * c + 1] - Po[3 * c + 1],
-                                pa[3 * c + 2] - Po[3 * c + 2], wx, wy, wz);
-                        q[3 * c] += wx;
-                        q[3 * c + 1] += wy;
-                        q[3 * c + 2] += wz;
+                        for (int u = 0; u < 4; ++u) {
+                            nA[u] = recA[rb + 64 * (s0 + u)];
+                            ob[u] = recB[rb + 64 * (s0 + u)];
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) po[u] = vp[ob[u].x];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const float g = __int_as_float(ob[u].y);
+                            const float dx = pa.x - po[u].x, dy = pa.y - po[u].y, dz = pa.z - po[u].z;
+                            const float cn = (nA[u].w - g) * (nA[u].x * dx + nA[u].y * dy + nA[u].z * dz);
+                            qx += fmaf(g, dx, cn * nA[u].x);
+                            qy += fmaf(g, dy, cn * nA[u].y);
+                            qz += fmaf(g, dz, cn * nA[u].z);
+                        }
                     }
-                }
-                float* Q = vq + a * W;
-#pragma unroll
-                for (int k = 0; k < W; ++k) Q[k] = q[k];
-#pragma unroll
-                for (int c = 0; c < NR; ++c)
-                    pq[c] += (double)pa[3 * c] * q[3 * c] + (double)pa[3 * c + 1] * q[3 * c + 1] +
-                             (double)pa[3 * c + 2] * q[3 * c + 2];
-            }
-            block_sum<NR, NT>(pq, sh);
-            float alpha[NR];
-#pragma unroll
-            for (int k = 0; k < NR; ++k) {
-                alpha[k] = 0.f;
-                if (active[k]) {
-                    if (!(pq[k] > 0.0)) {
-                        active[k] = false;
-                        done[k] = true;
-                        status = ST_CG_INDEFINITE;
-                    } else {
-                        alpha[k] = (float)(rr[k] / pq[k]);
-                    }
+                    vq[a] = make_float4(qx, qy, qz, 0.f);
+                    pq += (double)pa.x * qx + (double)pa.y * qy + (double)pa.z * qz;
                 }
             }
-            double rn[NR];
-#pragma unroll
-            for (int k = 0; k < NR; ++k) rn[k] = 0.0;
+            pq = uniformd(wsum(pq));
+            if (!(pq > 0.0)) {
+                status = ST_CG_INDEFINITE;
+                done = true;
+                break;
+            }
+            const float alpha = (float)(rz / pq);
+            double rn = 0.0, rzn = 0.0;
 #pragma unroll 1
-            for (int64_t a = tid; a < nf; a += NT) {
-                float* X = vx + a * W;
-                float* R = vr + a * W;
-                const float* P = vp + a * W;
-                const float* Q = vq + a * W;
-#pragma unroll
-                for (int c = 0; c < NR; ++c)
-#pragma unroll
-                    for (int p = 0; p < 3; ++p) {
-                        int k = 3 * c + p;
-                        X[k] += alpha[c] * P[k];
-                        float rk = R[k] - alpha[c] * Q[k];
-                        R[k] = rk;
-                        rn[c] += (double)rk * rk;
-                    }
+            for (int64_t a = lane; a < nf; a += 64) {
+                const float4 pa = vp[a], qa = vq[a];
+                float4 da = vd[a], ra = vr[a];
+                da.x = fmaf(alpha, pa.x, da.x);
+                da.y = fmaf(alpha, pa.y, da.y);
+                da.z = fmaf(alpha, pa.z, da.z);
+                ra.x = fmaf(-alpha, qa.x, ra.x);
+                ra.y = fmaf(-alpha, qa.y, ra.y);
+                ra.z = fmaf(-alpha, qa.z, ra.z);
+                const float4 za = precond_apply(Pc + 2 * a, ra);
+                vd[a] = da;
+                vr[a] = ra;
+                vz[a] = za;
+                rn += dot3(ra, ra);
+                rzn += dot3(ra, za);
             }
-            block_sum<NR, NT>(rn, sh);
-            float beta[NR];
-#pragma unroll
-            for (int k = 0; k < NR; ++k) {
-                beta[k] = active[k] ? (float)(rn[k] / rr[k]) : 0.f;
-                if (active[k]) {
-                    rr[k] = rn[k];
-                    if (rn[k] <= 1e-6 * rr0[k] || rn[k] <= 0.25 * tol2 * bnorm2[k]) active[k] = false;
-                }
-            }
+            rn = uniformd(wsum(rn));
+            rzn = uniformd(wsum(rzn));
+            if (rn <= 1e-6 * rr0 || rn <= 0.25 * tol2 * bb) break;
+            const float beta = (float)(rzn / rz);
+            rz = rzn;
 #pragma unroll 1
-            for (int64_t a = tid; a < nf; a += NT) {
-                float* P = vp + a * W;
-                const float* R = vr + a * W;
-#pragma unroll
-                for (int c = 0; c < NR; ++c)
-#pragma unroll
-                    for (int p = 0; p < 3; ++p) P[3 * c + p] = R[3 * c + p] + beta[c] * P[3 * c + p];
+            for (int64_t a = lane; a < nf; a += 64) {
+                const float4 za = vz[a];
+                float4 pa = vp[a];
+                pa.x = fmaf(beta, pa.x, za.x);
+                pa.y = fmaf(beta, pa.y, za.y);
+                pa.z = fmaf(beta, pa.z, za.z);
+                vp[a] = pa;
             }
             __syncthreads();
         }
         // x += d
-#pragma unroll 1
-        for (int64_t a = tid; a < nf; a += NT)
-#pragma unroll
-            for (int k = 0; k < W; ++k) xb[a * W + k] += (double)vx[a * W + k];
         __syncthreads();
-        if (outer == 7) {
-            bool left = false;
-#pragma unroll
-            for (int k = 0; k < NR; ++k) left = left || !done[k];
-            if (left && status == ST_CONVERGED) status = ST_CG_MAXITER;
+#pragma unroll 1
+        for (int64_t a = lane; a < nf; a += 64) {
+            const float4 da = vd[a];
+            x64[3 * a] += (double)da.x;
+            x64[3 * a + 1] += (double)da.y;
+            x64[3 * a + 2] += (double)da.z;
         }
+        __syncthreads();
+        if (outer == 7 && !done && status == ST_CONVERGED) status = ST_CG_MAXITER;
     }
 
-    // assembly over fibers with a boundary end (FP64 operators)
-    const double V0 = net.V0[r];
-    double Finv[9];
-    {
-        double id = 1.0 / J;
-        Finv[0] = (F[4] * F[8] - F[5] * F[7]) * id;
-        Finv[1] = (F[2] * F[7] - F[1] * F[8]) * id;
-        Finv[2] = (F[1] * F[5] - F[2] * F[4]) * id;
-        Finv[3] = (F[5] * F[6] - F[3] * F[8]) * id;
-        Finv[4] = (F[0] * F[8] - F[2] * F[6]) * id;
-        Finv[5] = (F[2] * F[3] - F[0] * F[5]) * id;
-        Finv[6] = (F[3] * F[7] - F[4] * F[6]) * id;
-        Finv[7] = (F[1] * F[6] - F[0] * F[7]) * id;
-        Finv[8] = (F[0] * F[4] - F[1] * F[3]) * id;
-    }
-    double sig[9];
-    for (int k = 0; k < 9; ++k) sig[k] = A.sigma[9 * r + k];
-    if (NR == 9) {
-        for (int col = 0; col < 9; ++col) {
-            const int kk = col / 3, l = col % 3;
-            double acc[9];
+    double acc[9];
+    assembly_partial<TAN>(A, c, r, kk, ll, x64, lane, 64, acc);
 #pragma unroll
-            for (int p = 0; p < 9; ++p) acc[p] = 0.0;
-#pragma unroll 1
-            for (int64_t k = tid; k < nfib; k += NT) {
-                uint32_t en = net.ends[f0 + k];
-                int i = en & 0xffff, j = en >> 16;
-                if (i < nf && j < nf) continue;
-                FiberOp o = fiber_op(A, F, f0, a0, nf, k);
-                const double* d0 = net.d0 + 3 * (f0 + k);
-                double u[3] = {0, 0, 0};
-                u[kk] = d0[l];
-                for (int p = 0; p < 3; ++p) {
-                    if (j < nf) u[p] += xb[j * W + 3 * col + p];
-                    if (i < nf) u[p] -= xb[i * W + 3 * col + p];
-                }
-                double dn = o.nx * u[0] + o.ny * u[1] + o.nz * u[2];
-                double cc = (o.a - o.g) * dn;
-                double w[3] = {o.g * u[0] + cc * o.nx, o.g * u[1] + cc * o.ny, o.g * u[2] + cc * o.nz};
-                double fv[3] = {o.T * o.nx, o.T * o.ny, o.T * o.nz};
-                for (int end = 0; end < 2; ++end) {
-                    int node = end ? j : i;
-                    if (node < nf) continue;
-                    double s = end ? 1.0 : -1.0;
-                    const double* Xm = net.Xb + 3 * (b0 + (node - nf));
-                    double x[3];
-                    for (int p = 0; p < 3; ++p) x[p] = F[3 * p] * Xm[0] + F[3 * p + 1] * Xm[1] + F[3 * p + 2] * Xm[2];
-                    // df_b x_b^T + f_b (E Xm_b)^T, (E Xm_b) = e_kk Xm_b,l
-                    for (int p = 0; p < 3; ++p) {
-                        for (int q = 0; q < 3; ++q) acc[3 * p + q] += s * w[p] * x[q];
-                        acc[3 * p + kk] += s * fv[p] * Xm[l];
-                    }
-                }
-            }
-            block_sum<9, NT>(acc, sh);
-            if (tid < 9) out[9 * tid + col] = acc[tid] / (J * V0) - sig[tid] * Finv[3 * l + kk];
-        }
-    } else {
-        double gs = 0.0;
-        for (int k = 0; k < 9; ++k) gs += G[k] * sig[k];
-        double acc[9];
-#pragma unroll
-        for (int p = 0; p < 9; ++p) acc[p] = 0.0;
-#pragma unroll 1
-        for (int64_t k = tid; k < nfib; k += NT) {
-            uint32_t en = net.ends[f0 + k];
-            int i = en & 0xffff, j = en >> 16;
-            if (i < nf && j < nf) continue;
-            FiberOp o = fiber_op(A, F, f0, a0, nf, k);
-            // u = [-lambda; y]
-            double ui[3], uj[3];
-            for (int end = 0; end < 2; ++end) {
-                int node = end ? j : i;
-                double* u = end ? uj : ui;
-                if (node < nf) {
-                    for (int p = 0; p < 3; ++p) u[p] = -xb[node * W + p];
-                } else {
-                    const double* Xm = net.Xb + 3 * (b0 + (node - nf));
-                    double x[3];
-                    for (int p = 0; p < 3; ++p) x[p] = F[3 * p] * Xm[0] + F[3 * p + 1] * Xm[1] + F[3 * p + 2] * Xm[2];
-                    for (int p = 0; p < 3; ++p) u[p] = G[3 * p] * x[0] + G[3 * p + 1] * x[1] + G[3 * p + 2] * x[2];
-                }
-            }
-            double du[3] = {uj[0] - ui[0], uj[1] - ui[1], uj[2] - ui[2]};
-            double dn = o.nx * du[0] + o.ny * du[1] + o.nz * du[2];
-            double cc = (o.a - o.g) * dn;
-            double w[3] = {o.g * du[0] + cc * o.nx, o.g * du[1] + cc * o.ny, o.g * du[2] + cc * o.nz};
-            double fv[3] = {o.T * o.nx, o.T * o.ny, o.T * o.nz};
-            double gtf[3];
-            for (int p = 0; p < 3; ++p) gtf[p] = G[p] * fv[0] + G[3 + p] * fv[1] + G[6 + p] * fv[2];
-            for (int end = 0; end < 2; ++end) {
-                int node = end ? j : i;
-                if (node < nf) continue;
-                double s = end ? 1.0 : -1.0;
-                const double* Xm = net.Xb + 3 * (b0 + (node - nf));
-                for (int p = 0; p < 3; ++p)
-                    for (int q = 0; q < 3; ++q) acc[3 * p + q] += s * (w[p] + gtf[p]) * Xm[q];
-            }
-        }
-        block_sum<9, NT>(acc, sh);
-        if (tid < 9) {
-            int kk = tid / 3, l = tid % 3;
-            out[tid] = acc[tid] / (J * V0) - gs * Finv[3 * l + kk];
-        }
-    }
-    if (tid == 0) A.status[r] = status;
+    for (int p = 0; p < 9; ++p) acc[p] = wsum(acc[p]);
+    if (lane == 0) assembly_write<TAN>(A, r, col, acc, status, it_total);
     __syncthreads();
 }
 
-template <int NR, int NT>
-__global__ __launch_bounds__(NT) void cg_kernel(TangentArgs A)
+template <bool TAN>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void cg_wave_kernel(TangentArgs A)
 {
-    __shared__ double sh[9][NT / 64];
+    constexpr int per = TAN ? 9 : 1;
+    const int64_t n_tasks = A.n_order * per;
+    for (;;) {
+        int t = 0;
+        if (threadIdx.x == 0) t = atomicAdd(A.queue, 1);
+        t = __builtin_amdgcn_readfirstlane(__shfl(t, 0, 64));
+        if (t >= n_tasks) break;
+        cg_wave_task<TAN>(A, __builtin_amdgcn_readfirstlane(A.order[t / per]), t % per);
+    }
+}
+
+// ------------------------------------------------------------------ resident tasks
+// One workgroup of T threads per task; thread tid owns free nodes
+// tid + T k (k < SN), so wavefront w owns ELL chunks w + (T/64) k.  The
+// solver vectors of the inner solve stay in registers, the vector the
+// matrix-free product gathers is exchanged through LDS.
+//
+// The inner solve is plain preconditioned CG with a fresh product q = K p
+// every iteration: three workgroup barriers per iteration (p exchanged, p.q
+// summed, (r,r) and (r,z) summed).  Recurrence forms with one reduction (the
+// Chronopoulos-Gear update of q) lose the sign of p.Kp to FP32 cancellation
+// on these ill-conditioned systems.
+struct CgRed {
+    double s[2][3][16];   // per-wavefront partial sums, alternating buffers
+};
+
+template <int NW>
+__device__ __forceinline__ void block_sum3(CgRed& red, int parity, double& a, double& b, double& c)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    a = wsum(a);
+    b = wsum(b);
+    c = wsum(c);
+    if (lane == 0) {
+        red.s[parity][0][wave] = a;
+        red.s[parity][1][wave] = b;
+        red.s[parity][2][wave] = c;
+    }
+    __syncthreads();
+    double x = 0.0, y = 0.0, z = 0.0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        x += red.s[parity][0][i];
+        y += red.s[parity][1][i];
+        z += red.s[parity][2][i];
+    }
+    a = uniformd(x);
+    b = uniformd(y);
+    c = uniformd(z);
+}
+
+template <bool TAN, int T, int SN>
+__device__ void cg_res_task(const TangentArgs& A, int r, int col, float4* zl, CgRed& red)
+{
+    constexpr int NW = T / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (__builtin_amdgcn_readfirstlane(A.solve_status[r]) != 0) {
+        no_state<TAN>(A, r, col);
+        return;
+    }
+    const Ctx c = make_ctx(A, r);
+    const int64_t nf = c.nf;
+    const int kk = col / 3, ll = col % 3;
+    const float4* Pc = A.precond + 2 * c.a0;
+    const int64_t cf = uni64(A.chunk_first[r]);
+    const int64_t S = A.slot_nodes;
+    double* x64 = A.slot_ws64 + (int64_t)blockIdx.x * 6 * S;
+    double* b64 = x64 + 3 * S;
+
+    // ELL chunk of each slot (uniform over the wavefront); width 0 past the end
+    int64_t rb[SN];
+    int wd[SN];
+#pragma unroll
+    for (int k = 0; k < SN; ++k) {
+        const int64_t ch = wave + NW * k;
+        rb[k] = 0;
+        wd[k] = 0;
+        if (64 * ch < nf) {
+            const int64_t c0 = uni64(A.chunk_rec[cf + ch]);
+            wd[k] = (int)((uni64(A.chunk_rec[cf + ch + 1]) - c0) >> 6);
+            rb[k] = c0 + lane;
+        }
+    }
+    int parity = 0;
+
+    // right-hand side (FP64)
+    double bb = 0.0;
+    {
+        double F[9], G[9];
+        for (int k = 0; k < 9; ++k) F[k] = A.F[9 * r + k];
+        if (!TAN)
+            for (int k = 0; k < 9; ++k) G[k] = A.gsigma[9 * r + k];
+#pragma unroll 1
+        for (int k = 0; k < SN; ++k) {
+            const int64_t a = tid + T * k;
+            if (a < nf) {
+                double b[3];
+                rhs_node<TAN>(A, c, a, kk, ll, F, G, b);
+                for (int p = 0; p < 3; ++p) {
+                    b64[3 * a + p] = b[p];
+                    x64[3 * a + p] = 0.0;
+                }
+                bb += b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+            }
+        }
+        if (tid < 3) x64[3 * nf + tid] = 0.0;
+    }
+    {
+        double u0 = 0.0, u1 = 0.0;
+        block_sum3<NW>(red, parity, bb, u0, u1);
+        parity ^= 1;
+    }
+
+    float R[SN][3], Z[SN][3], P[SN][3], Q[SN][3], D[SN][3];
+    int status = ST_CONVERGED;
+    const double tol2 = A.cg_tol * A.cg_tol;
+    const int64_t maxit = A.cg_max > 0 ? A.cg_max : 6 * nf + 100;
+    int64_t it_total = 0;
+    bool done = !(bb > 0.0);
+    for (int outer = 0; outer < 8 && !done; ++outer) {
+        // FP64 residual of the FP64 solution (x64 complete: barrier above)
+        double rr = 0.0;
+#pragma unroll
+        for (int k = 0; k < SN; ++k) {
+            const int64_t a = tid + T * k;
+            double ra[3] = {0.0, 0.0, 0.0};
+            float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = p0;
+            if (a < nf) {
+                residual_node(A, c, a, x64, b64, outer == 0, ra);
+                p0 = Pc[2 * a];
+                p1 = Pc[2 * a + 1];
+            }
+            for (int p = 0; p < 3; ++p) {
+                R[k][p] = (float)ra[p];
+                P[k][p] = Q[k][p] = D[k][p] = 0.f;
+            }
+            rr += ra[0] * ra[0] + ra[1] * ra[1] + ra[2] * ra[2];
+            Z[k][0] = p0.x * R[k][0] + p0.y * R[k][1] + p0.z * R[k][2];
+            Z[k][1] = p0.y * R[k][0] + p0.w * R[k][1] + p1.x * R[k][2];
+            Z[k][2] = p0.z * R[k][0] + p1.x * R[k][1] + p1.y * R[k][2];
+        }
+        {
+            double u0 = 0.0, u1 = 0.0;
+            block_sum3<NW>(red, parity, rr, u0, u1);
+            parity ^= 1;
+        }
+        if (rr <= tol2 * bb) {
+            done = true;
+            break;
+        }
+        if (it_total >= maxit) {
+            status = ST_CG_MAXITER;
+            break;
+        }
+        // inner preconditioned CG (FP32 vectors in registers, p exchanged
+        // through LDS): p = z, then q = K p, alpha, update, beta
+        double rz = 0.0;
+#pragma unroll
+        for (int k = 0; k < SN; ++k)
+            for (int p = 0; p < 3; ++p) {
+                P[k][p] = Z[k][p];
+                rz += (double)R[k][p] * Z[k][p];
+            }
+        {
+            double u0 = 0.0, u1 = 0.0;
+            block_sum3<NW>(red, parity, rz, u0, u1);
+            parity ^= 1;
+        }
+        const double rr0 = rr;
+        for (;;) {
+            if (it_total >= maxit) break;
+            ++it_total;
+#pragma unroll
+            for (int k = 0; k < SN; ++k) zl[tid + T * k] = make_float4(P[k][0], P[k][1], P[k][2], 0.f);
+            __syncthreads();
+            double pq = 0.0;
+#pragma unroll
+            for (int k = 0; k < SN; ++k) {
+                float sx = 0.f, sy = 0.f, sz = 0.f;
+#pragma unroll 1
+                for (int s0 = 0; s0 < wd[k]; s0 += 4) {
+                    float4 nA[4];
+                    int2 ob[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        nA[u] = A.recA[rb[k] + 64 * (s0 + u)];
+                        ob[u] = A.recB[rb[k] + 64 * (s0 + u)];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const float4 po = zl[ob[u].x];
+                        const float g = __int_as_float(ob[u].y);
+                        const float dx = P[k][0] - po.x, dy = P[k][1] - po.y, dz = P[k][2] - po.z;
+                        const float cn = (nA[u].w - g) * (nA[u].x * dx + nA[u].y * dy + nA[u].z * dz);
+                        sx += fmaf(g, dx, cn * nA[u].x);
+                        sy += fmaf(g, dy, cn * nA[u].y);
+                        sz += fmaf(g, dz, cn * nA[u].z);
+                    }
+                }
+                Q[k][0] = sx;
+                Q[k][1] = sy;
+                Q[k][2] = sz;
+                pq += (double)P[k][0] * sx + (double)P[k][1] * sy + (double)P[k][2] * sz;
+            }
+            {
+                double u0 = 0.0, u1 = 0.0;
+                block_sum3<NW>(red, parity, pq, u0, u1);
+                parity ^= 1;
+            }
+            if (!(pq > 0.0)) {
+                status = ST_CG_INDEFINITE;
+                done = true;
+                break;
+            }
+            const float af = (float)(rz / pq);
+            double rn = 0.0, rzn = 0.0;
+#pragma unroll
+            for (int k = 0; k < SN; ++k) {
+                const int64_t a = tid + T * k;
+                float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = p0;
+                if (a < nf) {
+                    p0 = Pc[2 * a];
+                    p1 = Pc[2 * a + 1];
+                }
+                for (int p = 0; p < 3; ++p) {
+                    D[k][p] = fmaf(af, P[k][p], D[k][p]);
+                    R[k][p] = fmaf(-af, Q[k][p], R[k][p]);
+                }
+                Z[k][0] = p0.x * R[k][0] + p0.y * R[k][1] + p0.z * R[k][2];
+                Z[k][1] = p0.y * R[k][0] + p0.w * R[k][1] + p1.x * R[k][2];
+                Z[k][2] = p0.z * R[k][0] + p1.x * R[k][1] + p1.y * R[k][2];
+                for (int p = 0; p < 3; ++p) {
+                    rn += (double)R[k][p] * R[k][p];
+                    rzn += (double)R[k][p] * Z[k][p];
+                }
+            }
+            {
+                double u0 = 0.0;
+                block_sum3<NW>(red, parity, rn, rzn, u0);
+                parity ^= 1;
+            }
+            if (rn <= 1e-6 * rr0 || rn <= 0.25 * tol2 * bb) break;
+            const float bf = (float)(rzn / rz);
+            rz = rzn;
+#pragma unroll
+            for (int k = 0; k < SN; ++k)
+                for (int p = 0; p < 3; ++p) P[k][p] = fmaf(bf, P[k][p], Z[k][p]);
+        }
+        // x += d
+#pragma unroll
+        for (int k = 0; k < SN; ++k) {
+            const int64_t a = tid + T * k;
+            if (a < nf)
+                for (int p = 0; p < 3; ++p) x64[3 * a + p] += (double)D[k][p];
+        }
+        __syncthreads();
+        if (outer == 7 && !done && status == ST_CONVERGED) status = ST_CG_MAXITER;
+    }
+
+    // assembly (x64 complete: barrier above, or no update since the RHS sum)
+    double acc[9];
+    assembly_partial<TAN>(A, c, r, kk, ll, x64, tid, T, acc);
+    double tot[9];
+#pragma unroll
+    for (int p = 0; p < 9; p += 3) {
+        double a1 = acc[p], a2 = acc[p + 1], a3 = acc[p + 2];
+        block_sum3<NW>(red, parity, a1, a2, a3);
+        parity ^= 1;
+        tot[p] = a1;
+        tot[p + 1] = a2;
+        tot[p + 2] = a3;
+    }
+    if (tid == 0) assembly_write<TAN>(A, r, col, tot, status, it_total);
+    __syncthreads();
+}
+
+template <bool TAN, int T, int SN>
+__global__ __launch_bounds__(T) void cg_res_kernel(TangentArgs A)
+{
+    extern __shared__ float4 zl[];   // [T * SN + 1]; the last entry stays zero
+    __shared__ CgRed red;
     __shared__ int task;
+    if (threadIdx.x == 0) zl[T * SN] = make_float4(0.f, 0.f, 0.f, 0.f);
+    constexpr int per = TAN ? 9 : 1;
+    const int64_t n_tasks = A.n_order * per;
     for (;;) {
         if (threadIdx.x == 0) task = atomicAdd(A.queue, 1);
         __syncthreads();
         const int t = __builtin_amdgcn_readfirstlane(task);
         __syncthreads();
-        if (t >= A.n_rve) break;
-        cg_one<NR, NT>(A, t, sh);
+        if (t >= n_tasks) break;
+        cg_res_task<TAN, T, SN>(A, __builtin_amdgcn_readfirstlane(A.order[t / per]), t % per, zl, red);
+    }
+}
+
+__global__ void zero_status(int32_t* st, unsigned long long* it, int64_t n)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) {
+        st[i] = 0;
+        it[i] = 0;
+    }
+}
+
+template <bool TAN, int T, int SN>
+const void* res_fn()
+{
+    return (const void*)cg_res_kernel<TAN, T, SN>;
+}
+
+const void* res_kernel(int v, bool vjp)
+{
+    switch (v) {
+    case 0: return vjp ? res_fn<false, 256, 2>() : res_fn<true, 256, 2>();
+    case 1: return vjp ? res_fn<false, 512, 2>() : res_fn<true, 512, 2>();
+    default: return vjp ? res_fn<false, 1024, 2>() : res_fn<true, 1024, 2>();
     }
 }
 
 }  // namespace
 
-hipError_t launch_tangent(const TangentArgs& a, int grid, hipStream_t s)
+const TangentVariant kTanRes[kNumTanRes] = {{256, 2}, {512, 2}, {1024, 2}};
+
+hipError_t launch_tangent_prep(const TangentArgs& a, hipStream_t s)
 {
-    if (a.mode == 0)
-        hipLaunchKernelGGL((cg_kernel<9, 256>), dim3(grid), dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL((cg_kernel<1, 256>), dim3(grid), dim3(256), 0, s, a);
+    if (a.n_rve <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_status, dim3((unsigned)((a.n_rve + 255) / 256)), dim3(256), 0, s, a.status, a.iters, a.n_rve);
+    if (a.build_static) hipLaunchKernelGGL(ell_build_kernel, dim3((unsigned)a.n_rve), dim3(kOpsThreads), 0, s, a);
+    hipLaunchKernelGGL(fiber_ops_kernel, dim3((unsigned)a.n_rve), dim3(kOpsThreads), 0, s, a);
     return hipGetLastError();
+}
+
+hipError_t launch_tangent_wave(const TangentArgs& a, int grid, hipStream_t s)
+{
+    if (a.n_order <= 0) return hipSuccess;
+    if (a.mode == 0)
+        hipLaunchKernelGGL(cg_wave_kernel<true>, dim3(grid), dim3(64), 0, s, a);
+    else
+        hipLaunchKernelGGL(cg_wave_kernel<false>, dim3(grid), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+static size_t res_lds(int v)
+{
+    return 16 * ((size_t)kTanRes[v].threads * kTanRes[v].sn + 1);
+}
+
+hipError_t tangent_res_blocks(int v, bool vjp, int* blocks_per_cu)
+{
+    if (v < 0 || v >= kNumTanRes) return hipErrorInvalidValue;
+    const void* k = res_kernel(v, vjp);
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)res_lds(v));
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, kTanRes[v].threads, res_lds(v));
+}
+
+hipError_t launch_tangent_res(int v, const TangentArgs& a, int grid, hipStream_t s)
+{
+    if (v < 0 || v >= kNumTanRes) return hipErrorInvalidValue;
+    if (a.n_order <= 0) return hipSuccess;
+    const void* k = res_kernel(v, a.mode != 0);
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)res_lds(v));
+    if (e != hipSuccess) return e;
+    void* args[] = {const_cast<TangentArgs*>(&a)};
+    return hipLaunchKernel(k, dim3(grid), dim3(kTanRes[v].threads), args, res_lds(v), s);
 }
 
 }  // namespace rve
