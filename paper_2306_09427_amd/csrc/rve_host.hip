@@ -1060,6 +1060,7 @@ static int run_cg(rve_batch* b, int mode, const double* gsigma, double* out, int
     int grid[kNumTanRes + 1];
     int64_t S[kNumTanRes + 1];
     size_t slot_bytes = 0;
+    const int stream_threads = b->opts.engine == RVE_ENGINE_AUTO ? 1024 : 64;
     for (int v = 0; v <= kNumTanRes; ++v) {
         const int64_t tasks = (gf[v + 1] - gf[v]) * per;
         grid[v] = 0;
@@ -1071,9 +1072,11 @@ static int run_cg(rve_batch* b, int mode, const double* gsigma, double* out, int
             if (bpc < 1) return fail(RVE_EDEVICE, "tangent kernel does not fit a compute unit");
             grid[v] = (int)std::min<int64_t>((int64_t)bpc * b->n_cu, tasks);
             S[v] = (int64_t)kTanRes[v].threads * kTanRes[v].sn + 1;
-            slot_bytes = std::max(slot_bytes, 48 * (size_t)S[v] * (size_t)grid[v]);
+            slot_bytes = std::max(slot_bytes, 64 * (size_t)S[v] * (size_t)grid[v]);
         } else {
-            grid[v] = (int)std::min<int64_t>((int64_t)b->n_cu * 8, tasks);
+            // streamed: one 1024-thread workgroup per CU for the RVEs too large
+            // for LDS, or one wavefront per task (8 per CU) on the STREAMED engine
+            grid[v] = (int)std::min<int64_t>((int64_t)b->n_cu * (stream_threads == 64 ? 8 : 1), tasks);
             for (int64_t r = 0; r < b->R; ++r) S[v] = std::max<int64_t>(S[v], b->nf_of[r] + 1);
             slot_bytes = std::max(slot_bytes, 128 * (size_t)S[v] * (size_t)grid[v]);
         }
@@ -1117,7 +1120,7 @@ static int run_cg(rve_batch* b, int mode, const double* gsigma, double* out, int
     for (int v = 0; v <= kNumTanRes; ++v) {
         if (grid[v] == 0) continue;
         // every RVE of the launch must fit its slot (and, resident, its LDS)
-        const size_t need = (v < kNumTanRes ? 48 : 128) * (size_t)S[v] * (size_t)grid[v];
+        const size_t need = (v < kNumTanRes ? 64 : 128) * (size_t)S[v] * (size_t)grid[v];
         if (need > b->t_slot_bytes || b->t_max_nf[v] >= S[v])
             return fail(RVE_EINVAL, "internal: tangent slot smaller than an RVE of its group");
         a.order = b->t_order + gf[v];
@@ -1128,7 +1131,7 @@ static int run_cg(rve_batch* b, int mode, const double* gsigma, double* out, int
         if (v < kNumTanRes)
             HIP_TRY(launch_tangent_res(v, a, grid[v], s));
         else
-            HIP_TRY(launch_tangent_wave(a, grid[v], s));
+            HIP_TRY(launch_tangent_stream(a, stream_threads, grid[v], s));
     }
     HIP_TRY(hipMemcpyAsync(out, b->t_out, (mode == 0 ? 648 : 72) * b->R, out_kind, s));
     HIP_TRY(hipMemcpyAsync(status, b->t_status, 4 * b->R, out_kind, s));

@@ -78,7 +78,8 @@ struct TangentArgs {
     int2* recB;                  // [NREC] (other end, bits of FP32 T/l)
     float4* precond;             // [NFREE][2] inverse 3x3 diagonal block: (00, 01, 02, 11), (12, 22, -, -)
     double* par64;               // [NF][6] FP64 fiber operators: n, k_t/L0, T/l, T
-    double* slot_ws64;           // [grid][2][3 slot_nodes] per-workgroup FP64 x and b
+    double* slot_ws64;           // per workgroup: FP64 x and b [3 slot_nodes] each (resident
+                                 // kernels: then FP32 d [slot_nodes] float4)
     float4* slot_ws32;           // [grid][5][slot_nodes] per-wavefront FP32 p, q, r, d, z (wave kernel)
     int64_t slot_nodes;          // free-node capacity of a slot + 1
     int32_t build_static;        // 1: fill rec_static from the incidence first
@@ -104,16 +105,17 @@ hipError_t launch_stress(const SolveArgs& a, int n_rve, hipStream_t s);
 hipError_t launch_reset(int32_t* counters, int n, hipStream_t s);   // n <= 64
 // Tangent / VJP.  prep: statuses, ELL records (first call), fiber operators
 // and preconditioner for every RVE.  Then the tasks of the RVEs in a.order:
-// register/LDS-resident workgroups (variant v, RVEs with fewer than
-// threads * slots free nodes) or one wavefront per task (any size).
+// register/LDS-resident workgroups (variant v, RVEs with at most
+// threads * sn free nodes) or streamed workgroups of 64 or 1024 threads with
+// the vectors in global slots (any size).
 struct TangentVariant {
     int threads, sn;
 };
-constexpr int kNumTanRes = 3;
+constexpr int kNumTanRes = 5;
 extern const TangentVariant kTanRes[kNumTanRes];
 hipError_t launch_tangent_prep(const TangentArgs& a, hipStream_t s);
 hipError_t launch_tangent_res(int variant, const TangentArgs& a, int grid, hipStream_t s);
-hipError_t launch_tangent_wave(const TangentArgs& a, int grid, hipStream_t s);
+hipError_t launch_tangent_stream(const TangentArgs& a, int threads, int grid, hipStream_t s);
 hipError_t tangent_res_blocks(int variant, bool vjp, int* blocks_per_cu);
 hipError_t max_resident_blocks(int variant, bool fp64, size_t lds_bytes, int* blocks_per_cu);
 // Private (spill) bytes per lane of a resident variant; > 0 means it spills.

@@ -420,14 +420,60 @@ __device__ void assembly_write(const TangentArgs& A, int r, int col, const doubl
     atomicAdd(&A.iters[r], (unsigned long long)iters);
 }
 
-// ------------------------------------------------------------------ wavefront tasks
-// A task is (RVE r, right-hand side col): col = 3k + l for the tangent, 0 for
-// the VJP.  One wavefront; lane = node within a chunk of 64.  Solver vectors
-// live in a per-wavefront global slot (any RVE size).
-template <bool TAN>
-__device__ void cg_wave_task(const TangentArgs& A, int r, int col)
+// ------------------------------------------------------------------ workgroup sums
+struct CgRed {
+    double s[2][3][16];   // per-wavefront partial sums, alternating buffers
+};
+
+template <int NW>
+__device__ __forceinline__ void block_sum3(CgRed& red, int parity, double& a, double& b, double& c)
 {
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    a = wsum(a);
+    b = wsum(b);
+    c = wsum(c);
+    if (lane == 0) {
+        red.s[parity][0][wave] = a;
+        red.s[parity][1][wave] = b;
+        red.s[parity][2][wave] = c;
+    }
+    __syncthreads();
+    double x = 0.0, y = 0.0, z = 0.0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        x += red.s[parity][0][i];
+        y += red.s[parity][1][i];
+        z += red.s[parity][2][i];
+    }
+    a = uniformd(x);
+    b = uniformd(y);
+    c = uniformd(z);
+}
+
+// ------------------------------------------------------------------ streamed tasks
+// A task is (RVE r, right-hand side col): col = 3k + l for the tangent, 0 for
+// the VJP.  One workgroup of T threads (T = 64: one wavefront); wavefront w
+// takes ELL chunks w, w + T/64, ... and lane = node within its chunk.
+// Solver vectors live in the workgroup's global slot (any RVE size).
+template <bool TAN, int T>
+__device__ void cg_stream_task(const TangentArgs& A, int r, int col, CgRed& red)
+{
+    constexpr int NW = T / 64;
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    int parity = 0;
+    // sums over the workgroup (every thread gets the same totals)
+    auto sum2 = [&](double& x, double& y) __attribute__((always_inline)) {
+        if (T == 64) {
+            x = uniformd(wsum(x));
+            y = uniformd(wsum(y));
+        } else {
+            double z = 0.0;
+            block_sum3<NW>(red, parity, x, y, z);
+            parity ^= 1;
+        }
+    };
     if (__builtin_amdgcn_readfirstlane(A.solve_status[r]) != 0) {
         no_state<TAN>(A, r, col);
         return;
@@ -450,8 +496,8 @@ __device__ void cg_wave_task(const TangentArgs& A, int r, int col)
     float4* vr = vq + S;
     float4* vd = vr + S;
     float4* vz = vd + S;
-    if (lane == 0) vp[nf] = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (lane < 3) x64[3 * nf + lane] = 0.0;
+    if (tid == 0) vp[nf] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (tid < 3) x64[3 * nf + tid] = 0.0;
 
     double bb = 0.0;
     {
@@ -460,7 +506,7 @@ __device__ void cg_wave_task(const TangentArgs& A, int r, int col)
         if (!TAN)
             for (int k = 0; k < 9; ++k) G[k] = A.gsigma[9 * r + k];
 #pragma unroll 1
-        for (int64_t a = lane; a < nf; a += 64) {
+        for (int64_t a = tid; a < nf; a += T) {
             double b[3];
             rhs_node<TAN>(A, c, a, kk, ll, F, G, b);
             for (int p = 0; p < 3; ++p) {
@@ -470,7 +516,10 @@ __device__ void cg_wave_task(const TangentArgs& A, int r, int col)
             bb += b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
         }
     }
-    bb = uniformd(wsum(bb));
+    {
+        double u = 0.0;
+        sum2(bb, u);
+    }
     __syncthreads();
 
     int status = ST_CONVERGED;
@@ -482,7 +531,7 @@ __device__ void cg_wave_task(const TangentArgs& A, int r, int col)
         // FP64 residual r = b - K x of the FP64 solution; z = P r, p = z
         double rr = 0.0, rz = 0.0;
 #pragma unroll 1
-        for (int64_t a = lane; a < nf; a += 64) {
+        for (int64_t a = tid; a < nf; a += T) {
             double ra[3];
             residual_node(A, c, a, x64, b64, outer == 0, ra);
             const float4 r4 = make_float4((float)ra[0], (float)ra[1], (float)ra[2], 0.f);
@@ -494,8 +543,7 @@ __device__ void cg_wave_task(const TangentArgs& A, int r, int col)
             rr += ra[0] * ra[0] + ra[1] * ra[1] + ra[2] * ra[2];
             rz += dot3(r4, z4);
         }
-        rr = uniformd(wsum(rr));
-        rz = uniformd(wsum(rz));
+        sum2(rr, rz);
         __syncthreads();
         if (rr <= tol2 * bb) {
             done = true;
@@ -513,7 +561,7 @@ __device__ void cg_wave_task(const TangentArgs& A, int r, int col)
             // q = K p over the ELL records of each chunk
             double pq = 0.0;
 #pragma unroll 1
-            for (int64_t ch = 0; ch < nch; ++ch) {
+            for (int64_t ch = wave; ch < nch; ch += NW) {
                 const int64_t a = 64 * ch + lane;
                 const int64_t c0 = uni64(A.chunk_rec[cf + ch]), w = (uni64(A.chunk_rec[cf + ch + 1]) - c0) >> 6;
                 const int64_t rb = c0 + lane;
@@ -547,7 +595,10 @@ __device__ void cg_wave_task(const TangentArgs& A, int r, int col)
                     pq += (double)pa.x * qx + (double)pa.y * qy + (double)pa.z * qz;
                 }
             }
-            pq = uniformd(wsum(pq));
+            {
+                double u = 0.0;
+                sum2(pq, u);
+            }
             if (!(pq > 0.0)) {
                 status = ST_CG_INDEFINITE;
                 done = true;
@@ -556,7 +607,7 @@ __device__ void cg_wave_task(const TangentArgs& A, int r, int col)
             const float alpha = (float)(rz / pq);
             double rn = 0.0, rzn = 0.0;
 #pragma unroll 1
-            for (int64_t a = lane; a < nf; a += 64) {
+            for (int64_t a = tid; a < nf; a += T) {
                 const float4 pa = vp[a], qa = vq[a];
                 float4 da = vd[a], ra = vr[a];
                 da.x = fmaf(alpha, pa.x, da.x);
@@ -572,13 +623,12 @@ __device__ void cg_wave_task(const TangentArgs& A, int r, int col)
                 rn += dot3(ra, ra);
                 rzn += dot3(ra, za);
             }
-            rn = uniformd(wsum(rn));
-            rzn = uniformd(wsum(rzn));
+            sum2(rn, rzn);
             if (rn <= 1e-6 * rr0 || rn <= 0.25 * tol2 * bb) break;
             const float beta = (float)(rzn / rz);
             rz = rzn;
 #pragma unroll 1
-            for (int64_t a = lane; a < nf; a += 64) {
+            for (int64_t a = tid; a < nf; a += T) {
                 const float4 za = vz[a];
                 float4 pa = vp[a];
                 pa.x = fmaf(beta, pa.x, za.x);
@@ -591,7 +641,7 @@ __device__ void cg_wave_task(const TangentArgs& A, int r, int col)
         // x += d
         __syncthreads();
 #pragma unroll 1
-        for (int64_t a = lane; a < nf; a += 64) {
+        for (int64_t a = tid; a < nf; a += T) {
             const float4 da = vd[a];
             x64[3 * a] += (double)da.x;
             x64[3 * a + 1] += (double)da.y;
@@ -602,24 +652,35 @@ __device__ void cg_wave_task(const TangentArgs& A, int r, int col)
     }
 
     double acc[9];
-    assembly_partial<TAN>(A, c, r, kk, ll, x64, lane, 64, acc);
+    assembly_partial<TAN>(A, c, r, kk, ll, x64, tid, T, acc);
+    if (T == 64) {
 #pragma unroll
-    for (int p = 0; p < 9; ++p) acc[p] = wsum(acc[p]);
-    if (lane == 0) assembly_write<TAN>(A, r, col, acc, status, it_total);
+        for (int p = 0; p < 9; ++p) acc[p] = wsum(acc[p]);
+    } else {
+#pragma unroll
+        for (int p = 0; p < 9; p += 3) {
+            block_sum3<NW>(red, parity, acc[p], acc[p + 1], acc[p + 2]);
+            parity ^= 1;
+        }
+    }
+    if (tid == 0) assembly_write<TAN>(A, r, col, acc, status, it_total);
     __syncthreads();
 }
 
-template <bool TAN>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void cg_wave_kernel(TangentArgs A)
+template <bool TAN, int T>
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) void cg_stream_kernel(TangentArgs A)
 {
+    __shared__ CgRed red;
+    __shared__ int task;
     constexpr int per = TAN ? 9 : 1;
     const int64_t n_tasks = A.n_order * per;
     for (;;) {
-        int t = 0;
-        if (threadIdx.x == 0) t = atomicAdd(A.queue, 1);
-        t = __builtin_amdgcn_readfirstlane(__shfl(t, 0, 64));
+        if (threadIdx.x == 0) task = atomicAdd(A.queue, 1);
+        __syncthreads();
+        const int t = __builtin_amdgcn_readfirstlane(task);
+        __syncthreads();
         if (t >= n_tasks) break;
-        cg_wave_task<TAN>(A, __builtin_amdgcn_readfirstlane(A.order[t / per]), t % per);
+        cg_stream_task<TAN, T>(A, __builtin_amdgcn_readfirstlane(A.order[t / per]), t % per, red);
     }
 }
 
@@ -634,40 +695,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void cg
 // summed, (r,r) and (r,z) summed).  Recurrence forms with one reduction (the
 // Chronopoulos-Gear update of q) lose the sign of p.Kp to FP32 cancellation
 // on these ill-conditioned systems.
-struct CgRed {
-    double s[2][3][16];   // per-wavefront partial sums, alternating buffers
-};
-
-template <int NW>
-__device__ __forceinline__ void block_sum3(CgRed& red, int parity, double& a, double& b, double& c)
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    a = wsum(a);
-    b = wsum(b);
-    c = wsum(c);
-    if (lane == 0) {
-        red.s[parity][0][wave] = a;
-        red.s[parity][1][wave] = b;
-        red.s[parity][2][wave] = c;
-    }
-    __syncthreads();
-    double x = 0.0, y = 0.0, z = 0.0;
-#pragma unroll
-    for (int i = 0; i < NW; ++i) {
-        x += red.s[parity][0][i];
-        y += red.s[parity][1][i];
-        z += red.s[parity][2][i];
-    }
-    a = uniformd(x);
-    b = uniformd(y);
-    c = uniformd(z);
-}
-
-template <bool TAN, int T, int SN>
+template <bool TAN, int T, int SN, bool PL>
 __device__ void cg_res_task(const TangentArgs& A, int r, int col, float4* zl, CgRed& red)
 {
     constexpr int NW = T / 64;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // thread id made opaque per task: otherwise the compiler hoists every
+    // per-thread address of every slot out of the persistent task loop and
+    // keeps them live (spilled) across the whole kernel
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     if (__builtin_amdgcn_readfirstlane(A.solve_status[r]) != 0) {
         no_state<TAN>(A, r, col);
         return;
@@ -678,11 +715,15 @@ __device__ void cg_res_task(const TangentArgs& A, int r, int col, float4* zl, Cg
     const float4* Pc = A.precond + 2 * c.a0;
     const int64_t cf = uni64(A.chunk_first[r]);
     const int64_t S = A.slot_nodes;
-    double* x64 = A.slot_ws64 + (int64_t)blockIdx.x * 6 * S;
+    double* x64 = A.slot_ws64 + (int64_t)blockIdx.x * 8 * S;   // x, b (3 S each), d32 (S float4)
     double* b64 = x64 + 3 * S;
 
-    // ELL chunk of each slot (uniform over the wavefront); width 0 past the end
-    int64_t rb[SN];
+    // ELL chunk of each slot (uniform over the wavefront); width 0 past the
+    // end.  Record offsets are 32-bit, relative to the RVE's first record.
+    const int64_t rec0 = uni64(A.chunk_rec[cf]);
+    const float4* recA = A.recA + rec0;
+    const int2* recB = A.recB + rec0;
+    int rb[SN];
     int wd[SN];
 #pragma unroll
     for (int k = 0; k < SN; ++k) {
@@ -692,7 +733,7 @@ __device__ void cg_res_task(const TangentArgs& A, int r, int col, float4* zl, Cg
         if (64 * ch < nf) {
             const int64_t c0 = uni64(A.chunk_rec[cf + ch]);
             wd[k] = (int)((uni64(A.chunk_rec[cf + ch + 1]) - c0) >> 6);
-            rb[k] = c0 + lane;
+            rb[k] = (int)(c0 - rec0) + lane;
         }
     }
     int parity = 0;
@@ -725,37 +766,64 @@ __device__ void cg_res_task(const TangentArgs& A, int r, int col, float4* zl, Cg
         parity ^= 1;
     }
 
-    float R[SN][3], Z[SN][3], P[SN][3], Q[SN][3], D[SN][3];
+    // Register state per node slot: r and q; unless PL also z, p and d.
+    // PL (lean, for large SN): p lives only in LDS, the correction d in the
+    // workgroup's global slot (d32), and z = P r is recomputed where needed.
+    float R[SN][3], Q[SN][3];
+    float Z[PL ? 1 : SN][3], P[PL ? 1 : SN][3], D[PL ? 1 : SN][3];
+    float4* d32 = reinterpret_cast<float4*>(b64 + 3 * S);   // [S] (PL only)
+    auto own_p = [&](int k) __attribute__((always_inline)) -> float4 {
+        return PL ? zl[tid + T * k] : make_float4(P[k][0], P[k][1], P[k][2], 0.f);
+    };
+    // z = P_a r for slot k (block reloaded every time: keeping the blocks of
+    // all slots live across the loop costs 8 registers per slot)
+    auto precond_r = [&](int k) __attribute__((always_inline)) -> float4 {
+        const int64_t a = tid + T * k;
+        float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = p0;
+        if (a < nf) {
+            const float4* pp = Pc + 2 * a;
+            asm volatile("" : "+v"(pp));
+            p0 = pp[0];
+            p1 = pp[1];
+        }
+        return make_float4(p0.x * R[k][0] + p0.y * R[k][1] + p0.z * R[k][2],
+                           p0.y * R[k][0] + p0.w * R[k][1] + p1.x * R[k][2],
+                           p0.z * R[k][0] + p1.x * R[k][1] + p1.y * R[k][2], 0.f);
+    };
     int status = ST_CONVERGED;
     const double tol2 = A.cg_tol * A.cg_tol;
     const int64_t maxit = A.cg_max > 0 ? A.cg_max : 6 * nf + 100;
     int64_t it_total = 0;
     bool done = !(bb > 0.0);
     for (int outer = 0; outer < 8 && !done; ++outer) {
-        // FP64 residual of the FP64 solution (x64 complete: barrier above)
-        double rr = 0.0;
+        // FP64 residual of the FP64 solution (x64 complete: barrier above);
+        // d = 0, p = z = P r
+        double rr = 0.0, rz = 0.0;
 #pragma unroll
         for (int k = 0; k < SN; ++k) {
             const int64_t a = tid + T * k;
             double ra[3] = {0.0, 0.0, 0.0};
-            float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = p0;
-            if (a < nf) {
-                residual_node(A, c, a, x64, b64, outer == 0, ra);
-                p0 = Pc[2 * a];
-                p1 = Pc[2 * a + 1];
-            }
+            if (a < nf) residual_node(A, c, a, x64, b64, outer == 0, ra);
             for (int p = 0; p < 3; ++p) {
                 R[k][p] = (float)ra[p];
-                P[k][p] = Q[k][p] = D[k][p] = 0.f;
+                Q[k][p] = 0.f;
             }
             rr += ra[0] * ra[0] + ra[1] * ra[1] + ra[2] * ra[2];
-            Z[k][0] = p0.x * R[k][0] + p0.y * R[k][1] + p0.z * R[k][2];
-            Z[k][1] = p0.y * R[k][0] + p0.w * R[k][1] + p1.x * R[k][2];
-            Z[k][2] = p0.z * R[k][0] + p1.x * R[k][1] + p1.y * R[k][2];
+            const float4 z = precond_r(k);
+            rz += (double)R[k][0] * z.x + (double)R[k][1] * z.y + (double)R[k][2] * z.z;
+            if (PL) {
+                zl[tid + T * k] = z;
+                if (a < nf) d32[a] = make_float4(0.f, 0.f, 0.f, 0.f);
+            } else {
+                Z[k][0] = P[k][0] = z.x;
+                Z[k][1] = P[k][1] = z.y;
+                Z[k][2] = P[k][2] = z.z;
+                D[k][0] = D[k][1] = D[k][2] = 0.f;
+            }
         }
         {
-            double u0 = 0.0, u1 = 0.0;
-            block_sum3<NW>(red, parity, rr, u0, u1);
+            double u0 = 0.0;
+            block_sum3<NW>(red, parity, rr, rz, u0);
             parity ^= 1;
         }
         if (rr <= tol2 * bb) {
@@ -766,45 +834,39 @@ __device__ void cg_res_task(const TangentArgs& A, int r, int col, float4* zl, Cg
             status = ST_CG_MAXITER;
             break;
         }
-        // inner preconditioned CG (FP32 vectors in registers, p exchanged
-        // through LDS): p = z, then q = K p, alpha, update, beta
-        double rz = 0.0;
-#pragma unroll
-        for (int k = 0; k < SN; ++k)
-            for (int p = 0; p < 3; ++p) {
-                P[k][p] = Z[k][p];
-                rz += (double)R[k][p] * Z[k][p];
-            }
-        {
-            double u0 = 0.0, u1 = 0.0;
-            block_sum3<NW>(red, parity, rz, u0, u1);
-            parity ^= 1;
-        }
+        // inner preconditioned CG (FP32 vectors, p exchanged through LDS):
+        // q = K p, alpha = rz / p.q, d += alpha p, r -= alpha q, z = P r,
+        // beta = r.z / rz, p = z + beta p
         const double rr0 = rr;
         for (;;) {
             if (it_total >= maxit) break;
             ++it_total;
+            if (!PL) {
 #pragma unroll
-            for (int k = 0; k < SN; ++k) zl[tid + T * k] = make_float4(P[k][0], P[k][1], P[k][2], 0.f);
+                for (int k = 0; k < SN; ++k) zl[tid + T * k] = make_float4(P[k][0], P[k][1], P[k][2], 0.f);
+            }
             __syncthreads();
             double pq = 0.0;
 #pragma unroll
             for (int k = 0; k < SN; ++k) {
+                const float4 pk = own_p(k);
                 float sx = 0.f, sy = 0.f, sz = 0.f;
+                // records in groups of RB (chunk widths are multiples of 4)
+                constexpr int RB = SN > 2 ? 2 : 4;
 #pragma unroll 1
-                for (int s0 = 0; s0 < wd[k]; s0 += 4) {
-                    float4 nA[4];
-                    int2 ob[4];
+                for (int s0 = 0; s0 < wd[k]; s0 += RB) {
+                    float4 nA[RB];
+                    int2 ob[RB];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        nA[u] = A.recA[rb[k] + 64 * (s0 + u)];
-                        ob[u] = A.recB[rb[k] + 64 * (s0 + u)];
+                    for (int u = 0; u < RB; ++u) {
+                        nA[u] = recA[rb[k] + 64 * (s0 + u)];
+                        ob[u] = recB[rb[k] + 64 * (s0 + u)];
                     }
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
+                    for (int u = 0; u < RB; ++u) {
                         const float4 po = zl[ob[u].x];
                         const float g = __int_as_float(ob[u].y);
-                        const float dx = P[k][0] - po.x, dy = P[k][1] - po.y, dz = P[k][2] - po.z;
+                        const float dx = pk.x - po.x, dy = pk.y - po.y, dz = pk.z - po.z;
                         const float cn = (nA[u].w - g) * (nA[u].x * dx + nA[u].y * dy + nA[u].z * dz);
                         sx += fmaf(g, dx, cn * nA[u].x);
                         sy += fmaf(g, dy, cn * nA[u].y);
@@ -814,7 +876,7 @@ __device__ void cg_res_task(const TangentArgs& A, int r, int col, float4* zl, Cg
                 Q[k][0] = sx;
                 Q[k][1] = sy;
                 Q[k][2] = sz;
-                pq += (double)P[k][0] * sx + (double)P[k][1] * sy + (double)P[k][2] * sz;
+                pq += (double)pk.x * sx + (double)pk.y * sy + (double)pk.z * sz;
             }
             {
                 double u0 = 0.0, u1 = 0.0;
@@ -830,23 +892,30 @@ __device__ void cg_res_task(const TangentArgs& A, int r, int col, float4* zl, Cg
             double rn = 0.0, rzn = 0.0;
 #pragma unroll
             for (int k = 0; k < SN; ++k) {
-                const int64_t a = tid + T * k;
-                float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = p0;
-                if (a < nf) {
-                    p0 = Pc[2 * a];
-                    p1 = Pc[2 * a + 1];
+                const float4 pk = own_p(k);
+                if (PL) {
+                    const int64_t a = tid + T * k;
+                    if (a < nf) {
+                        float4 d = d32[a];
+                        d.x = fmaf(af, pk.x, d.x);
+                        d.y = fmaf(af, pk.y, d.y);
+                        d.z = fmaf(af, pk.z, d.z);
+                        d32[a] = d;
+                    }
+                } else {
+                    D[k][0] = fmaf(af, pk.x, D[k][0]);
+                    D[k][1] = fmaf(af, pk.y, D[k][1]);
+                    D[k][2] = fmaf(af, pk.z, D[k][2]);
                 }
-                for (int p = 0; p < 3; ++p) {
-                    D[k][p] = fmaf(af, P[k][p], D[k][p]);
-                    R[k][p] = fmaf(-af, Q[k][p], R[k][p]);
+                for (int p = 0; p < 3; ++p) R[k][p] = fmaf(-af, Q[k][p], R[k][p]);
+                const float4 z = precond_r(k);
+                if (!PL) {
+                    Z[k][0] = z.x;
+                    Z[k][1] = z.y;
+                    Z[k][2] = z.z;
                 }
-                Z[k][0] = p0.x * R[k][0] + p0.y * R[k][1] + p0.z * R[k][2];
-                Z[k][1] = p0.y * R[k][0] + p0.w * R[k][1] + p1.x * R[k][2];
-                Z[k][2] = p0.z * R[k][0] + p1.x * R[k][1] + p1.y * R[k][2];
-                for (int p = 0; p < 3; ++p) {
-                    rn += (double)R[k][p] * R[k][p];
-                    rzn += (double)R[k][p] * Z[k][p];
-                }
+                rn += (double)R[k][0] * R[k][0] + (double)R[k][1] * R[k][1] + (double)R[k][2] * R[k][2];
+                rzn += (double)R[k][0] * z.x + (double)R[k][1] * z.y + (double)R[k][2] * z.z;
             }
             {
                 double u0 = 0.0;
@@ -857,15 +926,30 @@ __device__ void cg_res_task(const TangentArgs& A, int r, int col, float4* zl, Cg
             const float bf = (float)(rzn / rz);
             rz = rzn;
 #pragma unroll
-            for (int k = 0; k < SN; ++k)
-                for (int p = 0; p < 3; ++p) P[k][p] = fmaf(bf, P[k][p], Z[k][p]);
+            for (int k = 0; k < SN; ++k) {
+                if (PL) {
+                    const float4 z = precond_r(k);
+                    const float4 pk = zl[tid + T * k];
+                    zl[tid + T * k] = make_float4(fmaf(bf, pk.x, z.x), fmaf(bf, pk.y, z.y), fmaf(bf, pk.z, z.z), 0.f);
+                } else {
+                    for (int p = 0; p < 3; ++p) P[k][p] = fmaf(bf, P[k][p], Z[k][p]);
+                }
+            }
         }
         // x += d
 #pragma unroll
         for (int k = 0; k < SN; ++k) {
             const int64_t a = tid + T * k;
-            if (a < nf)
-                for (int p = 0; p < 3; ++p) x64[3 * a + p] += (double)D[k][p];
+            if (a < nf) {
+                if (PL) {
+                    const float4 d = d32[a];
+                    x64[3 * a] += (double)d.x;
+                    x64[3 * a + 1] += (double)d.y;
+                    x64[3 * a + 2] += (double)d.z;
+                } else {
+                    for (int p = 0; p < 3; ++p) x64[3 * a + p] += (double)D[k][p];
+                }
+            }
         }
         __syncthreads();
         if (outer == 7 && !done && status == ST_CONVERGED) status = ST_CG_MAXITER;
@@ -888,8 +972,8 @@ __device__ void cg_res_task(const TangentArgs& A, int r, int col, float4* zl, Cg
     __syncthreads();
 }
 
-template <bool TAN, int T, int SN>
-__global__ __launch_bounds__(T) void cg_res_kernel(TangentArgs A)
+template <bool TAN, int T, int SN, bool PL>
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) void cg_res_kernel(TangentArgs A)
 {
     extern __shared__ float4 zl[];   // [T * SN + 1]; the last entry stays zero
     __shared__ CgRed red;
@@ -903,7 +987,7 @@ __global__ __launch_bounds__(T) void cg_res_kernel(TangentArgs A)
         const int t = __builtin_amdgcn_readfirstlane(task);
         __syncthreads();
         if (t >= n_tasks) break;
-        cg_res_task<TAN, T, SN>(A, __builtin_amdgcn_readfirstlane(A.order[t / per]), t % per, zl, red);
+        cg_res_task<TAN, T, SN, PL>(A, __builtin_amdgcn_readfirstlane(A.order[t / per]), t % per, zl, red);
     }
 }
 
@@ -916,24 +1000,26 @@ __global__ void zero_status(int32_t* st, unsigned long long* it, int64_t n)
     }
 }
 
-template <bool TAN, int T, int SN>
+template <bool TAN, int T, int SN, bool PL>
 const void* res_fn()
 {
-    return (const void*)cg_res_kernel<TAN, T, SN>;
+    return (const void*)cg_res_kernel<TAN, T, SN, PL>;
 }
 
 const void* res_kernel(int v, bool vjp)
 {
     switch (v) {
-    case 0: return vjp ? res_fn<false, 256, 2>() : res_fn<true, 256, 2>();
-    case 1: return vjp ? res_fn<false, 512, 2>() : res_fn<true, 512, 2>();
-    default: return vjp ? res_fn<false, 1024, 2>() : res_fn<true, 1024, 2>();
+    case 0: return vjp ? res_fn<false, 256, 2, false>() : res_fn<true, 256, 2, false>();
+    case 1: return vjp ? res_fn<false, 512, 2, false>() : res_fn<true, 512, 2, false>();
+    case 2: return vjp ? res_fn<false, 1024, 2, false>() : res_fn<true, 1024, 2, false>();
+    case 3: return vjp ? res_fn<false, 1024, 4, true>() : res_fn<true, 1024, 4, true>();
+    default: return vjp ? res_fn<false, 1024, 8, true>() : res_fn<true, 1024, 8, true>();
     }
 }
 
 }  // namespace
 
-const TangentVariant kTanRes[kNumTanRes] = {{256, 2}, {512, 2}, {1024, 2}};
+const TangentVariant kTanRes[kNumTanRes] = {{256, 2}, {512, 2}, {1024, 2}, {1024, 4}, {1024, 8}};
 
 hipError_t launch_tangent_prep(const TangentArgs& a, hipStream_t s)
 {
@@ -944,13 +1030,22 @@ hipError_t launch_tangent_prep(const TangentArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_tangent_wave(const TangentArgs& a, int grid, hipStream_t s)
+hipError_t launch_tangent_stream(const TangentArgs& a, int threads, int grid, hipStream_t s)
 {
     if (a.n_order <= 0) return hipSuccess;
-    if (a.mode == 0)
-        hipLaunchKernelGGL(cg_wave_kernel<true>, dim3(grid), dim3(64), 0, s, a);
-    else
-        hipLaunchKernelGGL(cg_wave_kernel<false>, dim3(grid), dim3(64), 0, s, a);
+    if (threads == 64) {
+        if (a.mode == 0)
+            hipLaunchKernelGGL((cg_stream_kernel<true, 64>), dim3(grid), dim3(64), 0, s, a);
+        else
+            hipLaunchKernelGGL((cg_stream_kernel<false, 64>), dim3(grid), dim3(64), 0, s, a);
+    } else if (threads == 1024) {
+        if (a.mode == 0)
+            hipLaunchKernelGGL((cg_stream_kernel<true, 1024>), dim3(grid), dim3(1024), 0, s, a);
+        else
+            hipLaunchKernelGGL((cg_stream_kernel<false, 1024>), dim3(grid), dim3(1024), 0, s, a);
+    } else {
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
