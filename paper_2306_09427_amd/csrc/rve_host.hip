@@ -395,13 +395,14 @@ static void assign_groups(rve_batch* b)
         per[chosen < 0 ? kNumResident : chosen].push_back((int32_t)r);
     }
     for (int v = 0; v <= kNumResident; ++v) {
-        if (per[v].empty()) continue;
-        std::stable_sort(per[v].begin(), per[v].end(),
+        std::vector<int32_t>& members = per[v];
+        if (members.empty()) continue;
+        std::stable_sort(members.begin(), members.end(),
                          [&](int32_t a, int32_t c) { return b->nfib_of[a] > b->nfib_of[c]; });
         size_t lds = 0;
         if (v < kNumResident)
-            for (int32_t r : per[v]) lds = std::max(lds, resident_lds_bytes(fp64, b->nf_of[r], b->nfib_of[r], 0));
-        b->groups.push_back(per[v]);
+            for (int32_t r : members) lds = std::max(lds, resident_lds_bytes(fp64, b->nf_of[r], b->nfib_of[r], 0));
+        b->groups.push_back(members);
         b->group_variant.push_back(v < kNumResident ? v : -1);
         b->group_lds.push_back(lds);
     }
@@ -419,13 +420,34 @@ static int upload_groups(rve_batch* b)
     return RVE_OK;
 }
 
+// Streamed engine: entries per component of the LDS copy of h for a launch
+// over `rves`: the largest nf + 1 that fits the LDS budget (RVEs above it keep
+// h in the workspace), 0 when none fits; and workgroups per CU.
+static int64_t streamed_lds_nodes(const rve_batch* b, const int32_t* rves, size_t n, bool fp64)
+{
+    int64_t m = 0;
+    for (size_t q = 0; q < n; ++q) {
+        const int64_t need = b->nf_of[rves[q]] + 1;
+        if (3 * (fp64 ? 8 : 4) * (size_t)need <= streamed_lds_cap()) m = std::max<int64_t>(m, need);
+    }
+    return m;
+}
+
+static int streamed_blocks_per_cu(int threads, int64_t lds_nodes, bool fp64)
+{
+    const int base = threads == 256 ? 4 : 2;
+    if (lds_nodes <= 0) return base;
+    const size_t lds = 3 * (fp64 ? 8 : 4) * (size_t)lds_nodes + 1024;
+    return (int)std::max<size_t>(1, std::min<size_t>(base, (160 * 1024) / lds));
+}
+
 static int ensure_workspace(rve_batch* b)
 {
     bool need = false;
     for (int v : b->group_variant) need |= (v < 0);
     if (!need) return RVE_OK;
     const size_t r4 = b->opts.precision == RVE_FP64 ? 32 : 16;
-    size_t fb = r4 * 2 * (size_t)(b->NF + b->R);
+    size_t fb = r4 * 3 * (size_t)(b->NF + b->R);
     size_t nb = r4 * (2 * (size_t)(b->NFREE + b->R) + 2 * (size_t)b->NFREE + 1);
     if (fb > b->ws_fib_bytes) {
         if (b->ws_fib) (void)hipFree(b->ws_fib);
@@ -780,8 +802,11 @@ int rve_batch_solve(rve_batch* b, const double* F, double* sigma, int32_t* statu
                 HIP_TRY(launch_resident(v, fp64, a, b->group_lds[g], grid, s));
             } else {
                 int threads = b->opts.threads_per_rve == 256 ? 256 : 1024;
-                int grid = std::min<int64_t>((int64_t)b->n_cu * (threads == 256 ? 4 : 2), a.n_list);
+                a.lds_h_nodes = streamed_lds_nodes(b, b->groups[g].data(), b->groups[g].size(), fp64);
+                int grid = std::min<int64_t>((int64_t)b->n_cu * streamed_blocks_per_cu(threads, a.lds_h_nodes, fp64),
+                                             a.n_list);
                 HIP_TRY(launch_streamed(fp64, a, grid, threads, s));
+                a.lds_h_nodes = 0;
             }
             if (b->profile) HIP_TRY(hipEventRecord(b->ev[2 * g + 1], s));
         }
@@ -888,7 +913,9 @@ int rve_batch_autotune(rve_batch* b, const double* F, int32_t ptr_kind, int32_t 
                 if (max_resident_blocks(v, fp64, lds, &per_cu) != hipSuccess || per_cu < 1) continue;
                 grid = (int)std::min<int64_t>((int64_t)per_cu * b->n_cu, a.n_list);
             } else {
-                grid = (int)std::min<int64_t>((int64_t)b->n_cu * 2, a.n_list);
+                a.lds_h_nodes = streamed_lds_nodes(b, members.data(), members.size(), fp64);
+                grid = (int)std::min<int64_t>((int64_t)b->n_cu * streamed_blocks_per_cu(1024, a.lds_h_nodes, fp64),
+                                              a.n_list);
             }
             for (int rep = 0; rep < 2; ++rep) {   // first run warms up
                 HIP_TRY(launch_reset(a.queue, 1, s));
@@ -925,7 +952,9 @@ int rve_batch_describe(const rve_batch* b, char* buf, size_t n)
             d += "resident(" + std::to_string(kResident[v].threads) + "," + std::to_string(kResident[v].sf) + "," +
                  std::to_string(kResident[v].sn) + ")";
         else
-            d += "streamed";
+            d += streamed_lds_nodes(b, b->groups[g].data(), b->groups[g].size(), b->opts.precision == RVE_FP64) > 0
+                     ? "streamed(lds)"
+                     : "streamed";
         d += ":" + std::to_string(b->groups[g].size()) + ";";
     }
     std::snprintf(buf, n, "%s", d.c_str());

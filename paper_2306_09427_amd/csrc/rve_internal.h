@@ -47,8 +47,9 @@ struct SolveArgs {
     double* Bres;             // [R]
     double* h_state;          // [NFREE][3] fluctuation h (warm-start input, output)
     // workspace of the streamed engine (indexed with fib_off / free_off + r)
-    void* ws_fib;             // [NF + R] Real4 (D0, q0) then [NF + R] Real4 (fv, b)
-    void* ws_node;            // [NFREE + R] Real4 h, [NFREE] Real4 v, [NFREE] Real inv mass
+    void* ws_fib;             // [NF + R] Real4 (D0, q0), [NF + R] Real4 (fv, b), [NF + R] Real4 (L0, 1/L0, ends)
+    void* ws_node;            // [NFREE + R] Real4 h, [NFREE] Real4 (v, 1/M), [NFREE] Real mass, [NFREE] Real4 accel
+    int64_t lds_h_nodes;      // streamed engine: > 0 keeps h in LDS (this many entries per component)
 };
 
 struct TangentArgs {
@@ -101,6 +102,7 @@ size_t resident_lds_bytes(bool fp64, int64_t nf, int64_t nfib, int threads);
 hipError_t launch_resident(int variant, bool fp64, const SolveArgs& a, size_t lds_bytes, int grid,
                            hipStream_t s);
 hipError_t launch_streamed(bool fp64, const SolveArgs& a, int grid, int threads, hipStream_t s);
+size_t streamed_lds_cap();   // bytes of LDS the streamed engine may use for h
 hipError_t launch_stress(const SolveArgs& a, int n_rve, hipStream_t s);
 hipError_t launch_reset(int32_t* counters, int n, hipStream_t s);   // n <= 64
 // Tangent / VJP.  prep: statuses, ELL records (first call), fiber operators

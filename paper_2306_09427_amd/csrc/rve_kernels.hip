@@ -536,10 +536,27 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
     };
     // gather forces and Gershgorin sums of node slot s; lanes whose node has
     // fewer incidences than the wave's largest read the zero slot
+    // The first four incidences are read unconditionally (padding reads the
+    // zero slot), so their LDS reads are issued back to back; nodes of degree
+    // 5..8 (a wave-uniform test) add the rest.
     auto gather = [&](int s, Real& fx, Real& fy, Real& fz, Real& G) __attribute__((always_inline)) {
         fx = fy = fz = G = Real(0);
+        {
+            Real x[4], y[4], z[4], b[4];
+            uint32_t code[4];
 #pragma unroll
-        for (int q = 0; q < kMaxResidentDegree; ++q) {
+            for (int q = 0; q < 4; ++q) {
+                code[q] = (q & 1) ? (inc[s][q >> 1] >> 16) : (inc[s][q >> 1] & 0xffffu);
+                L.get_fv((int)(code[q] & 0x7fffu), x[q], y[q], z[q], b[q]);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const Real sg = (code[q] & 0x8000u) ? Real(-1) : Real(1);
+                fx = fma(sg, x[q], fx); fy = fma(sg, y[q], fy); fz = fma(sg, z[q], fz); G += b[q];
+            }
+        }
+#pragma unroll
+        for (int q = 4; q < kMaxResidentDegree; ++q) {
             if (q >= degw[s]) break;
             uint32_t code = (q & 1) ? (inc[s][q >> 1] >> 16) : (inc[s][q >> 1] & 0xffffu);
             int k = (int)(code & 0x7fffu);
@@ -598,6 +615,7 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
     int64_t n = 0;
     int status = ST_CONVERGED;
     const int ce = A.check_every > 0 ? A.check_every : 1;
+    int to_check = ce;
     double tol = fmax(A.tol_abs, A.tol_rel * sqrt(B2));
     bool done = (sqrt(R2) <= tol);   // v = 0: damping norm is 0
     double Rlast = sqrt(R2), Dlast = 0.0, Blast = sqrt(B2);
@@ -649,7 +667,9 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
         fiber_pass();
         __syncthreads();
         ++n;
-        const bool check = (n % ce) == 0;
+        // every ce-th iteration (a countdown: no 64-bit modulo in the loop)
+        const bool check = --to_check == 0;
+        if (check) to_check = ce;
         gpart = Real(0);
         r2p = 0.0;
         double d2p = 0.0;
@@ -737,27 +757,62 @@ __global__ __launch_bounds__(T) void dr_resident_kernel(SolveArgs A)
 }
 
 // ------------------------------------------------------------------ streamed kernel
-// Same iteration with fibers, state and exchange arrays in global memory
-// (per-RVE regions of the workspace).  One workgroup per RVE; every loop is
-// strided over the workgroup.
-template <typename Real, int T>
-__device__ __forceinline__ void streamed_solve(const SolveArgs& A, int r, RedSlots& red)
+// Same iteration for RVEs too large for the register-resident variants: one
+// workgroup per RVE, fibers and node state in per-RVE regions of the global
+// workspace, every loop strided over the workgroup.  HL: the positions h live
+// in LDS (structure of arrays, A.lds_h_nodes entries per component) instead of
+// the workspace, so the fiber pass gathers them from LDS.  Per-fiber constants
+// (F d0, q0, L0, 1/L0) are formed once per solve; the inverse mass is kept
+// next to the velocity; the loops issue the loads of two fibers, or of up to
+// four incidences, before using them.
+template <typename Real, int T, bool HL>
+__device__ __forceinline__ void streamed_solve(const SolveArgs& A, int r, RedSlots& red, char* smem)
 {
     using R4 = typename Vec4<Real>::T;
     constexpr int NW = T / 64;
-    const int tid = threadIdx.x;
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
     const DevNet& net = A.net;
     const int64_t f0 = net.fib_off[r], nfib = net.fib_off[r + 1] - f0;
     const int64_t a0 = net.free_off[r], nf = net.free_off[r + 1] - a0;
     const int64_t b0 = net.bnd_off[r], nb = net.bnd_off[r + 1] - b0;
     const int64_t NF = net.fib_off[net.n_rve], NFREE = net.free_off[net.n_rve];
 
-    R4* wsD = reinterpret_cast<R4*>(A.ws_fib) + (f0 + r);             // [nfib+1] (D0, q0)
-    R4* wsFv = reinterpret_cast<R4*>(A.ws_fib) + (NF + net.n_rve) + (f0 + r);   // [nfib+1]
-    R4* wsH = reinterpret_cast<R4*>(A.ws_node) + (a0 + r);            // [nf+1]
-    R4* wsV = reinterpret_cast<R4*>(A.ws_node) + (NFREE + net.n_rve) + a0;     // [nf]
+    R4* wsD = reinterpret_cast<R4*>(A.ws_fib) + (f0 + r);                             // [nfib+1] (D0, q0)
+    R4* wsFv = reinterpret_cast<R4*>(A.ws_fib) + (NF + net.n_rve) + (f0 + r);         // [nfib+1] (fv, b)
+    R4* wsL = reinterpret_cast<R4*>(A.ws_fib) + 2 * (NF + net.n_rve) + (f0 + r);      // [nfib] (L0, 1/L0, ends)
+    R4* wsH = reinterpret_cast<R4*>(A.ws_node) + (a0 + r);                            // [nf+1]
+    R4* wsV = reinterpret_cast<R4*>(A.ws_node) + (NFREE + net.n_rve) + a0;            // [nf] (v, 1/M)
     Real* wsM = reinterpret_cast<Real*>(reinterpret_cast<R4*>(A.ws_node) + (NFREE + net.n_rve) + NFREE) + a0;
     R4* wsA = reinterpret_cast<R4*>(A.ws_node) + 2 * (NFREE + net.n_rve) + NFREE + a0;   // [nf] accel
+    const int64_t nh = A.lds_h_nodes;
+    Real* lhx = reinterpret_cast<Real*>(smem);
+    Real* lhy = lhx + nh;
+    Real* lhz = lhy + nh;
+
+    auto get_h = [&](int64_t i, Real& x, Real& y, Real& z) __attribute__((always_inline)) {
+        if constexpr (HL) {
+            x = lhx[i];
+            y = lhy[i];
+            z = lhz[i];
+        } else {
+            R4 h = wsH[i];
+            x = h.x;
+            y = h.y;
+            z = h.z;
+        }
+    };
+    auto put_h = [&](int64_t i, Real x, Real y, Real z) __attribute__((always_inline)) {
+        if constexpr (HL) {
+            lhx[i] = x;
+            lhy[i] = y;
+            lhz[i] = z;
+        } else {
+            R4 h;
+            h.x = x; h.y = y; h.z = z; h.w = Real(0);
+            wsH[i] = h;
+        }
+    };
 
     double F[9];
     bool finite = true;
@@ -790,16 +845,26 @@ __device__ __forceinline__ void streamed_solve(const SolveArgs& A, int r, RedSlo
         q.x = (Real)Dx; q.y = (Real)Dy; q.z = (Real)Dz;
         q.w = (Real)((Dx * Dx + Dy * Dy + Dz * Dz) - L0 * L0);
         wsD[k] = q;
+        // boundary ends read the zero slot nf
+        uint32_t e = net.ends[f0 + k];
+        uint32_t i = e & 0xffffu, j = e >> 16;
+        i = i < (uint32_t)nf ? i : (uint32_t)nf;
+        j = j < (uint32_t)nf ? j : (uint32_t)nf;
+        R4 l;
+        l.x = (Real)L0;
+        l.y = (Real)(1.0 / L0);
+        l.z = (Real)i;
+        l.w = (Real)j;
+        wsL[k] = l;
     }
 #pragma unroll 1
     for (int64_t a = tid; a < nf; a += T) {
-        R4 h;
-        h.x = h.y = h.z = h.w = Real(0);
+        Real hx = Real(0), hy = Real(0), hz = Real(0);
         if (A.init == kInitWarm) {
             const double* hs = A.h_state + 3 * (a0 + a);
-            h.x = (Real)hs[0]; h.y = (Real)hs[1]; h.z = (Real)hs[2];
+            hx = (Real)hs[0]; hy = (Real)hs[1]; hz = (Real)hs[2];
         }
-        wsH[a] = h;
+        put_h(a, hx, hy, hz);
         R4 z;
         z.x = z.y = z.z = z.w = Real(0);
         wsV[a] = z;
@@ -808,35 +873,62 @@ __device__ __forceinline__ void streamed_solve(const SolveArgs& A, int r, RedSlo
     if (tid == 0) {
         R4 z;
         z.x = z.y = z.z = z.w = Real(0);
-        wsH[nf] = z;
+        put_h(nf, Real(0), Real(0), Real(0));
         wsFv[nfib] = z;
     }
     __syncthreads();
 
+    auto fiber_one = [&](const R4& D, const R4& l) __attribute__((always_inline)) -> R4 {
+        const int64_t i = (int64_t)l.z, j = (int64_t)l.w;
+        Real ix, iy, iz, jx, jy, jz;
+        get_h(i, ix, iy, iz);
+        get_h(j, jx, jy, jz);
+        FiberOut<Real> o = fiber_eval<Real>(A.law, EA, Bc, EAoB, D.x, D.y, D.z, D.w, l.x, l.y, jx - ix, jy - iy,
+                                            jz - iz);
+        R4 w;
+        w.x = o.fx; w.y = o.fy; w.z = o.fz; w.w = o.b;
+        return w;
+    };
     auto fiber_pass = [&]() __attribute__((always_inline)) {
-        #pragma unroll 1
-        for (int64_t k = tid; k < nfib; k += T) {
-            R4 D = wsD[k];
-            uint32_t e = net.ends[f0 + k];
-            uint32_t i = e & 0xffffu, j = e >> 16;
-            i = i < (uint32_t)nf ? i : (uint32_t)nf;
-            j = j < (uint32_t)nf ? j : (uint32_t)nf;
-            R4 hi = wsH[i], hj = wsH[j];
-            double L0d = net.L0[f0 + k];
-            FiberOut<Real> o = fiber_eval<Real>(A.law, EA, Bc, EAoB, D.x, D.y, D.z, D.w, (Real)L0d,
-                                                (Real)(1.0 / L0d), hj.x - hi.x, hj.y - hi.y, hj.z - hi.z);
-            R4 w;
-            w.x = o.fx; w.y = o.fy; w.z = o.fz; w.w = o.b;
-            wsFv[k] = w;
+#pragma unroll 1
+        for (int64_t k = tid; k < nfib; k += 2 * T) {
+            const int64_t k2 = k + T;
+            const bool two = k2 < nfib;
+            const R4 Da = wsD[k], la = wsL[k];
+            R4 Db = Da, lb = la;
+            if (two) {
+                Db = wsD[k2];
+                lb = wsL[k2];
+            }
+            const R4 wa = fiber_one(Da, la);
+            if (two) {
+                const R4 wb = fiber_one(Db, lb);
+                wsFv[k2] = wb;
+            }
+            wsFv[k] = wa;
         }
     };
+    // forces and Gershgorin sum at free node a: up to four incidences loaded
+    // together, the rest (high-degree nodes) one by one
     auto gather = [&](int64_t a, Real& fx, Real& fy, Real& fz, Real& G) __attribute__((always_inline)) {
         fx = fy = fz = G = Real(0);
+        const int64_t e0 = net.inc_off[a0 + a], e1 = net.inc_off[a0 + a + 1];
+        uint32_t w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w[q] = e0 + q < e1 ? net.inc[e0 + q] : (uint32_t)nfib;
+        R4 f[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) f[q] = wsFv[w[q] & 0x7fffffffu];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const Real sg = (w[q] >> 31) ? Real(-1) : Real(1);
+            fx += sg * f[q].x; fy += sg * f[q].y; fz += sg * f[q].z; G += f[q].w;
+        }
 #pragma unroll 1
-        for (int64_t e = net.inc_off[a0 + a]; e < net.inc_off[a0 + a + 1]; ++e) {
-            uint32_t w = net.inc[e];
-            R4 q = wsFv[w & 0x7fffffffu];
-            if (w >> 31) {
+        for (int64_t e = e0 + 4; e < e1; ++e) {
+            uint32_t we = net.inc[e];
+            R4 q = wsFv[we & 0x7fffffffu];
+            if (we >> 31) {
                 q.x = -q.x; q.y = -q.y; q.z = -q.z;
             }
             fx += q.x; fy += q.y; fz += q.z; G += q.w;
@@ -878,6 +970,9 @@ __device__ __forceinline__ void streamed_solve(const SolveArgs& A, int r, RedSlo
         R4 acc;
         acc.x = -fx * im; acc.y = -fy * im; acc.z = -fz * im; acc.w = Real(0);
         wsA[a] = acc;
+        R4 v = wsV[a];
+        v.w = im;
+        wsV[a] = v;
         gpart = fmax(gpart, G * im);
         r2p += (double)fx * fx + (double)fy * fy + (double)fz * fz;
     }
@@ -890,6 +985,7 @@ __device__ __forceinline__ void streamed_solve(const SolveArgs& A, int r, RedSlo
     int64_t n = 0;
     int status = ST_CONVERGED;
     const int ce = A.check_every > 0 ? A.check_every : 1;
+    int to_check = ce;
     double tol = fmax(A.tol_abs, A.tol_rel * sqrt(B2));
     bool done = (sqrt(R2) <= tol);
     double Rlast = sqrt(R2), Dlast = 0.0, Blast = sqrt(B2);
@@ -906,17 +1002,21 @@ __device__ __forceinline__ void streamed_solve(const SolveArgs& A, int r, RedSlo
         const Real hdt = (Real)(0.5 * dt), rdt = (Real)dt;
 #pragma unroll 1
         for (int64_t a = tid; a < nf; a += T) {
-            R4 v = wsV[a], h = wsH[a], acc = wsA[a];
+            R4 v = wsV[a], acc = wsA[a];
+            Real hx, hy, hz;
+            get_h(a, hx, hy, hz);
             v.x += hdt * acc.x; v.y += hdt * acc.y; v.z += hdt * acc.z;
-            h.x += rdt * v.x; h.y += rdt * v.y; h.z += rdt * v.z;
+            hx += rdt * v.x; hy += rdt * v.y; hz += rdt * v.z;
             wsV[a] = v;
-            wsH[a] = h;
+            put_h(a, hx, hy, hz);
         }
         __syncthreads();
         fiber_pass();
         __syncthreads();
         ++n;
-        const bool check = (n % ce) == 0;
+        // every ce-th iteration (a countdown: no 64-bit modulo in the loop)
+        const bool check = --to_check == 0;
+        if (check) to_check = ce;
         gpart = Real(0);
         r2p = 0.0;
         double d2p = 0.0;
@@ -924,8 +1024,8 @@ __device__ __forceinline__ void streamed_solve(const SolveArgs& A, int r, RedSlo
         for (int64_t a = tid; a < nf; a += T) {
             Real fx, fy, fz, G;
             gather(a, fx, fy, fz, G);
-            Real m = wsM[a], im = Real(1) / m;
             R4 v = wsV[a], acc;
+            const Real im = v.w;
             acc.x = -fx * im - c * v.x;
             acc.y = -fy * im - c * v.y;
             acc.z = -fz * im - c * v.z;
@@ -936,7 +1036,7 @@ __device__ __forceinline__ void streamed_solve(const SolveArgs& A, int r, RedSlo
             gpart = fmax(gpart, G * im);
             if (check) {
                 r2p += (double)fx * fx + (double)fy * fy + (double)fz * fz;
-                double md = (double)m * cd;
+                double md = (double)wsM[a] * cd;
                 double px = md * (double)v.x, py = md * (double)v.y, pz = md * (double)v.z;
                 d2p += px * px + py * py + pz * pz;
             }
@@ -968,9 +1068,10 @@ __device__ __forceinline__ void streamed_solve(const SolveArgs& A, int r, RedSlo
 
 #pragma unroll 1
     for (int64_t a = tid; a < nf; a += T) {
-        R4 h = wsH[a];
+        Real hx, hy, hz;
+        get_h(a, hx, hy, hz);
         double* hs = A.h_state + 3 * (a0 + a);
-        hs[0] = (double)h.x; hs[1] = (double)h.y; hs[2] = (double)h.z;
+        hs[0] = (double)hx; hs[1] = (double)hy; hs[2] = (double)hz;
     }
     if (tid == 0) {
         A.status[r] = status;
@@ -982,9 +1083,12 @@ __device__ __forceinline__ void streamed_solve(const SolveArgs& A, int r, RedSlo
     __syncthreads();
 }
 
+// RVEs whose positions fit the launch's LDS copy (nf + 1 <= lds_h_nodes) run
+// the LDS form, the others the workspace form, in one persistent launch.
 template <typename Real, int T>
 __global__ __launch_bounds__(T) void dr_streamed_kernel(SolveArgs A)
 {
+    extern __shared__ char smem_h[];
     __shared__ RedSlots red;
     __shared__ int task;
     for (;;) {
@@ -993,7 +1097,12 @@ __global__ __launch_bounds__(T) void dr_streamed_kernel(SolveArgs A)
         const int t = __builtin_amdgcn_readfirstlane(task);
         __syncthreads();
         if (t >= A.n_list) break;
-        streamed_solve<Real, T>(A, __builtin_amdgcn_readfirstlane(A.list[t]), red);
+        const int r = __builtin_amdgcn_readfirstlane(A.list[t]);
+        const int64_t nf = A.net.free_off[r + 1] - A.net.free_off[r];
+        if (nf + 1 <= A.lds_h_nodes)
+            streamed_solve<Real, T, true>(A, r, red, smem_h);
+        else
+            streamed_solve<Real, T, false>(A, r, red, smem_h);
     }
 }
 
@@ -1130,16 +1239,25 @@ hipError_t resident_scratch_bytes(int variant, bool fp64, size_t* bytes)
     RVE_RES_DISPATCH(spill_res, bytes)
 }
 
+template <typename Real, int T>
+static hipError_t launch_streamed_t(const SolveArgs& a, int grid, hipStream_t s)
+{
+    const size_t lds = 3 * sizeof(Real) * (size_t)a.lds_h_nodes;
+    const void* k = (const void*)dr_streamed_kernel<Real, T>;
+    if (lds > 0) {
+        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    void* args[] = {const_cast<SolveArgs*>(&a)};
+    return hipLaunchKernel(k, dim3(grid), dim3(T), args, lds, s);
+}
+
 hipError_t launch_streamed(bool fp64, const SolveArgs& a, int grid, int threads, hipStream_t s)
 {
-    if (threads == 256) {
-        if (fp64) hipLaunchKernelGGL((dr_streamed_kernel<double, 256>), dim3(grid), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((dr_streamed_kernel<float, 256>), dim3(grid), dim3(256), 0, s, a);
-    } else {
-        if (fp64) hipLaunchKernelGGL((dr_streamed_kernel<double, 1024>), dim3(grid), dim3(1024), 0, s, a);
-        else hipLaunchKernelGGL((dr_streamed_kernel<float, 1024>), dim3(grid), dim3(1024), 0, s, a);
-    }
-    return hipGetLastError();
+    if (threads == 256) return fp64 ? launch_streamed_t<double, 256>(a, grid, s) : launch_streamed_t<float, 256>(a, grid, s);
+    return fp64 ? launch_streamed_t<double, 1024>(a, grid, s) : launch_streamed_t<float, 1024>(a, grid, s);
 }
+
+size_t streamed_lds_cap() { return 150 * 1024; }
 
 }  // namespace rve
