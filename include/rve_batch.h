@@ -245,6 +245,20 @@ int rve_batch_tangent(rve_batch* b, double* dsdF, int32_t* status, int32_t ptr_k
 int rve_batch_vjp(rve_batch* b, const double* gsigma, double* gF, int32_t* status, int32_t ptr_kind);
 
 /*
+ * Fiber orientation at the state of the last solve (Section 6, degree of
+ * alignment; Section 4, orientation data sent to the macroscale): per RVE
+ * the orientation tensor omega_ab = <n_a n_b> (row-major 3x3, symmetric,
+ * trace 1) and the degree of alignment p2 = <(3 (n.e)^2 - 1)/2> in
+ * [-1/2, 1], averages over the RVE's fibers of the unit current direction n
+ * of each fiber; e (host pointer, 3 doubles, normalised here) is the
+ * reference direction, typically the loading direction.  omega[n_rve][9] and
+ * p2[n_rve] follow ptr_kind.  RVEs whose solve ended non-finite or with a bad
+ * F, and RVEs without fibers, get NaN.  RVE_EINVAL for a zero or non-finite
+ * e, RVE_ESTATE before the first solve.
+ */
+int rve_batch_orientation(rve_batch* b, const double* e, double* omega, double* p2, int32_t ptr_kind);
+
+/*
  * Inner CG iterations of the last rve_batch_tangent or rve_batch_vjp call,
  * summed over each RVE's right-hand sides: iters[n_rve].  RVE_ESTATE before
  * the first such call.

@@ -28,7 +28,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ESTATE = 0, -22, -12, -5, -3
 EXPORTS = ["rve_version", "rve_last_error", "rve_default_opts", "rve_batch_create", "rve_batch_set_opts",
            "rve_batch_set_stream", "rve_batch_sizes", "rve_batch_solve", "rve_batch_tangent", "rve_batch_vjp",
            "rve_batch_positions", "rve_batch_destroy", "rve_batch_profile", "rve_batch_kernel_ms",
-           "rve_batch_autotune", "rve_batch_describe", "rve_batch_groups", "rve_batch_tangent_iters"]
+           "rve_batch_autotune", "rve_batch_describe", "rve_batch_groups", "rve_batch_tangent_iters", "rve_batch_orientation"]
 
 
 class NetDesc(C.Structure):
@@ -84,6 +84,7 @@ def lib():
         L.rve_batch_describe.argtypes = [P, C.c_char_p, C.c_size_t]
         L.rve_batch_groups.argtypes = [P, P, P, P, C.c_int32, P]
         L.rve_batch_tangent_iters.argtypes = [P, P, C.c_int32]
+        L.rve_batch_orientation.argtypes = [P, P, P, P, C.c_int32]
         L.rve_batch_destroy.argtypes = [P]
         L.rve_batch_destroy.restype = None
         _lib = L
@@ -223,6 +224,15 @@ class Batch:
         gp, kind = _ptr(gsigma)
         _check(lib().rve_batch_vjp(self._h, gp, _ptr(gF)[0], _ptr(st)[0], kind))
         return gF, st
+
+    def orientation(self, e=(1.0, 0.0, 0.0), like=None):
+        """Orientation tensor [R,3,3] and degree of alignment P2 [R] along e at the last solve's state."""
+        ref = like if like is not None else np.empty(0)
+        om = self._outs(ref, (3, 3), np.float64)
+        p2 = self._outs(ref, (), np.float64)
+        ev = np.ascontiguousarray(np.asarray(e, dtype=np.float64).reshape(3))
+        _check(lib().rve_batch_orientation(self._h, ev.ctypes.data, _ptr(om)[0], _ptr(p2)[0], _ptr(om)[1]))
+        return om, p2
 
     def tangent_iters(self):
         """Inner CG iterations of the last tangent/vjp call, summed per RVE (host int64 [R])."""

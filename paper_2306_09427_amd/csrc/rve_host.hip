@@ -100,6 +100,7 @@ struct rve_batch {
     std::vector<int32_t> t_order_host;    // host copy of t_order
     std::vector<int64_t> t_max_nf;        // per launch of the last call: largest free-node count
     char* t_slots = nullptr;           // per-wavefront solver vectors
+    double* o_mem = nullptr;           // orientation outputs [R][9] + [R]
     size_t t_slot_bytes = 0;
     // profiling events: [group][start, stop], then the stress kernel
     bool profile = false;
@@ -1178,6 +1179,37 @@ int rve_batch_vjp(rve_batch* b, const double* gsigma, double* gF, int32_t* statu
     return run_cg(b, 1, gsigma, gF, status, ptr_kind);
 }
 
+int rve_batch_orientation(rve_batch* b, const double* e, double* omega, double* p2, int32_t ptr_kind)
+{
+    if (!b) return fail(RVE_EINVAL, "batch is NULL");
+    if (ptr_kind != RVE_PTR_HOST && ptr_kind != RVE_PTR_DEVICE) return fail(RVE_EINVAL, "bad ptr_kind");
+    if (!e) return fail(RVE_EINVAL, "reference direction is NULL");
+    const double en = std::sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+    if (!std::isfinite(en) || !(en > 0.0)) return fail(RVE_EINVAL, "reference direction must be finite and nonzero");
+    if (b->R == 0) return RVE_OK;
+    if (!omega || !p2) return fail(RVE_EINVAL, "NULL output");
+    if (!b->have_state) return fail(RVE_ESTATE, "no solve yet");
+    if (!b->o_mem && hipMalloc((void**)&b->o_mem, 80 * (size_t)b->R) != hipSuccess) {
+        b->o_mem = nullptr;
+        return fail(RVE_ENOMEM, "orientation output allocation failed");
+    }
+    hipStream_t s = (hipStream_t)b->opts.stream;
+    OrientArgs a{};
+    a.net = b->net;
+    a.F = b->dF;
+    a.h_state = b->dh;
+    a.status = b->dstatus;
+    for (int k = 0; k < 3; ++k) a.e[k] = e[k] / en;
+    a.omega = b->o_mem;
+    a.p2 = b->o_mem + 9 * b->R;
+    HIP_TRY(launch_orientation(a, b->R, s));
+    const hipMemcpyKind k = ptr_kind == RVE_PTR_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    HIP_TRY(hipMemcpyAsync(omega, a.omega, 72 * b->R, k, s));
+    HIP_TRY(hipMemcpyAsync(p2, a.p2, 8 * b->R, k, s));
+    if (ptr_kind == RVE_PTR_HOST) HIP_TRY(hipStreamSynchronize(s));
+    return RVE_OK;
+}
+
 int rve_batch_tangent_iters(rve_batch* b, int64_t* iters, int32_t ptr_kind)
 {
     if (!b) return fail(RVE_EINVAL, "batch is NULL");
@@ -1197,6 +1229,7 @@ void rve_batch_destroy(rve_batch* b)
     if (!b) return;
     for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
     if (b->t_mem) (void)hipFree(b->t_mem);
+    if (b->o_mem) (void)hipFree(b->o_mem);
     if (b->t_slots) (void)hipFree(b->t_slots);
     if (b->dtune_list) (void)hipFree(b->dtune_list);
     if (b->dmem) (void)hipFree(b->dmem);

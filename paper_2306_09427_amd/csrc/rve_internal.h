@@ -86,6 +86,18 @@ struct TangentArgs {
     int32_t build_static;        // 1: fill rec_static from the incidence first
 };
 
+// Fiber-orientation outputs at the state of the last solve.
+struct OrientArgs {
+    DevNet net;
+    const double* F;             // [R][9]
+    const double* h_state;       // [NFREE][3]
+    const int32_t* status;       // [R] of the last solve
+    double e[3];                 // unit reference direction
+    double* omega;               // [R][9] orientation tensor <n n^T>
+    double* p2;                  // [R] degree of alignment <(3 (n.e)^2 - 1)/2>
+};
+hipError_t launch_orientation(const OrientArgs& a, int64_t n_rve, hipStream_t s);
+
 // Which register-resident variants exist (threads per RVE, fiber slots per
 // thread, free-node slots per thread).
 struct ResidentVariant {
