@@ -245,6 +245,26 @@ int rve_batch_tangent(rve_batch* b, double* dsdF, int32_t* status, int32_t ptr_k
 int rve_batch_vjp(rve_batch* b, const double* gsigma, double* gF, int32_t* status, int32_t ptr_kind);
 
 /*
+ * The paper's material tangent by finite differences (Section 3.2, material
+ * stiffness), at the state of the last solve: with F = R U (polar
+ * decomposition), six probe relaxations under U + h T_c (T_c the six
+ * probing directions the paper prints, in Mandel form), each warm-started
+ * from the base state rotated back by R^T, give forward differences
+ * [P] = (Pi(U + h T_c) - Pi(F)) / h of the second Piola-Kirchhoff stress
+ * Pi = J F^-1 sigma F^-T; then [A] = [P] ([M][T])^-1 with [M] = [dE/dU]
+ * (A = dPi/dE) and C = F F A F F / J (push-forward, the updated-Lagrangian
+ * spatial tangent).  Mandel order 11, 22, 33, 23, 13, 12 with sqrt(2) on
+ * shear components.  C[n_rve][36] and A[n_rve][36] (A may be NULL) are
+ * row-major 6x6 Mandel matrices; status per RVE: 0, RVE_ST_NO_STATE when
+ * the base solve did not converge, else the worst probe status (outputs
+ * NaN when not 0).  h > 0 (e.g. 1e-4).  The first call builds an internal
+ * batch of six copies of every RVE (six times the device memory of the
+ * batch); every call runs one batched solve of it.  Host pointers or device
+ * pointers per ptr_kind; the call returns after the outputs are written.
+ */
+int rve_batch_fd_tangent(rve_batch* b, double h, double* C, double* A, int32_t* status, int32_t ptr_kind);
+
+/*
  * Fiber orientation at the state of the last solve (Section 6, degree of
  * alignment; Section 4, orientation data sent to the macroscale): per RVE
  * the orientation tensor omega_ab = <n_a n_b> (row-major 3x3, symmetric,

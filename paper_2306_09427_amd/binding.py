@@ -28,7 +28,8 @@ OK, EINVAL, ENOMEM, EDEVICE, ESTATE = 0, -22, -12, -5, -3
 EXPORTS = ["rve_version", "rve_last_error", "rve_default_opts", "rve_batch_create", "rve_batch_set_opts",
            "rve_batch_set_stream", "rve_batch_sizes", "rve_batch_solve", "rve_batch_tangent", "rve_batch_vjp",
            "rve_batch_positions", "rve_batch_destroy", "rve_batch_profile", "rve_batch_kernel_ms",
-           "rve_batch_autotune", "rve_batch_describe", "rve_batch_groups", "rve_batch_tangent_iters", "rve_batch_orientation"]
+           "rve_batch_autotune", "rve_batch_describe", "rve_batch_groups", "rve_batch_tangent_iters", "rve_batch_orientation",
+           "rve_batch_fd_tangent"]
 
 
 class NetDesc(C.Structure):
@@ -85,6 +86,7 @@ def lib():
         L.rve_batch_groups.argtypes = [P, P, P, P, C.c_int32, P]
         L.rve_batch_tangent_iters.argtypes = [P, P, C.c_int32]
         L.rve_batch_orientation.argtypes = [P, P, P, P, C.c_int32]
+        L.rve_batch_fd_tangent.argtypes = [P, C.c_double, P, P, P, C.c_int32]
         L.rve_batch_destroy.argtypes = [P]
         L.rve_batch_destroy.restype = None
         _lib = L
@@ -224,6 +226,16 @@ class Batch:
         gp, kind = _ptr(gsigma)
         _check(lib().rve_batch_vjp(self._h, gp, _ptr(gF)[0], _ptr(st)[0], kind))
         return gF, st
+
+    def fd_tangent(self, h=1e-4, like=None):
+        """The paper's finite-difference tangent at the last solve's state:
+        spatial C [R,6,6], A = dPi/dE [R,6,6] (Mandel) and status [R]."""
+        ref = like if like is not None else np.empty(0)
+        Cm = self._outs(ref, (6, 6), np.float64)
+        Am = self._outs(ref, (6, 6), np.float64)
+        st = self._outs(ref, (), np.int32)
+        _check(lib().rve_batch_fd_tangent(self._h, float(h), _ptr(Cm)[0], _ptr(Am)[0], _ptr(st)[0], _ptr(Cm)[1]))
+        return Cm, Am, st
 
     def orientation(self, e=(1.0, 0.0, 0.0), like=None):
         """Orientation tensor [R,3,3] and degree of alignment P2 [R] along e at the last solve's state."""

@@ -101,6 +101,11 @@ struct rve_batch {
     std::vector<int64_t> t_max_nf;        // per launch of the last call: largest free-node count
     char* t_slots = nullptr;           // per-wavefront solver vectors
     double* o_mem = nullptr;           // orientation outputs [R][9] + [R]
+    // finite-difference tangent: the probe batch (six copies of every RVE),
+    // the probe-to-base free-node map and the per-call rotations
+    rve_batch* probe = nullptr;
+    int64_t* d_probe_map = nullptr;
+    double* d_fd_rot = nullptr;
     size_t t_slot_bytes = 0;
     // profiling events: [group][start, stop], then the stress kernel
     bool profile = false;
@@ -1210,6 +1215,148 @@ int rve_batch_orientation(rve_batch* b, const double* e, double* omega, double* 
     return RVE_OK;
 }
 
+// The probe batch of the finite-difference tangent: the same networks, six
+// copies of each (copy c of RVE r is probe RVE 6 r + c), rebuilt in the
+// caller's original node order from the packed batch, and the map from each
+// probe free node to the base free node of the same original node.
+static int ensure_probe(rve_batch* b)
+{
+    if (b->probe) return RVE_OK;
+    const int64_t R = b->R;
+    std::vector<uint32_t> ends(b->NF);
+    std::vector<double> V0(R);
+    if (b->NF) HIP_TRY(hipMemcpy(ends.data(), b->net.ends, 4 * (size_t)b->NF, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(V0.data(), b->dV0, 8 * (size_t)R, hipMemcpyDeviceToHost));
+    std::vector<int64_t> node_off(1, 0), fib_off(1, 0);
+    std::vector<double> X, V0p, cp;
+    std::vector<uint8_t> isb;
+    std::vector<int32_t> fib;
+    try {
+        X.reserve(18 * (size_t)b->NN);
+        isb.reserve(6 * (size_t)b->NN);
+        fib.reserve(12 * (size_t)b->NF);
+        for (int64_t r = 0; r < R; ++r) {
+            const int64_t n0 = b->node_off[r], nn = b->node_off[r + 1] - n0;
+            const int64_t f0 = b->fib_off[r], nfib = b->fib_off[r + 1] - f0, nf = b->nf_of[r];
+            std::vector<int32_t> inv(nn);
+            for (int64_t q = 0; q < nn; ++q) inv[b->newid[n0 + q]] = (int32_t)q;
+            for (int c = 0; c < 6; ++c) {
+                for (int64_t q = 0; q < nn; ++q) {
+                    for (int k = 0; k < 3; ++k) X.push_back(b->Xm[3 * (n0 + q) + k] + 0.5);
+                    isb.push_back(b->newid[n0 + q] >= nf ? 1 : 0);
+                }
+                for (int64_t k = 0; k < nfib; ++k) {
+                    const uint32_t e = ends[f0 + k];
+                    fib.push_back(inv[e & 0xffffu]);
+                    fib.push_back(inv[e >> 16]);
+                }
+                node_off.push_back(node_off.back() + nn);
+                fib_off.push_back(fib_off.back() + nfib);
+                V0p.push_back(V0[r]);
+                cp.push_back(b->c_host[r]);
+            }
+        }
+    } catch (const std::bad_alloc&) {
+        return fail(RVE_ENOMEM, "host allocation failed while building the probe batch");
+    }
+    rve_net_desc d{};
+    d.n_rve = 6 * R;
+    d.node_off = node_off.data();
+    d.fib_off = fib_off.data();
+    d.X = X.data();
+    d.is_bnd = isb.data();
+    d.fib = fib.data();
+    d.V0 = V0p.data();
+    rve_opts o = b->opts;
+    o.init = RVE_INIT_WARM;
+    o.c_per_rve = cp.data();
+    rve_batch* pb = nullptr;
+    int rc = rve_batch_create(&d, &o, &pb);
+    if (rc) return rc;
+    std::vector<int64_t> map(pb->NFREE);
+    for (int64_t r = 0; r < R; ++r) {
+        const int64_t n0 = b->node_off[r], nn = b->node_off[r + 1] - n0, nf = b->nf_of[r];
+        for (int c = 0; c < 6; ++c) {
+            const int64_t p = 6 * r + c, pn0 = pb->node_off[p];
+            for (int64_t q = 0; q < nn; ++q) {
+                const int64_t np_ = pb->newid[pn0 + q];
+                if (np_ < nf) map[pb->free_off[p] + np_] = b->free_off[r] + b->newid[n0 + q];
+            }
+        }
+    }
+    if (hipMalloc((void**)&b->d_probe_map, 8 * (size_t)pb->NFREE + 8) != hipSuccess ||
+        hipMalloc((void**)&b->d_fd_rot, 72 * (size_t)R) != hipSuccess) {
+        rve_batch_destroy(pb);
+        return fail(RVE_ENOMEM, "probe map allocation failed");
+    }
+    if (pb->NFREE) HIP_TRY(hipMemcpy(b->d_probe_map, map.data(), 8 * (size_t)pb->NFREE, hipMemcpyHostToDevice));
+    b->probe = pb;
+    return RVE_OK;
+}
+
+int rve_batch_fd_tangent(rve_batch* b, double h, double* C, double* A, int32_t* status, int32_t ptr_kind)
+{
+    if (!b) return fail(RVE_EINVAL, "batch is NULL");
+    if (ptr_kind != RVE_PTR_HOST && ptr_kind != RVE_PTR_DEVICE) return fail(RVE_EINVAL, "bad ptr_kind");
+    if (!(h > 0.0) || !std::isfinite(h)) return fail(RVE_EINVAL, "h must be positive and finite");
+    if (b->R == 0) return RVE_OK;
+    if (!C || !status) return fail(RVE_EINVAL, "NULL output");
+    if (!b->have_state) return fail(RVE_ESTATE, "no solve yet");
+    int rc = ensure_probe(b);
+    if (rc) return rc;
+    const int64_t R = b->R;
+    rve_batch* pb = b->probe;
+    hipStream_t s = (hipStream_t)b->opts.stream;
+    // probe options follow the base batch (warm start, same stream)
+    {
+        rve_opts o = b->opts;
+        o.init = RVE_INIT_WARM;
+        std::vector<double> cp(6 * R);
+        for (int64_t r = 0; r < R; ++r)
+            for (int c = 0; c < 6; ++c) cp[6 * r + c] = b->c_host[r];
+        o.c_per_rve = cp.data();
+        rc = rve_batch_set_opts(pb, &o);
+        if (rc) return rc;
+    }
+    std::vector<double> F(9 * R), sig(9 * R), Fp(54 * R), Rm(9 * R), sp(54 * R);
+    std::vector<int32_t> st(R), stp(6 * R);
+    HIP_TRY(hipMemcpyAsync(F.data(), b->dF, 72 * R, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(sig.data(), b->dsigma, 72 * R, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(st.data(), b->dstatus, 4 * R, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int64_t r = 0; r < R; ++r) fd_prepare(&F[9 * r], h, &Fp[54 * r], &Rm[9 * r]);
+    HIP_TRY(hipMemcpyAsync(b->d_fd_rot, Rm.data(), 72 * R, hipMemcpyHostToDevice, s));
+    ProbeStateArgs pa{};
+    pa.probe_free_off = pb->net.free_off;
+    pa.map = b->d_probe_map;
+    pa.Rm = b->d_fd_rot;
+    pa.h_base = b->dh;
+    pa.h_probe = pb->dh;
+    HIP_TRY(launch_probe_state(pa, 6 * R, s));
+    pb->have_state = true;
+    rc = rve_batch_solve(pb, Fp.data(), sp.data(), stp.data(), nullptr, RVE_PTR_HOST);
+    if (rc) return rc;
+    std::vector<double> Cout(36 * R), Aout(36 * R);
+    std::vector<int32_t> sout(R);
+    for (int64_t r = 0; r < R; ++r) {
+        int worst = 0;
+        for (int c = 0; c < 6; ++c) worst = std::max(worst, (int)stp[6 * r + c]);
+        bool ok = st[r] == 0 && worst == 0 &&
+                  fd_finish(&F[9 * r], &sig[9 * r], &sp[54 * r], &Fp[54 * r], h, &Cout[36 * r], &Aout[36 * r]);
+        sout[r] = st[r] != 0 ? RVE_ST_NO_STATE : worst;
+        if (!ok) {
+            if (sout[r] == 0) sout[r] = RVE_ST_NONFINITE;
+            for (int k = 0; k < 36; ++k) Cout[36 * r + k] = Aout[36 * r + k] = NAN;
+        }
+    }
+    const hipMemcpyKind k = ptr_kind == RVE_PTR_HOST ? hipMemcpyHostToHost : hipMemcpyHostToDevice;
+    HIP_TRY(hipMemcpyAsync(C, Cout.data(), 288 * R, k, s));
+    if (A) HIP_TRY(hipMemcpyAsync(A, Aout.data(), 288 * R, k, s));
+    HIP_TRY(hipMemcpyAsync(status, sout.data(), 4 * R, k, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return RVE_OK;
+}
+
 int rve_batch_tangent_iters(rve_batch* b, int64_t* iters, int32_t ptr_kind)
 {
     if (!b) return fail(RVE_EINVAL, "batch is NULL");
@@ -1230,6 +1377,9 @@ void rve_batch_destroy(rve_batch* b)
     for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
     if (b->t_mem) (void)hipFree(b->t_mem);
     if (b->o_mem) (void)hipFree(b->o_mem);
+    if (b->probe) rve_batch_destroy(b->probe);
+    if (b->d_probe_map) (void)hipFree(b->d_probe_map);
+    if (b->d_fd_rot) (void)hipFree(b->d_fd_rot);
     if (b->t_slots) (void)hipFree(b->t_slots);
     if (b->dtune_list) (void)hipFree(b->dtune_list);
     if (b->dmem) (void)hipFree(b->dmem);

@@ -98,6 +98,23 @@ struct OrientArgs {
 };
 hipError_t launch_orientation(const OrientArgs& a, int64_t n_rve, hipStream_t s);
 
+// Finite-difference tangent (rve_fd.hip): per-RVE host algebra and the
+// kernel that seeds the probe batch (copy c of RVE r = probe RVE 6 r + c).
+struct ProbeStateArgs {
+    const int64_t* probe_free_off;   // [6R+1]
+    const int64_t* map;              // [NFREE_probe] global base free-node index
+    const double* Rm;                // [R][9] rotation of the polar decomposition
+    const double* h_base;            // [NFREE][3]
+    double* h_probe;                 // [NFREE_probe][3]
+};
+hipError_t launch_probe_state(const ProbeStateArgs& a, int64_t n_probe, hipStream_t s);
+// Fprobe[6][9] = U + h T_c and the rotation Rm[9] of F = R U.
+void fd_prepare(const double* F, double h, double* Fprobe, double* Rm);
+// C[36] (spatial tangent, Mandel 6x6) and A[36] (dPi/dE; may be NULL) from the
+// base stress and the six probe stresses; false when [M][T] is singular.
+bool fd_finish(const double* F, const double* sigma, const double* sigma_probe, const double* Fprobe, double h,
+               double* C, double* A);
+
 // Which register-resident variants exist (threads per RVE, fiber slots per
 // thread, free-node slots per thread).
 struct ResidentVariant {
