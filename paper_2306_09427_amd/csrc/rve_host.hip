@@ -371,7 +371,8 @@ static int default_variant(const rve_batch* b, int tier, bool fp64)
     for (int v = 0; v < kNumResident; ++v) {
         const ResidentVariant& rv = kResident[v];
         if (T && rv.threads != T) continue;
-        if (b->variant_spills[fp64 ? 1 : 0][v] && !T) continue;
+        // variants that spill are never launched (see the autotuner)
+        if (b->variant_spills[fp64 ? 1 : 0][v]) continue;
         if (!variant_fits_tier(v, tier)) continue;
         int64_t key = (int64_t)(rv.sf * 5 + rv.sn * 12) * 4096 - rv.threads;
         if (chosen < 0 || key < best) {
@@ -911,8 +912,12 @@ int rve_batch_autotune(rve_batch* b, const double* F, int32_t ptr_kind, int32_t 
         double best = 1e300;
         int best_v = -1;
         for (int v = -1; v < kNumResident; ++v) {
-            // spilling variants are timed too: for FP64 the register file is the limit
-            if (v >= 0 && !variant_fits_tier(v, (int)t)) continue;
+            // Variants that spill are not candidates: besides being slow, the
+            // FP64 (1024, 4, 2) build returned wrong stresses once its spill
+            // code changed with an unrelated edit (statuses and iteration
+            // counts right, final state wrong); the validity check below
+            // would not see that.
+            if (v >= 0 && (!variant_fits_tier(v, (int)t) || b->variant_spills[fp64 ? 1 : 0][v])) continue;
             int grid = 0;
             if (v >= 0) {
                 int per_cu = 0;
@@ -936,6 +941,18 @@ int rve_batch_autotune(rve_batch* b, const double* F, int32_t ptr_kind, int32_t 
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, b->ev[0], b->ev[1]));
             double per = ms / (fibs * n_iter);
+            // a candidate counts only if every RVE ran the n_iter iterations
+            // with finite state (tol = 0): a variant that stops early on a
+            // non-finite state would otherwise look fast
+            {
+                std::vector<int32_t> stv(b->R);
+                std::vector<int64_t> itv(b->R);
+                HIP_TRY(hipMemcpy(stv.data(), b->dstatus, 4 * (size_t)b->R, hipMemcpyDeviceToHost));
+                HIP_TRY(hipMemcpy(itv.data(), b->diters, 8 * (size_t)b->R, hipMemcpyDeviceToHost));
+                bool valid = true;
+                for (int32_t r : members) valid = valid && stv[r] == RVE_ST_MAXITER && itv[r] == n_iter;
+                if (!valid) continue;
+            }
             if (per < best) {
                 best = per;
                 best_v = v;

@@ -536,12 +536,14 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
     };
     // gather forces and Gershgorin sums of node slot s; lanes whose node has
     // fewer incidences than the wave's largest read the zero slot
-    // The first four incidences are read unconditionally (padding reads the
-    // zero slot), so their LDS reads are issued back to back; nodes of degree
-    // 5..8 (a wave-uniform test) add the rest.
+    // FP32: the first four incidences are read unconditionally (padding reads
+    // the zero slot), so their LDS reads are issued back to back; nodes of
+    // degree 5..8 (a wave-uniform test) add the rest.  FP64 keeps one read at
+    // a time (its register file is the limit).
     auto gather = [&](int s, Real& fx, Real& fy, Real& fz, Real& G) __attribute__((always_inline)) {
         fx = fy = fz = G = Real(0);
-        {
+        int q0 = 0;
+        if constexpr (sizeof(Real) == 4) {
             Real x[4], y[4], z[4], b[4];
             uint32_t code[4];
 #pragma unroll
@@ -554,9 +556,11 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
                 const Real sg = (code[q] & 0x8000u) ? Real(-1) : Real(1);
                 fx = fma(sg, x[q], fx); fy = fma(sg, y[q], fy); fz = fma(sg, z[q], fz); G += b[q];
             }
+            q0 = 4;
         }
 #pragma unroll
-        for (int q = 4; q < kMaxResidentDegree; ++q) {
+        for (int q = 0; q < kMaxResidentDegree; ++q) {
+            if (q < q0) continue;
             if (q >= degw[s]) break;
             uint32_t code = (q & 1) ? (inc[s][q >> 1] >> 16) : (inc[s][q >> 1] & 0xffffu);
             int k = (int)(code & 0x7fffu);
@@ -615,7 +619,6 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
     int64_t n = 0;
     int status = ST_CONVERGED;
     const int ce = A.check_every > 0 ? A.check_every : 1;
-    int to_check = ce;
     double tol = fmax(A.tol_abs, A.tol_rel * sqrt(B2));
     bool done = (sqrt(R2) <= tol);   // v = 0: damping norm is 0
     double Rlast = sqrt(R2), Dlast = 0.0, Blast = sqrt(B2);
@@ -667,9 +670,9 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
         fiber_pass();
         __syncthreads();
         ++n;
-        // every ce-th iteration (a countdown: no 64-bit modulo in the loop)
-        const bool check = --to_check == 0;
-        if (check) to_check = ce;
+        // every ce-th iteration (32-bit remainder: a 64-bit one expands to
+        // dozens of scalar instructions per iteration)
+        const bool check = ((uint32_t)n % (uint32_t)ce) == 0;
         gpart = Real(0);
         r2p = 0.0;
         double d2p = 0.0;
@@ -985,7 +988,6 @@ __device__ __forceinline__ void streamed_solve(const SolveArgs& A, int r, RedSlo
     int64_t n = 0;
     int status = ST_CONVERGED;
     const int ce = A.check_every > 0 ? A.check_every : 1;
-    int to_check = ce;
     double tol = fmax(A.tol_abs, A.tol_rel * sqrt(B2));
     bool done = (sqrt(R2) <= tol);
     double Rlast = sqrt(R2), Dlast = 0.0, Blast = sqrt(B2);
@@ -1014,9 +1016,9 @@ __device__ __forceinline__ void streamed_solve(const SolveArgs& A, int r, RedSlo
         fiber_pass();
         __syncthreads();
         ++n;
-        // every ce-th iteration (a countdown: no 64-bit modulo in the loop)
-        const bool check = --to_check == 0;
-        if (check) to_check = ce;
+        // every ce-th iteration (32-bit remainder: a 64-bit one expands to
+        // dozens of scalar instructions per iteration)
+        const bool check = ((uint32_t)n % (uint32_t)ce) == 0;
         gpart = Real(0);
         r2p = 0.0;
         double d2p = 0.0;
