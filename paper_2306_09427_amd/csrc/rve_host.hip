@@ -911,12 +911,15 @@ int rve_batch_autotune(rve_batch* b, const double* F, int32_t ptr_kind, int32_t 
         a.queue = b->dqueue + 62;
         double best = 1e300;
         int best_v = -1;
+        std::vector<double> href;   // final states, statuses and iterations of the streamed run
+        std::vector<int32_t> sref;
+        std::vector<int64_t> iref;
         for (int v = -1; v < kNumResident; ++v) {
-            // Variants that spill are not candidates: besides being slow, the
-            // FP64 (1024, 4, 2) build returned wrong stresses once its spill
-            // code changed with an unrelated edit (statuses and iteration
-            // counts right, final state wrong); the validity check below
-            // would not see that.
+            // Variants that spill registers are not candidates: the FP64
+            // (1024, 4, 2) build returned wrong final states after an unrelated
+            // edit changed its spill code, and a later build of it faulted.
+            // Each remaining candidate's final states must also stay close to
+            // those of the streamed kernel (timed first) on the tuning RVEs.
             if (v >= 0 && (!variant_fits_tier(v, (int)t) || b->variant_spills[fp64 ? 1 : 0][v])) continue;
             int grid = 0;
             if (v >= 0) {
@@ -941,16 +944,40 @@ int rve_batch_autotune(rve_batch* b, const double* F, int32_t ptr_kind, int32_t 
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, b->ev[0], b->ev[1]));
             double per = ms / (fibs * n_iter);
-            // a candidate counts only if every RVE ran the n_iter iterations
-            // with finite state (tol = 0): a variant that stops early on a
-            // non-finite state would otherwise look fast
+            // A candidate counts only if every tuning RVE that the streamed run
+            // (timed first) took through all n_iter iterations (tol = 0) also
+            // runs them all here, to a final state close to the streamed one.  A variant that stops early on a non-finite state
+            // would otherwise look fast.
             {
                 std::vector<int32_t> stv(b->R);
                 std::vector<int64_t> itv(b->R);
+                std::vector<double> hv(3 * (size_t)b->NFREE);
                 HIP_TRY(hipMemcpy(stv.data(), b->dstatus, 4 * (size_t)b->R, hipMemcpyDeviceToHost));
                 HIP_TRY(hipMemcpy(itv.data(), b->diters, 8 * (size_t)b->R, hipMemcpyDeviceToHost));
+                if (b->NFREE) HIP_TRY(hipMemcpy(hv.data(), b->dh, 24 * (size_t)b->NFREE, hipMemcpyDeviceToHost));
                 bool valid = true;
-                for (int32_t r : members) valid = valid && stv[r] == RVE_ST_MAXITER && itv[r] == n_iter;
+                if (v < 0) {
+                    href = hv;
+                    sref = stv;
+                    iref = itv;
+                } else if (!href.empty()) {
+                    // a coarse check for corrupted states: the trajectories of
+                    // the variants differ in rounding (e.g. 4/G against
+                    // 1/(G/4)), which floppy RVEs amplify over n_iter steps
+                    const double tolh = 0.05;
+                    for (int32_t r : members) {
+                        // RVEs the streamed run lost to a non-finite state say
+                        // nothing about the candidate
+                        if (sref[r] != RVE_ST_MAXITER) continue;
+                        valid = valid && stv[r] == RVE_ST_MAXITER && itv[r] == iref[r];
+                        double dmax = 0.0, hmax = 0.0;
+                        for (int64_t q = 3 * b->free_off[r]; q < 3 * b->free_off[r + 1]; ++q) {
+                            dmax = std::max(dmax, std::fabs(hv[q] - href[q]));
+                            hmax = std::max(hmax, std::fabs(href[q]));
+                        }
+                        valid = valid && std::isfinite(dmax) && dmax <= tolh * std::max(hmax, 1e-30);
+                    }
+                }
                 if (!valid) continue;
             }
             if (per < best) {
