@@ -209,6 +209,30 @@ int rve_batch_autotune(rve_batch* b, const double* F, int32_t ptr_kind, int32_t 
  * buf (NUL-terminated, truncated to n bytes). */
 int rve_batch_describe(const rve_batch* b, char* buf, size_t n);
 
+/*
+ * Caller-owned workspace.  rve_batch_workspace_size reports the bytes of
+ * device memory that cover every work area the batch would otherwise
+ * allocate on demand: the streamed relaxation workspace (sized for FP64, so
+ * any later precision or engine fits), the tangent/VJP arena (per-fiber
+ * operators, incidence records, preconditioner, task tables, outputs) and
+ * solver slots (the larger of tangent and VJP, both engines), the
+ * orientation outputs and the state-export map.  rve_batch_bind_workspace
+ * makes the batch carve those areas from [ptr, ptr + bytes): ptr must be
+ * device memory of the batch's device, 256-byte aligned, and bytes at least
+ * the reported size (RVE_EINVAL otherwise).  The caller keeps ownership
+ * (e.g. a torch tensor) and must keep the memory alive until the batch is
+ * destroyed or another workspace (or NULL) is bound.  Binding waits for the
+ * batch's stream, releases the areas the library had allocated, and
+ * discards what was built in them: the next tangent or VJP call rebuilds its
+ * tables, and rve_batch_tangent_iters reports RVE_ESTATE until then.  With
+ * a workspace bound, solve, tangent, vjp, orientation and state export or
+ * import allocate no device memory.  Binding NULL returns to library-owned
+ * areas.  Not covered: the network and state arrays allocated by create,
+ * the probe batch of rve_batch_fd_tangent and the autotuner's task list.
+ */
+int rve_batch_workspace_size(const rve_batch* b, size_t* bytes);
+int rve_batch_bind_workspace(rve_batch* b, void* ptr, size_t bytes);
+
 /* Number of RVEs, nodes and fibers of the batch. */
 int rve_batch_sizes(const rve_batch* b, int64_t* n_rve, int64_t* n_nodes, int64_t* n_fib);
 
@@ -288,6 +312,35 @@ int rve_batch_orientation(rve_batch* b, const double* e, double* omega, double* 
  * the first such call.
  */
 int rve_batch_tangent_iters(rve_batch* b, int64_t* iters, int32_t ptr_kind);
+
+/*
+ * State export and import (checkpoint and restart; moving RVE states between
+ * batches built from the same networks): the microscale state of an
+ * integration point is its converged fluctuation, from which the next
+ * increment starts (Algorithm "Dynamic Relaxation": free displacements of
+ * an increment start from the last state; Algorithm 1: one RVE state per
+ * macroscale integration point).
+ *   F[n_rve][9]: F of the last solve (or import).
+ *   h[n_nodes][3]: fluctuation x - F Xm of every node, in the caller's node
+ *     numbering of create() (node_off layout); rows of boundary nodes are 0
+ *     on export and ignored on import.
+ *   status[n_rve]: RVE_ST_* of the last solve.
+ * export writes them (RVE_ESTATE before any solve or import).  import
+ * replaces the batch's state with them: statuses outside 0..3 become
+ * RVE_ST_NONFINITE, a non-finite F or det F <= 0 gives RVE_ST_BAD_F; the
+ * stress is re-evaluated from the imported state (the stress kernel of
+ * rve_batch_solve, FP64) and written to sigma[n_rve][9] unless sigma is
+ * NULL; the stored diagnostics become iterations 0 and NaN norms.  Afterwards the batch behaves as after a solve that ended in
+ * that state: rve_batch_tangent, rve_batch_vjp, rve_batch_fd_tangent,
+ * rve_batch_orientation, rve_batch_positions and RVE_INIT_WARM solves use
+ * it.  The caller vouches that an imported "converged" state is one (an
+ * exported state is).  Host pointers (synchronous) or device pointers
+ * (stream-ordered; the first device-pointer call uploads a 4-byte-per-node
+ * map and synchronises).  RVE_EINVAL for batches of 2^31 or more free nodes.
+ */
+int rve_batch_export_state(rve_batch* b, double* F, double* h, int32_t* status, int32_t ptr_kind);
+int rve_batch_import_state(rve_batch* b, const double* F, const double* h, const int32_t* status,
+                           double* sigma, int32_t ptr_kind);
 
 /* Positions x[n_nodes_r][3] of RVE r after the last solve, in the caller's
  * original node order (host pointer; synchronous). */

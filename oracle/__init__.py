@@ -24,6 +24,8 @@ LINEAR, EXP = 0, 1
 INIT_AFFINE, INIT_REFERENCE, INIT_GIVEN = 0, 1, 2
 MASS_LUMPED, MASS_SCALED = 0, 1
 CONVERGED, MAXITER, NONFINITE, BAD_F = 0, 1, 2, 3
+ENERGY = 7
+DAMP_VISCOUS, DAMP_KINETIC, DAMP_ADAPTIVE = 0, 1, 2
 
 
 class Opts(C.Structure):
@@ -59,6 +61,9 @@ def lib():
         L.or_solve.restype = C.c_int
         L.or_solve_batch.argtypes = [i64, P, P, P, P, P, P, P, P, C.POINTER(Opts), C.c_int32,
                                      P, P, P, P, P, P]
+        L.or_solve_variant.argtypes = [i64, i64, P, P, P, C.c_double, P, C.c_double, C.POINTER(Opts),
+                                       C.c_int32, C.c_int32, C.c_double, P, P, P, P, P, P, P]
+        L.or_solve_variant.restype = C.c_int
         _lib = L
     return _lib
 
@@ -130,3 +135,37 @@ def solve_batch(batch, F, c, opts, threads=None, V0=None):
                          _p(np.ascontiguousarray(batch.fib, np.int32)), _p(V0a), _p(F), _p(c),
                          C.byref(opts), int(threads), _p(x), _p(sig), _p(iters), _p(Rr), _p(Dd), _p(st))
     return dict(sigma=sig.reshape(R_, 3, 3), x=x, iters=iters, R=Rr, D=Dd, status=st)
+
+
+def solve_variant(net, F, c, opts, damping=DAMP_VISCOUS, energy_check=False, energy_tol=0.05, x0=None, V0=1.0):
+    """Relax one network with a damping variant (viscous / kinetic / adaptive)
+    and the optional energy-balance check (dr_oracle.c, or_solve_variant).
+    Returns dict(sigma, x, iters, R, D, c, energy, status)."""
+    X = _f64(net.X); ib = np.ascontiguousarray(net.is_bnd, np.uint8)
+    fib = np.ascontiguousarray(net.fib, np.int32); F = _f64(F)
+    x = np.zeros_like(X) if x0 is None else _f64(x0).copy()
+    sig = np.empty(9); it = C.c_int64(0); R = C.c_double(0); D = C.c_double(0)
+    cf = C.c_double(0); e = C.c_double(0)
+    st = lib().or_solve_variant(len(X), len(fib), _p(X), _p(ib), _p(fib), float(V0), _p(F), float(c),
+                                C.byref(opts), int(damping), int(bool(energy_check)), float(energy_tol), _p(x),
+                                _p(sig), C.byref(it), C.byref(R), C.byref(D), C.byref(cf), C.byref(e))
+    return dict(sigma=sig.reshape(3, 3), x=x, iters=it.value, R=R.value, D=D.value, c=cf.value,
+                energy=e.value, status=st)
+
+
+def solve_variant_batch(batch, F, c, opts, damping=DAMP_VISCOUS, energy_check=False, energy_tol=0.05,
+                        threads=None):
+    """solve_variant over every RVE of a packed batch (RVEs spread over threads)."""
+    from concurrent.futures import ThreadPoolExecutor
+    R_ = batch.n_rve
+    F = _f64(F).reshape(R_, 3, 3)
+    c = np.broadcast_to(np.asarray(c, dtype=np.float64), (R_,))
+    with ThreadPoolExecutor(max_workers=threads or os.cpu_count() or 1) as ex:
+        outs = list(ex.map(lambda r: solve_variant(batch.network(r), F[r], c[r], opts, damping, energy_check,
+                                                   energy_tol), range(R_)))
+    keys = ("iters", "R", "D", "c", "energy", "status")
+    res = {k: np.array([o[k] for o in outs]) for k in keys}
+    res["status"] = res["status"].astype(np.int32)
+    res["sigma"] = np.array([o["sigma"] for o in outs])
+    res["x"] = np.concatenate([o["x"] for o in outs]) if outs else np.zeros((0, 3))
+    return res

@@ -302,6 +302,186 @@ int or_solve(int64_t n_nodes, int64_t n_fib, const double* X, const uint8_t* is_
     return status;
 }
 
+/*
+ * Dynamic relaxation with the alternatives the paper lists beside its
+ * constant viscous damping (Section 3.2: kinetic damping, an automatically
+ * updated damping coefficient, and the optional energy-balance check of
+ * the two-step central difference, three whole-state reductions per step).
+ *
+ *   damping 0  viscous, constant c (the same iteration as or_solve);
+ *   damping 1  kinetic: no viscous force; when the kinetic energy
+ *              KE = 1/2 sum M |v|^2 at the full step has dropped below its
+ *              value at the previous full step (a peak was passed), every
+ *              velocity is set to zero and the acceleration to -f/M;
+ *   damping 2  adaptive viscous: after each force evaluation the
+ *              coefficient becomes c = 2 sqrt(u.Ku / u.M u) (critical
+ *              damping of the mode the displacement u = x - x_start
+ *              excites), with the diagonal stiffness estimated from the
+ *              force change over the step, K_kk = df_k / (dt v_k) (DOFs
+ *              with v_k = 0 contribute nothing); c = 0 when u.Ku <= 0; the
+ *              new c enters the damping force of the same step.
+ *
+ *   Energy balance (energy_check != 0): with the boundary fixed during the
+ *   relaxation no external work is done, so the stored energy W, the
+ *   kinetic energy KE and the work removed by damping Wd (viscous: the sum
+ *   over steps of c M v^{n+1/2}.(x^{n+1} - x^n); kinetic: the kinetic
+ *   energy dropped at each reset) satisfy W + KE + Wd = W(x_start).  A
+ *   violation |W + KE + Wd - W0| > energy_tol * max(W0, W, KE, Wd) ends the
+ *   relaxation with OR_ENERGY (an unstable or unphysical trajectory).
+ *
+ * Convergence as in or_solve with the damping-force norm D = c |M v|_2 for
+ * damping 0 and 2, and D = |M v|_2 / dt for kinetic damping (the force that
+ * stops every node within one step).  Outputs as or_solve plus the final
+ * coefficient (c_out; 0 for kinetic damping) and the final relative energy
+ * balance |W + KE + Wd - W0| / max(W0, W, KE, Wd) (e_out; evaluated whether
+ * or not the check is enabled).
+ */
+#define OR_ENERGY 7
+
+int or_solve_variant(int64_t n_nodes, int64_t n_fib, const double* X, const uint8_t* is_bnd,
+                     const int32_t* fib, double V0, const double* F, double c, const or_opts* o,
+                     int32_t damping, int32_t energy_check, double energy_tol, double* x, double* sigma,
+                     int64_t* iters, double* R_out, double* D_out, double* c_out, double* e_out)
+{
+    for (int k = 0; k < 9; ++k) sigma[k] = NAN;
+    *iters = 0;
+    *R_out = NAN;
+    *D_out = NAN;
+    *c_out = NAN;
+    *e_out = NAN;
+    double J = det3(F);
+    int finite = 1;
+    for (int k = 0; k < 9; ++k) finite &= isfinite(F[k]);
+    if (!finite || !(J > 0.0)) return OR_BAD_F;
+
+    size_t nn = (size_t)n_nodes;
+    double* L0 = malloc(sizeof(double) * (size_t)(n_fib > 0 ? n_fib : 1));
+    double* M = calloc(nn ? nn : 1, sizeof(double));
+    double* v = calloc(3 * nn + 1, sizeof(double));
+    double* a = calloc(3 * nn + 1, sizeof(double));
+    double* f = calloc(3 * nn + 1, sizeof(double));
+    double* f_old = calloc(3 * nn + 1, sizeof(double));
+    double* x0 = calloc(3 * nn + 1, sizeof(double));
+    double* G = calloc(nn + 1, sizeof(double));
+
+    or_rest_lengths(n_fib, X, fib, L0);
+    for (int64_t k = 0; k < n_fib; ++k) {
+        M[fib[2 * k]] += 0.5 * o->rhoA * L0[k];
+        M[fib[2 * k + 1]] += 0.5 * o->rhoA * L0[k];
+    }
+    for (int64_t p = 0; p < n_nodes; ++p) {
+        double Xm[3] = {X[3 * p] - 0.5, X[3 * p + 1] - 0.5, X[3 * p + 2] - 0.5};
+        if (is_bnd[p] || o->init == OR_INIT_AFFINE) {
+            matvec3(F, Xm, &x[3 * p]);
+        } else if (o->init == OR_INIT_REFERENCE) {
+            x[3 * p] = Xm[0]; x[3 * p + 1] = Xm[1]; x[3 * p + 2] = Xm[2];
+        }
+    }
+    memcpy(x0, x, sizeof(double) * 3 * nn);
+
+    double W0 = 0.0, W = 0.0;
+    or_forces(n_nodes, n_fib, x, fib, L0, o, f, G, &W0);
+    W = W0;
+    if (o->mass == OR_MASS_SCALED)
+        for (int64_t p = 0; p < n_nodes; ++p) M[p] = G[p] > 0.0 ? G[p] / 4.0 : 1.0;
+    double R2 = 0.0, B2 = 0.0;
+    for (int64_t p = 0; p < n_nodes; ++p) {
+        double s = f[3 * p] * f[3 * p] + f[3 * p + 1] * f[3 * p + 1] + f[3 * p + 2] * f[3 * p + 2];
+        if (is_bnd[p]) { B2 += s; continue; }
+        R2 += s;
+        for (int k = 0; k < 3; ++k) a[3 * p + k] = -f[3 * p + k] / M[p];
+    }
+    double cc = damping == 1 ? 0.0 : c;
+    double R = sqrt(R2), D = 0.0, KE = 0.0, KE_prev = 0.0, Wd = 0.0, ebal = 0.0;
+    double tol = fmax(o->tol_abs, o->tol_rel * sqrt(B2));
+    int64_t n = 0;
+    int status = OR_CONVERGED;
+
+    while (!(R <= tol && D <= tol)) {
+        if (!isfinite(R)) { status = OR_NONFINITE; break; }
+        if (n >= o->n_max) { status = OR_MAXITER; break; }
+        double gmax = 0.0;
+        for (int64_t p = 0; p < n_nodes; ++p)
+            if (!is_bnd[p] && G[p] / M[p] > gmax) gmax = G[p] / M[p];
+        double dt = o->alpha * 2.0 / sqrt(gmax);
+        for (int64_t p = 0; p < n_nodes; ++p) {
+            if (is_bnd[p]) continue;
+            for (int k = 0; k < 3; ++k) {
+                v[3 * p + k] += 0.5 * dt * a[3 * p + k];
+                x[3 * p + k] += dt * v[3 * p + k];
+            }
+        }
+        memcpy(f_old, f, sizeof(double) * 3 * nn);
+        or_forces(n_nodes, n_fib, x, fib, L0, o, f, G, &W);
+        if (damping == 2) {
+            double num = 0.0, den = 0.0;
+            for (int64_t p = 0; p < n_nodes; ++p) {
+                if (is_bnd[p]) continue;
+                for (int k = 0; k < 3; ++k) {
+                    double u = x[3 * p + k] - x0[3 * p + k];
+                    double vk = v[3 * p + k];
+                    if (vk != 0.0) num += u * u * (f[3 * p + k] - f_old[3 * p + k]) / (dt * vk);
+                    den += M[p] * u * u;
+                }
+            }
+            cc = (num > 0.0 && den > 0.0) ? 2.0 * sqrt(num / den) : 0.0;
+        }
+        /* work of the damping force over the step, with the half-step velocity */
+        if (damping != 1)
+            for (int64_t p = 0; p < n_nodes; ++p) {
+                if (is_bnd[p]) continue;
+                for (int k = 0; k < 3; ++k) Wd += cc * M[p] * v[3 * p + k] * v[3 * p + k] * dt;
+            }
+        R2 = 0.0; B2 = 0.0;
+        double MV2 = 0.0;
+        KE = 0.0;
+        for (int64_t p = 0; p < n_nodes; ++p) {
+            double s = f[3 * p] * f[3 * p] + f[3 * p + 1] * f[3 * p + 1] + f[3 * p + 2] * f[3 * p + 2];
+            if (is_bnd[p]) { B2 += s; continue; }
+            R2 += s;
+            for (int k = 0; k < 3; ++k) {
+                a[3 * p + k] = -(f[3 * p + k] + cc * M[p] * v[3 * p + k]) / M[p];
+                v[3 * p + k] += 0.5 * dt * a[3 * p + k];
+                double mv = M[p] * v[3 * p + k];
+                MV2 += mv * mv;
+                KE += 0.5 * M[p] * v[3 * p + k] * v[3 * p + k];
+            }
+        }
+        if (damping == 1) {
+            if (KE < KE_prev) {
+                Wd += KE;
+                KE = 0.0;
+                MV2 = 0.0;
+                for (int64_t p = 0; p < n_nodes; ++p) {
+                    if (is_bnd[p]) continue;
+                    for (int k = 0; k < 3; ++k) {
+                        v[3 * p + k] = 0.0;
+                        a[3 * p + k] = -f[3 * p + k] / M[p];
+                    }
+                }
+            }
+            KE_prev = KE;
+        }
+        double scale = fmax(fmax(W0, W), fmax(KE, Wd));
+        ebal = scale > 0.0 ? fabs(W + KE + Wd - W0) / scale : 0.0;
+        R = sqrt(R2);
+        D = damping == 1 ? sqrt(MV2) / dt : cc * sqrt(MV2);
+        tol = fmax(o->tol_abs, o->tol_rel * sqrt(B2));
+        ++n;
+        if (energy_check && ebal > energy_tol) { status = OR_ENERGY; break; }
+    }
+    if (status == OR_CONVERGED && !isfinite(R)) status = OR_NONFINITE;
+    *iters = n;
+    *R_out = R;
+    *D_out = D;
+    *c_out = cc;
+    *e_out = ebal;
+    if (status != OR_NONFINITE) or_stress(n_nodes, x, f, is_bnd, F, V0, sigma);
+
+    free(L0); free(M); free(v); free(a); free(f); free(f_old); free(x0); free(G);
+    return status;
+}
+
 /* ------------------------------------------------------------ batch driver */
 typedef struct {
     int64_t n_rve;

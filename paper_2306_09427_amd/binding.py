@@ -29,7 +29,8 @@ EXPORTS = ["rve_version", "rve_last_error", "rve_default_opts", "rve_batch_creat
            "rve_batch_set_stream", "rve_batch_sizes", "rve_batch_solve", "rve_batch_tangent", "rve_batch_vjp",
            "rve_batch_positions", "rve_batch_destroy", "rve_batch_profile", "rve_batch_kernel_ms",
            "rve_batch_autotune", "rve_batch_describe", "rve_batch_groups", "rve_batch_tangent_iters", "rve_batch_orientation",
-           "rve_batch_fd_tangent"]
+           "rve_batch_fd_tangent", "rve_batch_export_state", "rve_batch_import_state",
+           "rve_batch_workspace_size", "rve_batch_bind_workspace"]
 
 
 class NetDesc(C.Structure):
@@ -87,6 +88,10 @@ def lib():
         L.rve_batch_tangent_iters.argtypes = [P, P, C.c_int32]
         L.rve_batch_orientation.argtypes = [P, P, P, P, C.c_int32]
         L.rve_batch_fd_tangent.argtypes = [P, C.c_double, P, P, P, C.c_int32]
+        L.rve_batch_export_state.argtypes = [P, P, P, P, C.c_int32]
+        L.rve_batch_import_state.argtypes = [P, P, P, P, P, C.c_int32]
+        L.rve_batch_workspace_size.argtypes = [P, C.POINTER(C.c_size_t)]
+        L.rve_batch_bind_workspace.argtypes = [P, P, C.c_size_t]
         L.rve_batch_destroy.argtypes = [P]
         L.rve_batch_destroy.restype = None
         _lib = L
@@ -245,6 +250,59 @@ class Batch:
         ev = np.ascontiguousarray(np.asarray(e, dtype=np.float64).reshape(3))
         _check(lib().rve_batch_orientation(self._h, ev.ctypes.data, _ptr(om)[0], _ptr(p2)[0], _ptr(om)[1]))
         return om, p2
+
+    def export_state(self, like=None):
+        """(F [R,3,3], h [nodes,3] in the caller's node order, status [R]) of the last solve or import."""
+        ref = like if like is not None else np.empty(0)
+        Fo = self._outs(ref, (3, 3), np.float64)
+        st = self._outs(ref, (), np.int32)
+        nn = int(self.node_off[-1])
+        if hasattr(ref, "data_ptr"):
+            import torch
+            h = torch.empty((nn, 3), dtype=torch.float64, device=ref.device)
+        else:
+            h = np.empty((nn, 3), np.float64)
+        _check(lib().rve_batch_export_state(self._h, _ptr(Fo)[0], _ptr(h)[0], _ptr(st)[0], _ptr(Fo)[1]))
+        return Fo, h, st
+
+    def import_state(self, F, h, status):
+        """Replace the batch's state (F, fluctuation h per caller node, status).
+        Returns the stress [R,3,3] re-evaluated at the imported state."""
+        nn = int(self.node_off[-1])
+        if hasattr(F, "data_ptr"):
+            import torch
+            F, h, status = F.contiguous(), h.contiguous(), status.contiguous()
+            if not (F.device == h.device == status.device):
+                raise ValueError("F, h and status must live on one device")
+            if F.dtype != torch.float64 or h.dtype != torch.float64 or status.dtype != torch.int32:
+                raise ValueError("F and h must be float64, status int32")
+            if F.numel() != 9 * self.n_rve or h.numel() != 3 * nn or status.numel() != self.n_rve:
+                raise ValueError("F, h or status has the wrong size")
+        else:
+            F = np.ascontiguousarray(F, np.float64).reshape(self.n_rve, 3, 3)
+            h = np.ascontiguousarray(h, np.float64).reshape(nn, 3)
+            status = np.ascontiguousarray(status, np.int32).reshape(self.n_rve)
+        sig = self._outs(F, (3, 3), np.float64)
+        fp, kind = _ptr(F)
+        _check(lib().rve_batch_import_state(self._h, fp, _ptr(h)[0], _ptr(status)[0], _ptr(sig)[0], kind))
+        return sig
+
+    def workspace_size(self):
+        """Bytes of device memory that cover every on-demand work area of the batch."""
+        n = C.c_size_t()
+        _check(lib().rve_batch_workspace_size(self._h, C.byref(n)))
+        return n.value
+
+    def bind_workspace(self, buf):
+        """Carve the batch's work areas from `buf` (a device tensor the caller
+        owns; kept referenced here), or return to library-owned areas (None)."""
+        if buf is None:
+            _check(lib().rve_batch_bind_workspace(self._h, None, 0))
+            self._ws = None
+            return
+        nbytes = buf.numel() * buf.element_size()
+        _check(lib().rve_batch_bind_workspace(self._h, buf.data_ptr(), nbytes))
+        self._ws = buf
 
     def tangent_iters(self):
         """Inner CG iterations of the last tangent/vjp call, summed per RVE (host int64 [R])."""

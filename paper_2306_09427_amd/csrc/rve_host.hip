@@ -114,6 +114,14 @@ struct rve_batch {
     // autotuner choice per [fp64][tier]: -2 untuned, -1 streamed, else a resident variant
     int tuned[2][8] = {{-2, -2, -2, -2, -2, -2, -2, -2}, {-2, -2, -2, -2, -2, -2, -2, -2}};
     int32_t* dtune_list = nullptr;
+    int32_t* d_state_map = nullptr;    // [NN] packed global free index of each caller node, -1 boundary
+    bool state_map_ready = false;
+    bool t_tables = false;             // tangent arena carved, task tables uploaded
+    // caller-provided workspace (rve_batch_bind_workspace): the streamed
+    // workspace, tangent arena and slots, orientation outputs and state map
+    // point into it and are never freed by the library
+    char* ws_user = nullptr;
+    size_t ws_user_bytes = 0;
 };
 
 // Size tiers: distinct (fiber, node) capacities of the resident variants, ascending.
@@ -456,6 +464,8 @@ static int ensure_workspace(rve_batch* b)
     const size_t r4 = b->opts.precision == RVE_FP64 ? 32 : 16;
     size_t fb = r4 * 3 * (size_t)(b->NF + b->R);
     size_t nb = r4 * (2 * (size_t)(b->NFREE + b->R) + 2 * (size_t)b->NFREE + 1);
+    if ((fb > b->ws_fib_bytes || nb > b->ws_node_bytes) && b->ws_user)
+        return fail(RVE_EINVAL, "internal: bound workspace smaller than the streamed workspace");
     if (fb > b->ws_fib_bytes) {
         if (b->ws_fib) (void)hipFree(b->ws_fib);
         b->ws_fib = nullptr;
@@ -1035,72 +1045,221 @@ int rve_batch_positions(rve_batch* b, int64_t r, double* x)
     return RVE_OK;
 }
 
+// Packed global free index of caller node n of the batch (-1: boundary node).
+static std::vector<int32_t> state_map_host(const rve_batch* b)
+{
+    std::vector<int32_t> map(b->NN);
+    for (int64_t r = 0; r < b->R; ++r) {
+        const int64_t n0 = b->node_off[r], nn = b->node_off[r + 1] - n0, nf = b->nf_of[r];
+        for (int64_t p = 0; p < nn; ++p) {
+            const int64_t q = b->newid[n0 + p];
+            map[n0 + p] = q < nf ? (int32_t)(b->free_off[r] + q) : -1;
+        }
+    }
+    return map;
+}
+
+static int ensure_state_map(rve_batch* b)
+{
+    if (b->state_map_ready) return RVE_OK;
+    if (b->NFREE >= INT32_MAX) return fail(RVE_EINVAL, "state export/import supports fewer than 2^31 free nodes");
+    std::vector<int32_t> map;
+    try {
+        map = state_map_host(b);
+    } catch (const std::bad_alloc&) {
+        return fail(RVE_ENOMEM, "host allocation failed for the state map");
+    }
+    if (!b->d_state_map && hipMalloc((void**)&b->d_state_map, 4 * (size_t)b->NN + 4) != hipSuccess) {
+        b->d_state_map = nullptr;
+        return fail(RVE_ENOMEM, "state map allocation failed");
+    }
+    HIP_TRY(hipMemcpy(b->d_state_map, map.data(), 4 * (size_t)b->NN, hipMemcpyHostToDevice));
+    b->state_map_ready = true;
+    return RVE_OK;
+}
+
+int rve_batch_export_state(rve_batch* b, double* F, double* h, int32_t* status, int32_t ptr_kind)
+{
+    if (!b) return fail(RVE_EINVAL, "batch is NULL");
+    if (ptr_kind != RVE_PTR_HOST && ptr_kind != RVE_PTR_DEVICE) return fail(RVE_EINVAL, "bad ptr_kind");
+    if (!b->have_state) return fail(RVE_ESTATE, "no solve or import yet");
+    if (b->R == 0) return RVE_OK;
+    if (!F || !h || !status) return fail(RVE_EINVAL, "F, h and status are required");
+    hipStream_t s = (hipStream_t)b->opts.stream;
+    if (ptr_kind == RVE_PTR_DEVICE) {
+        int rc = ensure_state_map(b);
+        if (rc) return rc;
+        HIP_TRY(launch_export_h(b->dh, b->d_state_map, b->NN, h, s));
+        HIP_TRY(hipMemcpyAsync(F, b->dF, 72 * (size_t)b->R, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(status, b->dstatus, 4 * (size_t)b->R, hipMemcpyDeviceToDevice, s));
+        return RVE_OK;
+    }
+    std::vector<double> hp;
+    std::vector<int32_t> map;
+    try {
+        hp.resize(3 * (size_t)b->NFREE);
+        map = state_map_host(b);
+    } catch (const std::bad_alloc&) {
+        return fail(RVE_ENOMEM, "host allocation failed for the state export");
+    }
+    if (b->NFREE) HIP_TRY(hipMemcpyAsync(hp.data(), b->dh, 24 * (size_t)b->NFREE, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(F, b->dF, 72 * (size_t)b->R, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(status, b->dstatus, 4 * (size_t)b->R, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int64_t n = 0; n < b->NN; ++n)
+        for (int c = 0; c < 3; ++c) h[3 * n + c] = map[n] >= 0 ? hp[3 * (size_t)map[n] + c] : 0.0;
+    return RVE_OK;
+}
+
+int rve_batch_import_state(rve_batch* b, const double* F, const double* h, const int32_t* status, double* sigma,
+                           int32_t ptr_kind)
+{
+    if (!b) return fail(RVE_EINVAL, "batch is NULL");
+    if (ptr_kind != RVE_PTR_HOST && ptr_kind != RVE_PTR_DEVICE) return fail(RVE_EINVAL, "bad ptr_kind");
+    if (b->R == 0) return RVE_OK;
+    if (!F || !h || !status) return fail(RVE_EINVAL, "F, h and status are required");
+    hipStream_t s = (hipStream_t)b->opts.stream;
+    if (ptr_kind == RVE_PTR_DEVICE) {
+        int rc = ensure_state_map(b);
+        if (rc) return rc;
+        HIP_TRY(launch_import_h(h, b->d_state_map, b->NN, b->dh, s));
+        HIP_TRY(hipMemcpyAsync(b->dF, F, 72 * (size_t)b->R, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(launch_import_status(b->dF, status, b->R, b->dstatus, b->diters, b->dR, b->dD, b->dB, s));
+    } else {
+        std::vector<double> hp;
+        std::vector<int32_t> map;
+        try {
+            hp.resize(3 * (size_t)b->NFREE);
+            map = state_map_host(b);
+        } catch (const std::bad_alloc&) {
+            return fail(RVE_ENOMEM, "host allocation failed for the state import");
+        }
+        for (int64_t n = 0; n < b->NN; ++n)
+            if (map[n] >= 0)
+                for (int c = 0; c < 3; ++c) hp[3 * (size_t)map[n] + c] = h[3 * n + c];
+        // the status input goes through the device copy of the last statuses
+        // (the kernel reads it before writing the checked value in place)
+        if (b->NFREE) HIP_TRY(hipMemcpyAsync(b->dh, hp.data(), 24 * (size_t)b->NFREE, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(b->dF, F, 72 * (size_t)b->R, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(b->dstatus, status, 4 * (size_t)b->R, hipMemcpyHostToDevice, s));
+        HIP_TRY(launch_import_status(b->dF, b->dstatus, b->R, b->dstatus, b->diters, b->dR, b->dD, b->dB, s));
+    }
+    SolveArgs a;
+    fill_solve_args(b, a);
+    HIP_TRY(launch_stress(a, (int)b->R, s));
+    if (sigma)
+        HIP_TRY(hipMemcpyAsync(sigma, b->dsigma, 72 * (size_t)b->R,
+                               ptr_kind == RVE_PTR_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s));
+    if (ptr_kind == RVE_PTR_HOST) HIP_TRY(hipStreamSynchronize(s));
+    b->have_state = true;
+    return RVE_OK;
+}
+
 // Tangent workspace: fiber operators, ELL records, preconditioner, chunk
 // tables and task groups for the whole batch (allocated once), and the
 // per-workgroup solver slots (`slot_bytes`, grown on demand).
+// Offsets of the tangent arena: fiber operators, ELL records,
+// preconditioner, chunk tables, outputs/inputs, statuses, iterations, order.
+struct TanArena {
+    size_t par, rs, ra, rb, pc, cf, cr, out, in, st, it, ord, bytes;
+};
+
+static TanArena tangent_arena(const rve_batch* b)
+{
+    const int64_t nch = (int64_t)b->chunk_rec.size() - 1, nrec = b->chunk_rec.back();
+    DeviceArena A;
+    TanArena t;
+    t.par = A.reserve(48 * (size_t)b->NF);
+    t.rs = A.reserve(8 * (size_t)nrec);
+    t.ra = A.reserve(16 * (size_t)nrec);
+    t.rb = A.reserve(8 * (size_t)nrec);
+    t.pc = A.reserve(32 * (size_t)b->NFREE);
+    t.cf = A.reserve(8 * (size_t)(b->R + 1));
+    t.cr = A.reserve(8 * (size_t)(nch + 1));
+    t.out = A.reserve(8 * 81 * (size_t)b->R);
+    t.in = A.reserve(8 * 9 * (size_t)b->R);
+    t.st = A.reserve(4 * (size_t)b->R);
+    t.it = A.reserve(8 * (size_t)b->R);
+    t.ord = A.reserve(4 * (size_t)b->R);
+    t.bytes = A.used + 256;
+    return t;
+}
+
+// Task groups of the tangent (host tables, computed once): RVEs for each
+// resident variant (smallest that holds the RVE), then the rest for the
+// streamed kernel; longest first in each.
+static void tangent_groups(rve_batch* b)
+{
+    if (!b->t_group_first.empty()) return;
+    std::vector<int32_t> lpt(b->R);
+    for (int64_t r = 0; r < b->R; ++r) lpt[r] = (int32_t)r;
+    std::stable_sort(lpt.begin(), lpt.end(), [&](int32_t x, int32_t y) { return b->nf_of[x] > b->nf_of[y]; });
+    std::vector<int32_t> order;
+    order.reserve(b->R);
+    std::vector<int64_t> first(kNumTanRes + 2, 0);
+    for (int v = 0; v <= kNumTanRes; ++v) {
+        first[v] = (int64_t)order.size();
+        for (int32_t r : lpt) {
+            int g = kNumTanRes;
+            for (int u = 0; u < kNumTanRes; ++u)
+                if (b->nf_of[r] <= (int64_t)kTanRes[u].threads * kTanRes[u].sn) {
+                    g = u;
+                    break;
+                }
+            if (g == v) order.push_back(r);
+        }
+    }
+    first[kNumTanRes + 1] = (int64_t)order.size();
+    b->t_order_host = order;
+    b->t_group_first = first;
+}
+
+// Tangent workspace: the arena (carved once, from the caller's workspace when
+// one is bound) with its task tables uploaded, and the per-workgroup solver
+// slots (`slot_bytes`, grown on demand unless the workspace is bound).
 static int ensure_tangent_ws(rve_batch* b, size_t slot_bytes)
 {
-    if (!b->t_mem) {
-        const int64_t nch = (int64_t)b->chunk_rec.size() - 1, nrec = b->chunk_rec.back();
-        DeviceArena A;
-        size_t o_par = A.reserve(48 * (size_t)b->NF), o_rs = A.reserve(8 * (size_t)nrec), o_ra = A.reserve(16 * (size_t)nrec),
-               o_rb = A.reserve(8 * (size_t)nrec), o_pc = A.reserve(32 * (size_t)b->NFREE),
-               o_cf = A.reserve(8 * (size_t)(b->R + 1)), o_cr = A.reserve(8 * (size_t)(nch + 1)),
-               o_out = A.reserve(8 * 81 * (size_t)b->R), o_in = A.reserve(8 * 9 * (size_t)b->R),
-               o_st = A.reserve(4 * (size_t)b->R), o_it = A.reserve(8 * (size_t)b->R),
-               o_ord = A.reserve(4 * (size_t)b->R);
-        if (hipMalloc((void**)&b->t_mem, A.used + 256) != hipSuccess) {
-            b->t_mem = nullptr;
-            return fail(RVE_ENOMEM, "tangent workspace allocation failed");
-        }
-        char* m = b->t_mem;
-        b->t_par64 = carve<double>(m, o_par);
-        b->t_rec_static = carve<int2>(m, o_rs);
-        b->t_recA = carve<float4>(m, o_ra);
-        b->t_recB = carve<int2>(m, o_rb);
-        b->t_precond = carve<float4>(m, o_pc);
-        b->t_chunk_first = carve<int64_t>(m, o_cf);
-        b->t_chunk_rec = carve<int64_t>(m, o_cr);
-        b->t_out = carve<double>(m, o_out);
-        b->t_in = carve<double>(m, o_in);
-        b->t_status = carve<int32_t>(m, o_st);
-        b->t_iters = carve<int64_t>(m, o_it);
-        b->t_order = carve<int32_t>(m, o_ord);
-        // task groups: RVEs for each resident variant (smallest that holds the
-        // RVE), then the rest for the wavefront kernel; longest first in each
-        std::vector<int32_t> lpt(b->R);
-        for (int64_t r = 0; r < b->R; ++r) lpt[r] = (int32_t)r;
-        std::stable_sort(lpt.begin(), lpt.end(), [&](int32_t x, int32_t y) { return b->nf_of[x] > b->nf_of[y]; });
-        std::vector<int32_t> order;
-        order.reserve(b->R);
-        b->t_group_first.assign(kNumTanRes + 2, 0);
-        for (int v = 0; v <= kNumTanRes; ++v) {
-            b->t_group_first[v] = (int64_t)order.size();
-            for (int32_t r : lpt) {
-                int g = kNumTanRes;
-                for (int u = 0; u < kNumTanRes; ++u)
-                    if (b->nf_of[r] <= (int64_t)kTanRes[u].threads * kTanRes[u].sn) {
-                        g = u;
-                        break;
-                    }
-                if (g == v) order.push_back(r);
+    if (!b->t_tables) {
+        const TanArena t = tangent_arena(b);
+        const int64_t nch = (int64_t)b->chunk_rec.size() - 1;
+        if (!b->t_mem) {
+            if (b->ws_user) return fail(RVE_EINVAL, "internal: bound workspace has no tangent arena");
+            if (hipMalloc((void**)&b->t_mem, t.bytes) != hipSuccess) {
+                b->t_mem = nullptr;
+                return fail(RVE_ENOMEM, "tangent workspace allocation failed");
             }
         }
-        b->t_group_first[kNumTanRes + 1] = (int64_t)order.size();
-        b->t_order_host = order;
-        hipError_t e = hipMemcpy(b->t_order, order.data(), 4 * (size_t)b->R, hipMemcpyHostToDevice);
+        char* m = b->t_mem;
+        b->t_par64 = carve<double>(m, t.par);
+        b->t_rec_static = carve<int2>(m, t.rs);
+        b->t_recA = carve<float4>(m, t.ra);
+        b->t_recB = carve<int2>(m, t.rb);
+        b->t_precond = carve<float4>(m, t.pc);
+        b->t_chunk_first = carve<int64_t>(m, t.cf);
+        b->t_chunk_rec = carve<int64_t>(m, t.cr);
+        b->t_out = carve<double>(m, t.out);
+        b->t_in = carve<double>(m, t.in);
+        b->t_status = carve<int32_t>(m, t.st);
+        b->t_iters = carve<int64_t>(m, t.it);
+        b->t_order = carve<int32_t>(m, t.ord);
+        tangent_groups(b);
+        hipError_t e = hipMemcpy(b->t_order, b->t_order_host.data(), 4 * (size_t)b->R, hipMemcpyHostToDevice);
         if (e == hipSuccess)
             e = hipMemcpy(b->t_chunk_first, b->chunk_first.data(), 8 * (size_t)(b->R + 1), hipMemcpyHostToDevice);
         if (e == hipSuccess)
             e = hipMemcpy(b->t_chunk_rec, b->chunk_rec.data(), 8 * (size_t)(nch + 1), hipMemcpyHostToDevice);
         if (e != hipSuccess) {
-            (void)hipFree(b->t_mem);
-            b->t_mem = nullptr;
+            if (!b->ws_user) {
+                (void)hipFree(b->t_mem);
+                b->t_mem = nullptr;
+            }
             return fail(RVE_EDEVICE, std::string("tangent table upload: ") + hipGetErrorString(e));
         }
         b->t_static_built = false;
+        b->t_tables = true;
     }
     if (slot_bytes > b->t_slot_bytes) {
+        if (b->ws_user) return fail(RVE_EINVAL, "internal: bound workspace smaller than the tangent slots");
         if (b->t_slots) (void)hipFree(b->t_slots);
         b->t_slots = nullptr;
         b->t_slot_bytes = 0;
@@ -1110,6 +1269,157 @@ static int ensure_tangent_ws(rve_batch* b, size_t slot_bytes)
         }
         b->t_slot_bytes = slot_bytes;
     }
+    return RVE_OK;
+}
+
+// Launch plan of a tangent (mode 0, nine right-hand sides per RVE) or VJP
+// (mode 1) call: task ranges per kernel variant in the task order, grid and
+// slot length S per launch, and the slot bytes the plan needs.  Engines other
+// than AUTO run every task on the 64-thread streamed kernel.
+static int tangent_plan(rve_batch* b, int mode, int engine, std::vector<int64_t>& gf, int* grid, int64_t* S,
+                        size_t* slot_bytes)
+{
+    tangent_groups(b);
+    const int per = mode == 0 ? 9 : 1;
+    gf = b->t_group_first;
+    if (engine != RVE_ENGINE_AUTO) {
+        for (int v = 0; v <= kNumTanRes; ++v) gf[v] = 0;
+        gf[kNumTanRes + 1] = b->R;
+    }
+    *slot_bytes = 0;
+    const int stream_threads = engine == RVE_ENGINE_AUTO ? 1024 : 64;
+    for (int v = 0; v <= kNumTanRes; ++v) {
+        const int64_t tasks = (gf[v + 1] - gf[v]) * per;
+        grid[v] = 0;
+        S[v] = 1;
+        if (tasks == 0) continue;
+        if (v < kNumTanRes) {
+            int bpc = 0;
+            HIP_TRY(tangent_res_blocks(v, mode != 0, &bpc));
+            if (bpc < 1) return fail(RVE_EDEVICE, "tangent kernel does not fit a compute unit");
+            grid[v] = (int)std::min<int64_t>((int64_t)bpc * b->n_cu, tasks);
+            S[v] = (int64_t)kTanRes[v].threads * kTanRes[v].sn + 1;
+            *slot_bytes = std::max(*slot_bytes, 64 * (size_t)S[v] * (size_t)grid[v]);
+        } else {
+            // streamed: one 1024-thread workgroup per CU for the RVEs too large
+            // for LDS, or one wavefront per task (8 per CU) on the STREAMED engine
+            grid[v] = (int)std::min<int64_t>((int64_t)b->n_cu * (stream_threads == 64 ? 8 : 1), tasks);
+            for (int64_t r = 0; r < b->R; ++r) S[v] = std::max<int64_t>(S[v], b->nf_of[r] + 1);
+            *slot_bytes = std::max(*slot_bytes, 128 * (size_t)S[v] * (size_t)grid[v]);
+        }
+    }
+    return RVE_OK;
+}
+
+// Caller-provided workspace: the streamed workspace (sized for FP64, so a
+// change of precision never outgrows it), the tangent arena, the largest
+// tangent/VJP slot area over both engines, the orientation outputs and the
+// state map, each at a 256-byte aligned offset.
+struct WsLayout {
+    size_t fib, node, tmem, slots, omem, smap;
+    size_t o_fib, o_node, o_tmem, o_slots, o_omem, o_smap, total;
+};
+
+static int ws_layout(rve_batch* b, WsLayout& L)
+{
+    L.fib = 32 * 3 * (size_t)(b->NF + b->R);
+    L.node = 32 * (2 * (size_t)(b->NFREE + b->R) + 2 * (size_t)b->NFREE + 1);
+    L.tmem = tangent_arena(b).bytes;
+    L.slots = 0;
+    for (int mode = 0; mode < 2; ++mode)
+        for (int engine : {(int)RVE_ENGINE_AUTO, (int)RVE_ENGINE_STREAMED}) {
+            std::vector<int64_t> gf;
+            int grid[kNumTanRes + 1];
+            int64_t S[kNumTanRes + 1];
+            size_t sb = 0;
+            int rc = tangent_plan(b, mode, engine, gf, grid, S, &sb);
+            if (rc) return rc;
+            L.slots = std::max(L.slots, sb);
+        }
+    L.omem = 80 * (size_t)b->R;
+    L.smap = 4 * (size_t)b->NN + 4;
+    DeviceArena A;
+    L.o_fib = A.reserve(L.fib);
+    L.o_node = A.reserve(L.node);
+    L.o_tmem = A.reserve(L.tmem);
+    L.o_slots = A.reserve(L.slots);
+    L.o_omem = A.reserve(L.omem);
+    L.o_smap = A.reserve(L.smap);
+    L.total = A.used;
+    return RVE_OK;
+}
+
+int rve_batch_workspace_size(const rve_batch* cb, size_t* bytes)
+{
+    if (!cb || !bytes) return fail(RVE_EINVAL, "NULL argument");
+    // the layout caches the tangent's host task tables in the batch
+    rve_batch* b = const_cast<rve_batch*>(cb);
+    WsLayout L;
+    int rc = ws_layout(b, L);
+    if (rc) return rc;
+    *bytes = L.total;
+    return RVE_OK;
+}
+
+// Free the library-owned workspace regions (when no caller workspace is
+// bound) and forget every region pointer; tables built in them are rebuilt.
+static void drop_workspace(rve_batch* b)
+{
+    if (!b->ws_user) {
+        if (b->ws_fib) (void)hipFree(b->ws_fib);
+        if (b->ws_node) (void)hipFree(b->ws_node);
+        if (b->t_mem) (void)hipFree(b->t_mem);
+        if (b->t_slots) (void)hipFree(b->t_slots);
+        if (b->o_mem) (void)hipFree(b->o_mem);
+        if (b->d_state_map) (void)hipFree(b->d_state_map);
+    }
+    b->ws_fib = b->ws_node = nullptr;
+    b->ws_fib_bytes = b->ws_node_bytes = 0;
+    b->t_mem = nullptr;
+    b->t_slots = nullptr;
+    b->t_slot_bytes = 0;
+    b->o_mem = nullptr;
+    b->d_state_map = nullptr;
+    b->t_tables = false;
+    b->t_static_built = false;
+    b->state_map_ready = false;
+    b->ws_user = nullptr;
+    b->ws_user_bytes = 0;
+}
+
+int rve_batch_bind_workspace(rve_batch* b, void* ptr, size_t bytes)
+{
+    if (!b) return fail(RVE_EINVAL, "batch is NULL");
+    WsLayout L;
+    int rc = ws_layout(b, L);
+    if (rc) return rc;
+    if (ptr) {
+        if (reinterpret_cast<uintptr_t>(ptr) & 255) return fail(RVE_EINVAL, "workspace must be 256-byte aligned");
+        if (bytes < L.total)
+            return fail(RVE_EINVAL, "workspace too small: " + std::to_string(L.total) + " bytes needed");
+        hipPointerAttribute_t at{};
+        if (hipPointerGetAttributes(&at, ptr) != hipSuccess || at.type != hipMemoryTypeDevice ||
+            at.device != b->device) {
+            (void)hipGetLastError();
+            return fail(RVE_EINVAL, "workspace must be device memory of the batch's device");
+        }
+    }
+    // work already queued may still use the current regions
+    HIP_TRY(hipStreamSynchronize((hipStream_t)b->opts.stream));
+    drop_workspace(b);
+    if (!ptr) return RVE_OK;
+    char* m = static_cast<char*>(ptr);
+    b->ws_user = m;
+    b->ws_user_bytes = bytes;
+    b->ws_fib = m + L.o_fib;
+    b->ws_fib_bytes = L.fib;
+    b->ws_node = m + L.o_node;
+    b->ws_node_bytes = L.node;
+    b->t_mem = m + L.o_tmem;
+    b->t_slots = m + L.o_slots;
+    b->t_slot_bytes = L.slots;
+    b->o_mem = reinterpret_cast<double*>(m + L.o_omem);
+    b->d_state_map = reinterpret_cast<int32_t*>(m + L.o_smap);
     return RVE_OK;
 }
 
@@ -1123,43 +1433,18 @@ static int run_cg(rve_batch* b, int mode, const double* gsigma, double* out, int
     // allocate the batch tables first (task groups), then size the slots
     int rc = ensure_tangent_ws(b, 0);
     if (rc) return rc;
-    const int per = mode == 0 ? 9 : 1;
-    // task ranges in t_order: one per resident variant, then the wavefront
-    // kernel; engines other than AUTO run every task on the wavefront kernel
-    std::vector<int64_t> gf = b->t_group_first;
-    if (b->opts.engine != RVE_ENGINE_AUTO) {
-        for (int v = 0; v <= kNumTanRes; ++v) gf[v] = 0;
-        gf[kNumTanRes + 1] = b->R;
-    }
+    const int stream_threads = b->opts.engine == RVE_ENGINE_AUTO ? 1024 : 64;
+    std::vector<int64_t> gf;
+    int grid[kNumTanRes + 1];
+    int64_t S[kNumTanRes + 1];
+    size_t slot_bytes = 0;
+    rc = tangent_plan(b, mode, b->opts.engine, gf, grid, S, &slot_bytes);
+    if (rc) return rc;
     // largest free-node count of each launch's RVEs
     b->t_max_nf.assign(kNumTanRes + 1, 0);
     for (int v = 0; v <= kNumTanRes; ++v)
         for (int64_t q = gf[v]; q < gf[v + 1]; ++q)
             b->t_max_nf[v] = std::max<int64_t>(b->t_max_nf[v], b->nf_of[b->t_order_host[q]]);
-    int grid[kNumTanRes + 1];
-    int64_t S[kNumTanRes + 1];
-    size_t slot_bytes = 0;
-    const int stream_threads = b->opts.engine == RVE_ENGINE_AUTO ? 1024 : 64;
-    for (int v = 0; v <= kNumTanRes; ++v) {
-        const int64_t tasks = (gf[v + 1] - gf[v]) * per;
-        grid[v] = 0;
-        S[v] = 1;
-        if (tasks == 0) continue;
-        if (v < kNumTanRes) {
-            int bpc = 0;
-            HIP_TRY(tangent_res_blocks(v, mode != 0, &bpc));
-            if (bpc < 1) return fail(RVE_EDEVICE, "tangent kernel does not fit a compute unit");
-            grid[v] = (int)std::min<int64_t>((int64_t)bpc * b->n_cu, tasks);
-            S[v] = (int64_t)kTanRes[v].threads * kTanRes[v].sn + 1;
-            slot_bytes = std::max(slot_bytes, 64 * (size_t)S[v] * (size_t)grid[v]);
-        } else {
-            // streamed: one 1024-thread workgroup per CU for the RVEs too large
-            // for LDS, or one wavefront per task (8 per CU) on the STREAMED engine
-            grid[v] = (int)std::min<int64_t>((int64_t)b->n_cu * (stream_threads == 64 ? 8 : 1), tasks);
-            for (int64_t r = 0; r < b->R; ++r) S[v] = std::max<int64_t>(S[v], b->nf_of[r] + 1);
-            slot_bytes = std::max(slot_bytes, 128 * (size_t)S[v] * (size_t)grid[v]);
-        }
-    }
     rc = ensure_tangent_ws(b, slot_bytes);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)b->opts.stream;
@@ -1419,16 +1704,12 @@ void rve_batch_destroy(rve_batch* b)
 {
     if (!b) return;
     for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
-    if (b->t_mem) (void)hipFree(b->t_mem);
-    if (b->o_mem) (void)hipFree(b->o_mem);
+    drop_workspace(b);
     if (b->probe) rve_batch_destroy(b->probe);
     if (b->d_probe_map) (void)hipFree(b->d_probe_map);
     if (b->d_fd_rot) (void)hipFree(b->d_fd_rot);
-    if (b->t_slots) (void)hipFree(b->t_slots);
     if (b->dtune_list) (void)hipFree(b->dtune_list);
     if (b->dmem) (void)hipFree(b->dmem);
-    if (b->ws_fib) (void)hipFree(b->ws_fib);
-    if (b->ws_node) (void)hipFree(b->ws_node);
     delete b;
 }
 

@@ -115,6 +115,15 @@ void fd_prepare(const double* F, double h, double* Fprobe, double* Rm);
 bool fd_finish(const double* F, const double* sigma, const double* sigma_probe, const double* Fprobe, double h,
                double* C, double* A);
 
+// State export/import (rve_state.hip).  map[n] = packed global free index of
+// caller node n, -1 for a boundary node; h arrays are [nodes][3] doubles.
+hipError_t launch_export_h(const double* dh, const int32_t* map, int64_t nn, double* out, hipStream_t s);
+hipError_t launch_import_h(const double* in, const int32_t* map, int64_t nn, double* dh, hipStream_t s);
+// st[r] = st_in[r] checked against F (BAD_F, codes out of range -> NONFINITE);
+// iterations 0 and norms NaN.
+hipError_t launch_import_status(const double* F, const int32_t* st_in, int64_t R, int32_t* st, int64_t* iters,
+                                double* Rn, double* Dn, double* Bn, hipStream_t s);
+
 // Which register-resident variants exist (threads per RVE, fiber slots per
 // thread, free-node slots per thread).
 struct ResidentVariant {

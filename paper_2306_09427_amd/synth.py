@@ -339,23 +339,28 @@ def seed_count(config_id: int, r: int) -> int:
     return {1: 100, 3: 2000, 4: 300}[config_id]
 
 
-def hex_mesh_F(nx=16, ny=16, nz=4, lam=1.1, amp=0.02, seed=5) -> np.ndarray:
-    """Deformation gradients at the 2x2x2 Gauss points of an nx*ny*nz mesh of
-    unit trilinear hexes under uniaxial extension plus a smooth random field.
-
-    Nodal u = (F_M - I) X + w(X), F_M = diag(lam, lam^-1/2, lam^-1/2),
+def hex_mesh_u(X, lam=1.1, amp=0.02, seed=5) -> np.ndarray:
+    """Displacement field of the hex-mesh workload at points X (n, 3):
+    u = (F_M - I) X + w(X), F_M = diag(lam, lam^-1/2, lam^-1/2),
     w = amp * sum of 8 sinusoids with random direction, phase and wavelength
-    in [4, 16].  Returns (nx*ny*nz*8, 3, 3)."""
+    in [4, 16]."""
     rng = np.random.default_rng([seed, 0, 3])
     FM = np.diag([lam, lam ** -0.5, lam ** -0.5])
     dirs = rng.standard_normal((8, 3)); dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
     pol = rng.standard_normal((8, 3)); pol /= np.linalg.norm(pol, axis=1, keepdims=True)
     wl = rng.uniform(4.0, 16.0, 8); ph = rng.uniform(0, 2 * np.pi, 8)
     kvec = dirs * (2 * np.pi / wl)[:, None]
+    X = np.asarray(X, dtype=np.float64)
+    return X @ (FM - np.eye(3)).T + amp * np.sin(X @ kvec.T + ph) @ pol
+
+
+def hex_mesh_F(nx=16, ny=16, nz=4, lam=1.1, amp=0.02, seed=5) -> np.ndarray:
+    """Deformation gradients at the 2x2x2 Gauss points of an nx*ny*nz mesh of
+    unit trilinear hexes under the displacement field of hex_mesh_u.
+    Returns (nx*ny*nz*8, 3, 3)."""
 
     def u_of(X):
-        arg = X @ kvec.T + ph
-        return X @ (FM - np.eye(3)).T + amp * np.sin(arg) @ pol
+        return hex_mesh_u(X, lam, amp, seed)
 
     gp = np.array([0.5 - 0.5 / np.sqrt(3.0), 0.5 + 0.5 / np.sqrt(3.0)])
     corners = np.array([[i, j, k] for i in (0, 1) for j in (0, 1) for k in (0, 1)], dtype=np.float64)
