@@ -88,6 +88,7 @@ def main():
     ap.add_argument("--no-naive", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tangent", action="store_true")
+    ap.add_argument("--no-kinetic", action="store_true", help="skip the kinetic-damping line")
     ap.add_argument("--tangent-steps", type=int, default=2)
     ap.add_argument("--autotune", action="store_true", help="autotune the mixed-precision kernel variants")
     ap.add_argument("--cache", default="/tmp/rve_bench_cfg2.npz",
@@ -248,6 +249,52 @@ def main():
         log(f"tangent: {t_ms:.1f} ms, status {np.bincount(ct, minlength=7).tolist()}, "
             f"{out['tangent']['roofline']['achieved']:.0f} GB/s algorithmic")
     b.close()
+
+    # ---------------- the same workload with kinetic damping (one of the
+    # alternatives to constant viscous damping the paper lists): same kernels
+    # in their kinetic builds, same tolerance; reported beside the headline
+    if not args.no_kinetic:
+        bk = rb.Batch(batch, precision=rb.MIXED, damping=rb.DAMP_KINETIC, **common)
+        log(f"kinetic kernel groups: {bk.describe()}")
+        bk.profile(True)
+        for _ in range(args.warmup):
+            bk.solve(Fd)
+        torch.cuda.synchronize()
+        tk = time.perf_counter()
+        for _ in range(args.steps):
+            sk, stk, statk = bk.solve(Fd, stats=True)
+        torch.cuda.synchronize()
+        k_ms = 1e3 * (time.perf_counter() - tk) / args.steps
+        stk = stk.cpu().numpy()
+        itk = statk["iters"].cpu().numpy()
+        sk = sk.cpu().numpy()
+        bk.close()
+        out["kinetic_damping"] = {
+            "workload": "same batch and tolerance, kinetic damping (velocities zeroed at kinetic-energy peaks)",
+            "solves_per_s": int((stk == 0).sum()) / (k_ms / 1e3),
+            "ms_per_step": k_ms,
+            "status_counts": np.bincount(stk, minlength=4).tolist(),
+            "iters_median": float(np.median(itk)),
+        }
+        log(f"kinetic: {k_ms:.1f} ms/step, status {np.bincount(stk, minlength=4).tolist()}, "
+            f"iters median {np.median(itk):.0f}")
+        if not args.no_cpu:
+            # accuracy of the kinetic mixed solve against the oracle's FP64
+            # kinetic relaxation (tol 1e-8) on the first RVEs of the batch
+            import oracle
+            o_k = oracle.make_opts(law=oracle.EXP, alpha=args.alpha, tol_abs=0.0, tol_rel=1e-8, n_max=args.n_max,
+                                   mass=args.mass)
+            ns = min(args.cpu_sample, batch.n_rve)
+            sub = batch.subset(np.arange(ns))
+            rk = oracle.solve_variant_batch(sub, F[:ns], args.c, o_k, damping=oracle.DAMP_KINETIC,
+                                            threads=min(os.cpu_count() or 1, 16))
+            both = (stk[:ns] == 0) & (rk["status"] == 0)
+            ek = np.abs(sk[:ns] - rk["sigma"]).reshape(ns, -1).max(1) / np.abs(rk["sigma"]).reshape(ns, -1).max(1)
+            out["kinetic_damping"]["sigma_relerr_vs_fp64_oracle_kinetic"] = {
+                "rves": int(both.sum()), "max": float(ek[both].max()) if both.any() else None,
+                "frac_le_1e-4": float(np.mean(ek[both] <= 1e-4)) if both.any() else None}
+            log(f"kinetic vs FP64 oracle (kinetic, tol 1e-8) on {int(both.sum())} RVEs: "
+                f"max {ek[both].max() if both.any() else float('nan'):.2e}")
 
     # ---------------- FP64 batched (same batch, tol scaled to FP64)
     if not args.no_fp64:

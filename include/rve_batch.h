@@ -55,6 +55,7 @@ extern "C" {
 #define RVE_ST_NO_STATE 4      /* tangent: RVE has no converged state */
 #define RVE_ST_CG_MAXITER 5    /* tangent: CG stopped at its iteration cap */
 #define RVE_ST_CG_INDEFINITE 6 /* tangent: K_ff not positive (unstable state) */
+#define RVE_ST_ENERGY 7        /* energy-balance check failed (opts.energy_check) */
 
 /* options */
 #define RVE_FP64 0             /* all arithmetic in double */
@@ -72,6 +73,9 @@ extern "C" {
 #define RVE_ENGINE_STREAMED 1  /* persistent kernel, state in global memory */
 #define RVE_ENGINE_NAIVE 2     /* one RVE at a time, one launch per step of
                                   every iteration, atomics, FP64 only */
+#define RVE_DAMP_VISCOUS 0     /* constant mass-proportional damping c M v */
+#define RVE_DAMP_KINETIC 1     /* kinetic damping: v = 0 at kinetic-energy peaks */
+#define RVE_DAMP_ADAPTIVE 2    /* c re-estimated each step (Rayleigh quotient) */
 #define RVE_PTR_HOST 0
 #define RVE_PTR_DEVICE 1
 
@@ -120,6 +124,27 @@ typedef struct {
  *   cg_tol, cg_max_iter: conjugate-gradient controls of rve_batch_tangent and
  *     rve_batch_vjp.
  *   stream: hipStream_t for every launch and copy (NULL: the null stream).
+ *   damping, energy_check, energy_tol: the alternatives the paper lists
+ *     beside constant viscous damping (Section 3.2).  RVE_DAMP_KINETIC: no
+ *     viscous force; whenever the kinetic energy 1/2 sum M |v|^2 at a full
+ *     step is below its value at the previous full step, every velocity is
+ *     set to zero (the damping-force norm of the convergence test becomes
+ *     |M v|_2 / dt).  RVE_DAMP_ADAPTIVE: after each force evaluation
+ *     c = 2 sqrt(u.K u / u.M u), the critical damping of the Rayleigh
+ *     quotient of u, the displacement since the start of the solve, with K
+ *     the tangent stiffness at the current positions (0 when u.K u <= 0);
+ *     c of the opts is only the value before the first step.
+ *     energy_check = 1: after every step the stored energy W, kinetic energy
+ *     KE and the work Wd removed by damping must satisfy
+ *     |W + KE + Wd - W_start| <= energy_tol max(W_start, W, KE, Wd), else the
+ *     RVE stops with RVE_ST_ENERGY (an unstable trajectory).  Kinetic
+ *     damping alone runs on the ordinary engines (kinetic builds of the
+ *     resident and streamed kernels, either precision; the kinetic-energy
+ *     peak is tested every iteration).  Adaptive damping or the energy
+ *     check run every RVE on an FP64 engine with one workgroup per RVE and
+ *     a convergence test every iteration (precision must be RVE_FP64);
+ *     check_every and threads_per_rve do not apply there.  None of them
+ *     with RVE_ENGINE_NAIVE.
  */
 typedef struct {
     int32_t precision;
@@ -138,6 +163,9 @@ typedef struct {
     double cg_tol;          /* tangent/vjp CG: stop at |r_k| <= cg_tol |b_k| */
     int64_t cg_max_iter;    /* tangent/vjp CG iteration cap per right-hand side (0: 2 x free DOFs + 100) */
     void* stream;
+    int32_t damping;        /* RVE_DAMP_* */
+    int32_t energy_check;   /* 0 or 1 */
+    double energy_tol;      /* relative energy-balance tolerance (> 0) */
 } rve_opts;
 
 /* Optional per-RVE diagnostics of a solve (each pointer may be NULL; same
@@ -154,7 +182,8 @@ const char* rve_last_error(void);
 
 /* Fill *o with defaults: FP64, linear law, EA 1, B 10, rhoA 1, alpha 0.9,
  * c 2, tol_abs 1e-10, tol_rel 0, n_max 1e6, check_every 1, auto engine,
- * cg_tol 1e-6, cg_max_iter 0. */
+ * cg_tol 1e-6, cg_max_iter 0, viscous damping, no energy check,
+ * energy_tol 0.05. */
 void rve_default_opts(rve_opts* o);
 
 /*
@@ -204,6 +233,15 @@ int rve_batch_groups(rve_batch* b, int32_t* group_of_rve, int32_t* variant, doub
  * state of the last solve.
  */
 int rve_batch_autotune(rve_batch* b, const double* F, int32_t ptr_kind, int32_t n_iter);
+
+/*
+ * After a solve that used adaptive damping or the energy check: the
+ * damping coefficient at the end of each RVE's relaxation (c_final[n_rve];
+ * 0 for kinetic damping, the constant c for viscous damping) and the final
+ * relative energy balance |W + KE + Wd - W_start| / max(W_start, W, KE, Wd)
+ * (energy[n_rve]); either pointer may be NULL.  RVE_ESTATE otherwise.
+ */
+int rve_batch_damping_stats(rve_batch* b, double* c_final, double* energy, int32_t ptr_kind);
 
 /* Describe the kernel groups of the next solve ("variant:count;...") into
  * buf (NUL-terminated, truncated to n bytes). */

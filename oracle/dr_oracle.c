@@ -314,12 +314,13 @@ int or_solve(int64_t n_nodes, int64_t n_fib, const double* X, const uint8_t* is_
  *              value at the previous full step (a peak was passed), every
  *              velocity is set to zero and the acceleration to -f/M;
  *   damping 2  adaptive viscous: after each force evaluation the
- *              coefficient becomes c = 2 sqrt(u.Ku / u.M u) (critical
- *              damping of the mode the displacement u = x - x_start
- *              excites), with the diagonal stiffness estimated from the
- *              force change over the step, K_kk = df_k / (dt v_k) (DOFs
- *              with v_k = 0 contribute nothing); c = 0 when u.Ku <= 0; the
- *              new c enters the damping force of the same step.
+ *              coefficient becomes c = 2 sqrt(u.K u / u.M u), the critical
+ *              damping of the Rayleigh quotient of the displacement since
+ *              the start, u = x - x_start, with K the tangent stiffness at
+ *              the new positions (per fiber (k_t/L0) (n.du)^2 +
+ *              (T/l) (|du|^2 - (n.du)^2), du the difference of u over the
+ *              fiber); c = 0 when u.K u <= 0 or u = 0; the new c enters
+ *              the damping force of the same step.
  *
  *   Energy balance (energy_check != 0): with the boundary fixed during the
  *   relaxation no external work is done, so the stored energy W, the
@@ -360,7 +361,6 @@ int or_solve_variant(int64_t n_nodes, int64_t n_fib, const double* X, const uint
     double* v = calloc(3 * nn + 1, sizeof(double));
     double* a = calloc(3 * nn + 1, sizeof(double));
     double* f = calloc(3 * nn + 1, sizeof(double));
-    double* f_old = calloc(3 * nn + 1, sizeof(double));
     double* x0 = calloc(3 * nn + 1, sizeof(double));
     double* G = calloc(nn + 1, sizeof(double));
 
@@ -411,16 +411,27 @@ int or_solve_variant(int64_t n_nodes, int64_t n_fib, const double* X, const uint
                 x[3 * p + k] += dt * v[3 * p + k];
             }
         }
-        memcpy(f_old, f, sizeof(double) * 3 * nn);
         or_forces(n_nodes, n_fib, x, fib, L0, o, f, G, &W);
         if (damping == 2) {
             double num = 0.0, den = 0.0;
+            for (int64_t k = 0; k < n_fib; ++k) {
+                int32_t i = fib[2 * k], j = fib[2 * k + 1];
+                double d[3], du[3];
+                for (int q = 0; q < 3; ++q) {
+                    d[q] = x[3 * j + q] - x[3 * i + q];
+                    du[q] = (x[3 * j + q] - x0[3 * j + q]) - (x[3 * i + q] - x0[3 * i + q]);
+                }
+                double l = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                double T, kt;
+                fiber_law(o, l / L0[k] - 1.0, &T, &kt);
+                double nd = (d[0] * du[0] + d[1] * du[1] + d[2] * du[2]) / l;
+                double du2 = du[0] * du[0] + du[1] * du[1] + du[2] * du[2];
+                num += kt / L0[k] * nd * nd + T / l * (du2 - nd * nd);
+            }
             for (int64_t p = 0; p < n_nodes; ++p) {
                 if (is_bnd[p]) continue;
-                for (int k = 0; k < 3; ++k) {
-                    double u = x[3 * p + k] - x0[3 * p + k];
-                    double vk = v[3 * p + k];
-                    if (vk != 0.0) num += u * u * (f[3 * p + k] - f_old[3 * p + k]) / (dt * vk);
+                for (int q = 0; q < 3; ++q) {
+                    double u = x[3 * p + q] - x0[3 * p + q];
                     den += M[p] * u * u;
                 }
             }
@@ -478,7 +489,7 @@ int or_solve_variant(int64_t n_nodes, int64_t n_fib, const double* X, const uint
     *e_out = ebal;
     if (status != OR_NONFINITE) or_stress(n_nodes, x, f, is_bnd, F, V0, sigma);
 
-    free(L0); free(M); free(v); free(a); free(f); free(f_old); free(x0); free(G);
+    free(L0); free(M); free(v); free(a); free(f); free(x0); free(G);
     return status;
 }
 

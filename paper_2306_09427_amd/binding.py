@@ -22,7 +22,8 @@ MASS_LUMPED, MASS_SCALED = 0, 1
 INIT_AFFINE, INIT_WARM = 0, 2
 ENGINE_AUTO, ENGINE_STREAMED, ENGINE_NAIVE = 0, 1, 2
 PTR_HOST, PTR_DEVICE = 0, 1
-ST_CONVERGED, ST_MAXITER, ST_NONFINITE, ST_BAD_F, ST_NO_STATE, ST_CG_MAXITER, ST_CG_INDEFINITE = range(7)
+ST_CONVERGED, ST_MAXITER, ST_NONFINITE, ST_BAD_F, ST_NO_STATE, ST_CG_MAXITER, ST_CG_INDEFINITE, ST_ENERGY = range(8)
+DAMP_VISCOUS, DAMP_KINETIC, DAMP_ADAPTIVE = 0, 1, 2
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE = 0, -22, -12, -5, -3
 
 EXPORTS = ["rve_version", "rve_last_error", "rve_default_opts", "rve_batch_create", "rve_batch_set_opts",
@@ -30,7 +31,7 @@ EXPORTS = ["rve_version", "rve_last_error", "rve_default_opts", "rve_batch_creat
            "rve_batch_positions", "rve_batch_destroy", "rve_batch_profile", "rve_batch_kernel_ms",
            "rve_batch_autotune", "rve_batch_describe", "rve_batch_groups", "rve_batch_tangent_iters", "rve_batch_orientation",
            "rve_batch_fd_tangent", "rve_batch_export_state", "rve_batch_import_state",
-           "rve_batch_workspace_size", "rve_batch_bind_workspace"]
+           "rve_batch_workspace_size", "rve_batch_bind_workspace", "rve_batch_damping_stats"]
 
 
 class NetDesc(C.Structure):
@@ -44,7 +45,8 @@ class Opts(C.Structure):
                 ("c", C.c_double), ("c_per_rve", C.c_void_p), ("tol_abs", C.c_double), ("tol_rel", C.c_double),
                 ("n_max", C.c_int64), ("check_every", C.c_int32), ("engine", C.c_int32),
                 ("threads_per_rve", C.c_int32), ("cg_tol", C.c_double), ("cg_max_iter", C.c_int64),
-                ("stream", C.c_void_p)]
+                ("stream", C.c_void_p), ("damping", C.c_int32), ("energy_check", C.c_int32),
+                ("energy_tol", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -92,6 +94,7 @@ def lib():
         L.rve_batch_import_state.argtypes = [P, P, P, P, P, C.c_int32]
         L.rve_batch_workspace_size.argtypes = [P, C.POINTER(C.c_size_t)]
         L.rve_batch_bind_workspace.argtypes = [P, P, C.c_size_t]
+        L.rve_batch_damping_stats.argtypes = [P, P, P, C.c_int32]
         L.rve_batch_destroy.argtypes = [P]
         L.rve_batch_destroy.restype = None
         _lib = L
@@ -109,7 +112,8 @@ def _check(rc):
 
 def make_opts(precision=FP64, law=LAW_EXP, mass=MASS_LUMPED, init=INIT_AFFINE, EA=1.0, B=10.0, rhoA=1.0,
               alpha=0.9, c=2.0, tol_abs=1e-10, tol_rel=0.0, n_max=1_000_000, check_every=1,
-              engine=ENGINE_AUTO, threads_per_rve=0, cg_tol=1e-6, cg_max_iter=0) -> Opts:
+              engine=ENGINE_AUTO, threads_per_rve=0, cg_tol=1e-6, cg_max_iter=0, damping=DAMP_VISCOUS,
+              energy_check=False, energy_tol=0.05) -> Opts:
     o = Opts()
     lib().rve_default_opts(C.byref(o))
     o.precision, o.law, o.mass, o.init = int(precision), int(law), int(mass), int(init)
@@ -117,6 +121,7 @@ def make_opts(precision=FP64, law=LAW_EXP, mass=MASS_LUMPED, init=INIT_AFFINE, E
     o.tol_abs, o.tol_rel, o.n_max, o.check_every = float(tol_abs), float(tol_rel), int(n_max), int(check_every)
     o.engine, o.threads_per_rve = int(engine), int(threads_per_rve)
     o.cg_tol, o.cg_max_iter = float(cg_tol), int(cg_max_iter)
+    o.damping, o.energy_check, o.energy_tol = int(damping), int(bool(energy_check)), float(energy_tol)
     return o
 
 
@@ -286,6 +291,14 @@ class Batch:
         fp, kind = _ptr(F)
         _check(lib().rve_batch_import_state(self._h, fp, _ptr(h)[0], _ptr(status)[0], _ptr(sig)[0], kind))
         return sig
+
+    def damping_stats(self):
+        """(final damping coefficient [R], final relative energy balance [R]) of
+        the last solve with a damping alternative or the energy check."""
+        cf = np.empty(self.n_rve)
+        en = np.empty(self.n_rve)
+        _check(lib().rve_batch_damping_stats(self._h, cf.ctypes.data, en.ctypes.data, PTR_HOST))
+        return cf, en
 
     def workspace_size(self):
         """Bytes of device memory that cover every on-demand work area of the batch."""

@@ -83,7 +83,7 @@ struct rve_batch {
     std::vector<int32_t> group_first;          // offset of each group's ids in dlist
     std::vector<size_t> group_lds;
     bool have_state = false;
-    bool variant_spills[2][kNumResident] = {};   // [fp64][variant]: the variant uses private memory
+    bool variant_spills[2][2][kNumResident] = {};   // [kinetic][fp64][variant]: the build uses private memory
     // tangent / vjp workspace
     char* t_mem = nullptr;             // operators, records, preconditioner, chunk tables, I/O
     bool t_static_built = false;       // records' (fiber, other end) filled
@@ -122,7 +122,28 @@ struct rve_batch {
     // point into it and are never freed by the library
     char* ws_user = nullptr;
     size_t ws_user_bytes = 0;
+    // damping alternatives / energy check: node and fiber state, then
+    // c_final [R] and the energy balance [R]; whether the last solve used them
+    double* v_ws = nullptr;
+    bool last_variant = false;
 };
+
+// Adaptive damping and the energy check run on the FP64 variant engine;
+// kinetic damping alone runs on the ordinary engines (their kinetic builds).
+static bool variant_mode(const rve_opts& o)
+{
+    return o.damping == RVE_DAMP_ADAPTIVE || o.energy_check != 0;
+}
+
+static bool kinetic_mode(const rve_opts& o)
+{
+    return o.damping == RVE_DAMP_KINETIC && !variant_mode(o);
+}
+
+static bool spills(const rve_batch* b, int v, bool fp64)
+{
+    return b->variant_spills[kinetic_mode(b->opts) ? 1 : 0][fp64 ? 1 : 0][v];
+}
 
 // Size tiers: distinct (fiber, node) capacities of the resident variants, ascending.
 static std::vector<std::pair<int64_t, int64_t>> tier_caps()
@@ -191,6 +212,15 @@ static int validate_opts(const rve_opts* o, int64_t R)
     if (o->threads_per_rve != 0 && o->threads_per_rve != 256 && o->threads_per_rve != 512 &&
         o->threads_per_rve != 1024)
         return fail(RVE_EINVAL, "threads_per_rve must be 0, 256, 512 or 1024");
+    if (o->damping != RVE_DAMP_VISCOUS && o->damping != RVE_DAMP_KINETIC && o->damping != RVE_DAMP_ADAPTIVE)
+        return fail(RVE_EINVAL, "bad damping mode");
+    if (!(o->energy_tol > 0) || !std::isfinite(o->energy_tol)) return fail(RVE_EINVAL, "energy_tol must be > 0");
+    if (o->damping != RVE_DAMP_VISCOUS || o->energy_check) {
+        if (o->engine == RVE_ENGINE_NAIVE)
+            return fail(RVE_EINVAL, "the naive engine has constant viscous damping only");
+        if ((o->damping == RVE_DAMP_ADAPTIVE || o->energy_check) && o->precision != RVE_FP64)
+            return fail(RVE_EINVAL, "adaptive damping and the energy check are FP64 only");
+    }
     return RVE_OK;
 }
 
@@ -380,7 +410,7 @@ static int default_variant(const rve_batch* b, int tier, bool fp64)
         const ResidentVariant& rv = kResident[v];
         if (T && rv.threads != T) continue;
         // variants that spill are never launched (see the autotuner)
-        if (b->variant_spills[fp64 ? 1 : 0][v]) continue;
+        if (spills(b, v, fp64)) continue;
         if (!variant_fits_tier(v, tier)) continue;
         int64_t key = (int64_t)(rv.sf * 5 + rv.sn * 12) * 4096 - rv.threads;
         if (chosen < 0 || key < best) {
@@ -404,6 +434,7 @@ static void assign_groups(rve_batch* b)
             int t = tier_of(b, r, fp64);
             if (t >= 0) {
                 int tv = b->tuned[fp64 ? 1 : 0][t];
+                if (tv >= 0 && spills(b, tv, fp64)) tv = -2;   // tuned for the other damping build
                 chosen = (tv != -2 && !b->opts.threads_per_rve) ? tv : default_variant(b, t, fp64);
             }
         }
@@ -454,6 +485,14 @@ static int streamed_blocks_per_cu(int threads, int64_t lds_nodes, bool fp64)
     if (lds_nodes <= 0) return base;
     const size_t lds = 3 * (fp64 ? 8 : 4) * (size_t)lds_nodes + 1024;
     return (int)std::max<size_t>(1, std::min<size_t>(base, (160 * 1024) / lds));
+}
+
+// Workgroup size of the streamed engine: 256 when asked for, and for the
+// FP64 kinetic build (its 1024-thread form keeps values in private memory),
+// else 1024.
+static int streamed_threads(const rve_batch* b, bool fp64)
+{
+    return (b->opts.threads_per_rve == 256 || (fp64 && kinetic_mode(b->opts))) ? 256 : 1024;
 }
 
 static int ensure_workspace(rve_batch* b)
@@ -514,6 +553,9 @@ void rve_default_opts(rve_opts* o)
     o->engine = RVE_ENGINE_AUTO;
     o->cg_tol = 1e-6;
     o->cg_max_iter = 0;
+    o->damping = RVE_DAMP_VISCOUS;
+    o->energy_check = 0;
+    o->energy_tol = 0.05;
 }
 
 int rve_batch_create(const rve_net_desc* net, const rve_opts* opts, rve_batch** out)
@@ -538,13 +580,14 @@ int rve_batch_create(const rve_net_desc* net, const rve_opts* opts, rve_batch** 
     if (!b) return fail(RVE_ENOMEM, "host allocation failed");
     b->device = dev;
     b->n_cu = prop.multiProcessorCount;
-    for (int p = 0; p < 2; ++p)
-        for (int v = 0; v < kNumResident; ++v) {
-            size_t sb = 0;
-            // a few spilled scalars outside the relaxation loop are harmless;
-            // more than that means the loop itself spills
-            if (resident_scratch_bytes(v, p == 1, &sb) == hipSuccess) b->variant_spills[p][v] = sb > 64;
-        }
+    for (int k = 0; k < 2; ++k)
+        for (int p = 0; p < 2; ++p)
+            for (int v = 0; v < kNumResident; ++v) {
+                size_t sb = 0;
+                // a few spilled scalars outside the relaxation loop are harmless;
+                // more than that means the loop itself spills
+                if (resident_scratch_bytes(v, p == 1, k == 1, &sb) == hipSuccess) b->variant_spills[k][p][v] = sb > 64;
+            }
     b->R = net->n_rve;
     b->opts = *opts;
     b->c_host.assign(b->R, opts->c);
@@ -789,8 +832,44 @@ int rve_batch_solve(rve_batch* b, const double* F, double* sigma, int32_t* statu
     a.h_state = b->dh;
     a.ws_fib = b->ws_fib;
     a.ws_node = b->ws_node;
+    a.kinetic = kinetic_mode(b->opts) ? 1 : 0;
 
-    if (b->opts.engine == RVE_ENGINE_NAIVE) {
+    b->last_variant = false;
+    if (variant_mode(b->opts)) {
+        if (!b->v_ws) {
+            if (b->ws_user) return fail(RVE_EINVAL, "internal: bound workspace has no variant area");
+            if (hipMalloc((void**)&b->v_ws, variant_ws_bytes(b->NFREE, b->NF) + 16 * (size_t)b->R) != hipSuccess) {
+                b->v_ws = nullptr;
+                return fail(RVE_ENOMEM, "variant workspace allocation failed");
+            }
+        }
+        VariantArgs va{};
+        va.s = a;
+        va.damping = b->opts.damping;
+        va.energy_check = b->opts.energy_check;
+        va.energy_tol = b->opts.energy_tol;
+        va.ws_node = b->v_ws;
+        va.ws_fib = b->v_ws + 17 * (size_t)b->NFREE;
+        va.c_final = reinterpret_cast<double*>(reinterpret_cast<char*>(b->v_ws) + variant_ws_bytes(b->NFREE, b->NF));
+        va.energy = va.c_final + b->R;
+        b->ev_used = 0;
+        if (b->profile) {
+            rc = ensure_events(b, 4);
+            if (rc) return rc;
+            HIP_TRY(hipEventRecord(b->ev[0], s));
+        }
+        HIP_TRY(launch_variant(va, b->R, s));
+        if (b->profile) {
+            HIP_TRY(hipEventRecord(b->ev[1], s));
+            HIP_TRY(hipEventRecord(b->ev[2], s));
+        }
+        HIP_TRY(launch_stress(a, (int)b->R, s));
+        if (b->profile) {
+            HIP_TRY(hipEventRecord(b->ev[3], s));
+            b->ev_used = 4;
+        }
+        b->last_variant = true;
+    } else if (b->opts.engine == RVE_ENGINE_NAIVE) {
         std::vector<double> Fh(9 * b->R);
         HIP_TRY(hipMemcpyAsync(Fh.data(), b->dF, 72 * b->R, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
@@ -813,12 +892,12 @@ int rve_batch_solve(rve_batch* b, const double* F, double* sigma, int32_t* statu
             if (b->profile) HIP_TRY(hipEventRecord(b->ev[2 * g], s));
             if (v >= 0) {
                 int per_cu = 1;
-                HIP_TRY(max_resident_blocks(v, fp64, b->group_lds[g], &per_cu));
+                HIP_TRY(max_resident_blocks(v, fp64, a.kinetic != 0, b->group_lds[g], &per_cu));
                 if (per_cu < 1) return fail(RVE_EDEVICE, "resident kernel variant does not fit a CU");
                 int grid = std::min<int64_t>((int64_t)per_cu * b->n_cu, a.n_list);
                 HIP_TRY(launch_resident(v, fp64, a, b->group_lds[g], grid, s));
             } else {
-                int threads = b->opts.threads_per_rve == 256 ? 256 : 1024;
+                int threads = streamed_threads(b, fp64);
                 a.lds_h_nodes = streamed_lds_nodes(b, b->groups[g].data(), b->groups[g].size(), fp64);
                 int grid = std::min<int64_t>((int64_t)b->n_cu * streamed_blocks_per_cu(threads, a.lds_h_nodes, fp64),
                                              a.n_list);
@@ -874,6 +953,7 @@ static void fill_solve_args(rve_batch* b, SolveArgs& a)
     a.h_state = b->dh;
     a.ws_fib = b->ws_fib;
     a.ws_node = b->ws_node;
+    a.kinetic = kinetic_mode(b->opts) ? 1 : 0;
 }
 
 int rve_batch_autotune(rve_batch* b, const double* F, int32_t ptr_kind, int32_t n_iter)
@@ -881,7 +961,7 @@ int rve_batch_autotune(rve_batch* b, const double* F, int32_t ptr_kind, int32_t 
     if (!b || !F) return fail(RVE_EINVAL, "NULL argument");
     if (ptr_kind != RVE_PTR_HOST && ptr_kind != RVE_PTR_DEVICE) return fail(RVE_EINVAL, "bad ptr_kind");
     if (n_iter < 1) return fail(RVE_EINVAL, "n_iter must be >= 1");
-    if (b->R == 0 || b->opts.engine != RVE_ENGINE_AUTO) return RVE_OK;
+    if (b->R == 0 || b->opts.engine != RVE_ENGINE_AUTO || variant_mode(b->opts)) return RVE_OK;
     hipStream_t s = (hipStream_t)b->opts.stream;
     const bool fp64 = b->opts.precision == RVE_FP64;
     HIP_TRY(hipMemcpyAsync(b->dF, F, 72 * b->R, ptr_kind == RVE_PTR_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s));
@@ -930,15 +1010,16 @@ int rve_batch_autotune(rve_batch* b, const double* F, int32_t ptr_kind, int32_t 
             // edit changed its spill code, and a later build of it faulted.
             // Each remaining candidate's final states must also stay close to
             // those of the streamed kernel (timed first) on the tuning RVEs.
-            if (v >= 0 && (!variant_fits_tier(v, (int)t) || b->variant_spills[fp64 ? 1 : 0][v])) continue;
+            if (v >= 0 && (!variant_fits_tier(v, (int)t) || spills(b, v, fp64))) continue;
             int grid = 0;
             if (v >= 0) {
                 int per_cu = 0;
-                if (max_resident_blocks(v, fp64, lds, &per_cu) != hipSuccess || per_cu < 1) continue;
+                if (max_resident_blocks(v, fp64, a.kinetic != 0, lds, &per_cu) != hipSuccess || per_cu < 1) continue;
                 grid = (int)std::min<int64_t>((int64_t)per_cu * b->n_cu, a.n_list);
             } else {
                 a.lds_h_nodes = streamed_lds_nodes(b, members.data(), members.size(), fp64);
-                grid = (int)std::min<int64_t>((int64_t)b->n_cu * streamed_blocks_per_cu(1024, a.lds_h_nodes, fp64),
+                grid = (int)std::min<int64_t>((int64_t)b->n_cu * streamed_blocks_per_cu(streamed_threads(b, fp64),
+                                                                                          a.lds_h_nodes, fp64),
                                               a.n_list);
             }
             for (int rep = 0; rep < 2; ++rep) {   // first run warms up
@@ -947,7 +1028,7 @@ int rve_batch_autotune(rve_batch* b, const double* F, int32_t ptr_kind, int32_t 
                 if (v >= 0)
                     HIP_TRY(launch_resident(v, fp64, a, lds, grid, s));
                 else
-                    HIP_TRY(launch_streamed(fp64, a, grid, 1024, s));
+                    HIP_TRY(launch_streamed(fp64, a, grid, streamed_threads(b, fp64), s));
                 HIP_TRY(hipEventRecord(b->ev[1], s));
             }
             HIP_TRY(hipEventSynchronize(b->ev[1]));
@@ -1002,10 +1083,30 @@ int rve_batch_autotune(rve_batch* b, const double* F, int32_t ptr_kind, int32_t 
     return upload_groups(b);
 }
 
+int rve_batch_damping_stats(rve_batch* b, double* c_final, double* energy, int32_t ptr_kind)
+{
+    if (!b) return fail(RVE_EINVAL, "batch is NULL");
+    if (ptr_kind != RVE_PTR_HOST && ptr_kind != RVE_PTR_DEVICE) return fail(RVE_EINVAL, "bad ptr_kind");
+    if (!b->last_variant) return fail(RVE_ESTATE, "the last solve did not use a damping alternative or the energy check");
+    if (b->R == 0) return RVE_OK;
+    hipStream_t s = (hipStream_t)b->opts.stream;
+    const hipMemcpyKind k = ptr_kind == RVE_PTR_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    const double* cf = reinterpret_cast<const double*>(reinterpret_cast<const char*>(b->v_ws) +
+                                                       variant_ws_bytes(b->NFREE, b->NF));
+    if (c_final) HIP_TRY(hipMemcpyAsync(c_final, cf, 8 * (size_t)b->R, k, s));
+    if (energy) HIP_TRY(hipMemcpyAsync(energy, cf + b->R, 8 * (size_t)b->R, k, s));
+    if (ptr_kind == RVE_PTR_HOST) HIP_TRY(hipStreamSynchronize(s));
+    return RVE_OK;
+}
+
 int rve_batch_describe(const rve_batch* b, char* buf, size_t n)
 {
     if (!b || !buf || n == 0) return fail(RVE_EINVAL, "NULL argument");
     std::string d;
+    if (variant_mode(b->opts)) {
+        std::snprintf(buf, n, "variants(fp64):%lld;", (long long)b->R);
+        return RVE_OK;
+    }
     for (size_t g = 0; g < b->groups.size(); ++g) {
         int v = b->group_variant[g];
         if (v >= 0)
@@ -1316,8 +1417,8 @@ static int tangent_plan(rve_batch* b, int mode, int engine, std::vector<int64_t>
 // tangent/VJP slot area over both engines, the orientation outputs and the
 // state map, each at a 256-byte aligned offset.
 struct WsLayout {
-    size_t fib, node, tmem, slots, omem, smap;
-    size_t o_fib, o_node, o_tmem, o_slots, o_omem, o_smap, total;
+    size_t fib, node, tmem, slots, omem, smap, var;
+    size_t o_fib, o_node, o_tmem, o_slots, o_omem, o_smap, o_var, total;
 };
 
 static int ws_layout(rve_batch* b, WsLayout& L)
@@ -1338,6 +1439,7 @@ static int ws_layout(rve_batch* b, WsLayout& L)
         }
     L.omem = 80 * (size_t)b->R;
     L.smap = 4 * (size_t)b->NN + 4;
+    L.var = variant_ws_bytes(b->NFREE, b->NF) + 16 * (size_t)b->R;
     DeviceArena A;
     L.o_fib = A.reserve(L.fib);
     L.o_node = A.reserve(L.node);
@@ -1345,6 +1447,7 @@ static int ws_layout(rve_batch* b, WsLayout& L)
     L.o_slots = A.reserve(L.slots);
     L.o_omem = A.reserve(L.omem);
     L.o_smap = A.reserve(L.smap);
+    L.o_var = A.reserve(L.var);
     L.total = A.used;
     return RVE_OK;
 }
@@ -1372,6 +1475,7 @@ static void drop_workspace(rve_batch* b)
         if (b->t_slots) (void)hipFree(b->t_slots);
         if (b->o_mem) (void)hipFree(b->o_mem);
         if (b->d_state_map) (void)hipFree(b->d_state_map);
+        if (b->v_ws) (void)hipFree(b->v_ws);
     }
     b->ws_fib = b->ws_node = nullptr;
     b->ws_fib_bytes = b->ws_node_bytes = 0;
@@ -1380,6 +1484,8 @@ static void drop_workspace(rve_batch* b)
     b->t_slot_bytes = 0;
     b->o_mem = nullptr;
     b->d_state_map = nullptr;
+    b->v_ws = nullptr;
+    b->last_variant = false;
     b->t_tables = false;
     b->t_static_built = false;
     b->state_map_ready = false;
@@ -1420,6 +1526,7 @@ int rve_batch_bind_workspace(rve_batch* b, void* ptr, size_t bytes)
     b->t_slot_bytes = L.slots;
     b->o_mem = reinterpret_cast<double*>(m + L.o_omem);
     b->d_state_map = reinterpret_cast<int32_t*>(m + L.o_smap);
+    b->v_ws = reinterpret_cast<double*>(m + L.o_var);
     return RVE_OK;
 }
 

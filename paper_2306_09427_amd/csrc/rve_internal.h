@@ -50,6 +50,7 @@ struct SolveArgs {
     void* ws_fib;             // [NF + R] Real4 (D0, q0), [NF + R] Real4 (fv, b), [NF + R] Real4 (L0, 1/L0, ends)
     void* ws_node;            // [NFREE + R] Real4 h, [NFREE] Real4 (v, 1/M), [NFREE] Real mass, [NFREE] Real4 accel
     int64_t lds_h_nodes;      // streamed engine: > 0 keeps h in LDS (this many entries per component)
+    int32_t kinetic;          // 1: kinetic damping (c ignored; v = 0 at kinetic-energy peaks)
 };
 
 struct TangentArgs {
@@ -124,6 +125,23 @@ hipError_t launch_import_h(const double* in, const int32_t* map, int64_t nn, dou
 hipError_t launch_import_status(const double* F, const int32_t* st_in, int64_t R, int32_t* st, int64_t* iters,
                                 double* Rn, double* Dn, double* Bn, hipStream_t s);
 
+// Relaxation with the damping alternatives and the energy-balance check
+// (rve_variants.hip): FP64, one workgroup per RVE (grid = n_rve, RVE r =
+// block r), state in ws_node / ws_fib.  Writes h_state, status, iters and
+// the residual norms; the stress kernel runs afterwards as for any solve.
+struct VariantArgs {
+    SolveArgs s;
+    int32_t damping;        // 0 viscous, 1 kinetic, 2 adaptive
+    int32_t energy_check;   // 1: stop with status 7 on an energy-balance violation
+    double energy_tol;
+    double* ws_node;        // [NFREE][17]
+    double* ws_fib;         // [NF][5]
+    double* c_final;        // [R] damping coefficient at the end
+    double* energy;         // [R] final relative energy balance
+};
+hipError_t launch_variant(const VariantArgs& a, int64_t n_rve, hipStream_t s);
+size_t variant_ws_bytes(int64_t n_free, int64_t n_fib);
+
 // Which register-resident variants exist (threads per RVE, fiber slots per
 // thread, free-node slots per thread).
 struct ResidentVariant {
@@ -157,9 +175,10 @@ hipError_t launch_tangent_prep(const TangentArgs& a, hipStream_t s);
 hipError_t launch_tangent_res(int variant, const TangentArgs& a, int grid, hipStream_t s);
 hipError_t launch_tangent_stream(const TangentArgs& a, int threads, int grid, hipStream_t s);
 hipError_t tangent_res_blocks(int variant, bool vjp, int* blocks_per_cu);
-hipError_t max_resident_blocks(int variant, bool fp64, size_t lds_bytes, int* blocks_per_cu);
+// kin: the kinetic-damping build of the variant (launch_resident reads a.kinetic).
+hipError_t max_resident_blocks(int variant, bool fp64, bool kin, size_t lds_bytes, int* blocks_per_cu);
 // Private (spill) bytes per lane of a resident variant; > 0 means it spills.
-hipError_t resident_scratch_bytes(int variant, bool fp64, size_t* bytes);
+hipError_t resident_scratch_bytes(int variant, bool fp64, bool kin, size_t* bytes);
 
 
 }  // namespace rve

@@ -296,6 +296,7 @@ size_t resident_lds_bytes(bool fp64, int64_t nf, int64_t nfib, int /*threads*/)
 // maximum (LDS atomic max on the bit pattern of a non-negative number).
 struct RedSlots {
     double v[3][16];
+    double ke[16];      // kinetic damping: per-wave kinetic energy
     unsigned long long g64[2];
     unsigned g32[2];
 };
@@ -313,11 +314,16 @@ __device__ __forceinline__ void reset_gslots(RedSlots& red)
 // summation order.  One barrier; the max slot alternates with `parity`, the
 // other slot is cleared for the next call (at least two barriers separate a
 // clear from the next atomic on that slot).
-template <typename Real, int NW>
+template <typename Real, int NW, bool KE = false>
 __device__ __forceinline__ void block_reduce(RedSlots& red, int parity, Real gpart, double r2, double d2, double b2,
-                                             bool full, double& gmax_o, double& r2_o, double& d2_o, double& b2_o)
+                                             bool full, double& gmax_o, double& r2_o, double& d2_o, double& b2_o,
+                                             double ke = 0.0, double* ke_o = nullptr)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if constexpr (KE) {
+        ke = wave_sum(ke);
+        if (lane == 0) red.ke[wave] = ke;
+    }
     if constexpr (sizeof(Real) == 4) {
         float g = wave_max_nonneg((float)gpart);
         if (lane == 0) atomicMax(&red.g32[parity], __float_as_uint(g));
@@ -355,6 +361,12 @@ __device__ __forceinline__ void block_reduce(RedSlots& red, int parity, Real gpa
         r2_o = uniform(a);
         d2_o = uniform(b);
         b2_o = uniform(c);
+    }
+    if constexpr (KE) {
+        double k = 0.0;
+#pragma unroll 4
+        for (int w = 0; w < NW; ++w) k += red.ke[w];
+        *ke_o = uniform(k);
     }
 }
 
@@ -404,7 +416,7 @@ __device__ __forceinline__ void stress_finish(double* s, double J, double V0, do
 }
 
 // ------------------------------------------------------------------ resident kernel
-template <typename Real, int T, int SF, int SN>
+template <typename Real, int T, int SF, int SN, bool KIN>
 __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* smem, RedSlots& red)
 {
     constexpr int NW = T / 64;
@@ -441,7 +453,9 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
         return;
     }
     const Real EA = (Real)A.EA, Bc = (Real)A.B, EAoB = (Real)(A.EA / A.B);
-    const double cd = A.c[r];
+    // kinetic damping: no viscous force (c = 0); velocities are zeroed at
+    // kinetic-energy peaks below
+    const double cd = KIN ? 0.0 : A.c[r];
     const Real c = (Real)cd;
 
     Lds<Real> L;
@@ -639,6 +653,7 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
             return A.alpha * 2.0 / sqrt(g);
     };
     double dt = time_step(gmax);
+    double ke_prev = 0.0;   // kinetic damping: kinetic energy at the previous full step
 
     while (!done) {
         // Keep the packed fiber ends and incidence lists packed: without this the
@@ -675,7 +690,10 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
         const bool check = ((uint32_t)n % (uint32_t)ce) == 0;
         gpart = Real(0);
         r2p = 0.0;
-        double d2p = 0.0;
+        double d2p = 0.0, kep = 0.0;
+        // damping-force norm of the convergence test: c |M v|, or |M v| / dt
+        // for kinetic damping
+        const Real dfac = KIN ? (Real)(1.0 / dt) : c;
 #pragma unroll
         for (int s = 0; s < SN; ++s) {
             int a = s * T + tid;
@@ -688,10 +706,12 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
                 az[s] = -fz * iM[s] - c * vz[s];
                 vx[s] += hdt * ax[s]; vy[s] += hdt * ay[s]; vz[s] += hdt * az[s];
                 gpart = fmax(gpart, G * iM[s]);
+                if constexpr (KIN)
+                    kep += 0.5 * (double)((vx[s] * vx[s] + vy[s] * vy[s] + vz[s] * vz[s]) * dev_rcp(iM[s]));
                 if (check) {
                     r2p += (double)fx * fx + (double)fy * fy + (double)fz * fz;
-                    // damping force c M v of this node (only tested against the tolerance)
-                    const Real cm = c * dev_rcp(iM[s]);
+                    // damping-force norm of this node (only tested against the tolerance)
+                    const Real cm = dfac * dev_rcp(iM[s]);
                     const double px = (double)(cm * vx[s]), py = (double)(cm * vy[s]), pz = (double)(cm * vz[s]);
                     d2p += px * px + py * py + pz * pz;
                 }
@@ -700,7 +720,19 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
         }
         if (check) b2p = boundary_norm2_partial<Real, T>(net, L, b0, nb);
         parity ^= 1;
-        block_reduce<Real, NW>(red, parity, gpart, r2p, d2p, b2p, check, gmax, R2, D2, B2);
+        double ke = 0.0;
+        block_reduce<Real, NW, KIN>(red, parity, gpart, r2p, d2p, b2p, check, gmax, R2, D2, B2, kep, &ke);
+        if constexpr (KIN) {
+            // a kinetic-energy peak was passed: restart every node from rest
+            // (the acceleration is already -f/M)
+            if (ke < ke_prev) {
+#pragma unroll
+                for (int s = 0; s < SN; ++s) vx[s] = vy[s] = vz[s] = Real(0);
+                ke = 0.0;
+                D2 = 0.0;
+            }
+            ke_prev = ke;
+        }
         if (check) {
             Rlast = sqrt(R2);
             Dlast = sqrt(D2);
@@ -742,7 +774,7 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
     __syncthreads();
 }
 
-template <typename Real, int T, int SF, int SN>
+template <typename Real, int T, int SF, int SN, bool KIN>
 __global__ __launch_bounds__(T) void dr_resident_kernel(SolveArgs A)
 {
     extern __shared__ char smem[];
@@ -755,7 +787,7 @@ __global__ __launch_bounds__(T) void dr_resident_kernel(SolveArgs A)
         const int t = __builtin_amdgcn_readfirstlane(task);
         __syncthreads();
         if (t >= A.n_list) break;
-        resident_solve<Real, T, SF, SN>(A, __builtin_amdgcn_readfirstlane(A.list[t]), smem, red);
+        resident_solve<Real, T, SF, SN, KIN>(A, __builtin_amdgcn_readfirstlane(A.list[t]), smem, red);
     }
 }
 
@@ -768,7 +800,7 @@ __global__ __launch_bounds__(T) void dr_resident_kernel(SolveArgs A)
 // (F d0, q0, L0, 1/L0) are formed once per solve; the inverse mass is kept
 // next to the velocity; the loops issue the loads of two fibers, or of up to
 // four incidences, before using them.
-template <typename Real, int T, bool HL>
+template <typename Real, int T, bool HL, bool KIN>
 __device__ __forceinline__ void streamed_solve(const SolveArgs& A, int r, RedSlots& red, char* smem)
 {
     using R4 = typename Vec4<Real>::T;
@@ -834,7 +866,7 @@ __device__ __forceinline__ void streamed_solve(const SolveArgs& A, int r, RedSlo
         return;
     }
     const Real EA = (Real)A.EA, Bc = (Real)A.B, EAoB = (Real)(A.EA / A.B);
-    const double cd = A.c[r];
+    const double cd = KIN ? 0.0 : A.c[r];   // kinetic damping: no viscous force
     const Real c = (Real)cd;
 
 #pragma unroll 1
@@ -1000,6 +1032,7 @@ __device__ __forceinline__ void streamed_solve(const SolveArgs& A, int r, RedSlo
         done = true;
     }
     double dt = A.alpha * 2.0 / sqrt(gmax);
+    double ke_prev = 0.0;   // kinetic damping: kinetic energy at the previous full step
     while (!done) {
         const Real hdt = (Real)(0.5 * dt), rdt = (Real)dt;
 #pragma unroll 1
@@ -1021,7 +1054,10 @@ __device__ __forceinline__ void streamed_solve(const SolveArgs& A, int r, RedSlo
         const bool check = ((uint32_t)n % (uint32_t)ce) == 0;
         gpart = Real(0);
         r2p = 0.0;
-        double d2p = 0.0;
+        double d2p = 0.0, kep = 0.0;
+        // damping-force norm of the convergence test: c |M v|, or |M v| / dt
+        // for kinetic damping
+        const double dfac = KIN ? 1.0 / dt : cd;
 #pragma unroll 1
         for (int64_t a = tid; a < nf; a += T) {
             Real fx, fy, fz, G;
@@ -1036,16 +1072,34 @@ __device__ __forceinline__ void streamed_solve(const SolveArgs& A, int r, RedSlo
             wsV[a] = v;
             wsA[a] = acc;
             gpart = fmax(gpart, G * im);
+            if constexpr (KIN)
+                kep += 0.5 * (double)wsM[a] * ((double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z);
             if (check) {
                 r2p += (double)fx * fx + (double)fy * fy + (double)fz * fz;
-                double md = (double)wsM[a] * cd;
+                double md = (double)wsM[a] * dfac;
                 double px = md * (double)v.x, py = md * (double)v.y, pz = md * (double)v.z;
                 d2p += px * px + py * py + pz * pz;
             }
         }
         if (check) b2p = bnorm2();
         parity ^= 1;
-        block_reduce<Real, NW>(red, parity, gpart, r2p, d2p, b2p, check, gmax, R2, D2, B2);
+        double ke = 0.0;
+        block_reduce<Real, NW, KIN>(red, parity, gpart, r2p, d2p, b2p, check, gmax, R2, D2, B2, kep, &ke);
+        if constexpr (KIN) {
+            // a kinetic-energy peak was passed: restart every node from rest
+            // (the stored acceleration is already -f/M)
+            if (ke < ke_prev) {
+#pragma unroll 1
+                for (int64_t a = tid; a < nf; a += T) {
+                    R4 v = wsV[a];
+                    v.x = v.y = v.z = Real(0);
+                    wsV[a] = v;
+                }
+                ke = 0.0;
+                D2 = 0.0;
+            }
+            ke_prev = ke;
+        }
         if (check) {
             Rlast = sqrt(R2);
             Dlast = sqrt(D2);
@@ -1087,7 +1141,7 @@ __device__ __forceinline__ void streamed_solve(const SolveArgs& A, int r, RedSlo
 
 // RVEs whose positions fit the launch's LDS copy (nf + 1 <= lds_h_nodes) run
 // the LDS form, the others the workspace form, in one persistent launch.
-template <typename Real, int T>
+template <typename Real, int T, bool KIN>
 __global__ __launch_bounds__(T) void dr_streamed_kernel(SolveArgs A)
 {
     extern __shared__ char smem_h[];
@@ -1102,9 +1156,9 @@ __global__ __launch_bounds__(T) void dr_streamed_kernel(SolveArgs A)
         const int r = __builtin_amdgcn_readfirstlane(A.list[t]);
         const int64_t nf = A.net.free_off[r + 1] - A.net.free_off[r];
         if (nf + 1 <= A.lds_h_nodes)
-            streamed_solve<Real, T, true>(A, r, red, smem_h);
+            streamed_solve<Real, T, true, KIN>(A, r, red, smem_h);
         else
-            streamed_solve<Real, T, false>(A, r, red, smem_h);
+            streamed_solve<Real, T, false, KIN>(A, r, red, smem_h);
     }
 }
 
@@ -1187,56 +1241,61 @@ hipError_t launch_stress(const SolveArgs& a, int n_rve, hipStream_t s)
 }
 
 // ------------------------------------------------------------------ launch helpers
-template <typename Real, int T, int SF, int SN>
+template <typename Real, int T, int SF, int SN, bool KIN>
 static hipError_t launch_res(const SolveArgs& a, size_t lds, int grid, hipStream_t s)
 {
-    auto k = dr_resident_kernel<Real, T, SF, SN>;
+    auto k = dr_resident_kernel<Real, T, SF, SN, KIN>;
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3(grid), dim3(T), lds, s, a);
     return hipGetLastError();
 }
 
-template <typename Real, int T, int SF, int SN>
+template <typename Real, int T, int SF, int SN, bool KIN>
 static hipError_t spill_res(size_t* bytes)
 {
     hipFuncAttributes at;
-    hipError_t e = hipFuncGetAttributes(&at, (const void*)dr_resident_kernel<Real, T, SF, SN>);
+    hipError_t e = hipFuncGetAttributes(&at, (const void*)dr_resident_kernel<Real, T, SF, SN, KIN>);
     *bytes = at.localSizeBytes;
     return e;
 }
 
-template <typename Real, int T, int SF, int SN>
+template <typename Real, int T, int SF, int SN, bool KIN>
 static hipError_t occ_res(size_t lds, int* blocks)
 {
-    auto k = dr_resident_kernel<Real, T, SF, SN>;
+    auto k = dr_resident_kernel<Real, T, SF, SN, KIN>;
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, (const void*)k, T, lds);
 }
 
+// precision x damping (viscous or kinetic) for one resident variant
+#define RVE_RES_PK(FN, T, SF, SN, ...)                                                                \
+    (kin ? (fp64 ? FN<double, T, SF, SN, true>(__VA_ARGS__) : FN<float, T, SF, SN, true>(__VA_ARGS__))  \
+         : (fp64 ? FN<double, T, SF, SN, false>(__VA_ARGS__) : FN<float, T, SF, SN, false>(__VA_ARGS__)))
 #define RVE_RES_DISPATCH(FN, ...)                                                                     \
     switch (variant) {                                                                                \
-    case 0: return fp64 ? FN<double, 256, 4, 2>(__VA_ARGS__) : FN<float, 256, 4, 2>(__VA_ARGS__);     \
-    case 1: return fp64 ? FN<double, 512, 4, 2>(__VA_ARGS__) : FN<float, 512, 4, 2>(__VA_ARGS__);     \
-    case 2: return fp64 ? FN<double, 1024, 4, 2>(__VA_ARGS__) : FN<float, 1024, 4, 2>(__VA_ARGS__);   \
-    case 3: return fp64 ? FN<double, 512, 8, 4>(__VA_ARGS__) : FN<float, 512, 8, 4>(__VA_ARGS__);     \
-    case 4: return fp64 ? FN<double, 1024, 6, 3>(__VA_ARGS__) : FN<float, 1024, 6, 3>(__VA_ARGS__);   \
-    case 5: return fp64 ? FN<double, 256, 16, 8>(__VA_ARGS__) : FN<float, 256, 16, 8>(__VA_ARGS__);   \
+    case 0: return RVE_RES_PK(FN, 256, 4, 2, __VA_ARGS__);                                            \
+    case 1: return RVE_RES_PK(FN, 512, 4, 2, __VA_ARGS__);                                            \
+    case 2: return RVE_RES_PK(FN, 1024, 4, 2, __VA_ARGS__);                                           \
+    case 3: return RVE_RES_PK(FN, 512, 8, 4, __VA_ARGS__);                                            \
+    case 4: return RVE_RES_PK(FN, 1024, 6, 3, __VA_ARGS__);                                           \
+    case 5: return RVE_RES_PK(FN, 256, 16, 8, __VA_ARGS__);                                           \
     default: return hipErrorInvalidValue;                                                             \
     }
 
 hipError_t launch_resident(int variant, bool fp64, const SolveArgs& a, size_t lds, int grid, hipStream_t s)
 {
+    const bool kin = a.kinetic != 0;
     RVE_RES_DISPATCH(launch_res, a, lds, grid, s)
 }
 
-hipError_t max_resident_blocks(int variant, bool fp64, size_t lds, int* blocks)
+hipError_t max_resident_blocks(int variant, bool fp64, bool kin, size_t lds, int* blocks)
 {
     RVE_RES_DISPATCH(occ_res, lds, blocks)
 }
 
-hipError_t resident_scratch_bytes(int variant, bool fp64, size_t* bytes)
+hipError_t resident_scratch_bytes(int variant, bool fp64, bool kin, size_t* bytes)
 {
     RVE_RES_DISPATCH(spill_res, bytes)
 }
@@ -1245,7 +1304,7 @@ template <typename Real, int T>
 static hipError_t launch_streamed_t(const SolveArgs& a, int grid, hipStream_t s)
 {
     const size_t lds = 3 * sizeof(Real) * (size_t)a.lds_h_nodes;
-    const void* k = (const void*)dr_streamed_kernel<Real, T>;
+    const void* k = a.kinetic ? (const void*)dr_streamed_kernel<Real, T, true> : (const void*)dr_streamed_kernel<Real, T, false>;
     if (lds > 0) {
         hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;

@@ -25,10 +25,14 @@ Loading: extension along x with stretch lam, u_x = 0 on x = 0 and
 u_x = (lam - 1) L_x on x = L_x, either with symmetry planes u_y = 0 on
 y = 0 and u_z = 0 on z = 0 and traction-free lateral faces ("uniaxial",
 the paper's tissue test) or with both x faces gripped (u_y = u_z = 0 there,
-"clamped").  A sub-isostatic fiber network carries almost no load in
-uniaxial tension until its fibers have rotated towards the load (the toe
-region), so the reactions of the first uniaxial steps are tiny; the
-clamped setup loads the networks from the first step.
+"clamped"), or every boundary node on the affine map of
+F_M = diag(lam, lam_t, lam_t), lam_t = 1 + (lam - 1)/2 ("affine": the
+whole box in tension, heterogeneous inside).  A sub-isostatic fiber network
+carries almost no load, and has a singular stiffness, until its fibers have
+rotated towards the load (the toe region): under uniaxial loading the
+first steps see tiny reactions, Gauss points in lateral compression relax
+slowly and their tangents do not exist; the affine setup keeps every
+network in tension.
 
 Host code (numpy/scipy): the macro problem has a few thousand unknowns; all
 microscale work runs in the library's kernels.
@@ -104,10 +108,19 @@ class HexMesh:
         n = 3 * self.n_nodes
         return sp.coo_matrix((Ke.ravel(), (self._rows, self._cols)), shape=(n, n)).tocsr()
 
-    def uniaxial_bc(self, lam: float, kind: str = "uniaxial"):
+    def boundary_dofs(self, lam: float, kind: str = "uniaxial"):
         """Fixed DOFs and their values for extension along x ("uniaxial":
         symmetry planes y = 0 and z = 0; "clamped": both x faces gripped)."""
         X = self.X
+        if kind == "affine":
+            on = np.zeros(len(X), bool)
+            for k in range(3):
+                on |= (X[:, k] == 0) | (X[:, k] == self.L[k])
+            ids = np.nonzero(on)[0]
+            lam_t = 1.0 + 0.5 * (lam - 1.0)
+            U = X[ids] * (np.array([lam, lam_t, lam_t]) - 1.0)
+            dofs = (3 * ids[:, None] + np.arange(3)[None, :]).ravel()
+            return dofs, U.ravel()
         x0, x1 = X[:, 0] == 0, X[:, 0] == self.L[0]
         spec = [(x0, 0, 0.0), (x1, 0, (lam - 1.0) * self.L[0])]
         if kind == "uniaxial":
@@ -215,6 +228,7 @@ class FE2:
         self.sigma = None
         self.F = None
         self.status = None
+        self.A_last = None
 
     def _micro_stress(self, u, rec):
         F = self.mesh.deformation_gradients(u)
@@ -230,11 +244,13 @@ class FE2:
         moves only if the step converges."""
         m = self.mesh
         rec = NewtonRecord(lam=lam_to)
-        dofs, vals = m.uniaxial_bc(lam_to, self.bc)
+        dofs, vals = m.boundary_dofs(lam_to, self.bc)
         free = np.ones(3 * m.n_nodes, bool)
         free[dofs] = False
         u = self.u.copy()
         u[:, 0] += (lam_to - self.lam) * m.X[:, 0]        # predictor: affine stretch increment
+        if self.bc == "affine":
+            u[:, 1:] += 0.5 * (lam_to - self.lam) * m.X[:, 1:]
         u.reshape(-1)[dofs] = vals
         for it in range(self.max_newton + 1):
             F, sig, st = self._micro_stress(u, rec)
@@ -267,9 +283,13 @@ class FE2:
                 return rec
             _, A = first_pk(F, sig, np.where(ok[:, None, None], ds, 0.0))
             # Gauss points without a tangent (no converged state, or K_ff not
-            # positive definite there) take the mean tangent of the others:
-            # the residual stays exact, only the Newton matrix is approximate
-            A[~ok] = A[ok].mean(axis=0)
+            # positive definite there) keep their last tangent, else take the
+            # mean of the others: the residual stays exact, only the Newton
+            # matrix is approximate
+            if self.A_last is None:
+                self.A_last = np.broadcast_to(A[ok].mean(axis=0), A.shape).copy()
+            A[~ok] = self.A_last[~ok]
+            self.A_last = A.copy()
             rec.tangent_fallback.append(int((~ok).sum()))
             K = m.stiffness(A)
             Kff = K[free][:, free]
@@ -313,7 +333,7 @@ def _config5_main(argv=None):
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--cold", action="store_true", help="start every micro solve from the affine state")
     ap.add_argument("--mesh", type=int, nargs=3, default=[16, 16, 4])
-    ap.add_argument("--bc", default="clamped", choices=["clamped", "uniaxial"])
+    ap.add_argument("--bc", default="affine", choices=["affine", "clamped", "uniaxial"])
     args = ap.parse_args(argv)
     mesh = HexMesh(*args.mesh)
     t0 = time.perf_counter()

@@ -38,6 +38,7 @@ def test_version_and_defaults():
     rb.lib().rve_default_opts(C.byref(o))
     assert o.precision == rb.FP64 and o.alpha == 0.9 and o.n_max == 1_000_000 and o.check_every == 1
     assert o.cg_tol == 1e-6
+    assert o.damping == rb.DAMP_VISCOUS and o.energy_check == 0 and o.energy_tol == 0.05
 
 
 def _create(nets, **kw):
@@ -77,6 +78,11 @@ def test_zero_length_fiber_rejected():
     (dict(check_every=0), "check_every"), (dict(n_max=-1), "n_max"), (dict(precision=7), "precision"),
     (dict(engine=rb.ENGINE_NAIVE, precision=rb.MIXED), "naive"), (dict(threads_per_rve=100), "threads"),
     (dict(EA=0.0), "EA"), (dict(cg_tol=0.0), "cg_tol"), (dict(tol_rel=-1.0), "tolerances"),
+    (dict(damping=5), "damping"), (dict(energy_tol=0.0), "energy_tol"),
+    (dict(damping=rb.DAMP_ADAPTIVE, precision=rb.MIXED), "FP64 only"),
+    (dict(energy_check=True, precision=rb.MIXED), "FP64 only"),
+    (dict(damping=rb.DAMP_KINETIC, engine=rb.ENGINE_NAIVE), "naive"),
+    (dict(damping=rb.DAMP_ADAPTIVE, engine=rb.ENGINE_NAIVE), "naive"),
 ])
 def test_bad_options_rejected_on_host(kw, needle):
     with pytest.raises(rb.RVEError) as e:

@@ -15,6 +15,8 @@
 * With gripped x faces the solution is not homogeneous; the driver still
   converges quadratically, the fixed DOFs are the two x faces, and the
   reactions on the two faces balance.
+* With every boundary node on an affine map the homogeneous material's
+  solution is that affine map: the predictor already satisfies equilibrium.
 * A failing step is retried with half the increment after the micro state
   is restored from the last checkpoint.
 """
@@ -152,7 +154,7 @@ def test_failed_step_is_cut_back_and_restored():
 
 def test_driver_clamped_converges():
     mesh = fe2.HexMesh(3, 2, 2)
-    dofs, vals = mesh.uniaxial_bc(1.1, "clamped")
+    dofs, vals = mesh.boundary_dofs(1.1, "clamped")
     x_faces = (mesh.X[:, 0] == 0) | (mesh.X[:, 0] == 3)
     assert len(dofs) == 3 * x_faces.sum()
     drv = fe2.FE2(mesh, NeoHookeMicro(), tol=1e-12, max_newton=12, bc="clamped")
@@ -166,4 +168,18 @@ def test_driver_clamped_converges():
     f = mesh.internal_force(P)
     np.testing.assert_allclose(f[mesh.X[:, 0] == 0].sum(0), -f[mesh.X[:, 0] == 3].sum(0), atol=1e-10)
     with pytest.raises(ValueError):
-        mesh.uniaxial_bc(1.1, "periodic")
+        mesh.boundary_dofs(1.1, "periodic")
+
+
+def test_driver_affine_boundary_homogeneous():
+    mesh = fe2.HexMesh(3, 3, 3)
+    dofs, vals = mesh.boundary_dofs(1.1, "affine")
+    on = np.zeros(mesh.n_nodes, bool)
+    for k in range(3):
+        on |= (mesh.X[:, k] == 0) | (mesh.X[:, k] == 3)
+    assert len(dofs) == 3 * on.sum()
+    drv = fe2.FE2(mesh, NeoHookeMicro(), tol=1e-12, bc="affine")
+    hist = drv.run(1.1, 2)
+    assert all(h.converged for h in hist)
+    np.testing.assert_allclose(drv.F, np.broadcast_to(np.diag([1.1, 1.05, 1.05]), drv.F.shape), atol=1e-12)
+    assert all(len(h.residual) <= 2 for h in hist)

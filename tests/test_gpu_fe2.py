@@ -1,23 +1,22 @@
 """GPU FE^2 driver (Algorithm 1 around the batched micro solve), small mesh.
 
-A 2 x 2 x 1 hex mesh with gripped x faces (32 Gauss points, one 60-seed
-Voronoi RVE each, FP64 micro solves to tol_rel 1e-7) is stretched to 1.1 in
-three load steps.
+A 3 x 3 x 3 hex mesh (216 Gauss points, one 60-seed Voronoi RVE each, FP64
+micro solves to tol_rel 1e-8) whose boundary follows the affine map of
+diag(1.1, 1.05, 1.05), reached in two load steps; the eight interior nodes
+find their equilibrium from the heterogeneous RVE responses.
 
-* Every step converges to a macro residual of 1e-5 (relative to the
+* Every step converges to a macro residual of 1e-6 (relative to the
   reactions; the micro tolerance bounds what the macro loop can reach).
 * Parity with the oracle: at the driver's final Gauss-point F the oracle's
   stresses (independent FP64 relaxation from the affine start, same
-  options) agree with the GPU's (reached through warm starts) to 1e-4 on at
-  least three quarters of the RVEs both sides converge, with a median error
-  below 1e-5.  These sub-isostatic networks can settle in different
-  equilibria from different starts, and some relax slowly and stop at
-  n_max, so agreement on every RVE is not a property of the method; the
-  oracle's stresses of all RVEs still leave the macro residual below 1e-2.
+  options) agree with the GPU's (reached through warm starts) to 1e-5 on
+  at least 90% of the RVEs both sides converge, with a median error below
+  1e-6 (sub-isostatic networks can settle in different equilibria from
+  different starts, so agreement on every RVE is not a property of the
+  method), and the oracle's stresses leave the macro residual below 1e-3.
 * Warm starts (each micro solve continues from the previous state) take
-  fewer relaxation iterations than cold starts (affine start every time);
-  the two macro solutions agree to 1e-2 (a floppy network may settle in a
-  different equilibrium from a different start).
+  fewer relaxation iterations than cold starts (affine start every time)
+  and reach the same macro solution to 1e-4.
 """
 import numpy as np
 import pytest
@@ -36,48 +35,48 @@ def rb():
 
 def _run(rb, batch, mesh, warm):
     opts = dict(precision=rb.FP64, law=rb.LAW_EXP, mass=rb.MASS_SCALED, alpha=0.5, c=0.1, tol_abs=0.0,
-                tol_rel=1e-7, n_max=400000, cg_tol=1e-10)
+                tol_rel=1e-8, n_max=400000, cg_tol=1e-10)
     micro = fe2.GpuMicro(batch, warm=warm, **opts)
-    drv = fe2.FE2(mesh, micro, tol=1e-5, max_newton=12, bc="clamped", verbose=True)
-    hist = drv.run(1.1, 3)
+    drv = fe2.FE2(mesh, micro, tol=1e-6, max_newton=12, bc="affine", verbose=True)
+    hist = drv.run(1.1, 2)
     micro.close()
     return drv, hist
 
 
 def test_fe2_small_mesh_matches_oracle_and_warm_starts_pay(rb):
-    mesh = fe2.HexMesh(2, 2, 1)
+    mesh = fe2.HexMesh(3, 3, 3)
     nets = [synth.voronoi_network(60, [83, k, 0]) for k in range(mesh.n_gp)]
     batch = synth.pack(nets)
-    log("fe2 2x2x1 warm")
+    log("fe2 3x3x3 warm")
     drv, hist = _run(rb, batch, mesh, warm=True)
     for h in hist:
         log(f"  lam {h.lam:.4f} converged {h.converged} residuals {['%.1e' % r for r in h.residual]} "
-            f"micro iters {h.micro_iters} tangent fallbacks {h.tangent_fallback}")
+            f"tangent fallbacks {h.tangent_fallback}")
     assert hist[-1].converged and abs(drv.lam - 1.1) <= 1e-14
-    o = oracle.make_opts(law=oracle.EXP, alpha=0.5, tol_abs=0.0, tol_rel=1e-7, n_max=400000,
+    o = oracle.make_opts(law=oracle.EXP, alpha=0.5, tol_abs=0.0, tol_rel=1e-8, n_max=400000,
                          mass=oracle.MASS_SCALED)
     ref = oracle.solve_batch(batch, drv.F, 0.1, o)
-    st_gpu = np.bincount(drv.status, minlength=4)
     both = (ref["status"] == 0) & (drv.status == 0)
     err = rel_err(drv.sigma, ref["sigma"])
-    log(f"  oracle statuses {np.bincount(ref['status'], minlength=4).tolist()}, GPU {st_gpu.tolist()}; "
-        f"sigma rel err on {both.sum()} oracle-converged RVEs: max {err[both].max():.2e}, all RVEs {err.max():.2e}")
-    assert both.sum() >= mesh.n_gp // 2
-    assert np.mean(err[both] <= 1e-4) >= 0.75 and np.median(err[both]) <= 1e-5
+    log(f"  oracle statuses {np.bincount(ref['status'], minlength=4).tolist()}, GPU "
+        f"{np.bincount(drv.status, minlength=4).tolist()}; sigma rel err on {both.sum()} jointly converged: "
+        f"median {np.median(err[both]):.2e}, within 1e-5 {np.mean(err[both] <= 1e-5):.3f}")
+    assert both.sum() >= 0.75 * mesh.n_gp
+    assert np.mean(err[both] <= 1e-5) >= 0.9 and np.median(err[both]) <= 1e-6
     P, _ = fe2.first_pk(drv.F, ref["sigma"])
     r = mesh.internal_force(P).ravel()
-    dofs, _ = mesh.uniaxial_bc(drv.lam, "clamped")
+    dofs, _ = mesh.boundary_dofs(drv.lam, "affine")
     free = np.ones(r.size, bool)
     free[dofs] = False
     res = np.linalg.norm(r[free]) / np.linalg.norm(r[~free])
     log(f"  macro residual with the oracle's stresses: {res:.2e}")
-    assert res <= 1e-2
-    log("fe2 2x2x1 cold")
+    assert res <= 1e-3
+    log("fe2 3x3x3 cold")
     drv_c, hist_c = _run(rb, batch, mesh, warm=False)
     assert hist_c[-1].converged
     du = np.abs(drv_c.u - drv.u).max() / np.abs(drv.u).max()
     it_w = sum(sum(h.micro_iters) for h in hist)
     it_c = sum(sum(h.micro_iters) for h in hist_c)
     log(f"  warm vs cold: |du| rel {du:.2e}, relaxation iterations {it_w} vs {it_c}")
-    assert du <= 1e-2
+    assert du <= 1e-4
     assert it_w < it_c
