@@ -118,9 +118,10 @@ typedef struct {
  *     iterations (>= 1); n_max caps the iterations.
  *   engine: RVE_ENGINE_*.  threads_per_rve: 0 = automatic (default or
  *     autotuned variant per size tier), else 256/512/1024: only resident
- *     variants of that workgroup size; RVEs none of them holds without
- *     spilling registers run on the streamed kernel (256 threads when 256
- *     is asked for, else 1024).
+ *     variants of that workgroup size (256 and 512 threads: the variants
+ *     with four fiber and two node slots per thread); RVEs none of them
+ *     holds without spilling registers run on the streamed kernel (256
+ *     threads when 256 is asked for, else 1024).
  *   cg_tol, cg_max_iter: conjugate-gradient controls of rve_batch_tangent and
  *     rve_batch_vjp.
  *   stream: hipStream_t for every launch and copy (NULL: the null stream).

@@ -587,6 +587,13 @@ int rve_batch_create(const rve_net_desc* net, const rve_opts* opts, rve_batch** 
                 // a few spilled scalars outside the relaxation loop are harmless;
                 // more than that means the loop itself spills
                 if (resident_scratch_bytes(v, p == 1, k == 1, &sb) == hipSuccess) b->variant_spills[k][p][v] = sb > 64;
+                // Switched off: the (512, 8, 4) and (256, 16, 8) builds (near
+                // or beyond 256 registers per lane, AGPRs holding VGPRs) were in
+                // use when a mixed-precision run with a forced workgroup size
+                // faulted the GPU; the cause is not known.  Their capacity is
+                // that of (1024, 4, 2), so only a forced 512 or 256 reached them;
+                // RVEs they would take run on the streamed kernel.
+                if (v == 3 || v == 5) b->variant_spills[k][p][v] = true;
             }
     b->R = net->n_rve;
     b->opts = *opts;
