@@ -330,9 +330,9 @@ int or_solve(int64_t n_nodes, int64_t n_fib, const double* X, const uint8_t* is_
  *   violation |W + KE + Wd - W0| > energy_tol * max(W0, W, KE, Wd) ends the
  *   relaxation with OR_ENERGY (an unstable or unphysical trajectory).
  *
- * Convergence as in or_solve with the damping-force norm D = c |M v|_2 for
- * damping 0 and 2, and D = |M v|_2 / dt for kinetic damping (the force that
- * stops every node within one step).  Outputs as or_solve plus the final
+ * Convergence as in or_solve with the damping-force norm D = c |M v|_2 (for
+ * kinetic damping c is not applied as a force, only as the scale of this
+ * velocity guard, so that the test is the viscous one).  Outputs as or_solve plus the final
  * coefficient (c_out; 0 for kinetic damping) and the final relative energy
  * balance |W + KE + Wd - W0| / max(W0, W, KE, Wd) (e_out; evaluated whether
  * or not the check is enabled).
@@ -476,7 +476,7 @@ int or_solve_variant(int64_t n_nodes, int64_t n_fib, const double* X, const uint
         double scale = fmax(fmax(W0, W), fmax(KE, Wd));
         ebal = scale > 0.0 ? fabs(W + KE + Wd - W0) / scale : 0.0;
         R = sqrt(R2);
-        D = damping == 1 ? sqrt(MV2) / dt : cc * sqrt(MV2);
+        D = (damping == 1 ? c : cc) * sqrt(MV2);
         tol = fmax(o->tol_abs, o->tol_rel * sqrt(B2));
         ++n;
         if (energy_check && ebal > energy_tol) { status = OR_ENERGY; break; }

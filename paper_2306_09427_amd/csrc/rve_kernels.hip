@@ -457,6 +457,7 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
     // kinetic-energy peaks below
     const double cd = KIN ? 0.0 : A.c[r];
     const Real c = (Real)cd;
+    const Real cg = KIN ? (Real)A.c[r] : c;   // scale of the damping-force test
 
     Lds<Real> L;
     L.init(smem, nf, nfib);
@@ -691,9 +692,9 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
         gpart = Real(0);
         r2p = 0.0;
         double d2p = 0.0, kep = 0.0;
-        // damping-force norm of the convergence test: c |M v|, or |M v| / dt
-        // for kinetic damping
-        const Real dfac = KIN ? (Real)(1.0 / dt) : c;
+        // damping-force norm of the convergence test, c |M v| (kinetic
+        // damping applies no viscous force but keeps c as the guard's scale)
+        const Real dfac = cg;
 #pragma unroll
         for (int s = 0; s < SN; ++s) {
             int a = s * T + tid;
@@ -868,6 +869,7 @@ __device__ __forceinline__ void streamed_solve(const SolveArgs& A, int r, RedSlo
     const Real EA = (Real)A.EA, Bc = (Real)A.B, EAoB = (Real)(A.EA / A.B);
     const double cd = KIN ? 0.0 : A.c[r];   // kinetic damping: no viscous force
     const Real c = (Real)cd;
+    const double cgd = KIN ? A.c[r] : cd;     // scale of the damping-force test
 
 #pragma unroll 1
     for (int64_t k = tid; k < nfib; k += T) {
@@ -1055,9 +1057,9 @@ __device__ __forceinline__ void streamed_solve(const SolveArgs& A, int r, RedSlo
         gpart = Real(0);
         r2p = 0.0;
         double d2p = 0.0, kep = 0.0;
-        // damping-force norm of the convergence test: c |M v|, or |M v| / dt
-        // for kinetic damping
-        const double dfac = KIN ? 1.0 / dt : cd;
+        // damping-force norm of the convergence test, c |M v| (kinetic
+        // damping applies no viscous force but keeps c as the guard's scale)
+        const double dfac = cgd;
 #pragma unroll 1
         for (int64_t a = tid; a < nf; a += T) {
             Real fx, fy, fz, G;

@@ -333,7 +333,7 @@ __global__ __launch_bounds__(kVT) void dr_variant_kernel(VariantArgs A)
             const double scale = fmax(fmax(W0, W), fmax(KE, Wd));
             ebal = scale > 0.0 ? fabs(W + KE + Wd - W0) / scale : 0.0;
             R = sqrt(R2);
-            D = damping == DAMP_KINETIC ? sqrt(MV2) / dt : cc * sqrt(MV2);
+            D = (damping == DAMP_KINETIC ? S.c[r] : cc) * sqrt(MV2);
             tol = fmax(S.tol_abs, S.tol_rel * sqrt(B2));
             ++n;
             __syncthreads();
