@@ -334,6 +334,7 @@ def _config5_main(argv=None):
     ap.add_argument("--cold", action="store_true", help="start every micro solve from the affine state")
     ap.add_argument("--mesh", type=int, nargs=3, default=[16, 16, 4])
     ap.add_argument("--bc", default="affine", choices=["affine", "clamped", "uniaxial"])
+    ap.add_argument("--damping", default="viscous", choices=["viscous", "kinetic"])
     args = ap.parse_args(argv)
     mesh = HexMesh(*args.mesh)
     t0 = time.perf_counter()
@@ -341,13 +342,14 @@ def _config5_main(argv=None):
     gen_s = time.perf_counter() - t0
     from . import binding as rb
     micro = GpuMicro(batch, warm=not args.cold, precision=rb.MIXED, law=rb.LAW_EXP, mass=rb.MASS_SCALED, alpha=0.5,
-                     c=0.1, tol_abs=0.0, tol_rel=1e-5, n_max=100000, check_every=8, cg_tol=1e-6)
+                     c=0.1, tol_abs=0.0, tol_rel=1e-5, n_max=100000, check_every=8, cg_tol=1e-6,
+                     damping=rb.DAMP_KINETIC if args.damping == "kinetic" else rb.DAMP_VISCOUS)
     drv = FE2(mesh, micro, tol=args.tol, bc=args.bc, verbose=True)
     t0 = time.perf_counter()
     hist = drv.run(args.lam, args.steps)
     wall = time.perf_counter() - t0
     micro.close()
-    out = {"mesh": args.mesh, "bc": args.bc, "rves": mesh.n_gp, "lam": args.lam, "steps": args.steps, "warm": not args.cold,
+    out = {"mesh": args.mesh, "bc": args.bc, "damping": args.damping, "rves": mesh.n_gp, "lam": args.lam, "steps": args.steps, "warm": not args.cold,
            "generation_s": round(gen_s, 1), "wall_s": round(wall, 2),
            "micro_solve_s": round(sum(sum(h.micro_ms) for h in hist) / 1e3, 2),
            "tangent_s": round(sum(sum(h.tangent_ms) for h in hist) / 1e3, 2),
