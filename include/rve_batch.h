@@ -130,8 +130,8 @@ typedef struct {
  *     viscous force; whenever the kinetic energy 1/2 sum M |v|^2 at a full
  *     step is below its value at the previous full step, every velocity is
  *     set to zero (c is applied as no force, only as the scale of the
- *     damping-force test c |M v|_2).  RVE_DAMP_ADAPTIVE: after each force evaluation
- *     c = 2 sqrt(u.K u / u.M u), the critical damping of the Rayleigh
+ *     damping-force test c |M v|_2).  RVE_DAMP_ADAPTIVE: after each force
+ *     evaluation c = 2 sqrt(u.K u / u.M u), the critical damping of the Rayleigh
  *     quotient of u, the displacement since the start of the solve, with K
  *     the tangent stiffness at the current positions (0 when u.K u <= 0);
  *     c of the opts is only the value before the first step.
