@@ -225,7 +225,7 @@ __global__ __launch_bounds__(kVT) void dr_variant_kernel(VariantArgs A)
         double* nd = C.node + kNodeDoubles * a;
         double f[3], G;
         gather_free(C, a, f, G);
-        const double M = S.mass_mode == MASS_SCALED ? (G > 0.0 ? G / 4.0 : 1.0) : net.mass[C.a0 + a];
+        const double M = S.mass_mode == MASS_SCALED ? (G > 0.0 ? G / 4.0 : 1.0) : net.mass[C.a0 + a] * S.rhoA;
         for (int c = 0; c < 3; ++c) {
             nd[9 + c] = f[c];
             nd[6 + c] = -f[c] / M;

@@ -149,3 +149,21 @@ def test_kinetic_on_ordinary_engines(rb, engine):
     err_m = rel_err(sig_m, ref["sigma"])
     log(f"  mixed: statuses {st_m.tolist()}, sigma rel err vs FP64 oracle {err_m[both].tolist()}")
     assert both.sum() >= 3 and np.mean(err_m[both] <= 1e-4) >= 0.75
+
+
+def test_lumped_mass_density_on_the_variant_engine(rb):
+    """Lumped mass with rhoA != 1 (energy check on, so the variant engine
+    runs): the same iterations as the oracle, hence the same masses."""
+    log("variant engine, lumped mass, rhoA 2.5")
+    batch, F = synth.make_config_batch(2, idx=IDX[:3])
+    b = rb.Batch(batch, precision=rb.FP64, law=rb.LAW_EXP, mass=rb.MASS_LUMPED, rhoA=2.5, alpha=0.5, c=2.0,
+                 tol_abs=0.0, tol_rel=1e-8, n_max=20000, energy_check=True)
+    sig, st, stats = b.solve(F, stats=True)
+    b.close()
+    o = oracle.make_opts(law=oracle.EXP, rhoA=2.5, alpha=0.5, tol_abs=0.0, tol_rel=1e-8, n_max=20000,
+                         mass=oracle.MASS_LUMPED)
+    ref = oracle.solve_variant_batch(batch, F, 2.0, o, energy_check=True)
+    log(f"  iterations {stats['iters'].tolist()} oracle {ref['iters'].tolist()}")
+    np.testing.assert_array_equal(st, ref["status"])
+    np.testing.assert_array_equal(stats["iters"], ref["iters"])
+    assert rel_err(sig, ref["sigma"]).max() <= 1e-6
