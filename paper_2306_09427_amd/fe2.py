@@ -166,6 +166,7 @@ class GpuMicro:
         from . import binding as rb
         self.rb = rb
         self.opts = dict(opts)
+        self.opts.pop("init", None)   # the driver chooses the start (affine, then warm)
         self.warm = warm
         self.batch = rb.Batch(nets, **self.opts)
         self.has_state = False
@@ -174,7 +175,9 @@ class GpuMicro:
     def solve(self, F):
         use_warm = self.warm and self.has_state
         if use_warm != self.warm_now:
-            self.batch.set_opts(init=self.rb.INIT_WARM if use_warm else self.rb.INIT_AFFINE, **self.opts)
+            o = dict(self.opts)
+            o["init"] = self.rb.INIT_WARM if use_warm else self.rb.INIT_AFFINE
+            self.batch.set_opts(**o)
             self.warm_now = use_warm
         sig, st, stats = self.batch.solve(F, stats=True)
         self.has_state = True
