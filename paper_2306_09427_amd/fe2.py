@@ -160,9 +160,16 @@ def first_pk(F: np.ndarray, sigma: np.ndarray, dsdF: np.ndarray | None = None):
 
 
 class GpuMicro:
-    """Microscale of the driver: one batch of RVEs, one per Gauss point."""
+    """Microscale of the driver: one batch of RVEs, one per Gauss point.
 
-    def __init__(self, nets, warm: bool = True, **opts):
+    refine_tangent: with a mixed-precision batch, take the tangent at an FP64
+    state instead: the mixed state is exported, imported into an FP64 twin
+    batch of the same networks, relaxed further from there (warm start,
+    tol_rel refine_tol) and linearised in FP64.  Floppy RVEs that stop at the
+    mixed tolerance can sit on the unstable side of a soft mode, where K_ff is
+    indefinite and no tangent exists; the FP64 state is usually stable."""
+
+    def __init__(self, nets, warm: bool = True, refine_tangent: bool = False, refine_tol: float = 1e-8, **opts):
         from . import binding as rb
         self.rb = rb
         self.opts = dict(opts)
@@ -171,6 +178,12 @@ class GpuMicro:
         self.batch = rb.Batch(nets, **self.opts)
         self.has_state = False
         self.warm_now = False
+        self.twin = None
+        self.last_F = None
+        if refine_tangent:
+            o = dict(self.opts)
+            o.update(precision=rb.FP64, tol_rel=refine_tol, init=rb.INIT_WARM)
+            self.twin = rb.Batch(nets, **o)
 
     def solve(self, F):
         use_warm = self.warm and self.has_state
@@ -181,10 +194,18 @@ class GpuMicro:
             self.warm_now = use_warm
         sig, st, stats = self.batch.solve(F, stats=True)
         self.has_state = True
+        self.last_F = F
         return sig, st, stats["iters"]
 
     def tangent(self):
-        return self.batch.tangent()
+        if self.twin is None:
+            return self.batch.tangent()
+        import torch
+        # device-to-device: the state never leaves the GPU
+        Fe, h, st = self.batch.export_state(like=torch.empty(1, device="cuda"))
+        self.twin.import_state(Fe, h, st)
+        self.twin.solve(self.last_F)
+        return self.twin.tangent()
 
     def checkpoint(self):
         return self.batch.export_state() if self.has_state else None
@@ -198,6 +219,8 @@ class GpuMicro:
 
     def close(self):
         self.batch.close()
+        if self.twin is not None:
+            self.twin.close()
 
 
 @dataclass
