@@ -69,6 +69,14 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                                "(hipcc --offload-arch=gfx950); there is no CPU fallback")
+        # The library links the system HIP runtime while torch carries its
+        # own copy; torch's copy finds no GPU once the other one has opened
+        # the device, so let torch open it first when torch is installed.
+        try:
+            import torch
+            torch.cuda.is_available()
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         P = C.c_void_p
         L.rve_version.restype = C.c_int

@@ -200,9 +200,7 @@ class GpuMicro:
     def tangent(self):
         if self.twin is None:
             return self.batch.tangent()
-        import torch
-        # device-to-device: the state never leaves the GPU
-        Fe, h, st = self.batch.export_state(like=torch.empty(1, device="cuda"))
+        Fe, h, st = self.batch.export_state()
         self.twin.import_state(Fe, h, st)
         self.twin.solve(self.last_F)
         return self.twin.tangent()
