@@ -2,7 +2,9 @@
 
 Each case plants one mistake in a private copy of the C oracle (a dropped
 term, a flipped sign, a transposed operand, a wrong factor), builds it, and
-runs the pin suite against it in a subprocess; the suite has to fail.
+runs the pin suite against it in a subprocess; the suite has to fail.  The
+mistakes in the relaxation alternatives (or_solve_variant) are checked
+against their own pins (tests/test_oracle_variants.py).
 """
 import os
 import subprocess
@@ -34,6 +36,36 @@ MUTANTS = {
     "mass_missing_half_step": ("v[3 * p + k] += 0.5 * dt * a[3 * p + k];\n                x[3 * p + k]",
                                "v[3 * p + k] += dt * a[3 * p + k];\n                x[3 * p + k]"),
 }
+
+
+# mistakes in the relaxation alternatives (or_solve_variant)
+VARIANT_MUTANTS = {
+    "kinetic_reset_inverted": ("if (KE < KE_prev) {", "if (KE > KE_prev) {"),
+    "adaptive_geometric_sign": ("num += kt / L0[k] * nd * nd + T / l * (du2 - nd * nd);",
+                                "num += kt / L0[k] * nd * nd - T / l * (du2 - nd * nd);"),
+    "adaptive_without_mass": ("den += M[p] * u * u;", "den += u * u;"),
+    "damping_work_dropped": ("Wd += cc * M[p] * v[3 * p + k] * v[3 * p + k] * dt;", "Wd += 0.0;"),
+}
+
+
+def _run_mutant(old, new, pins, tmp_path):
+    src = open(SRC).read()
+    assert src.count(old) >= 1, f"mutation anchor not found: {old}"
+    mut = tmp_path / "mutant.c"
+    mut.write_text(src.replace(old, new, 1))
+    lib = tmp_path / "libmutant.so"
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", str(lib), str(mut), "-lm", "-lpthread"])
+    env = dict(os.environ, RVE_ORACLE_LIB=str(lib))
+    return subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                           os.path.join(ROOT, "tests", pins)], cwd=ROOT, env=env, capture_output=True, text=True,
+                          timeout=600)
+
+
+@pytest.mark.parametrize("name", sorted(VARIANT_MUTANTS))
+def test_variant_pins_reject_mutant(name, tmp_path):
+    old, new = VARIANT_MUTANTS[name]
+    r = _run_mutant(old, new, "test_oracle_variants.py", tmp_path)
+    assert r.returncode != 0, f"variant pins accepted mutant {name}:\n{r.stdout[-2000:]}"
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))

@@ -6,9 +6,17 @@ check), CPU only.
   iterations, same stress.
 * Every mode reaches the closed-form stress of the relaxed lattice from a
   random start, and the brute-force Newton equilibrium of tiny networks.
+* Kinetic damping relaxes a single mode within a few of its periods (the
+  first reset falls near the equilibrium), far faster than a light viscous
+  damping.
 * Adaptive damping on a one-DOF linear system: the Rayleigh quotient of the
   displacement is k/m, so the coefficient is critical damping 2 sqrt(k/m),
-  which relaxes the mode in far fewer steps than a small constant c.
+  which relaxes the mode in far fewer steps than a small constant c; for the
+  transverse mode of the same pre-tensioned chain the stiffness is the
+  geometric one, 2 T / l.
+* On config-2 networks (many modes) kinetic damping converges within twice
+  the iterations of the tuned viscous damping (a wrong reset test turns it
+  into a slow gradient descent).
 * Energy bookkeeping: on a damped linear chain the balance
   W + KE + Wd - W_start shrinks like dt^2 (halving alpha divides it by about
   four), so no term is missing; an unstable run (exponential fibers at
@@ -124,3 +132,39 @@ def test_energy_check_stops_unstable_runs_only():
             else:
                 assert chk["status"] == free["status"] != oracle.ENERGY
                 assert chk["iters"] == free["iters"] and chk["energy"] <= 0.05
+
+
+def test_kinetic_damping_relaxes_a_single_mode_quickly():
+    net, F, x0 = _axial_one_dof()
+    o = oracle.make_opts(law=oracle.LINEAR, EA=1.0, alpha=0.5, tol_abs=1e-13, tol_rel=0.0, n_max=100000,
+                         init=oracle.INIT_GIVEN)
+    kin = oracle.solve_variant(net, F, 0.1, o, damping=oracle.DAMP_KINETIC, x0=x0)
+    visc = oracle.solve_variant(net, F, 0.1, o, damping=oracle.DAMP_VISCOUS, x0=x0)
+    assert kin["status"] == oracle.CONVERGED and visc["status"] == oracle.CONVERGED
+    assert kin["iters"] < 300 and kin["iters"] * 10 < visc["iters"]
+    assert abs(kin["x"][1, 0]) <= 1e-12
+    assert kin["c"] == 0.0
+
+
+def test_adaptive_coefficient_sees_the_geometric_stiffness():
+    net, F, x0 = _axial_one_dof()
+    x0[1, 0] -= 0.01
+    x0[1, 1] += 0.01                     # transverse displacement only
+    o = oracle.make_opts(law=oracle.LINEAR, EA=1.0, alpha=0.5, tol_abs=1e-13, tol_rel=0.0, n_max=100000,
+                         init=oracle.INIT_GIVEN)
+    r = oracle.solve_variant(net, F, 0.0, o, damping=oracle.DAMP_ADAPTIVE, x0=x0)
+    assert r["status"] == oracle.CONVERGED
+    L0, l, m = 0.3, 0.33, 0.3
+    T = 1.0 * (l / L0 - 1.0)
+    assert abs(r["c"] - 2.0 * np.sqrt(2.0 * T / l / m)) <= 1e-9 * r["c"]
+
+
+def test_kinetic_damping_on_networks_keeps_pace_with_viscous():
+    batch, F = synth.make_config_batch(2, idx=[1, 3])
+    o = oracle.make_opts(law=oracle.EXP, alpha=0.5, tol_abs=0.0, tol_rel=1e-8, n_max=60000, mass=oracle.MASS_SCALED)
+    for r in range(2):
+        net = batch.network(r)
+        kin = oracle.solve_variant(net, F[r], 0.1, o, damping=oracle.DAMP_KINETIC)
+        visc = oracle.solve_variant(net, F[r], 0.1, o, damping=oracle.DAMP_VISCOUS)
+        assert kin["status"] == oracle.CONVERGED and visc["status"] == oracle.CONVERGED
+        assert kin["iters"] <= 2 * visc["iters"]
