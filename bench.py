@@ -378,8 +378,12 @@ def main():
         out["cpu_baseline"] = {"value": args.cpu_sample / tc, "unit": "RVE solves/s", "cores": threads,
                                "kind": "oracle",
                                "sample": f"first {args.cpu_sample} RVEs of the batch, same options, {tc:.1f}s"}
-        out["sigma_relerr_vs_oracle_sample"] = {"converged_both": int(both.sum()),
-                                                "max": float(err[both].max()) if both.any() else None}
+        # both sides stop at the same loose tolerance (tol_rel 1e-5), so
+        # their difference is bounded by the two stopping errors; the accuracy
+        # check is against the FP64 oracle converged to 1e-8 below
+        out["sigma_diff_vs_oracle_same_tol"] = {"converged_both": int(both.sum()),
+                                                "max": float(err[both].max()) if both.any() else None,
+                                                "note": "both stopped at tol_rel %g; not the accuracy check" % args.tol_rel}
         log(f"oracle: {tc:.1f}s on {threads} threads; max rel err {err[both].max() if both.any() else float('nan'):.2e}")
 
     # ---------------- sigma accuracy against the FP64 oracle converged to tol_rel 1e-8
