@@ -25,6 +25,7 @@ INIT_AFFINE, INIT_REFERENCE, INIT_GIVEN = 0, 1, 2
 MASS_LUMPED, MASS_SCALED = 0, 1
 CONVERGED, MAXITER, NONFINITE, BAD_F = 0, 1, 2, 3
 ENERGY = 7
+STAGNATED = 8
 DAMP_VISCOUS, DAMP_KINETIC, DAMP_ADAPTIVE = 0, 1, 2
 
 
@@ -32,13 +33,14 @@ class Opts(C.Structure):
     _fields_ = [("law", C.c_int32), ("init", C.c_int32), ("mass", C.c_int32), ("pad_", C.c_int32),
                 ("EA", C.c_double), ("B", C.c_double),
                 ("rhoA", C.c_double), ("alpha", C.c_double), ("tol_abs", C.c_double),
-                ("tol_rel", C.c_double), ("n_max", C.c_int64)]
+                ("tol_rel", C.c_double), ("n_max", C.c_int64), ("floor_tol_rel", C.c_double),
+                ("stall_checks", C.c_int32), ("pad2_", C.c_int32)]
 
 
 def make_opts(law=EXP, EA=1.0, B=10.0, rhoA=1.0, alpha=0.9, tol_abs=1e-10, tol_rel=0.0,
-              n_max=1_000_000, init=INIT_AFFINE, mass=MASS_LUMPED) -> Opts:
+              n_max=1_000_000, init=INIT_AFFINE, mass=MASS_LUMPED, floor_tol_rel=0.0, stall_checks=16) -> Opts:
     return Opts(int(law), int(init), int(mass), 0, float(EA), float(B), float(rhoA), float(alpha),
-                float(tol_abs), float(tol_rel), int(n_max))
+                float(tol_abs), float(tol_rel), int(n_max), float(floor_tol_rel), int(stall_checks), 0)
 
 
 _lib = None

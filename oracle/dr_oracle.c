@@ -31,6 +31,12 @@
  *   O8  Two-step central difference, stopped on the free-DOF residual
  *       R = |f_free|_2 (external force is zero) and on the damping-force
  *       norm c |M v|_2, both against max(tol_abs, tol_rel |f_bnd|_2).
+ *       Optional stagnation stop (floor_tol_rel > 0): after
+ *       stall_checks consecutive tests in which R did not fall below half
+ *       of a reference value (R of the start, replaced by R each time R
+ *       falls below half of it), with R and c |M v|_2 both within
+ *       floor_tol_rel |f_bnd|_2, the run stops as stagnated at the
+ *       precision floor; the stress is evaluated as for a converged run.
  *   O9  Homogenized Cauchy stress from the boundary reactions:
  *       sigma_ij = 1/(det F V0) sum_b f_b,i x_b,j.
  *
@@ -57,6 +63,7 @@
 #define OR_MAXITER 1
 #define OR_NONFINITE 2
 #define OR_BAD_F 3
+#define OR_STAGNATED 8
 
 typedef struct {
     int32_t law;
@@ -66,6 +73,9 @@ typedef struct {
     double EA, B, rhoA, alpha;
     double tol_abs, tol_rel;
     int64_t n_max;
+    double floor_tol_rel;   /* stagnation stop; 0 = off */
+    int32_t stall_checks;
+    int32_t pad2_;
 } or_opts;
 
 /* ---------------------------------------------------------------- fiber law */
@@ -255,9 +265,23 @@ int or_solve(int64_t n_nodes, int64_t n_fib, const double* X, const uint8_t* is_
     double tol = fmax(o->tol_abs, o->tol_rel * sqrt(B2));
     int64_t n = 0;
     int status = OR_CONVERGED;
+    /* stagnation stop (O8): reference residual and the tests since R last
+       fell below half of it */
+    double Rref = R;
+    int64_t stall = 0;
 
     while (!(R <= tol && D <= tol)) {
         if (!isfinite(R)) { status = OR_NONFINITE; break; }
+        if (n > 0 && o->floor_tol_rel > 0.0) {
+            double ftol = o->floor_tol_rel * sqrt(B2);
+            if (R < 0.5 * Rref) {
+                Rref = R;
+                stall = 0;
+            } else if (++stall >= o->stall_checks && R <= ftol && D <= ftol) {
+                status = OR_STAGNATED;
+                break;
+            }
+        }
         if (n >= o->n_max) { status = OR_MAXITER; break; }
         /* O6 time step from the current state */
         double gmax = 0.0;

@@ -3,8 +3,9 @@
 Each case plants one mistake in a private copy of the C oracle (a dropped
 term, a flipped sign, a transposed operand, a wrong factor), builds it, and
 runs the pin suite against it in a subprocess; the suite has to fail.  The
-mistakes in the relaxation alternatives (or_solve_variant) are checked
-against their own pins (tests/test_oracle_variants.py).
+mistakes in the relaxation alternatives (or_solve_variant) and in the
+stagnation stop are checked against their own pins
+(tests/test_oracle_variants.py, tests/test_oracle_floor.py).
 """
 import os
 import subprocess
@@ -59,6 +60,22 @@ def _run_mutant(old, new, pins, tmp_path):
     return subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                            os.path.join(ROOT, "tests", pins)], cwd=ROOT, env=env, capture_output=True, text=True,
                           timeout=600)
+
+
+# mistakes in the stagnation stop of or_solve
+FLOOR_MUTANTS = {
+    "stall_never_reset": ("                stall = 0;\n", "\n"),
+    "window_off_by_one": ("++stall >= o->stall_checks", "++stall > o->stall_checks"),
+    "floor_not_tested": ("R <= ftol && D <= ftol", "D <= ftol"),
+    "halving_against_start": ("if (R < 0.5 * Rref) {", "if (R < 0.5 * Rref && n < 0) {"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(FLOOR_MUTANTS))
+def test_floor_pins_reject_mutant(name, tmp_path):
+    old, new = FLOOR_MUTANTS[name]
+    r = _run_mutant(old, new, "test_oracle_floor.py", tmp_path)
+    assert r.returncode != 0, f"floor pins accepted mutant {name}:\n{r.stdout[-2000:]}"
 
 
 @pytest.mark.parametrize("name", sorted(VARIANT_MUTANTS))
