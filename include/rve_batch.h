@@ -56,6 +56,7 @@ extern "C" {
 #define RVE_ST_CG_MAXITER 5    /* tangent: CG stopped at its iteration cap */
 #define RVE_ST_CG_INDEFINITE 6 /* tangent: K_ff not positive (unstable state) */
 #define RVE_ST_ENERGY 7        /* energy-balance check failed (opts.energy_check) */
+#define RVE_ST_STAGNATED 8     /* stopped at the precision floor (opts.floor_tol_rel) */
 
 /* options */
 #define RVE_FP64 0             /* all arithmetic in double */
@@ -146,6 +147,19 @@ typedef struct {
  *     a convergence test every iteration (precision must be RVE_FP64);
  *     check_every and threads_per_rve do not apply there.  None of them
  *     with RVE_ENGINE_NAIVE.
+ *   floor_tol_rel, stall_checks: stagnation stop for a tol below what the
+ *     arithmetic can reach (float positions put a floor under R, about
+ *     1e-5 |f_bnd|_2 on Voronoi networks in RVE_MIXED).  With
+ *     floor_tol_rel > 0 (0 = off, the default) a convergence test that
+ *     does not converge also compares R with a reference value: R of the
+ *     start, replaced by R whenever R falls below half of it.  After
+ *     stall_checks (>= 1) consecutive tests without such a halving, with R
+ *     and c |M v|_2 both <= floor_tol_rel |f_bnd|_2, the RVE stops with
+ *     RVE_ST_STAGNATED; its stress is evaluated as for a converged RVE.
+ *     The tangent and VJP treat it as an RVE without a converged state.
+ *     Constant viscous damping on the resident and streamed engines only
+ *     (RVE_EINVAL with kinetic or adaptive damping, the energy check or
+ *     RVE_ENGINE_NAIVE).
  */
 typedef struct {
     int32_t precision;
@@ -167,6 +181,8 @@ typedef struct {
     int32_t damping;        /* RVE_DAMP_* */
     int32_t energy_check;   /* 0 or 1 */
     double energy_tol;      /* relative energy-balance tolerance (> 0) */
+    double floor_tol_rel;   /* stagnation stop (0: off) */
+    int32_t stall_checks;   /* tests without R halving before the stop (>= 1) */
 } rve_opts;
 
 /* Optional per-RVE diagnostics of a solve (each pointer may be NULL; same
@@ -365,8 +381,8 @@ int rve_batch_tangent_iters(rve_batch* b, int64_t* iters, int32_t ptr_kind);
  *     on export and ignored on import.
  *   status[n_rve]: RVE_ST_* of the last solve.
  * export writes them (RVE_ESTATE before any solve or import).  import
- * replaces the batch's state with them: statuses outside 0..3 become
- * RVE_ST_NONFINITE, a non-finite F or det F <= 0 gives RVE_ST_BAD_F; the
+ * replaces the batch's state with them: statuses other than 0..3 and
+ * RVE_ST_STAGNATED become RVE_ST_NONFINITE, a non-finite F or det F <= 0 gives RVE_ST_BAD_F; the
  * stress is re-evaluated from the imported state (the stress kernel of
  * rve_batch_solve, FP64) and written to sigma[n_rve][9] unless sigma is
  * NULL; the stored diagnostics become iterations 0 and NaN norms.  Afterwards the batch behaves as after a solve that ended in

@@ -23,6 +23,7 @@ INIT_AFFINE, INIT_WARM = 0, 2
 ENGINE_AUTO, ENGINE_STREAMED, ENGINE_NAIVE = 0, 1, 2
 PTR_HOST, PTR_DEVICE = 0, 1
 ST_CONVERGED, ST_MAXITER, ST_NONFINITE, ST_BAD_F, ST_NO_STATE, ST_CG_MAXITER, ST_CG_INDEFINITE, ST_ENERGY = range(8)
+ST_STAGNATED = 8
 DAMP_VISCOUS, DAMP_KINETIC, DAMP_ADAPTIVE = 0, 1, 2
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE = 0, -22, -12, -5, -3
 
@@ -46,7 +47,7 @@ class Opts(C.Structure):
                 ("n_max", C.c_int64), ("check_every", C.c_int32), ("engine", C.c_int32),
                 ("threads_per_rve", C.c_int32), ("cg_tol", C.c_double), ("cg_max_iter", C.c_int64),
                 ("stream", C.c_void_p), ("damping", C.c_int32), ("energy_check", C.c_int32),
-                ("energy_tol", C.c_double)]
+                ("energy_tol", C.c_double), ("floor_tol_rel", C.c_double), ("stall_checks", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -121,7 +122,7 @@ def _check(rc):
 def make_opts(precision=FP64, law=LAW_EXP, mass=MASS_LUMPED, init=INIT_AFFINE, EA=1.0, B=10.0, rhoA=1.0,
               alpha=0.9, c=2.0, tol_abs=1e-10, tol_rel=0.0, n_max=1_000_000, check_every=1,
               engine=ENGINE_AUTO, threads_per_rve=0, cg_tol=1e-6, cg_max_iter=0, damping=DAMP_VISCOUS,
-              energy_check=False, energy_tol=0.05) -> Opts:
+              energy_check=False, energy_tol=0.05, floor_tol_rel=0.0, stall_checks=16) -> Opts:
     o = Opts()
     lib().rve_default_opts(C.byref(o))
     o.precision, o.law, o.mass, o.init = int(precision), int(law), int(mass), int(init)
@@ -130,6 +131,7 @@ def make_opts(precision=FP64, law=LAW_EXP, mass=MASS_LUMPED, init=INIT_AFFINE, E
     o.engine, o.threads_per_rve = int(engine), int(threads_per_rve)
     o.cg_tol, o.cg_max_iter = float(cg_tol), int(cg_max_iter)
     o.damping, o.energy_check, o.energy_tol = int(damping), int(bool(energy_check)), float(energy_tol)
+    o.floor_tol_rel, o.stall_checks = float(floor_tol_rel), int(stall_checks)
     return o
 
 

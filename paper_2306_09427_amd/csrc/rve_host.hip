@@ -221,6 +221,14 @@ static int validate_opts(const rve_opts* o, int64_t R)
         if ((o->damping == RVE_DAMP_ADAPTIVE || o->energy_check) && o->precision != RVE_FP64)
             return fail(RVE_EINVAL, "adaptive damping and the energy check are FP64 only");
     }
+    if (!(o->floor_tol_rel >= 0) || !std::isfinite(o->floor_tol_rel))
+        return fail(RVE_EINVAL, "floor_tol_rel must be >= 0 and finite");
+    if (o->floor_tol_rel > 0) {
+        if (o->stall_checks < 1) return fail(RVE_EINVAL, "stall_checks must be >= 1");
+        if (o->engine == RVE_ENGINE_NAIVE || o->damping != RVE_DAMP_VISCOUS || o->energy_check)
+            return fail(RVE_EINVAL,
+                        "the stagnation stop needs constant viscous damping on the resident or streamed engine");
+    }
     return RVE_OK;
 }
 
@@ -556,6 +564,8 @@ void rve_default_opts(rve_opts* o)
     o->damping = RVE_DAMP_VISCOUS;
     o->energy_check = 0;
     o->energy_tol = 0.05;
+    o->floor_tol_rel = 0.0;
+    o->stall_checks = 16;
 }
 
 int rve_batch_create(const rve_net_desc* net, const rve_opts* opts, rve_batch** out)
@@ -840,6 +850,8 @@ int rve_batch_solve(rve_batch* b, const double* F, double* sigma, int32_t* statu
     a.ws_fib = b->ws_fib;
     a.ws_node = b->ws_node;
     a.kinetic = kinetic_mode(b->opts) ? 1 : 0;
+    a.floor_tol_rel = b->opts.floor_tol_rel;
+    a.stall_checks = b->opts.stall_checks;
 
     b->last_variant = false;
     if (variant_mode(b->opts)) {
@@ -961,6 +973,8 @@ static void fill_solve_args(rve_batch* b, SolveArgs& a)
     a.ws_fib = b->ws_fib;
     a.ws_node = b->ws_node;
     a.kinetic = kinetic_mode(b->opts) ? 1 : 0;
+    a.floor_tol_rel = b->opts.floor_tol_rel;
+    a.stall_checks = b->opts.stall_checks;
 }
 
 int rve_batch_autotune(rve_batch* b, const double* F, int32_t ptr_kind, int32_t n_iter)

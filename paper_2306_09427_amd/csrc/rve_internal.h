@@ -51,6 +51,8 @@ struct SolveArgs {
     void* ws_node;            // [NFREE + R] Real4 h, [NFREE] Real4 (v, 1/M), [NFREE] Real mass, [NFREE] Real4 accel
     int64_t lds_h_nodes;      // streamed engine: > 0 keeps h in LDS (this many entries per component)
     int32_t kinetic;          // 1: kinetic damping (c ignored; v = 0 at kinetic-energy peaks)
+    int32_t stall_checks;     // stagnation stop: tests without R halving
+    double floor_tol_rel;     // stagnation stop: floor relative to |f_bnd| (0: off)
 };
 
 struct TangentArgs {

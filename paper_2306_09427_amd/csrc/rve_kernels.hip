@@ -43,7 +43,27 @@ constexpr int kLawLinear = 0;
 constexpr int kMassScaled = 1;
 constexpr int kInitWarm = 2;
 
-constexpr int ST_CONVERGED = 0, ST_MAXITER = 1, ST_NONFINITE = 2, ST_BAD_F = 3;
+constexpr int ST_CONVERGED = 0, ST_MAXITER = 1, ST_NONFINITE = 2, ST_BAD_F = 3, ST_STAGNATED = 8;
+
+// Stagnation stop, evaluated at a convergence test that did not converge
+// (floor_tol_rel > 0): Rref is the residual of the start, replaced by R
+// whenever R falls below half of it, and stall counts the tests since (it
+// saturates at stall_checks).  The run stops once stall_checks tests have
+// passed without a halving while R and the damping-force norm D are both
+// within floor_tol_rel |f_bnd|.
+__device__ __forceinline__ bool stagnated(const SolveArgs& A, double R, double D, double B, double& Rref,
+                                          int& stall)
+{
+    if (!(A.floor_tol_rel > 0.0)) return false;
+    if (R < 0.5 * Rref) {
+        Rref = R;
+        stall = 0;
+        return false;
+    }
+    if (stall < A.stall_checks) ++stall;
+    const double ftol = A.floor_tol_rel * B;
+    return stall >= A.stall_checks && R <= ftol && D <= ftol;
+}
 
 // ------------------------------------------------------------------ helpers
 template <typename Real>
@@ -637,6 +657,8 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
     double tol = fmax(A.tol_abs, A.tol_rel * sqrt(B2));
     bool done = (sqrt(R2) <= tol);   // v = 0: damping norm is 0
     double Rlast = sqrt(R2), Dlast = 0.0, Blast = sqrt(B2);
+    double Rref = Rlast;   // stagnation stop: reference residual
+    int stall = 0;         // stagnation stop: tests since R last halved
     if (!isfinite(R2)) {
         status = ST_NONFINITE;
         done = true;
@@ -744,6 +766,10 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
                 break;
             }
             if (Rlast <= tol && Dlast <= tol) break;
+            if (stagnated(A, Rlast, Dlast, Blast, Rref, stall)) {
+                status = ST_STAGNATED;
+                break;
+            }
         }
         if (!(gmax > 0.0) || !isfinite(gmax)) {
             status = ST_NONFINITE;
@@ -1025,6 +1051,8 @@ __device__ __forceinline__ void streamed_solve(const SolveArgs& A, int r, RedSlo
     double tol = fmax(A.tol_abs, A.tol_rel * sqrt(B2));
     bool done = (sqrt(R2) <= tol);
     double Rlast = sqrt(R2), Dlast = 0.0, Blast = sqrt(B2);
+    double Rref = Rlast;   // stagnation stop: reference residual
+    int stall = 0;         // stagnation stop: tests since R last halved
     if (!isfinite(R2)) {
         status = ST_NONFINITE;
         done = true;
@@ -1112,6 +1140,10 @@ __device__ __forceinline__ void streamed_solve(const SolveArgs& A, int r, RedSlo
                 break;
             }
             if (Rlast <= tol && Dlast <= tol) break;
+            if (stagnated(A, Rlast, Dlast, Blast, Rref, stall)) {
+                status = ST_STAGNATED;
+                break;
+            }
         }
         if (!(gmax > 0.0) || !isfinite(gmax)) {
             status = ST_NONFINITE;
@@ -1169,7 +1201,8 @@ __global__ __launch_bounds__(T) void dr_streamed_kernel(SolveArgs A)
 // workgroup per RVE: each fiber with a boundary end is re-evaluated in FP64
 // and f_b (x) x_b is accumulated at that end (x_b = F Xm_b); per-thread sums,
 // pairwise wave sums and a compensated sum over waves, then / (det F V0).
-// RVEs whose status is NONFINITE or BAD_F get NaN.
+// RVEs whose status is NONFINITE or BAD_F get NaN (a stagnated RVE gets its
+// stress like a converged one).
 constexpr int kStressThreads = 256;
 
 __global__ __launch_bounds__(kStressThreads) void stress_kernel(SolveArgs A)

@@ -16,7 +16,7 @@ namespace rve {
 namespace {
 
 constexpr int kStateThreads = 256;
-constexpr int ST_NONFINITE = 2, ST_BAD_F = 3;
+constexpr int ST_NONFINITE = 2, ST_BAD_F = 3, ST_STAGNATED = 8;
 
 __global__ __launch_bounds__(kStateThreads) void export_h_kernel(const double* __restrict__ dh,
                                                                   const int32_t* __restrict__ map, int64_t nn,
@@ -39,8 +39,8 @@ __global__ __launch_bounds__(kStateThreads) void import_h_kernel(const double* _
     for (int c = 0; c < 3; ++c) dh[3 * (int64_t)q + c] = in[3 * n + c];
 }
 
-// Imported statuses: codes outside CONVERGED..BAD_F become NONFINITE (no
-// usable state); a non-finite F or det F <= 0 becomes BAD_F.  st_in may be
+// Imported statuses: codes other than CONVERGED..BAD_F and STAGNATED become
+// NONFINITE (no usable state); a non-finite F or det F <= 0 becomes BAD_F.  st_in may be
 // st itself (each thread reads its entry before writing it).  The stored
 // diagnostics of the imported state are unknown: iterations 0, norms NaN.
 __global__ __launch_bounds__(kStateThreads) void import_status_kernel(const double* __restrict__ F,
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(kStateThreads) void import_status_kernel(const doub
     const int64_t r = (int64_t)blockIdx.x * kStateThreads + threadIdx.x;
     if (r >= R) return;
     int s = st_in[r];
-    if (s < 0 || s > ST_BAD_F) s = ST_NONFINITE;
+    if (!((s >= 0 && s <= ST_BAD_F) || s == ST_STAGNATED)) s = ST_NONFINITE;
     const double* f = F + 9 * r;
     bool finite = true;
     for (int k = 0; k < 9; ++k) finite = finite && isfinite(f[k]);

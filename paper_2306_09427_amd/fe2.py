@@ -278,8 +278,11 @@ class FE2:
         u.reshape(-1)[dofs] = vals
         for it in range(self.max_newton + 1):
             F, sig, st = self._micro_stress(u, rec)
-            if (st >= 2).any():
-                rec.reason = f"{int((st >= 2).sum())} micro states non-finite or with a bad F"
+            # non-finite, bad F or a failed energy check: no usable stress
+            # (n_max and the stagnation stop leave one)
+            bad = np.isin(st, (2, 3, 7))
+            if bad.any():
+                rec.reason = f"{int(bad.sum())} micro states non-finite, with a bad F or an energy-check failure"
                 return rec
             P, _ = first_pk(F, sig)
             r = m.internal_force(P).reshape(-1)

@@ -1,9 +1,10 @@
 """C-ABI checks that need no GPU: the library loads, exports every function
-declared in include/rve_batch.h, and rejects malformed input on the host
-before any device call."""
+declared in include/rve_batch.h, mirrors its option struct, and rejects
+malformed input on the host before any device call."""
 import ctypes as C
 import os
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -39,6 +40,22 @@ def test_version_and_defaults():
     assert o.precision == rb.FP64 and o.alpha == 0.9 and o.n_max == 1_000_000 and o.check_every == 1
     assert o.cg_tol == 1e-6
     assert o.damping == rb.DAMP_VISCOUS and o.energy_check == 0 and o.energy_tol == 0.05
+    assert o.floor_tol_rel == 0.0 and o.stall_checks == 16
+
+
+def test_opts_layout_matches_the_header(tmp_path):
+    """The binding's rve_opts mirror has the C struct's size and offsets
+    (compiled against include/rve_batch.h with the host compiler)."""
+    names = [f[0] for f in rb.Opts._fields_]
+    prog = tmp_path / "layout.c"
+    prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "rve_batch.h"\nint main(void){\n'
+                    'printf("%zu\\n", sizeof(rve_opts));\n'
+                    + "".join(f'printf("%zu\\n", offsetof(rve_opts, {n}));\n' for n in names) + "return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.dirname(HEADER), str(prog), "-o", str(exe)])
+    out = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    assert out[0] == C.sizeof(rb.Opts)
+    assert out[1:] == [getattr(rb.Opts, n).offset for n in names]
 
 
 def _create(nets, **kw):
@@ -83,6 +100,11 @@ def test_zero_length_fiber_rejected():
     (dict(energy_check=True, precision=rb.MIXED), "FP64 only"),
     (dict(damping=rb.DAMP_KINETIC, engine=rb.ENGINE_NAIVE), "naive"),
     (dict(damping=rb.DAMP_ADAPTIVE, engine=rb.ENGINE_NAIVE), "naive"),
+    (dict(floor_tol_rel=-1.0), "floor_tol_rel"), (dict(floor_tol_rel=float("inf")), "floor_tol_rel"),
+    (dict(floor_tol_rel=1e-5, stall_checks=0), "stall_checks"),
+    (dict(floor_tol_rel=1e-5, engine=rb.ENGINE_NAIVE), "stagnation stop"),
+    (dict(floor_tol_rel=1e-5, damping=rb.DAMP_KINETIC), "stagnation stop"),
+    (dict(floor_tol_rel=1e-5, energy_check=True), "stagnation stop"),
 ])
 def test_bad_options_rejected_on_host(kw, needle):
     with pytest.raises(rb.RVEError) as e:
