@@ -25,8 +25,8 @@
  *  - A batch object is not thread-safe: one call at a time per object.
  *    Distinct objects may be used from distinct threads.
  *  - Per-RVE outcomes are written to status[r] (RVE_ST_*); the outputs of an
- *    RVE that did not converge hold the last state's values (MAXITER) or NaN
- *    (NONFINITE, BAD_F).
+ *    RVE that did not converge hold the last state's values (MAXITER,
+ *    STAGNATED, ENERGY) or NaN (NONFINITE, BAD_F).
  */
 #ifndef RVE_BATCH_H
 #define RVE_BATCH_H
