@@ -208,6 +208,7 @@ def main():
         "all_rves_per_s": batch.n_rve / (ms_per_step / 1e3),
         "status_counts": np.bincount(st, minlength=4).tolist(),
         "iters_median": float(np.median(iters)),
+        "iters_total": int(np.asarray(iters).sum()),
         "element_updates_per_s": elem_updates / (ms_per_step / 1e3),
         "relax_kernel_ms": relax_ms,
         "kernel_groups": groups,
