@@ -26,7 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM = 8.0e12          # B/s, MI355X HBM3E
-# FP32 vector peak without packed-FP32 instructions (this build disables them):
+# FP32 vector peak without packed-FP32 instructions (the library is compiled without them):
 # 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP (FMA) x 2.4 GHz = 78.6 TFLOP/s; the
 # published 157.3 TFLOP/s needs packed (two-wide) FP32 math.
 PEAK_FP32_VALU = 78.6e12
