@@ -89,6 +89,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tangent", action="store_true")
     ap.add_argument("--no-kinetic", action="store_true", help="skip the kinetic-damping line")
+    ap.add_argument("--no-floor", action="store_true", help="skip the stagnation-stop line")
     ap.add_argument("--tangent-steps", type=int, default=2)
     ap.add_argument("--autotune", action="store_true", help="autotune the mixed-precision kernel variants")
     ap.add_argument("--cache", default="/tmp/rve_bench_cfg2.npz",
@@ -297,6 +298,33 @@ def main():
             log(f"kinetic vs FP64 oracle (kinetic, tol 1e-8) on {int(both.sum())} RVEs: "
                 f"max {ek[both].max() if both.any() else float('nan'):.2e}")
 
+    # ---------------- stagnation stop: the same batch asked for tol_rel 1e-8,
+    # below what float positions can reach; RVEs whose residual has levelled
+    # off within 3e-5 |f_bnd| (no halving over 32 tests) stop with status 8
+    sf = stf = None
+    if not args.no_floor:
+        bf = rb.Batch(batch, precision=rb.MIXED, floor_tol_rel=3e-5, stall_checks=32, **dict(common, tol_rel=1e-8))
+        for _ in range(args.warmup):
+            bf.solve(Fd)
+        torch.cuda.synchronize()
+        tf = time.perf_counter()
+        for _ in range(args.steps):
+            sf, stf, statf = bf.solve(Fd, stats=True)
+        torch.cuda.synchronize()
+        f_ms = 1e3 * (time.perf_counter() - tf) / args.steps
+        sf, stf = sf.cpu().numpy(), stf.cpu().numpy()
+        itf = statf["iters"].cpu().numpy()
+        bf.close()
+        out["floor_stop"] = {
+            "workload": "same batch, tol_rel 1e-8 with the stagnation stop (floor_tol_rel 3e-5, 32 tests)",
+            "ms_per_step": f_ms,
+            "converged_or_stagnated_per_s": int(np.isin(stf, (0, 8)).sum()) / (f_ms / 1e3),
+            "status_counts": np.bincount(stf, minlength=9).tolist(),
+            "iters_median": float(np.median(itf)),
+        }
+        log(f"floor stop: {f_ms:.1f} ms/step, status {np.bincount(stf, minlength=9).tolist()}, "
+            f"iters median {np.median(itf):.0f}")
+
     # ---------------- FP64 batched (same batch, tol scaled to FP64)
     if not args.no_fp64:
         b64 = rb.Batch(batch, precision=rb.FP64, **common)
@@ -400,6 +428,16 @@ def main():
             "rves": int(both.sum()), "max": float(err[both].max()) if both.any() else None,
             "frac_le_1e-4": float(np.mean(err[both] <= 1e-4)) if both.any() else None}
         log(f"sigma vs FP64 oracle (tol 1e-8) on {both.sum()} RVEs: max {err[both].max():.2e}")
+        if stf is not None:
+            okf = (g["status"] == 0) & np.isin(stf[gi], (0, 8))
+            errf = np.abs(sf[gi] - g["sigma"]).reshape(len(gi), -1).max(1) / scale
+            out["floor_stop"]["sigma_relerr_vs_fp64_oracle_tol1e-8"] = {
+                "rves": int(okf.sum()), "stagnated": int((okf & (stf[gi] == 8)).sum()),
+                "max": float(errf[okf].max()) if okf.any() else None,
+                "frac_le_1e-4": float(np.mean(errf[okf] <= 1e-4)) if okf.any() else None}
+            log(f"floor stop vs FP64 oracle (tol 1e-8) on {int(okf.sum())} RVEs: "
+                f"max {errf[okf].max() if okf.any() else float('nan'):.2e}, "
+                f"within 1e-4 {np.mean(errf[okf] <= 1e-4) if okf.any() else float('nan'):.3f}")
 
     print(json.dumps(out), flush=True)
 
