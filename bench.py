@@ -325,7 +325,7 @@ def main():
         log(f"floor stop: {f_ms:.1f} ms/step, status {np.bincount(stf, minlength=9).tolist()}, "
             f"iters median {np.median(itf):.0f}")
 
-    # ---------------- FP64 batched (same batch, tol scaled to FP64)
+    # ---------------- FP64 batched (same batch, same tolerance: the speed baseline)
     if not args.no_fp64:
         b64 = rb.Batch(batch, precision=rb.FP64, **common)
         b64.autotune(Fd, 300)   # FP64 register pressure makes the best variant workload-dependent
