@@ -344,6 +344,9 @@ def main():
         out["fp64_batched_solves_per_s"] = int((st64 == 0).sum()) / t64
         out["mixed_vs_fp64_batched_speedup"] = value / max(out["fp64_batched_solves_per_s"], 1e-30)
         out["mixed_vs_fp64_sigma_relerr_frac_le_1e-4"] = float(np.mean(err[both] <= 1e-4)) if both.any() else None
+        # conservative count: converged in both precisions and within 1e-4 of
+        # the FP64 stress (floppy RVEs that settle differently do not count)
+        out["converged_within_1e-4_of_fp64_per_s"] = int((both & (err <= 1e-4)).sum()) / (ms_per_step / 1e3)
         log(f"fp64 batched: {t64:.2f}s; mixed-vs-fp64 sigma: {np.mean(err[both] <= 1e-4):.3f} of {both.sum()} <= 1e-4")
         b64.close()
 
