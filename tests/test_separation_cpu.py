@@ -47,3 +47,15 @@ def test_bench_refuses_multi_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_run_config_needs_a_gpu():
+    """The workload runner has no CPU path: without a GPU it exits with a
+    message instead of falling back."""
+    import pytest
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    r = subprocess.run([sys.executable, "-m", "paper_2306_09427_amd.run_config", "--config", "1"], cwd=ROOT,
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "needs a GPU" in r.stderr
