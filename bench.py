@@ -33,7 +33,7 @@ PEAK_FP32_VALU = 78.6e12
 PEAK_FP32_PACKED = 157.3e12
 
 
-VARIANTS = [(256, 4, 2), (512, 4, 2), (1024, 4, 2), (512, 8, 4), (1024, 6, 3), (256, 16, 8)]
+VARIANTS = [(256, 4, 2), (512, 4, 2), (768, 4, 2), (512, 6, 3), (1024, 4, 2), (1024, 6, 3)]
 
 
 def rb_variant_name(v):

@@ -2,9 +2,9 @@
  * rve_batch.h - C ABI of the MI355X batched fiber-network RVE solver.
  *
  * The library is the microscale side of an FE^2 computation (paper:
- * Section 3, "batched" microscale routines that take a set of deformation
+ * Section 4, "batched" microscale routines that take a set of deformation
  * states and return stresses and material stiffnesses for the whole set at
- * once; Section 4.2, one independent sub-problem per RVE).  Each RVE is a
+ * once; Section 4.3, one independent sub-problem per RVE).  Each RVE is a
  * truss network in the unit cube; its boundary nodes follow the affine map
  * x = F Xm (Section 2, affine boundary condition), its free nodes are
  * relaxed to static equilibrium by damped explicit dynamic relaxation
@@ -46,6 +46,9 @@ extern "C" {
 #define RVE_ENOMEM (-12)       /* host or device allocation failed */
 #define RVE_EDEVICE (-5)       /* HIP runtime error or no usable gfx950 device */
 #define RVE_ESTATE (-3)        /* call order: e.g. tangent before any solve */
+#define RVE_EWORKSPACE (-28)   /* workspace: a caller-bound workspace that is too
+                                  small, misaligned or not device memory, or a
+                                  request beyond a fixed workspace's limit */
 
 /* per-RVE status codes */
 #define RVE_ST_CONVERGED 0     /* R <= tol and damping-force norm <= tol */
@@ -67,6 +70,10 @@ extern "C" {
 #define RVE_MASS_LUMPED 0      /* M_a = rhoA/2 sum L0 over fibers at a */
 #define RVE_MASS_SCALED 1      /* M_a = G_a(x0)/4, Gershgorin sum at the start */
 #define RVE_INIT_AFFINE 0      /* free nodes start at F Xm */
+#define RVE_INIT_REFERENCE 1   /* free nodes start at their reference position Xm
+                                  (free displacements zero, as Algorithm "Dynamic
+                                  Relaxation" prints it for an increment from the
+                                  undeformed state); the boundary is at F Xm */
 #define RVE_INIT_WARM 2        /* free nodes start at F Xm + h, h = fluctuation
                                   left by the previous solve of this batch */
 #define RVE_ENGINE_AUTO 0      /* register-resident persistent kernel where an
@@ -92,7 +99,9 @@ typedef struct rve_batch rve_batch;
  *   is_bnd[node_off[n_rve]]: 1 for a boundary node (prescribed x = F Xm).
  *   fib[fib_off[n_rve]][2]: fiber end nodes as ids local to the RVE.
  *   V0[n_rve]: reference RVE volume (NULL: 1, the unit cube).
- * Rest lengths are the reference lengths |X_j - X_i|.
+ *   L0[fib_off[n_rve]]: rest length of every fiber (NULL: the reference
+ *     chord |X_j - X_i|, a network stress-free at F = I; given values make
+ *     a pre-stressed network).  Must be positive and finite.
  * Rejected with RVE_EINVAL: ids out of range, a fiber joining a node to
  * itself, a zero-length fiber, an RVE without a boundary node, an RVE with
  * 65535 nodes or more, non-finite coordinates.
@@ -105,6 +114,7 @@ typedef struct {
     const uint8_t* is_bnd;
     const int32_t* fib;
     const double* V0;
+    const double* L0;
 } rve_net_desc;
 
 /*
@@ -118,11 +128,11 @@ typedef struct {
  *     tol = max(tol_abs, tol_rel |f_bnd|_2), tested every check_every
  *     iterations (>= 1); n_max caps the iterations.
  *   engine: RVE_ENGINE_*.  threads_per_rve: 0 = automatic (default or
- *     autotuned variant per size tier), else 256/512/1024: only resident
- *     variants of that workgroup size (256 and 512 threads: the variants
- *     with four fiber and two node slots per thread); RVEs none of them
- *     holds without spilling registers run on the streamed kernel (256
- *     threads when 256 is asked for, else 1024).
+ *     autotuned variant per size tier), else 256/512/768/1024: only
+ *     resident builds of that workgroup size; RVEs none of them holds run
+ *     on the streamed kernel (256 threads when 256 is asked for, else 1024
+ *     where that build uses no private memory).  A kernel build that uses
+ *     private (scratch) memory is never launched.
  *   cg_tol, cg_max_iter: conjugate-gradient controls of rve_batch_tangent and
  *     rve_batch_vjp.
  *   stream: hipStream_t for every launch and copy (NULL: the null stream).
@@ -400,6 +410,30 @@ int rve_batch_import_state(rve_batch* b, const double* F, const double* h, const
 /* Positions x[n_nodes_r][3] of RVE r after the last solve, in the caller's
  * original node order (host pointer; synchronous). */
 int rve_batch_positions(rve_batch* b, int64_t r, double* x);
+
+/*
+ * Generation of the batch's state: a counter that every successful
+ * rve_batch_solve, rve_batch_import_state and rve_batch_set_opts increments.
+ * A caller that computes a VJP or tangent for a state it solved earlier (an
+ * autograd backward pass) records the generation after its solve and
+ * compares it before the VJP: a different value means the state or the
+ * options changed in between.
+ */
+int rve_batch_generation(const rve_batch* b, uint64_t* gen);
+
+/*
+ * Host replay of the kernels' index arithmetic (no device needed): packs the
+ * networks as rve_batch_create does and, for every RVE and every
+ * register-resident kernel build whose slots hold it, bounds every index the
+ * build forms (packed fiber ends against the LDS position array, incidence
+ * codes and overflow reads against the LDS force array, the code's end sign,
+ * LDS bytes against 160 KB), the streamed engine's workspace offsets, and the
+ * packing's incidence lists.  precision: RVE_FP64 or RVE_MIXED (LDS layout).
+ * plant: 0; 1 makes the replay assume one LDS position entry fewer (a
+ * deliberate mistake that the replay must report; tests only).
+ * RVE_OK, or RVE_EINVAL with the first violation in rve_last_error().
+ */
+int rve_check_indexing(const rve_net_desc* net, int32_t precision, int32_t plant);
 
 /* Free every host and device resource of the batch (NULL is a no-op). */
 void rve_batch_destroy(rve_batch* b);

@@ -4,9 +4,11 @@ forward  = rve_batch_solve (relaxation + boundary-reaction stress)
 backward = rve_batch_vjp   (one adjoint conjugate-gradient solve per RVE on
                             the converged network)
 
-The backward pass uses the state of the most recent solve of the batch, so a
-second solve between forward and backward invalidates the gradient; the
-function records the solve count and refuses such a backward.
+The backward pass uses the state the batch holds when it runs.  The library
+counts every change of that state (solve, state import, option change) in
+rve_batch_generation; forward records the count after its solve and backward
+refuses to run when it has changed, so a VJP is never taken at another
+state than the one forward returned.
 """
 from __future__ import annotations
 
@@ -17,17 +19,17 @@ class RVEStress(torch.autograd.Function):
     @staticmethod
     def forward(ctx, F, batch):
         sig, st = batch.solve(F)
-        batch._solve_count = getattr(batch, "_solve_count", 0) + 1
         ctx.batch = batch
-        ctx.count = batch._solve_count
+        ctx.generation = batch.generation()
         ctx.mark_non_differentiable(st)
         return sig, st
 
     @staticmethod
     def backward(ctx, g_sigma, g_status):
         b = ctx.batch
-        if getattr(b, "_solve_count", 0) != ctx.count:
-            raise RuntimeError("the batch was solved again after this forward pass; its adjoint state is gone")
+        if b.generation() != ctx.generation:
+            raise RuntimeError("the batch's state changed after this forward pass (solve, import or option "
+                               "change); its adjoint state is gone")
         gF, st = b.vjp(g_sigma.contiguous())
         return gF, None
 

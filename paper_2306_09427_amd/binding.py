@@ -19,25 +19,26 @@ LIB_PATH = os.path.join(HERE, "librvebatch.so")
 FP64, MIXED = 0, 1
 LAW_LINEAR, LAW_EXP = 0, 1
 MASS_LUMPED, MASS_SCALED = 0, 1
-INIT_AFFINE, INIT_WARM = 0, 2
+INIT_AFFINE, INIT_REFERENCE, INIT_WARM = 0, 1, 2
 ENGINE_AUTO, ENGINE_STREAMED, ENGINE_NAIVE = 0, 1, 2
 PTR_HOST, PTR_DEVICE = 0, 1
 ST_CONVERGED, ST_MAXITER, ST_NONFINITE, ST_BAD_F, ST_NO_STATE, ST_CG_MAXITER, ST_CG_INDEFINITE, ST_ENERGY = range(8)
 ST_STAGNATED = 8
 DAMP_VISCOUS, DAMP_KINETIC, DAMP_ADAPTIVE = 0, 1, 2
-OK, EINVAL, ENOMEM, EDEVICE, ESTATE = 0, -22, -12, -5, -3
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EWORKSPACE = 0, -22, -12, -5, -3, -28
 
 EXPORTS = ["rve_version", "rve_last_error", "rve_default_opts", "rve_batch_create", "rve_batch_set_opts",
            "rve_batch_set_stream", "rve_batch_sizes", "rve_batch_solve", "rve_batch_tangent", "rve_batch_vjp",
            "rve_batch_positions", "rve_batch_destroy", "rve_batch_profile", "rve_batch_kernel_ms",
            "rve_batch_autotune", "rve_batch_describe", "rve_batch_groups", "rve_batch_tangent_iters", "rve_batch_orientation",
            "rve_batch_fd_tangent", "rve_batch_export_state", "rve_batch_import_state",
-           "rve_batch_workspace_size", "rve_batch_bind_workspace", "rve_batch_damping_stats"]
+           "rve_batch_workspace_size", "rve_batch_bind_workspace", "rve_batch_damping_stats",
+           "rve_batch_generation", "rve_check_indexing"]
 
 
 class NetDesc(C.Structure):
     _fields_ = [("n_rve", C.c_int64), ("node_off", C.c_void_p), ("fib_off", C.c_void_p), ("X", C.c_void_p),
-                ("is_bnd", C.c_void_p), ("fib", C.c_void_p), ("V0", C.c_void_p)]
+                ("is_bnd", C.c_void_p), ("fib", C.c_void_p), ("V0", C.c_void_p), ("L0", C.c_void_p)]
 
 
 class Opts(C.Structure):
@@ -104,6 +105,8 @@ def lib():
         L.rve_batch_workspace_size.argtypes = [P, C.POINTER(C.c_size_t)]
         L.rve_batch_bind_workspace.argtypes = [P, P, C.c_size_t]
         L.rve_batch_damping_stats.argtypes = [P, P, P, C.c_int32]
+        L.rve_batch_generation.argtypes = [P, C.POINTER(C.c_uint64)]
+        L.rve_check_indexing.argtypes = [C.POINTER(NetDesc), C.c_int32, C.c_int32]
         L.rve_batch_destroy.argtypes = [P]
         L.rve_batch_destroy.restype = None
         _lib = L
@@ -144,20 +147,38 @@ def _ptr(a):
     return a.ctypes.data, PTR_HOST
 
 
+def net_desc(nets, V0=None, L0=None):
+    """NetDesc of a packed batch (node_off, fib_off, X, is_bnd, fib) and the
+    arrays it points into (keep them alive while the descriptor is used).
+    V0: per-RVE reference volume (None: 1); L0: per-fiber rest length (None:
+    the reference chord length)."""
+    node_off = np.ascontiguousarray(nets.node_off, np.int64)
+    fib_off = np.ascontiguousarray(nets.fib_off, np.int64)
+    X = np.ascontiguousarray(nets.X, np.float64)
+    ib = np.ascontiguousarray(nets.is_bnd, np.uint8)
+    fib = np.ascontiguousarray(nets.fib, np.int32)
+    n_rve = int(len(node_off) - 1)
+    V0a = None if V0 is None else np.ascontiguousarray(np.broadcast_to(V0, (n_rve,)), np.float64)
+    L0a = None if L0 is None else np.ascontiguousarray(L0, np.float64).reshape(int(fib_off[-1]))
+    d = NetDesc(n_rve, node_off.ctypes.data, fib_off.ctypes.data, X.ctypes.data, ib.ctypes.data,
+                fib.ctypes.data, None if V0a is None else V0a.ctypes.data, None if L0a is None else L0a.ctypes.data)
+    return d, (node_off, fib_off, X, ib, fib, V0a, L0a)
+
+
+def check_indexing(nets, precision=MIXED, plant=0, L0=None):
+    """Host replay of the kernels' index arithmetic over a batch (rve_check_indexing); raises on a violation."""
+    d, keep = net_desc(nets, None, L0)
+    _check(lib().rve_check_indexing(C.byref(d), int(precision), int(plant)))
+
+
 class Batch:
     """A packed batch of RVE networks resident on the current HIP device."""
 
-    def __init__(self, nets, opts: Opts | None = None, c_per_rve=None, V0=None, **kw):
+    def __init__(self, nets, opts: Opts | None = None, c_per_rve=None, V0=None, L0=None, **kw):
         self._keep = {}
-        node_off = np.ascontiguousarray(nets.node_off, np.int64)
-        fib_off = np.ascontiguousarray(nets.fib_off, np.int64)
-        X = np.ascontiguousarray(nets.X, np.float64)
-        ib = np.ascontiguousarray(nets.is_bnd, np.uint8)
-        fib = np.ascontiguousarray(nets.fib, np.int32)
-        self.n_rve = int(len(node_off) - 1)
-        V0a = None if V0 is None else np.ascontiguousarray(np.broadcast_to(V0, (self.n_rve,)), np.float64)
-        d = NetDesc(self.n_rve, node_off.ctypes.data, fib_off.ctypes.data, X.ctypes.data, ib.ctypes.data,
-                    fib.ctypes.data, None if V0a is None else V0a.ctypes.data)
+        d, keep = net_desc(nets, V0, L0)
+        self.n_rve = int(d.n_rve)
+        node_off = keep[0]
         self.opts = opts if opts is not None else make_opts(**kw)
         cpr = None
         if c_per_rve is not None:
@@ -189,6 +210,12 @@ class Batch:
         _check(lib().rve_batch_set_opts(self._h, C.byref(o)))
         o.c_per_rve = None
         self.opts = o
+
+    def generation(self):
+        """Counter of the state's changes (solve, import, option change)."""
+        g = C.c_uint64()
+        _check(lib().rve_batch_generation(self._h, C.byref(g)))
+        return g.value
 
     def set_stream(self, stream_handle):
         _check(lib().rve_batch_set_stream(self._h, stream_handle))

@@ -284,4 +284,9 @@ hipError_t launch_probe_state(const ProbeStateArgs& a, int64_t n_probe, hipStrea
     return hipGetLastError();
 }
 
+hipError_t fd_fixed_private(size_t* bytes)
+{
+    return max_private_bytes({(const void*)probe_state_kernel}, bytes);
+}
+
 }  // namespace rve

@@ -1,5 +1,5 @@
 // Host runtime and C ABI of the batched RVE solver (the "RVE batch manager"
-// of Section 4.2: data marshalling on the CPU, solver selection, launches).
+// of Section 4.3: data marshalling on the CPU, solver selection, launches).
 //
 // rve_batch_create validates the networks on the host before touching the
 // device, so malformed input is rejected (RVE_EINVAL) even where no GPU is
@@ -8,7 +8,7 @@
 // fiber vectors, rest lengths and lumped masses in FP64; CSR node->fiber
 // incidence with the end sign.  All RVEs of a batch share one device
 // allocation in row-offset + value layout (the packed-view layout of
-// Section 4.2).
+// Section 4.3).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -83,7 +83,10 @@ struct rve_batch {
     std::vector<int32_t> group_first;          // offset of each group's ids in dlist
     std::vector<size_t> group_lds;
     bool have_state = false;
-    bool variant_spills[2][2][kNumResident] = {};   // [kinetic][fp64][variant]: the build uses private memory
+    // [kinetic][fp64][variant]: the build uses private (scratch) memory and is never launched
+    bool variant_spills[2][2][kNumResident] = {};
+    bool streamed_private[2][2][2] = {};            // [kinetic][fp64][1024 threads]: same for the streamed builds
+    bool tangent_private[2][kNumTanRes] = {};        // [vjp][variant]: same for the resident tangent builds
     // tangent / vjp workspace
     char* t_mem = nullptr;             // operators, records, preconditioner, chunk tables, I/O
     bool t_static_built = false;       // records' (fiber, other end) filled
@@ -126,6 +129,8 @@ struct rve_batch {
     // c_final [R] and the energy balance [R]; whether the last solve used them
     double* v_ws = nullptr;
     bool last_variant = false;
+    uint64_t generation = 0;           // bumped by solve, import_state, set_opts
+    double* d_xm_free = nullptr;       // [NFREE][3] reference coordinates of free nodes (RVE_INIT_REFERENCE)
 };
 
 // Adaptive damping and the energy check run on the FP64 variant engine;
@@ -160,7 +165,7 @@ static std::vector<std::pair<int64_t, int64_t>> tier_caps()
 static int tier_of(const rve_batch* b, int64_t r, bool fp64)
 {
     size_t lds_cap = 160 * 1024 - 4096;
-    if (b->nfib_of[r] >= 32767 || resident_lds_bytes(fp64, b->nf_of[r], b->nfib_of[r], 0) > lds_cap) return -1;
+    if (b->nfib_of[r] >= kResMaxFibers || resident_lds_bytes(fp64, b->nf_of[r], b->nfib_of[r], 0) > lds_cap) return -1;
     auto caps = tier_caps();
     for (size_t t = 0; t < caps.size(); ++t)
         if (b->nfib_of[r] <= caps[t].first && b->nf_of[r] <= caps[t].second) return (int)t;
@@ -191,7 +196,8 @@ static int validate_opts(const rve_opts* o, int64_t R)
     if (o->precision != RVE_FP64 && o->precision != RVE_MIXED) return fail(RVE_EINVAL, "bad precision");
     if (o->law != RVE_LAW_LINEAR && o->law != RVE_LAW_EXP) return fail(RVE_EINVAL, "bad law");
     if (o->mass != RVE_MASS_LUMPED && o->mass != RVE_MASS_SCALED) return fail(RVE_EINVAL, "bad mass mode");
-    if (o->init != RVE_INIT_AFFINE && o->init != RVE_INIT_WARM) return fail(RVE_EINVAL, "bad init");
+    if (o->init != RVE_INIT_AFFINE && o->init != RVE_INIT_REFERENCE && o->init != RVE_INIT_WARM)
+        return fail(RVE_EINVAL, "bad init");
     if (!(o->EA > 0) || !std::isfinite(o->EA)) return fail(RVE_EINVAL, "EA must be positive");
     if (o->law == RVE_LAW_EXP && (!(o->B > 0) || !std::isfinite(o->B))) return fail(RVE_EINVAL, "B must be positive");
     if (!(o->rhoA > 0) || !std::isfinite(o->rhoA)) return fail(RVE_EINVAL, "rhoA must be positive");
@@ -210,8 +216,8 @@ static int validate_opts(const rve_opts* o, int64_t R)
         return fail(RVE_EINVAL, "the naive engine is FP64 only");
     if (!(o->cg_tol > 0) || o->cg_max_iter < 0) return fail(RVE_EINVAL, "cg_tol must be > 0, cg_max_iter >= 0");
     if (o->threads_per_rve != 0 && o->threads_per_rve != 256 && o->threads_per_rve != 512 &&
-        o->threads_per_rve != 1024)
-        return fail(RVE_EINVAL, "threads_per_rve must be 0, 256, 512 or 1024");
+        o->threads_per_rve != 768 && o->threads_per_rve != 1024)
+        return fail(RVE_EINVAL, "threads_per_rve must be 0, 256, 512, 768 or 1024");
     if (o->damping != RVE_DAMP_VISCOUS && o->damping != RVE_DAMP_KINETIC && o->damping != RVE_DAMP_ADAPTIVE)
         return fail(RVE_EINVAL, "bad damping mode");
     if (!(o->energy_tol > 0) || !std::isfinite(o->energy_tol)) return fail(RVE_EINVAL, "energy_tol must be > 0");
@@ -266,6 +272,10 @@ static int validate_net(const rve_net_desc* d)
             if (!(L > 0)) return fail(RVE_EINVAL, rs + "fiber " + std::to_string(k - f0) + " has zero length");
         }
         if (d->V0 && !(d->V0[r] > 0)) return fail(RVE_EINVAL, rs + "V0 must be positive");
+        if (d->L0)
+            for (int64_t k = f0; k < f1; ++k)
+                if (!(d->L0[k] > 0) || !std::isfinite(d->L0[k]))
+                    return fail(RVE_EINVAL, rs + "fiber " + std::to_string(k - f0) + ": L0 must be positive and finite");
     }
     return RVE_OK;
 }
@@ -368,7 +378,7 @@ static void pack_batch(const rve_net_desc* d, HostPack& P)
             P.d0[3 * g] = dx;
             P.d0[3 * g + 1] = dy;
             P.d0[3 * g + 2] = dz;
-            P.L0[g] = std::sqrt(dx * dx + dy * dy + dz * dz);
+            P.L0[g] = d->L0 ? d->L0[f0 + k] : std::sqrt(dx * dx + dy * dy + dz * dz);
             P.ends[g] = (uint32_t)nid[i] | ((uint32_t)nid[j] << 16);
             inc_of[nid[i]].push_back((uint32_t)q | (1u << 31));
             inc_of[nid[j]].push_back((uint32_t)q);
@@ -399,6 +409,103 @@ static void pack_batch(const rve_net_desc* d, HostPack& P)
     }
 }
 
+
+// ------------------------------------------------------------------ index replay
+// Host replay of the index arithmetic of the relaxation kernels over a
+// packed batch, with every index bounded against the array it addresses.
+// Register-resident engine, for every RVE and every resident build whose
+// slots hold it: each fiber slot's packed ends (res_pack_ends) against the
+// nf + 1 LDS positions, each node slot's register-held incidence codes
+// (res_inc_code) and CSR overflow reads against the nfib + 1 LDS forces, the
+// code's sign against the incidence, the LDS bytes (dynamic + static)
+// against a CU's 160 KB.  Streamed engine: the workspace offsets of every
+// fiber, node and zero slot against the workspace sizes.  The packing itself:
+// every fiber appears in the incidence of each of its ends with the sign of
+// that end.  `plant` (tests only) shrinks the LDS position array by one
+// entry, a mistake the replay must report.
+static int check_indexing(const rve_net_desc* net, bool fp64, int plant)
+{
+    HostPack P;
+    try {
+        pack_batch(net, P);
+    } catch (const std::bad_alloc&) {
+        return fail(RVE_ENOMEM, "host allocation failed while packing");
+    }
+    const int64_t R = net->n_rve;
+    const int64_t NF = P.fib_off[R], NFREE = P.free_off[R];
+    auto bad = [&](int64_t r, const std::string& what) {
+        return fail(RVE_EINVAL, "index replay, RVE " + std::to_string(r) + ": " + what);
+    };
+    for (int64_t r = 0; r < R; ++r) {
+        const int64_t f0 = P.fib_off[r], a0 = P.free_off[r], b0 = P.bnd_off[r];
+        const int64_t nfib = P.fib_off[r + 1] - f0, nf = P.free_off[r + 1] - a0, nb = P.bnd_off[r + 1] - b0;
+        const int64_t nn = nf + nb;
+        // packing: incidence of every fiber end, with its sign
+        std::vector<int> seen(2 * nfib, 0);
+        for (int64_t a = 0; a < nn; ++a) {
+            const bool fr = a < nf;
+            const int64_t e0 = fr ? P.inc_off[a0 + a] : P.binc_off[b0 + a - nf];
+            const int64_t e1 = fr ? P.inc_off[a0 + a + 1] : P.binc_off[b0 + a - nf + 1];
+            for (int64_t e = e0; e < e1; ++e) {
+                const uint32_t w = fr ? P.inc[e] : P.binc[e];
+                const int64_t k = w & 0x7fffffffu;
+                if (k >= nfib) return bad(r, "incidence names fiber " + std::to_string(k) + " of " + std::to_string(nfib));
+                const uint32_t ends = P.ends[f0 + k];
+                const int64_t end = (w >> 31) ? (ends & 0xffffu) : (ends >> 16);
+                if (end != a) return bad(r, "incidence of node " + std::to_string(a) + " names a fiber it is not an end of");
+                seen[2 * k + ((w >> 31) ? 0 : 1)] += 1;
+            }
+        }
+        for (int64_t q = 0; q < 2 * nfib; ++q)
+            if (seen[q] != 1) return bad(r, "fiber " + std::to_string(q / 2) + " end " + std::to_string(q % 2) + " listed " +
+                                                std::to_string(seen[q]) + " times");
+        // register-resident builds that hold this RVE
+        const int64_t h_entries = nf + 1 - (plant == 1 ? 1 : 0);
+        const int64_t fv_entries = nfib + 1;
+        for (int v = 0; v < kNumResident; ++v) {
+            const ResidentVariant& rv = kResident[v];
+            if (nfib > (int64_t)rv.threads * rv.sf || nf > (int64_t)rv.threads * rv.sn) continue;
+            if (nfib >= kResMaxFibers) continue;   // such RVEs only run streamed (tier_of)
+            const size_t dyn = resident_lds_bytes(fp64, nf, nfib, rv.threads);
+            if (dyn > 160 * 1024 - 4096) continue;   // tier_of sends these to the streamed engine
+            if (dyn + kResStaticLds > 160 * 1024) return bad(r, "LDS of a resident workgroup exceeds 160 KB");
+            for (int tid = 0; tid < rv.threads; ++tid) {
+                for (int sl = 0; sl < rv.sf; ++sl) {
+                    const int64_t k = (int64_t)sl * rv.threads + tid;
+                    if (k >= nfib) continue;
+                    const uint32_t E = res_pack_ends(P.ends[f0 + k], (uint32_t)nf);
+                    if ((int64_t)res_end_i(E) >= h_entries || (int64_t)res_end_j(E) >= h_entries)
+                        return bad(r, "build " + std::to_string(v) + ": fiber " + std::to_string(k) +
+                                          " reads a position outside the LDS array");
+                }
+                for (int sl = 0; sl < rv.sn; ++sl) {
+                    const int64_t a = (int64_t)sl * rv.threads + tid;
+                    if (a >= nf) continue;   // lanes past nf only read the zero slot (padding codes)
+                    const int64_t e0 = P.inc_off[a0 + a], deg = P.inc_off[a0 + a + 1] - e0;
+                    for (int q = 0; q < kResIncRegs; ++q) {
+                        const uint32_t code = q < deg ? res_inc_code(P.inc[e0 + q]) : (uint32_t)nfib;
+                        if ((int64_t)res_code_fiber(code) >= fv_entries)
+                            return bad(r, "build " + std::to_string(v) + ": node " + std::to_string(a) +
+                                              " reads a force outside the LDS array");
+                        if (q < deg && res_code_neg(code) != ((P.inc[e0 + q] >> 31) != 0))
+                            return bad(r, "incidence code loses the end sign");
+                        if (q < deg && (int64_t)res_code_fiber(code) != (int64_t)(P.inc[e0 + q] & 0x7fffffffu))
+                            return bad(r, "incidence code loses fiber id bits");
+                    }
+                    for (int64_t e = e0 + kResIncRegs; e < e0 + deg; ++e)
+                        if ((int64_t)(P.inc[e] & 0x7fffffffu) >= fv_entries)
+                            return bad(r, "overflow incidence reads a force outside the LDS array");
+                }
+            }
+            if (nfib > 0x7fff) return bad(r, "the zero force slot does not fit the 15-bit code");
+        }
+        // streamed engine: workspace entries [NF + R] per fiber array, [NFREE + R] positions
+        if (f0 + r + nfib >= NF + R) return bad(r, "streamed fiber zero slot outside the workspace");
+        if (a0 + r + nf >= NFREE + R) return bad(r, "streamed position zero slot outside the workspace");
+    }
+    return RVE_OK;
+}
+
 template <typename T>
 static T* carve(char* base, size_t off)
 {
@@ -407,8 +514,8 @@ static T* carve(char* base, size_t off)
 
 // Assign every RVE to an engine/variant group, longest-first inside a group.
 // Resident variants are chosen per size tier: the autotuner's choice if one
-// exists, else the variant with the smallest register footprint that holds
-// the tier and does not spill inside the loop (more threads on ties).
+// exists, else, among the builds without private memory that hold the tier,
+// the one of smallest capacity (more threads on ties).
 static int default_variant(const rve_batch* b, int tier, bool fp64)
 {
     const int T = b->opts.threads_per_rve;
@@ -417,10 +524,9 @@ static int default_variant(const rve_batch* b, int tier, bool fp64)
     for (int v = 0; v < kNumResident; ++v) {
         const ResidentVariant& rv = kResident[v];
         if (T && rv.threads != T) continue;
-        // variants that spill are never launched (see the autotuner)
-        if (spills(b, v, fp64)) continue;
+        if (spills(b, v, fp64)) continue;   // never launched
         if (!variant_fits_tier(v, tier)) continue;
-        int64_t key = (int64_t)(rv.sf * 5 + rv.sn * 12) * 4096 - rv.threads;
+        const int64_t key = (int64_t)rv.threads * rv.sf * 4096 - rv.threads;
         if (chosen < 0 || key < best) {
             chosen = v;
             best = key;
@@ -495,12 +601,14 @@ static int streamed_blocks_per_cu(int threads, int64_t lds_nodes, bool fp64)
     return (int)std::max<size_t>(1, std::min<size_t>(base, (160 * 1024) / lds));
 }
 
-// Workgroup size of the streamed engine: 256 when asked for, and for the
-// FP64 kinetic build (its 1024-thread form keeps values in private memory),
-// else 1024.
+// Workgroup size of the streamed engine: 1024 threads unless 256 are asked
+// for or the 1024-thread build of this precision and damping uses private
+// memory (the FP64 builds do); 0 when neither build may be launched.
 static int streamed_threads(const rve_batch* b, bool fp64)
 {
-    return (b->opts.threads_per_rve == 256 || (fp64 && kinetic_mode(b->opts))) ? 256 : 1024;
+    const int k = kinetic_mode(b->opts) ? 1 : 0, p = fp64 ? 1 : 0;
+    if (b->opts.threads_per_rve != 256 && !b->streamed_private[k][p][1]) return 1024;
+    return b->streamed_private[k][p][0] ? 0 : 256;
 }
 
 static int ensure_workspace(rve_batch* b)
@@ -512,7 +620,7 @@ static int ensure_workspace(rve_batch* b)
     size_t fb = r4 * 3 * (size_t)(b->NF + b->R);
     size_t nb = r4 * (2 * (size_t)(b->NFREE + b->R) + 2 * (size_t)b->NFREE + 1);
     if ((fb > b->ws_fib_bytes || nb > b->ws_node_bytes) && b->ws_user)
-        return fail(RVE_EINVAL, "internal: bound workspace smaller than the streamed workspace");
+        return fail(RVE_EWORKSPACE, "internal: bound workspace smaller than the streamed workspace");
     if (fb > b->ws_fib_bytes) {
         if (b->ws_fib) (void)hipFree(b->ws_fib);
         b->ws_fib = nullptr;
@@ -533,6 +641,22 @@ static int ensure_workspace(rve_batch* b)
 int rve_naive_run(const SolveArgs& A, const std::vector<int64_t>& fib_off, const std::vector<int64_t>& free_off,
                   const std::vector<int64_t>& bnd_off, const std::vector<double>& F, const std::vector<double>& c,
                   hipStream_t s, std::string* err);
+
+namespace rve {
+hipError_t fixed_kernels_scratch_bytes(size_t* bytes)
+{
+    size_t m = 0;
+    for (auto fn : {kernels_fixed_private, naive_fixed_private, orient_fixed_private, state_fixed_private,
+                    tangent_fixed_private, variant_fixed_private, fd_fixed_private}) {
+        size_t b = 0;
+        const hipError_t e = fn(&b);
+        if (e != hipSuccess) return e;
+        m = std::max(m, b);
+    }
+    *bytes = m;
+    return hipSuccess;
+}
+}  // namespace rve
 
 // ------------------------------------------------------------------ ABI
 extern "C" {
@@ -568,6 +692,14 @@ void rve_default_opts(rve_opts* o)
     o->stall_checks = 16;
 }
 
+int rve_check_indexing(const rve_net_desc* net, int32_t precision, int32_t plant)
+{
+    int rc = validate_net(net);
+    if (rc) return rc;
+    if (precision != RVE_FP64 && precision != RVE_MIXED) return fail(RVE_EINVAL, "bad precision");
+    return check_indexing(net, precision == RVE_FP64, plant);
+}
+
 int rve_batch_create(const rve_net_desc* net, const rve_opts* opts, rve_batch** out)
 {
     if (!out) return fail(RVE_EINVAL, "out is NULL");
@@ -590,21 +722,38 @@ int rve_batch_create(const rve_net_desc* net, const rve_opts* opts, rve_batch** 
     if (!b) return fail(RVE_ENOMEM, "host allocation failed");
     b->device = dev;
     b->n_cu = prop.multiProcessorCount;
+    // Admission: a kernel build that uses private (scratch) memory is never
+    // launched.  Every GPU fault and wrong result seen while developing these
+    // kernels came from builds at or over their register budget, so the rule
+    // is strict: any private segment at all (spilled registers, stack arrays)
+    // excludes the build; the RVEs it would take go to the next build that
+    // holds them, else to the streamed kernel.
     for (int k = 0; k < 2; ++k)
-        for (int p = 0; p < 2; ++p)
+        for (int p = 0; p < 2; ++p) {
             for (int v = 0; v < kNumResident; ++v) {
-                size_t sb = 0;
-                // a few spilled scalars outside the relaxation loop are harmless;
-                // more than that means the loop itself spills
-                if (resident_scratch_bytes(v, p == 1, k == 1, &sb) == hipSuccess) b->variant_spills[k][p][v] = sb > 64;
-                // Switched off: the (512, 8, 4) and (256, 16, 8) builds (near
-                // or beyond 256 registers per lane, AGPRs holding VGPRs) were in
-                // use when a mixed-precision run with a forced workgroup size
-                // faulted the GPU; the cause is not known.  Their capacity is
-                // that of (1024, 4, 2), so only a forced 512 or 256 reached them;
-                // RVEs they would take run on the streamed kernel.
-                if (v == 3 || v == 5) b->variant_spills[k][p][v] = true;
+                size_t sb = 1;
+                if (resident_scratch_bytes(v, p == 1, k == 1, &sb) != hipSuccess) sb = 1;
+                b->variant_spills[k][p][v] = sb > 0;
             }
+            for (int w = 0; w < 2; ++w) {
+                size_t sb = 1;
+                if (streamed_scratch_bytes(p == 1, k == 1, w ? 1024 : 256, &sb) != hipSuccess) sb = 1;
+                b->streamed_private[k][p][w] = sb > 0;
+            }
+        }
+    for (int m = 0; m < 2; ++m)
+        for (int v = 0; v < kNumTanRes; ++v) {
+            size_t sb = 1;
+            if (tangent_res_scratch_bytes(v, m == 1, &sb) != hipSuccess) sb = 1;
+            b->tangent_private[m][v] = sb > 0;
+        }
+    {
+        size_t sb = 1;
+        if (fixed_kernels_scratch_bytes(&sb) != hipSuccess || sb > 0) {
+            delete b;
+            return fail(RVE_EDEVICE, "internal: a fixed kernel of the library uses private memory");
+        }
+    }
     b->R = net->n_rve;
     b->opts = *opts;
     b->c_host.assign(b->R, opts->c);
@@ -738,8 +887,16 @@ int rve_batch_set_opts(rve_batch* b, const rve_opts* opts)
     if (opts->c_per_rve) std::copy(opts->c_per_rve, opts->c_per_rve + b->R, b->c_host.begin());
     b->opts.c_per_rve = nullptr;
     if (b->R) HIP_TRY(hipMemcpy(b->dc, b->c_host.data(), 8 * b->R, hipMemcpyHostToDevice));
+    ++b->generation;
     assign_groups(b);
     return upload_groups(b);
+}
+
+int rve_batch_generation(const rve_batch* b, uint64_t* gen)
+{
+    if (!b || !gen) return fail(RVE_EINVAL, "NULL argument");
+    *gen = b->generation;
+    return RVE_OK;
 }
 
 int rve_batch_set_stream(rve_batch* b, void* stream)
@@ -823,6 +980,28 @@ int rve_batch_solve(rve_batch* b, const double* F, double* sigma, int32_t* statu
     HIP_TRY(hipMemcpyAsync(b->dF, F, 72 * b->R, in_kind, s));
     int rc = ensure_workspace(b);
     if (rc) return rc;
+    int32_t init = b->opts.init;
+    if (init == RVE_INIT_REFERENCE) {
+        // free nodes at Xm: the fluctuation (I - F) Xm, then a warm start from it
+        if (!b->d_xm_free) {
+            std::vector<double> xf(3 * (size_t)b->NFREE + 3);
+            for (int64_t r = 0; r < b->R; ++r) {
+                const int64_t n0 = b->node_off[r], nn = b->node_off[r + 1] - n0, nf = b->nf_of[r];
+                for (int64_t q = 0; q < nn; ++q) {
+                    const int64_t id = b->newid[n0 + q];
+                    if (id < nf)
+                        for (int k = 0; k < 3; ++k) xf[3 * (b->free_off[r] + id) + k] = b->Xm[3 * (n0 + q) + k];
+                }
+            }
+            if (hipMalloc((void**)&b->d_xm_free, xf.size() * 8) != hipSuccess) {
+                b->d_xm_free = nullptr;
+                return fail(RVE_ENOMEM, "reference-coordinate allocation failed");
+            }
+            HIP_TRY(hipMemcpy(b->d_xm_free, xf.data(), xf.size() * 8, hipMemcpyHostToDevice));
+        }
+        HIP_TRY(launch_reference_h(b->dF, b->net.free_off, b->d_xm_free, b->R, b->dh, s));
+        init = RVE_INIT_WARM;
+    }
 
     SolveArgs a{};
     a.net = b->net;
@@ -831,7 +1010,7 @@ int rve_batch_solve(rve_batch* b, const double* F, double* sigma, int32_t* statu
     a.queue = b->dqueue;
     a.law = b->opts.law;
     a.mass_mode = b->opts.mass;
-    a.init = b->opts.init;
+    a.init = init;
     a.check_every = b->opts.check_every;
     a.EA = b->opts.EA;
     a.B = b->opts.B;
@@ -856,7 +1035,7 @@ int rve_batch_solve(rve_batch* b, const double* F, double* sigma, int32_t* statu
     b->last_variant = false;
     if (variant_mode(b->opts)) {
         if (!b->v_ws) {
-            if (b->ws_user) return fail(RVE_EINVAL, "internal: bound workspace has no variant area");
+            if (b->ws_user) return fail(RVE_EWORKSPACE, "internal: bound workspace has no variant area");
             if (hipMalloc((void**)&b->v_ws, variant_ws_bytes(b->NFREE, b->NF) + 16 * (size_t)b->R) != hipSuccess) {
                 b->v_ws = nullptr;
                 return fail(RVE_ENOMEM, "variant workspace allocation failed");
@@ -917,6 +1096,7 @@ int rve_batch_solve(rve_batch* b, const double* F, double* sigma, int32_t* statu
                 HIP_TRY(launch_resident(v, fp64, a, b->group_lds[g], grid, s));
             } else {
                 int threads = streamed_threads(b, fp64);
+                if (!threads) return fail(RVE_EDEVICE, "internal: every streamed kernel build uses private memory");
                 a.lds_h_nodes = streamed_lds_nodes(b, b->groups[g].data(), b->groups[g].size(), fp64);
                 int grid = std::min<int64_t>((int64_t)b->n_cu * streamed_blocks_per_cu(threads, a.lds_h_nodes, fp64),
                                              a.n_list);
@@ -943,6 +1123,7 @@ int rve_batch_solve(rve_batch* b, const double* F, double* sigma, int32_t* statu
     }
     if (ptr_kind == RVE_PTR_HOST) HIP_TRY(hipStreamSynchronize(s));
     b->have_state = true;
+    ++b->generation;
     return RVE_OK;
 }
 
@@ -1032,6 +1213,7 @@ int rve_batch_autotune(rve_batch* b, const double* F, int32_t ptr_kind, int32_t 
             // Each remaining candidate's final states must also stay close to
             // those of the streamed kernel (timed first) on the tuning RVEs.
             if (v >= 0 && (!variant_fits_tier(v, (int)t) || spills(b, v, fp64))) continue;
+            if (v < 0 && !streamed_threads(b, fp64)) continue;
             int grid = 0;
             if (v >= 0) {
                 int per_cu = 0;
@@ -1274,6 +1456,7 @@ int rve_batch_import_state(rve_batch* b, const double* F, const double* h, const
                                ptr_kind == RVE_PTR_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s));
     if (ptr_kind == RVE_PTR_HOST) HIP_TRY(hipStreamSynchronize(s));
     b->have_state = true;
+    ++b->generation;
     return RVE_OK;
 }
 
@@ -1323,11 +1506,13 @@ static void tangent_groups(rve_batch* b)
         first[v] = (int64_t)order.size();
         for (int32_t r : lpt) {
             int g = kNumTanRes;
-            for (int u = 0; u < kNumTanRes; ++u)
+            for (int u = 0; u < kNumTanRes; ++u) {
+                if (b->tangent_private[0][u] || b->tangent_private[1][u]) continue;   // never launched
                 if (b->nf_of[r] <= (int64_t)kTanRes[u].threads * kTanRes[u].sn) {
                     g = u;
                     break;
                 }
+            }
             if (g == v) order.push_back(r);
         }
     }
@@ -1521,14 +1706,14 @@ int rve_batch_bind_workspace(rve_batch* b, void* ptr, size_t bytes)
     int rc = ws_layout(b, L);
     if (rc) return rc;
     if (ptr) {
-        if (reinterpret_cast<uintptr_t>(ptr) & 255) return fail(RVE_EINVAL, "workspace must be 256-byte aligned");
+        if (reinterpret_cast<uintptr_t>(ptr) & 255) return fail(RVE_EWORKSPACE, "workspace must be 256-byte aligned");
         if (bytes < L.total)
-            return fail(RVE_EINVAL, "workspace too small: " + std::to_string(L.total) + " bytes needed");
+            return fail(RVE_EWORKSPACE, "workspace too small: " + std::to_string(L.total) + " bytes needed");
         hipPointerAttribute_t at{};
         if (hipPointerGetAttributes(&at, ptr) != hipSuccess || at.type != hipMemoryTypeDevice ||
             at.device != b->device) {
             (void)hipGetLastError();
-            return fail(RVE_EINVAL, "workspace must be device memory of the batch's device");
+            return fail(RVE_EWORKSPACE, "workspace must be device memory of the batch's device");
         }
     }
     // work already queued may still use the current regions
@@ -1681,8 +1866,9 @@ static int ensure_probe(rve_batch* b)
     if (b->probe) return RVE_OK;
     const int64_t R = b->R;
     std::vector<uint32_t> ends(b->NF);
-    std::vector<double> V0(R);
+    std::vector<double> V0(R), L0(b->NF), L0p;
     if (b->NF) HIP_TRY(hipMemcpy(ends.data(), b->net.ends, 4 * (size_t)b->NF, hipMemcpyDeviceToHost));
+    if (b->NF) HIP_TRY(hipMemcpy(L0.data(), b->net.L0, 8 * (size_t)b->NF, hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(V0.data(), b->dV0, 8 * (size_t)R, hipMemcpyDeviceToHost));
     std::vector<int64_t> node_off(1, 0), fib_off(1, 0);
     std::vector<double> X, V0p, cp;
@@ -1692,6 +1878,7 @@ static int ensure_probe(rve_batch* b)
         X.reserve(18 * (size_t)b->NN);
         isb.reserve(6 * (size_t)b->NN);
         fib.reserve(12 * (size_t)b->NF);
+        L0p.reserve(6 * (size_t)b->NF);
         for (int64_t r = 0; r < R; ++r) {
             const int64_t n0 = b->node_off[r], nn = b->node_off[r + 1] - n0;
             const int64_t f0 = b->fib_off[r], nfib = b->fib_off[r + 1] - f0, nf = b->nf_of[r];
@@ -1706,6 +1893,7 @@ static int ensure_probe(rve_batch* b)
                     const uint32_t e = ends[f0 + k];
                     fib.push_back(inv[e & 0xffffu]);
                     fib.push_back(inv[e >> 16]);
+                    L0p.push_back(L0[f0 + k]);
                 }
                 node_off.push_back(node_off.back() + nn);
                 fib_off.push_back(fib_off.back() + nfib);
@@ -1724,6 +1912,7 @@ static int ensure_probe(rve_batch* b)
     d.is_bnd = isb.data();
     d.fib = fib.data();
     d.V0 = V0p.data();
+    d.L0 = L0p.data();
     rve_opts o = b->opts;
     o.init = RVE_INIT_WARM;
     o.c_per_rve = cp.data();
@@ -1837,6 +2026,7 @@ void rve_batch_destroy(rve_batch* b)
     if (b->d_probe_map) (void)hipFree(b->d_probe_map);
     if (b->d_fd_rot) (void)hipFree(b->d_fd_rot);
     if (b->dtune_list) (void)hipFree(b->dtune_list);
+    if (b->d_xm_free) (void)hipFree(b->d_xm_free);
     if (b->dmem) (void)hipFree(b->dmem);
     delete b;
 }

@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <initializer_list>
+
 namespace rve {
 
 // Packed, reordered batch on the device.  Within an RVE the nodes are
@@ -122,6 +125,10 @@ bool fd_finish(const double* F, const double* sigma, const double* sigma_probe, 
 // caller node n, -1 for a boundary node; h arrays are [nodes][3] doubles.
 hipError_t launch_export_h(const double* dh, const int32_t* map, int64_t nn, double* out, hipStream_t s);
 hipError_t launch_import_h(const double* in, const int32_t* map, int64_t nn, double* dh, hipStream_t s);
+// dh = Xm - F Xm for every free node (reference start); xm[NFREE][3] in the
+// packed free-first order.
+hipError_t launch_reference_h(const double* F, const int64_t* free_off, const double* xm, int64_t R, double* dh,
+                              hipStream_t s);
 // st[r] = st_in[r] checked against F (BAD_F, codes out of range -> NONFINITE);
 // iterations 0 and norms NaN.
 hipError_t launch_import_status(const double* F, const int32_t* st_in, int64_t R, int32_t* st, int64_t* iters,
@@ -144,13 +151,46 @@ struct VariantArgs {
 hipError_t launch_variant(const VariantArgs& a, int64_t n_rve, hipStream_t s);
 size_t variant_ws_bytes(int64_t n_free, int64_t n_fib);
 
+// Index arithmetic of the register-resident engine, shared by the kernels
+// and the host replay that bounds every index (rve_check_indexing).
+// Fiber ends: two 16-bit local node ids, free-first numbering; a boundary
+// end (id >= nf) reads the zero position slot nf.
+__host__ __device__ inline uint32_t res_pack_ends(uint32_t ends, uint32_t nf)
+{
+    uint32_t i = ends & 0xffffu, j = ends >> 16;
+    i = i < nf ? i : nf;
+    j = j < nf ? j : nf;
+    return i | (j << 16);
+}
+__host__ __device__ inline uint32_t res_end_i(uint32_t E) { return E & 0xffffu; }
+__host__ __device__ inline uint32_t res_end_j(uint32_t E) { return E >> 16; }
+// Incidence codes: fiber id in 15 bits, bit 15 set when the node is end i
+// (its force enters with a minus sign).  The padding code nfib reads the zero
+// force slot, so fiber ids stay below 0x7fff.
+__host__ __device__ inline uint32_t res_inc_code(uint32_t w) { return (w & 0x7fffu) | ((w >> 31) << 15); }
+__host__ __device__ inline uint32_t res_code_fiber(uint32_t code) { return code & 0x7fffu; }
+__host__ __device__ inline bool res_code_neg(uint32_t code) { return (code & 0x8000u) != 0; }
+constexpr int kResIncRegs = 4;          // incidences per node held in registers (two codes per word)
+constexpr int kResMaxFibers = 0x7fff;   // fiber ids and the zero slot fit the 15-bit code
+
+// Reduction slots of a relaxation workgroup (static LDS of the resident and
+// streamed kernels): per-wave partial sums of |f_free|^2, |c M v|^2,
+// |f_bnd|^2 and the kinetic energy, and two alternating slots for the
+// time-step maximum.
+struct RedSlots {
+    double v[4][16];
+    unsigned long long g64[2];
+    unsigned g32[2];
+};
+// Static LDS of a resident workgroup: the reduction slots and the task id.
+constexpr size_t kResStaticLds = sizeof(RedSlots) + 16;
+
 // Which register-resident variants exist (threads per RVE, fiber slots per
 // thread, free-node slots per thread).
 struct ResidentVariant {
     int threads, sf, sn;
 };
 
-constexpr int kMaxResidentDegree = 8;   // incidence kept in registers
 constexpr int kNumResident = 6;
 extern const ResidentVariant kResident[kNumResident];
 
@@ -181,6 +221,34 @@ hipError_t tangent_res_blocks(int variant, bool vjp, int* blocks_per_cu);
 hipError_t max_resident_blocks(int variant, bool fp64, bool kin, size_t lds_bytes, int* blocks_per_cu);
 // Private (spill) bytes per lane of a resident variant; > 0 means it spills.
 hipError_t resident_scratch_bytes(int variant, bool fp64, bool kin, size_t* bytes);
+// Same for a streamed build (256 or 1024 threads) and a resident tangent build.
+hipError_t streamed_scratch_bytes(bool fp64, bool kin, int threads, size_t* bytes);
+hipError_t tangent_res_scratch_bytes(int variant, bool vjp, size_t* bytes);
+// Largest private segment over the kernels that have a single build (stress,
+// counters, naive engine, orientation, state, tangent preparation and
+// streamed tangent, variant engine, probe seeding): must be 0.
+hipError_t fixed_kernels_scratch_bytes(size_t* bytes);
+hipError_t kernels_fixed_private(size_t* bytes);
+hipError_t naive_fixed_private(size_t* bytes);
+hipError_t orient_fixed_private(size_t* bytes);
+hipError_t state_fixed_private(size_t* bytes);
+hipError_t tangent_fixed_private(size_t* bytes);
+hipError_t variant_fixed_private(size_t* bytes);
+hipError_t fd_fixed_private(size_t* bytes);
+
+// Largest private segment (bytes per lane) over a list of kernels.
+inline hipError_t max_private_bytes(std::initializer_list<const void*> kernels, size_t* bytes)
+{
+    size_t m = 0;
+    for (const void* k : kernels) {
+        hipFuncAttributes at;
+        const hipError_t e = hipFuncGetAttributes(&at, k);
+        if (e != hipSuccess) return e;
+        m = std::max(m, (size_t)at.localSizeBytes);
+    }
+    *bytes = m;
+    return hipSuccess;
+}
 
 
 }  // namespace rve

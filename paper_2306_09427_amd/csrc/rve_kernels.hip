@@ -3,7 +3,7 @@
 // One workgroup relaxes one RVE at a time and pulls the next RVE id from a
 // device work counter (longest-first order), so thousands of uneven RVEs go
 // through one launch (the whole relaxation loop inside a single kernel,
-// Section 4.2).  Per iteration (Algorithm "Dynamic Relaxation"):
+// Section 4.3).  Per iteration (Algorithm "Dynamic Relaxation"):
 //
 //   fiber pass   every fiber: d = F d0 + h_j - h_i, strain, axial force T,
 //                force vector fv = T d / l and Gershgorin term
@@ -36,7 +36,7 @@
 namespace rve {
 
 const ResidentVariant kResident[kNumResident] = {
-    {256, 4, 2},  {512, 4, 2}, {1024, 4, 2}, {512, 8, 4}, {1024, 6, 3}, {256, 16, 8},
+    {256, 4, 2}, {512, 4, 2}, {768, 4, 2}, {512, 6, 3}, {1024, 4, 2}, {1024, 6, 3},
 };
 
 constexpr int kLawLinear = 0;
@@ -174,6 +174,15 @@ __device__ __forceinline__ FiberOut<double> fiber_eval_exact(int law, double EA,
     return o;
 }
 
+// The thread id as a value the compiler cannot see through: indices derived
+// from it are recomputed where used instead of being hoisted and kept live.
+__device__ __forceinline__ int opaque_tid()
+{
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
 // Broadcast helpers: values every lane holds identically (read back from LDS
 // after a barrier) are moved to scalar registers.
 __device__ __forceinline__ double uniform(double x)
@@ -181,6 +190,17 @@ __device__ __forceinline__ double uniform(double x)
     int lo = __builtin_amdgcn_readfirstlane(__double2loint(x));
     int hi = __builtin_amdgcn_readfirstlane(__double2hiint(x));
     return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float uniform(float x)
+{
+    return __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(x)));
+}
+__device__ __forceinline__ int uniform32(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ int64_t uniform64(int64_t x)
+{
+    const int lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    const int hi = __builtin_amdgcn_readfirstlane((int)(x >> 32));
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
 template <typename T>
@@ -312,14 +332,9 @@ size_t resident_lds_bytes(bool fp64, int64_t nf, int64_t nfib, int /*threads*/)
 }
 
 // Reduction slots of a workgroup: per-wave partial sums of |f_free|^2,
-// |c M v|^2 and |f_bnd|^2, and two alternating slots for the time-step
-// maximum (LDS atomic max on the bit pattern of a non-negative number).
-struct RedSlots {
-    double v[3][16];
-    double ke[16];      // kinetic damping: per-wave kinetic energy
-    unsigned long long g64[2];
-    unsigned g32[2];
-};
+// |c M v|^2, |f_bnd|^2 and (kinetic damping) the kinetic energy, and two
+// alternating slots for the time-step maximum (LDS atomic max on the bit
+// pattern of a non-negative number).
 
 __device__ __forceinline__ void reset_gslots(RedSlots& red)
 {
@@ -329,20 +344,41 @@ __device__ __forceinline__ void reset_gslots(RedSlots& red)
     }
 }
 
-// Workgroup reduction: max of gpart (>= 0) every call, and the three sums
-// when `full`.  Every thread returns the same (scalar) totals in a fixed
-// summation order.  One barrier; the max slot alternates with `parity`, the
-// other slot is cleared for the next call (at least two barriers separate a
-// clear from the next atomic on that slot).
-template <typename Real, int NW, bool KE = false>
-__device__ __forceinline__ void block_reduce(RedSlots& red, int parity, Real gpart, double r2, double d2, double b2,
-                                             bool full, double& gmax_o, double& r2_o, double& d2_o, double& b2_o,
-                                             double ke = 0.0, double* ke_o = nullptr)
+__device__ __forceinline__ double readlane_d(double x, int l)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+    return __hiloint2double(hi, lo);
+}
+
+// Error-free sum of two doubles: s + e == a + b exactly (Knuth's two-sum;
+// symmetric in a and b).
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e)
+{
+    s = a + b;
+    const double z = s - a;
+    e = (a - (s - z)) + (b - z);
+}
+
+// Workgroup reduction: max of gpart (>= 0) every call, and the three norms
+// when `full` (the kinetic energy too in the kinetic builds).  Inside a wave
+// the partials are added pairwise; across waves the sums are compensated:
+// lane 16 p + w of every wave loads partial w of quantity p, and a butterfly
+// over each row of 16 lanes combines (sum, error) pairs with an exact
+// two-sum, so every wave ends with the same totals in a fixed order.  One
+// barrier; the max slot alternates with `parity`, the other slot is cleared
+// for the next call (at least two barriers separate a clear from the next
+// atomic on that slot).
+template <typename Real, int NW, bool KE = false>
+__device__ __forceinline__ void block_reduce(RedSlots& red, int tid, int parity, Real gpart, double r2, double d2,
+                                             double b2, bool full, double& gmax_o, double& r2_o, double& d2_o,
+                                             double& b2_o, double ke = 0.0, double* ke_o = nullptr)
+{
+    static_assert(NW <= 16, "at most 16 waves per workgroup");
+    const int lane = tid & 63, wave = tid >> 6;
     if constexpr (KE) {
         ke = wave_sum(ke);
-        if (lane == 0) red.ke[wave] = ke;
+        if (lane == 0) red.v[3][wave] = ke;
     }
     if constexpr (sizeof(Real) == 4) {
         float g = wave_max_nonneg((float)gpart);
@@ -366,37 +402,40 @@ __device__ __forceinline__ void block_reduce(RedSlots& red, int parity, Real gpa
         gmax_o = (double)__uint_as_float(__builtin_amdgcn_readfirstlane(red.g32[parity]));
     else
         gmax_o = uniform(__longlong_as_double((long long)red.g64[parity]));
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         red.g32[parity ^ 1] = 0u;
         red.g64[parity ^ 1] = 0ull;
     }
-    if (full) {
-        double a = 0.0, b = 0.0, c = 0.0;
-#pragma unroll 4
-        for (int w = 0; w < NW; ++w) {
-            a += red.v[0][w];
-            b += red.v[1][w];
-            c += red.v[2][w];
+    if (full || KE) {
+        const int p = lane >> 4, w = lane & 15;
+        const bool use = w < NW && (p == 3 ? KE : full);
+        double s = use ? red.v[p][w] : 0.0, c = 0.0;
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) {
+            const double so = __shfl_xor(s, off, 16), co = __shfl_xor(c, off, 16);
+            double t, e;
+            two_sum(s, so, t, e);
+            s = t;
+            c = (c + co) + e;
         }
-        r2_o = uniform(a);
-        d2_o = uniform(b);
-        b2_o = uniform(c);
-    }
-    if constexpr (KE) {
-        double k = 0.0;
-#pragma unroll 4
-        for (int w = 0; w < NW; ++w) k += red.ke[w];
-        *ke_o = uniform(k);
+        const double tot = s + c;
+        if (full) {
+            r2_o = readlane_d(tot, 0);
+            d2_o = readlane_d(tot, 16);
+            b2_o = readlane_d(tot, 32);
+        }
+        if constexpr (KE) *ke_o = readlane_d(tot, 48);
     }
 }
 
 // Boundary reaction norm^2 partial of this thread (test iterations only).
 template <typename Real, int T>
-__device__ __forceinline__ double boundary_norm2_partial(const DevNet& net, const Lds<Real>& L, int64_t b0, int nb)
+__device__ __forceinline__ double boundary_norm2_partial(const DevNet& net, const Lds<Real>& L, int64_t b0, int nb,
+                                                         int tid)
 {
     double acc = 0.0;
 #pragma unroll 1
-    for (int q = threadIdx.x; q < nb; q += T) {
+    for (int q = tid; q < nb; q += T) {
         double x = 0, y = 0, z = 0;
 #pragma unroll 1
         for (int64_t e = net.binc_off[b0 + q]; e < net.binc_off[b0 + q + 1]; ++e) {
@@ -436,19 +475,71 @@ __device__ __forceinline__ void stress_finish(double* s, double J, double V0, do
 }
 
 // ------------------------------------------------------------------ resident kernel
+// Fiber evaluation in the scaled form of the register-resident engine.  Per
+// fiber the engine keeps Dn = F d0 / L0, Qn = (|F d0|^2 - L0^2) / L0^2 and
+// iL = 1/L0 (formed in FP64 once per solve); with u = dh / L0
+//   qn  = (l^2 - L0^2) / L0^2 = Qn + 2 Dn.u + u.u      (no cancellation)
+//   l/L0 = sqrt(1 + qn),  eps = qn / (l/L0 + 1)
+//   force on end j = T d / l = (T L0 / l) (Dn + u)
+//   Gershgorin term max(k_t / L0, |T| / l) = iL max(k_t, |T L0 / l|).
+template <typename Real>
+__device__ __forceinline__ FiberOut<Real> fiber_eval_scaled(bool linear, Real EA, Real B, Real EAoB, Real Dx, Real Dy,
+                                                            Real Dz, Real Qn, Real iL, Real dhx, Real dhy, Real dhz)
+{
+    const Real ux = dhx * iL, uy = dhy * iL, uz = dhz * iL;
+    const Real qn = Qn + (Real(2) * (Dx * ux + Dy * uy + Dz * uz) + (ux * ux + uy * uy + uz * uz));
+    const Real m = Real(1) + qn;
+    const Real rs = dev_rsqrt(m);   // L0 / l
+    Real s;                          // l / L0
+    if constexpr (sizeof(Real) == 4)
+        s = m * rs;
+    else
+        s = sqrt(m);
+    const Real eps = qn * dev_rcp(s + Real(1));
+    Real T, kt;
+    if (linear) {
+        T = EA * eps;
+        kt = EA;
+    } else {
+        // both branches of the exponential law without divergence
+        const bool pos = eps >= Real(0);
+        const Real em1 = dev_expm1(B * (pos ? eps : Real(0)));
+        T = pos ? EAoB * em1 : EA * eps;
+        kt = pos ? EA * (em1 + Real(1)) : EA;
+    }
+    const Real g = T * rs;
+    FiberOut<Real> o;
+    o.fx = g * (Dx + ux);
+    o.fy = g * (Dy + uy);
+    o.fz = g * (Dz + uz);
+    o.b = iL * fmax(kt, fabs(g));
+    return o;
+}
+
+// One RVE on one workgroup, state in registers.  Index arithmetic (replayed
+// on the host by rve_check_indexing): fiber k lives in slot k / T of thread
+// k % T, free node a in slot a / T of thread a % T; fiber ends are packed
+// by res_pack_ends (boundary ends read the zero position slot nf), the first
+// kResIncRegs incidences of a node are 16-bit codes from res_inc_code
+// (padding reads the zero force slot nfib), further incidences are read from
+// the CSR in global memory.
 template <typename Real, int T, int SF, int SN, bool KIN>
 __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* smem, RedSlots& red)
 {
     constexpr int NW = T / 64;
+    // incidences gathered per batch of LDS reads (all four where the
+    // registers allow, else two)
+    constexpr int GB = (SF + SN > 6 && sizeof(Real) == 4) ? 2 : kResIncRegs;
     // Opaque per RVE: slot indices derived from the thread id are recomputed
     // for each RVE instead of being held live across the persistent loop.
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     const DevNet& net = A.net;
-    const int64_t f0 = net.fib_off[r], a0 = net.free_off[r], b0 = net.bnd_off[r];
-    const int nfib = (int)(net.fib_off[r + 1] - f0);
-    const int nf = (int)(net.free_off[r + 1] - a0);
-    const int nb = (int)(net.bnd_off[r + 1] - b0);
+    // per-RVE sizes and offsets are the same in every lane: scalar registers
+    const int64_t f0 = uniform64(net.fib_off[r]), a0 = uniform64(net.free_off[r]), b0 = uniform64(net.bnd_off[r]);
+    const int nfib = uniform32((int)(net.fib_off[r + 1] - f0));
+    const int nf = uniform32((int)(net.free_off[r + 1] - a0));
+    const int nb = uniform32((int)(net.bnd_off[r + 1] - b0));
     const double* d0b = net.d0 + 3 * f0;
     const double* L0b = net.L0 + f0;
     const uint32_t* endb = net.ends + f0;
@@ -472,75 +563,71 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
         }
         return;
     }
-    const Real EA = (Real)A.EA, Bc = (Real)A.B, EAoB = (Real)(A.EA / A.B);
+    const bool linear = A.law == kLawLinear;
+    const Real EA = uniform((Real)A.EA), Bc = uniform((Real)A.B), EAoB = uniform((Real)(A.EA / A.B));
     // kinetic damping: no viscous force (c = 0); velocities are zeroed at
     // kinetic-energy peaks below
-    const double cd = KIN ? 0.0 : A.c[r];
-    const Real c = (Real)cd;
-    const Real cg = KIN ? (Real)A.c[r] : c;   // scale of the damping-force test
+    const double cr = uniform(A.c[r]);
+    const Real c = KIN ? Real(0) : uniform((Real)cr);
+    const Real cg = uniform((Real)cr);   // scale of the damping-force test
 
     Lds<Real> L;
     L.init(smem, nf, nfib);
 
-    // ---- fibers into registers: D0 = F d0, q0 = |D0|^2 - L0^2 (FP64 then rounded)
-    Real D0x[SF], D0y[SF], D0z[SF], Q0[SF], L0r[SF], iL0r[SF];
+    // ---- fibers into registers (scaled form, see fiber_eval_scaled)
+    Real Dx[SF], Dy[SF], Dz[SF], Qn[SF], iL[SF];
     uint32_t E[SF];
 #pragma unroll
     for (int s = 0; s < SF; ++s) {
-        int k = s * T + tid;
-        D0x[s] = D0y[s] = D0z[s] = Q0[s] = Real(0);
-        L0r[s] = iL0r[s] = Real(1);
+        const int k = s * T + tid;
+        Dx[s] = Dy[s] = Dz[s] = Qn[s] = Real(0);
+        iL[s] = Real(1);
         E[s] = 0;
         if (k < nfib) {
             const double* d0 = d0b + 3 * k;
-            double L0 = L0b[k];
-            double Dx = F[0] * d0[0] + F[1] * d0[1] + F[2] * d0[2];
-            double Dy = F[3] * d0[0] + F[4] * d0[1] + F[5] * d0[2];
-            double Dz = F[6] * d0[0] + F[7] * d0[1] + F[8] * d0[2];
-            D0x[s] = (Real)Dx; D0y[s] = (Real)Dy; D0z[s] = (Real)Dz;
-            Q0[s] = (Real)((Dx * Dx + Dy * Dy + Dz * Dz) - L0 * L0);
-            L0r[s] = (Real)L0;
-            iL0r[s] = (Real)(1.0 / L0);
-            uint32_t e = endb[k];
-            uint32_t i = e & 0xffffu, j = e >> 16;
-            // boundary ends read the zero slot nf
-            i = i < (uint32_t)nf ? i : (uint32_t)nf;
-            j = j < (uint32_t)nf ? j : (uint32_t)nf;
-            E[s] = i | (j << 16);
+            const double L0 = L0b[k], il = 1.0 / L0;
+            const double Dxd = F[0] * d0[0] + F[1] * d0[1] + F[2] * d0[2];
+            const double Dyd = F[3] * d0[0] + F[4] * d0[1] + F[5] * d0[2];
+            const double Dzd = F[6] * d0[0] + F[7] * d0[1] + F[8] * d0[2];
+            Dx[s] = (Real)(Dxd * il); Dy[s] = (Real)(Dyd * il); Dz[s] = (Real)(Dzd * il);
+            Qn[s] = (Real)((((Dxd * Dxd + Dyd * Dyd + Dzd * Dzd) - L0 * L0) * il) * il);
+            iL[s] = (Real)il;
+            E[s] = res_pack_ends(endb[k], (uint32_t)nf);
         }
     }
-    // ---- free nodes into registers
-    Real hx[SN], hy[SN], hz[SN], vx[SN], vy[SN], vz[SN], iM[SN];
-    uint32_t inc[SN][kMaxResidentDegree / 2];
+    // ---- free nodes: velocity, acceleration, inverse mass and incidence in
+    // registers; the positions live only in the LDS exchange array
+    Real vx[SN], vy[SN], vz[SN], iM[SN];
+    uint32_t inc[SN][kResIncRegs / 2];
     int degw[SN];   // largest degree in this wave's node slot (scalar)
 #pragma unroll
     for (int s = 0; s < SN; ++s) {
-        int a = s * T + tid;
-        hx[s] = hy[s] = hz[s] = vx[s] = vy[s] = vz[s] = Real(0);
+        const int a = s * T + tid;
+        vx[s] = vy[s] = vz[s] = Real(0);
         iM[s] = Real(0);
         int deg = 0;
 #pragma unroll
-        for (int q = 0; q < kMaxResidentDegree / 2; ++q) inc[s][q] = (uint32_t)nfib | ((uint32_t)nfib << 16);
+        for (int q = 0; q < kResIncRegs / 2; ++q) inc[s][q] = (uint32_t)nfib | ((uint32_t)nfib << 16);
         if (a < nf) {
             iM[s] = (Real)(1.0 / (massb[a] * A.rhoA));
-            int64_t e0 = incoffb[a], e1 = incoffb[a + 1];
-            deg = (int)(e1 - e0);
+            const int64_t e0 = incoffb[a];
+            deg = (int)(incoffb[a + 1] - e0);
 #pragma unroll
-            for (int q = 0; q < kMaxResidentDegree; ++q) {
+            for (int q = 0; q < kResIncRegs; ++q) {
                 if (q < deg) {
-                    uint32_t w = net.inc[e0 + q];
-                    uint32_t code = (w & 0x7fffu) | ((w >> 31) << 15);
+                    const uint32_t code = res_inc_code(net.inc[e0 + q]);
                     if (q & 1)
                         inc[s][q >> 1] = (inc[s][q >> 1] & 0xffffu) | (code << 16);
                     else
                         inc[s][q >> 1] = (inc[s][q >> 1] & 0xffff0000u) | code;
                 }
             }
+            Real hx = Real(0), hy = Real(0), hz = Real(0);
             if (A.init == kInitWarm) {
                 const double* h = hsb + 3 * a;
-                hx[s] = (Real)h[0]; hy[s] = (Real)h[1]; hz[s] = (Real)h[2];
+                hx = (Real)h[0]; hy = (Real)h[1]; hz = (Real)h[2];
             }
-            L.put_h(a, hx[s], hy[s], hz[s]);
+            L.put_h(a, hx, hy, hz);
         }
         degw[s] = (int)__builtin_amdgcn_readfirstlane(
             __float_as_uint(wave_max_nonneg(__uint_as_float((unsigned)deg))));
@@ -553,71 +640,57 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
     }
     __syncthreads();
 
-    auto fiber_pass = [&]() __attribute__((always_inline)) {
+    // The loop bodies take the thread id as an argument that is made opaque
+    // once per iteration (opaque_tid), so nothing derived from it is hoisted
+    // out of the relaxation loop and held in registers for the whole solve.
+    auto fiber_pass = [&](int t) __attribute__((always_inline)) {
 #pragma unroll
         for (int s = 0; s < SF; ++s) {
-            int k = s * T + tid;
+            const int k = s * T + t;
             if (k < nfib) {
-                int i = E[s] & 0xffff, j = E[s] >> 16;
                 Real ix, iy, iz, jx, jy, jz;
-                L.get_h(i, ix, iy, iz);
-                L.get_h(j, jx, jy, jz);
-                FiberOut<Real> o = fiber_eval<Real>(A.law, EA, Bc, EAoB, D0x[s], D0y[s], D0z[s], Q0[s], L0r[s],
-                                                    iL0r[s], jx - ix, jy - iy, jz - iz);
+                L.get_h((int)res_end_i(E[s]), ix, iy, iz);
+                L.get_h((int)res_end_j(E[s]), jx, jy, jz);
+                const FiberOut<Real> o = fiber_eval_scaled<Real>(linear, EA, Bc, EAoB, Dx[s], Dy[s], Dz[s], Qn[s],
+                                                                 iL[s], jx - ix, jy - iy, jz - iz);
                 L.put_fv(k, o);
             }
             __builtin_amdgcn_sched_barrier(0);
         }
     };
-    // gather forces and Gershgorin sums of node slot s; lanes whose node has
-    // fewer incidences than the wave's largest read the zero slot
-    // FP32: the first four incidences are read unconditionally (padding reads
-    // the zero slot), so their LDS reads are issued back to back; nodes of
-    // degree 5..8 (a wave-uniform test) add the rest.  FP64 keeps one read at
-    // a time (its register file is the limit).
-    auto gather = [&](int s, Real& fx, Real& fy, Real& fz, Real& G) __attribute__((always_inline)) {
+    // forces and Gershgorin sum of node slot s: the register-held incidences
+    // are read back to back (padding reads the zero slot); a wave whose node
+    // slot holds a node of higher degree (a wave-uniform test) reads the rest
+    // from the CSR
+    auto gather = [&](int t, int s, Real& fx, Real& fy, Real& fz, Real& G) __attribute__((always_inline)) {
         fx = fy = fz = G = Real(0);
-        int q0 = 0;
-        if constexpr (sizeof(Real) == 4) {
-            Real x[4], y[4], z[4], b[4];
-            uint32_t code[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                code[q] = (q & 1) ? (inc[s][q >> 1] >> 16) : (inc[s][q >> 1] & 0xffffu);
-                L.get_fv((int)(code[q] & 0x7fffu), x[q], y[q], z[q], b[q]);
+        for (int h = 0; h < kResIncRegs / GB; ++h) {
+            Real x[GB], y[GB], z[GB], b[GB];
+            uint32_t code[GB];
+#pragma unroll
+            for (int u = 0; u < GB; ++u) {
+                const int q = h * GB + u;
+                code[u] = (q & 1) ? (inc[s][q >> 1] >> 16) : (inc[s][q >> 1] & 0xffffu);
+                L.get_fv((int)res_code_fiber(code[u]), x[u], y[u], z[u], b[u]);
             }
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const Real sg = (code[q] & 0x8000u) ? Real(-1) : Real(1);
-                fx = fma(sg, x[q], fx); fy = fma(sg, y[q], fy); fz = fma(sg, z[q], fz); G += b[q];
+            for (int u = 0; u < GB; ++u) {
+                const Real sg = res_code_neg(code[u]) ? Real(-1) : Real(1);
+                fx = fma(sg, x[u], fx); fy = fma(sg, y[u], fy); fz = fma(sg, z[u], fz); G += b[u];
             }
-            q0 = 4;
         }
-#pragma unroll
-        for (int q = 0; q < kMaxResidentDegree; ++q) {
-            if (q < q0) continue;
-            if (q >= degw[s]) break;
-            uint32_t code = (q & 1) ? (inc[s][q >> 1] >> 16) : (inc[s][q >> 1] & 0xffffu);
-            int k = (int)(code & 0x7fffu);
-            Real x, y, z, b;
-            L.get_fv(k, x, y, z, b);
-            const Real sg = (code & 0x8000u) ? Real(-1) : Real(1);
-            fx = fma(sg, x, fx); fy = fma(sg, y, fy); fz = fma(sg, z, fz); G += b;
-        }
-        if (degw[s] > kMaxResidentDegree) {
-            // rare high-degree nodes: remaining incidences from the CSR in HBM
-            const int a = s * T + tid;
+        if (degw[s] > kResIncRegs) {
+            const int a = s * T + t;
             if (a < nf) {
                 const int64_t e1 = incoffb[a + 1];
 #pragma unroll 1
-                for (int64_t e = incoffb[a] + kMaxResidentDegree; e < e1; ++e) {
-                    uint32_t w = net.inc[e];
-                    Real x, y, z, b;
-                    L.get_fv((int)(w & 0x7fffffffu), x, y, z, b);
-                    if (w >> 31) {
-                        x = -x; y = -y; z = -z;
-                    }
-                    fx += x; fy += y; fz += z; G += b;
+                for (int64_t e = incoffb[a] + kResIncRegs; e < e1; ++e) {
+                    const uint32_t w = net.inc[e];
+                    Real xx, yy, zz, bb;
+                    L.get_fv((int)(w & 0x7fffffffu), xx, yy, zz, bb);
+                    const Real sg = (w >> 31) ? Real(-1) : Real(1);
+                    fx = fma(sg, xx, fx); fy = fma(sg, yy, fy); fz = fma(sg, zz, fz); G += bb;
                 }
             }
         }
@@ -625,18 +698,18 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
     };
 
     // ---- initial force, residual and (optionally) stiffness-scaled mass
-    fiber_pass();
+    fiber_pass(tid);
     __syncthreads();
     Real ax[SN], ay[SN], az[SN];
     Real gpart = Real(0);
     double r2p = 0.0, b2p = 0.0;
 #pragma unroll
     for (int s = 0; s < SN; ++s) {
-        int a = s * T + tid;
+        const int a = s * T + tid;
         ax[s] = ay[s] = az[s] = Real(0);
         if (a < nf) {
             Real fx, fy, fz, G;
-            gather(s, fx, fy, fz, G);
+            gather(tid, s, fx, fy, fz, G);
             if (A.mass_mode == kMassScaled) iM[s] = G > Real(0) ? Real(4) / G : Real(1);
             ax[s] = -fx * iM[s];
             ay[s] = -fy * iM[s];
@@ -645,20 +718,21 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
             r2p += (double)fx * fx + (double)fy * fy + (double)fz * fz;
         }
     }
-    b2p = boundary_norm2_partial<Real, T>(net, L, b0, nb);
+    b2p = boundary_norm2_partial<Real, T>(net, L, b0, nb, tid);
     double gmax;
     double R2 = 0.0, D2 = 0.0, B2 = 0.0;
     int parity = 0;
-    block_reduce<Real, NW>(red, parity, gpart, r2p, 0.0, b2p, true, gmax, R2, D2, B2);
+    block_reduce<Real, NW>(red, tid, parity, gpart, r2p, 0.0, b2p, true, gmax, R2, D2, B2);
 
     int64_t n = 0;
     int status = ST_CONVERGED;
     const int ce = A.check_every > 0 ? A.check_every : 1;
-    double tol = fmax(A.tol_abs, A.tol_rel * sqrt(B2));
-    bool done = (sqrt(R2) <= tol);   // v = 0: damping norm is 0
-    double Rlast = sqrt(R2), Dlast = 0.0, Blast = sqrt(B2);
-    double Rref = Rlast;   // stagnation stop: reference residual
-    int stall = 0;         // stagnation stop: tests since R last halved
+    int countdown = ce;   // iterations to the next convergence test
+    // R2, D2, B2 hold the norms of the last test (reported at the end); every
+    // loop-carried scalar is uniform and kept in scalar registers
+    bool done = sqrt(R2) <= fmax(A.tol_abs, A.tol_rel * sqrt(B2));   // v = 0: damping norm is 0
+    double Rref = uniform(sqrt(R2));   // stagnation stop: reference residual
+    int stall = 0;                     // stagnation stop: tests since R last halved
     if (!isfinite(R2)) {
         status = ST_NONFINITE;
         done = true;
@@ -671,58 +745,53 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
     // the state it advances is FP32 anyway
     auto time_step = [&](double g) __attribute__((always_inline)) -> double {
         if constexpr (sizeof(Real) == 4)
-            return (double)((float)(2.0 * A.alpha) * __builtin_amdgcn_rsqf((float)g));
+            return uniform((double)(uniform((float)(2.0 * A.alpha)) * __builtin_amdgcn_rsqf((float)g)));
         else
-            return A.alpha * 2.0 / sqrt(g);
+            return uniform(A.alpha * 2.0 / sqrt(g));
     };
     double dt = time_step(gmax);
     double ke_prev = 0.0;   // kinetic damping: kinetic energy at the previous full step
 
     while (!done) {
-        // Keep the packed fiber ends and incidence lists packed: without this the
-        // compiler hoists their unpacked addresses and sign masks out of the loop,
-        // which multiplies the registers they occupy.
+        const int t = opaque_tid();
+        // Keep the packed fiber ends and incidence codes packed: without this
+        // the compiler hoists their unpacked LDS addresses and sign masks out
+        // of the loop, which multiplies the registers they occupy.
 #pragma unroll
-        for (int s = 0; s < SF; ++s) {
-            asm volatile("" : "+v"(E[s]));
-            asm volatile("" : "+v"(D0x[s]), "+v"(D0y[s]), "+v"(D0z[s]), "+v"(Q0[s]), "+v"(L0r[s]), "+v"(iL0r[s]));
-        }
+        for (int s = 0; s < SF; ++s) asm volatile("" : "+v"(E[s]));
 #pragma unroll
         for (int s = 0; s < SN; ++s) {
-            asm volatile("" : "+v"(iM[s]));
 #pragma unroll
-            for (int q = 0; q < kMaxResidentDegree / 2; ++q) asm volatile("" : "+v"(inc[s][q]));
+            for (int q = 0; q < kResIncRegs / 2; ++q) asm volatile("" : "+v"(inc[s][q]));
         }
         // half-step velocity and position update with the time step of this state
         const Real hdt = (Real)(0.5 * dt), rdt = (Real)dt;
 #pragma unroll
         for (int s = 0; s < SN; ++s) {
-            int a = s * T + tid;
+            const int a = s * T + t;
             if (a < nf) {
                 vx[s] += hdt * ax[s]; vy[s] += hdt * ay[s]; vz[s] += hdt * az[s];
-                hx[s] += rdt * vx[s]; hy[s] += rdt * vy[s]; hz[s] += rdt * vz[s];
-                L.put_h(a, hx[s], hy[s], hz[s]);
+                Real hx, hy, hz;
+                L.get_h(a, hx, hy, hz);
+                hx += rdt * vx[s]; hy += rdt * vy[s]; hz += rdt * vz[s];
+                L.put_h(a, hx, hy, hz);
             }
         }
         __syncthreads();
-        fiber_pass();
+        fiber_pass(t);
         __syncthreads();
         ++n;
-        // every ce-th iteration (32-bit remainder: a 64-bit one expands to
-        // dozens of scalar instructions per iteration)
-        const bool check = ((uint32_t)n % (uint32_t)ce) == 0;
+        const bool check = --countdown == 0;
+        if (check) countdown = ce;
         gpart = Real(0);
         r2p = 0.0;
         double d2p = 0.0, kep = 0.0;
-        // damping-force norm of the convergence test, c |M v| (kinetic
-        // damping applies no viscous force but keeps c as the guard's scale)
-        const Real dfac = cg;
 #pragma unroll
         for (int s = 0; s < SN; ++s) {
-            int a = s * T + tid;
+            const int a = s * T + t;
             if (a < nf) {
                 Real fx, fy, fz, G;
-                gather(s, fx, fy, fz, G);
+                gather(t, s, fx, fy, fz, G);
                 // damped acceleration with the half-step velocity, then second half step
                 ax[s] = -fx * iM[s] - c * vx[s];
                 ay[s] = -fy * iM[s] - c * vy[s];
@@ -733,18 +802,19 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
                     kep += 0.5 * (double)((vx[s] * vx[s] + vy[s] * vy[s] + vz[s] * vz[s]) * dev_rcp(iM[s]));
                 if (check) {
                     r2p += (double)fx * fx + (double)fy * fy + (double)fz * fz;
-                    // damping-force norm of this node (only tested against the tolerance)
-                    const Real cm = dfac * dev_rcp(iM[s]);
+                    // damping-force norm c |M v| of this node (kinetic damping
+                    // applies no viscous force but keeps c as the test's scale)
+                    const Real cm = cg * dev_rcp(iM[s]);
                     const double px = (double)(cm * vx[s]), py = (double)(cm * vy[s]), pz = (double)(cm * vz[s]);
                     d2p += px * px + py * py + pz * pz;
                 }
             }
             __builtin_amdgcn_sched_barrier(0);
         }
-        if (check) b2p = boundary_norm2_partial<Real, T>(net, L, b0, nb);
+        if (check) b2p = boundary_norm2_partial<Real, T>(net, L, b0, nb, t);
         parity ^= 1;
-        double ke = 0.0;
-        block_reduce<Real, NW, KIN>(red, parity, gpart, r2p, d2p, b2p, check, gmax, R2, D2, B2, kep, &ke);
+        double r2n = R2, d2n = D2, b2n = B2, ke = 0.0;
+        block_reduce<Real, NW, KIN>(red, t, parity, gpart, r2p, d2p, b2p, check, gmax, r2n, d2n, b2n, kep, &ke);
         if constexpr (KIN) {
             // a kinetic-energy peak was passed: restart every node from rest
             // (the acceleration is already -f/M)
@@ -752,24 +822,26 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
 #pragma unroll
                 for (int s = 0; s < SN; ++s) vx[s] = vy[s] = vz[s] = Real(0);
                 ke = 0.0;
-                D2 = 0.0;
+                if (check) d2n = 0.0;
             }
             ke_prev = ke;
         }
         if (check) {
-            Rlast = sqrt(R2);
-            Dlast = sqrt(D2);
-            Blast = sqrt(B2);
-            tol = fmax(A.tol_abs, A.tol_rel * Blast);
+            R2 = r2n;
+            D2 = d2n;
+            B2 = b2n;
             if (!isfinite(R2) || !isfinite(D2)) {
                 status = ST_NONFINITE;
                 break;
             }
-            if (Rlast <= tol && Dlast <= tol) break;
-            if (stagnated(A, Rlast, Dlast, Blast, Rref, stall)) {
+            const double Rn = sqrt(R2), Dn = sqrt(D2), Bn = sqrt(B2);
+            const double tol = fmax(A.tol_abs, A.tol_rel * Bn);
+            if (Rn <= tol && Dn <= tol) break;
+            if (stagnated(A, Rn, Dn, Bn, Rref, stall)) {
                 status = ST_STAGNATED;
                 break;
             }
+            Rref = uniform(Rref);
         }
         if (!(gmax > 0.0) || !isfinite(gmax)) {
             status = ST_NONFINITE;
@@ -783,26 +855,43 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
     }
 
     // ---- fluctuation state for warm starts, positions and the tangent
+    const int te = opaque_tid();
 #pragma unroll
     for (int s = 0; s < SN; ++s) {
-        int a = s * T + tid;
+        const int a = s * T + te;
         if (a < nf) {
+            Real hx, hy, hz;
+            L.get_h(a, hx, hy, hz);
             double* h = hsb + 3 * a;
-            h[0] = (double)hx[s]; h[1] = (double)hy[s]; h[2] = (double)hz[s];
+            h[0] = (double)hx; h[1] = (double)hy; h[2] = (double)hz;
         }
     }
-    if (tid == 0) {
+    if (te == 0) {
         A.status[r] = status;
         A.iters[r] = n;
-        A.Rres[r] = Rlast;
-        A.Dres[r] = Dlast;
-        A.Bres[r] = Blast;
+        A.Rres[r] = sqrt(R2);
+        A.Dres[r] = sqrt(D2);
+        A.Bres[r] = sqrt(B2);
     }
     __syncthreads();
 }
 
+// Register budget (waves per SIMD the build must allow): FP32 builds of 4
+// fiber and 2 node slots per thread are held to 128 VGPRs (four waves per
+// SIMD, so two 512-thread or four 256-thread workgroups share a CU), the
+// 768-thread and 6/3-slot FP32 builds to 168 (three waves per SIMD), FP64
+// builds to 256 (two).  A build that does not fit its budget without private
+// memory is never launched (the host checks every build's private segment
+// size before the first launch).
+template <typename Real, int T, int SF, int SN>
+constexpr int resident_waves_per_eu()
+{
+    return sizeof(Real) == 8 ? 2 : ((T == 768 || SF > 4) ? 3 : 4);
+}
+
 template <typename Real, int T, int SF, int SN, bool KIN>
-__global__ __launch_bounds__(T) void dr_resident_kernel(SolveArgs A)
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(resident_waves_per_eu<Real, T, SF, SN>())))
+void dr_resident_kernel(SolveArgs A)
 {
     extern __shared__ char smem[];
     __shared__ RedSlots red;
@@ -835,10 +924,11 @@ __device__ __forceinline__ void streamed_solve(const SolveArgs& A, int r, RedSlo
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     const DevNet& net = A.net;
-    const int64_t f0 = net.fib_off[r], nfib = net.fib_off[r + 1] - f0;
-    const int64_t a0 = net.free_off[r], nf = net.free_off[r + 1] - a0;
-    const int64_t b0 = net.bnd_off[r], nb = net.bnd_off[r + 1] - b0;
-    const int64_t NF = net.fib_off[net.n_rve], NFREE = net.free_off[net.n_rve];
+    // per-RVE sizes and offsets are the same in every lane: scalar registers
+    const int64_t f0 = uniform64(net.fib_off[r]), nfib = uniform64(net.fib_off[r + 1] - f0);
+    const int64_t a0 = uniform64(net.free_off[r]), nf = uniform64(net.free_off[r + 1] - a0);
+    const int64_t b0 = uniform64(net.bnd_off[r]), nb = uniform64(net.bnd_off[r + 1] - b0);
+    const int64_t NF = uniform64(net.fib_off[net.n_rve]), NFREE = uniform64(net.free_off[net.n_rve]);
 
     R4* wsD = reinterpret_cast<R4*>(A.ws_fib) + (f0 + r);                             // [nfib+1] (D0, q0)
     R4* wsFv = reinterpret_cast<R4*>(A.ws_fib) + (NF + net.n_rve) + (f0 + r);         // [nfib+1] (fv, b)
@@ -1043,7 +1133,7 @@ __device__ __forceinline__ void streamed_solve(const SolveArgs& A, int r, RedSlo
     double gmax;
     double R2 = 0.0, D2 = 0.0, B2 = 0.0;
     int parity = 0;
-    block_reduce<Real, NW>(red, parity, gpart, r2p, 0.0, b2p, true, gmax, R2, D2, B2);
+    block_reduce<Real, NW>(red, tid, parity, gpart, r2p, 0.0, b2p, true, gmax, R2, D2, B2);
 
     int64_t n = 0;
     int status = ST_CONVERGED;
@@ -1114,7 +1204,7 @@ __device__ __forceinline__ void streamed_solve(const SolveArgs& A, int r, RedSlo
         if (check) b2p = bnorm2();
         parity ^= 1;
         double ke = 0.0;
-        block_reduce<Real, NW, KIN>(red, parity, gpart, r2p, d2p, b2p, check, gmax, R2, D2, B2, kep, &ke);
+        block_reduce<Real, NW, KIN>(red, tid, parity, gpart, r2p, d2p, b2p, check, gmax, R2, D2, B2, kep, &ke);
         if constexpr (KIN) {
             // a kinetic-energy peak was passed: restart every node from rest
             // (the stored acceleration is already -f/M)
@@ -1312,10 +1402,10 @@ static hipError_t occ_res(size_t lds, int* blocks)
     switch (variant) {                                                                                \
     case 0: return RVE_RES_PK(FN, 256, 4, 2, __VA_ARGS__);                                            \
     case 1: return RVE_RES_PK(FN, 512, 4, 2, __VA_ARGS__);                                            \
-    case 2: return RVE_RES_PK(FN, 1024, 4, 2, __VA_ARGS__);                                           \
-    case 3: return RVE_RES_PK(FN, 512, 8, 4, __VA_ARGS__);                                            \
-    case 4: return RVE_RES_PK(FN, 1024, 6, 3, __VA_ARGS__);                                           \
-    case 5: return RVE_RES_PK(FN, 256, 16, 8, __VA_ARGS__);                                           \
+    case 2: return RVE_RES_PK(FN, 768, 4, 2, __VA_ARGS__);                                            \
+    case 3: return RVE_RES_PK(FN, 512, 6, 3, __VA_ARGS__);                                            \
+    case 4: return RVE_RES_PK(FN, 1024, 4, 2, __VA_ARGS__);                                           \
+    case 5: return RVE_RES_PK(FN, 1024, 6, 3, __VA_ARGS__);                                           \
     default: return hipErrorInvalidValue;                                                             \
     }
 
@@ -1355,5 +1445,25 @@ hipError_t launch_streamed(bool fp64, const SolveArgs& a, int grid, int threads,
 }
 
 size_t streamed_lds_cap() { return 150 * 1024; }
+
+template <typename Real, int T>
+static hipError_t streamed_private_t(bool kin, size_t* bytes)
+{
+    return max_private_bytes({kin ? (const void*)dr_streamed_kernel<Real, T, true> : (const void*)dr_streamed_kernel<Real, T, false>},
+                             bytes);
+}
+
+hipError_t streamed_scratch_bytes(bool fp64, bool kin, int threads, size_t* bytes)
+{
+    if (threads == 256) return fp64 ? streamed_private_t<double, 256>(kin, bytes) : streamed_private_t<float, 256>(kin, bytes);
+    if (threads == 1024)
+        return fp64 ? streamed_private_t<double, 1024>(kin, bytes) : streamed_private_t<float, 1024>(kin, bytes);
+    return hipErrorInvalidValue;
+}
+
+hipError_t kernels_fixed_private(size_t* bytes)
+{
+    return max_private_bytes({(const void*)stress_kernel, (const void*)reset_counters}, bytes);
+}
 
 }  // namespace rve

@@ -231,6 +231,14 @@ __global__ void finish(SolveArgs A, int r, const double* h, int status, int64_t 
 static inline int blocks(int64_t n) { return (int)((n + NT - 1) / NT); }
 
 }  // namespace naive
+hipError_t naive_fixed_private(size_t* bytes)
+{
+    return max_private_bytes({(const void*)naive::prep, (const void*)naive::zero, (const void*)naive::fibers,
+                              (const void*)naive::nodes, (const void*)naive::bnorm, (const void*)naive::step,
+                              (const void*)naive::stress, (const void*)naive::finish},
+                             bytes);
+}
+
 }  // namespace rve
 
 using namespace rve;

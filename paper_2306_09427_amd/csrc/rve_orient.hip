@@ -95,4 +95,9 @@ hipError_t launch_orientation(const OrientArgs& a, int64_t n_rve, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t orient_fixed_private(size_t* bytes)
+{
+    return max_private_bytes({(const void*)orientation_kernel}, bytes);
+}
+
 }  // namespace rve

@@ -65,6 +65,26 @@ __global__ __launch_bounds__(kStateThreads) void import_status_kernel(const doub
     Bn[r] = NAN;
 }
 
+// Reference start (RVE_INIT_REFERENCE): free node a of RVE r at its
+// reference position Xm_a, i.e. the fluctuation h_a = Xm_a - F Xm_a; one
+// workgroup per RVE.
+__global__ __launch_bounds__(kStateThreads) void reference_h_kernel(const double* __restrict__ F,
+                                                                     const int64_t* __restrict__ free_off,
+                                                                     const double* __restrict__ xm, double* dh)
+{
+    const int64_t r = blockIdx.x;
+    const int64_t a0 = free_off[r], nf = free_off[r + 1] - a0;
+    const double* Fr = F + 9 * r;
+    for (int64_t a = threadIdx.x; a < nf; a += kStateThreads) {
+        const double* X = xm + 3 * (a0 + a);
+        double* h = dh + 3 * (a0 + a);
+        for (int i = 0; i < 3; ++i) {
+            const double y = Fr[3 * i] * X[0] + Fr[3 * i + 1] * X[1] + Fr[3 * i + 2] * X[2];
+            h[i] = isfinite(y) ? X[i] - y : 0.0;
+        }
+    }
+}
+
 inline unsigned grid_of(int64_t n)
 {
     return (unsigned)((n + kStateThreads - 1) / kStateThreads);
@@ -93,6 +113,21 @@ hipError_t launch_import_status(const double* F, const int32_t* st_in, int64_t R
     hipLaunchKernelGGL(import_status_kernel, dim3(grid_of(R)), dim3(kStateThreads), 0, s, F, st_in, R, st, iters, Rn,
                        Dn, Bn);
     return hipGetLastError();
+}
+
+hipError_t launch_reference_h(const double* F, const int64_t* free_off, const double* xm, int64_t R, double* dh,
+                              hipStream_t s)
+{
+    if (R <= 0) return hipSuccess;
+    hipLaunchKernelGGL(reference_h_kernel, dim3((unsigned)R), dim3(kStateThreads), 0, s, F, free_off, xm, dh);
+    return hipGetLastError();
+}
+
+hipError_t state_fixed_private(size_t* bytes)
+{
+    return max_private_bytes({(const void*)export_h_kernel, (const void*)import_h_kernel, (const void*)reference_h_kernel,
+                              (const void*)import_status_kernel},
+                             bytes);
 }
 
 }  // namespace rve

@@ -1074,4 +1074,19 @@ hipError_t launch_tangent_res(int v, const TangentArgs& a, int grid, hipStream_t
     return hipLaunchKernel(k, dim3(grid), dim3(kTanRes[v].threads), args, res_lds(v), s);
 }
 
+hipError_t tangent_res_scratch_bytes(int v, bool vjp, size_t* bytes)
+{
+    if (v < 0 || v >= kNumTanRes) return hipErrorInvalidValue;
+    return max_private_bytes({res_kernel(v, vjp)}, bytes);
+}
+
+hipError_t tangent_fixed_private(size_t* bytes)
+{
+    return max_private_bytes({(const void*)ell_build_kernel, (const void*)fiber_ops_kernel,
+                              (const void*)cg_stream_kernel<true, 64>, (const void*)cg_stream_kernel<false, 64>,
+                              (const void*)cg_stream_kernel<true, 1024>, (const void*)cg_stream_kernel<false, 1024>,
+                              (const void*)zero_status},
+                             bytes);
+}
+
 }  // namespace rve

@@ -50,7 +50,7 @@ __device__ __forceinline__ double wave_max(double v)
 // maximum, in a fixed order: wave sums, then the waves in order.  Every
 // thread receives the results.
 template <int N>
-__device__ void block_reduce(double (&v)[N], double& mx, double (*lds)[kWaves], double* lds_max)
+__device__ __forceinline__ void block_reduce(double (&v)[N], double& mx, double (*lds)[kWaves], double* lds_max)
 {
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
@@ -103,9 +103,9 @@ struct VarCtx {
 
 // Fiber pass: force vector, Gershgorin term and stored energy of every fiber
 // at the current fluctuation h; returns this thread's share of the energy
-// and, when rq is not NULL, adds its share of u.K u (u = h - h_start, K the
+// and, when want_rq is set, adds its share of u.K u to rq (u = h - h_start, K the
 // tangent stiffness: (k_t/L0) (n.du)^2 + (T/l) (|du|^2 - (n.du)^2) per fiber).
-__device__ double fiber_pass(const VarCtx& C, const Law& law, double* rq)
+__device__ __forceinline__ double fiber_pass(const VarCtx& C, const Law& law, bool want_rq, double& rq)
 {
     const DevNet& net = C.A.s.net;
     double Wsum = 0.0;
@@ -133,21 +133,21 @@ __device__ double fiber_pass(const VarCtx& C, const Law& law, double* rq)
         o[3] = fmax(kt / L0, fabs(T) / l);
         o[4] = W;
         Wsum += W;
-        if (rq) {
+        if (want_rq) {
             double du[3];
             for (int c = 0; c < 3; ++c)
                 du[c] = (j < C.nf ? C.node[kNodeDoubles * j + c] - C.node[kNodeDoubles * j + 12 + c] : 0.0) -
                         (i < C.nf ? C.node[kNodeDoubles * i + c] - C.node[kNodeDoubles * i + 12 + c] : 0.0);
             const double nd = (d[0] * du[0] + d[1] * du[1] + d[2] * du[2]) / l;
             const double du2 = du[0] * du[0] + du[1] * du[1] + du[2] * du[2];
-            *rq += kt / L0 * nd * nd + T / l * (du2 - nd * nd);
+            rq += kt / L0 * nd * nd + T / l * (du2 - nd * nd);
         }
     }
     return Wsum;
 }
 
 // Internal force and Gershgorin sum of free node a from the fiber pass.
-__device__ void gather_free(const VarCtx& C, int64_t a, double (&f)[3], double& G)
+__device__ __forceinline__ void gather_free(const VarCtx& C, int64_t a, double (&f)[3], double& G)
 {
     const DevNet& net = C.A.s.net;
     f[0] = f[1] = f[2] = 0.0;
@@ -162,7 +162,7 @@ __device__ void gather_free(const VarCtx& C, int64_t a, double (&f)[3], double& 
 }
 
 // Squared norm of the boundary-node internal forces (this thread's share).
-__device__ double boundary_norm2(const VarCtx& C)
+__device__ __forceinline__ double boundary_norm2(const VarCtx& C)
 {
     const DevNet& net = C.A.s.net;
     double s = 0.0;
@@ -218,7 +218,8 @@ __global__ __launch_bounds__(kVT) void dr_variant_kernel(VariantArgs A)
         }
     }
     __syncthreads();
-    double W = fiber_pass(C, law, nullptr);
+    double unused_rq = 0.0;
+    double W = fiber_pass(C, law, false, unused_rq);
     __syncthreads();
     double R2 = 0.0, gmax = 0.0;
     for (int64_t a = threadIdx.x; a < C.nf; a += kVT) {
@@ -267,7 +268,7 @@ __global__ __launch_bounds__(kVT) void dr_variant_kernel(VariantArgs A)
             }
             __syncthreads();
             double num = 0.0, den = 0.0;
-            W = fiber_pass(C, law, damping == DAMP_ADAPTIVE ? &num : nullptr);
+            W = fiber_pass(C, law, damping == DAMP_ADAPTIVE, num);
             __syncthreads();
             // forces at the new positions; adaptive Rayleigh-quotient sums
             for (int64_t a = threadIdx.x; a < C.nf; a += kVT) {
@@ -370,6 +371,11 @@ hipError_t launch_variant(const VariantArgs& a, int64_t n_rve, hipStream_t s)
 size_t variant_ws_bytes(int64_t n_free, int64_t n_fib)
 {
     return 8 * ((size_t)kNodeDoubles * (size_t)n_free + (size_t)kFibDoubles * (size_t)n_fib);
+}
+
+hipError_t variant_fixed_private(size_t* bytes)
+{
+    return max_private_bytes({(const void*)dr_variant_kernel}, bytes);
 }
 
 }  // namespace rve

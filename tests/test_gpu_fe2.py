@@ -61,8 +61,11 @@ def test_fe2_small_mesh_matches_oracle_and_warm_starts_pay(rb):
     log(f"  oracle statuses {np.bincount(ref['status'], minlength=4).tolist()}, GPU "
         f"{np.bincount(drv.status, minlength=4).tolist()}; sigma rel err on {both.sum()} jointly converged: "
         f"median {np.median(err[both]):.2e}, within 1e-5 {np.mean(err[both] <= 1e-5):.3f}")
+    # every Gauss point the oracle relaxes converges on the GPU too, and every
+    # jointly converged one is within the FP64 tolerance (no allowance)
+    assert np.all(drv.status[ref["status"] == 0] == 0)
     assert both.sum() >= 0.75 * mesh.n_gp
-    assert np.mean(err[both] <= 1e-5) >= 0.9 and np.median(err[both]) <= 1e-6
+    assert np.all(err[both] <= 1e-5), np.sort(err[both])[-3:]
     P, _ = fe2.first_pk(drv.F, ref["sigma"])
     r = mesh.internal_force(P).ravel()
     dofs, _ = mesh.boundary_dofs(drv.lam, "affine")

@@ -4,10 +4,16 @@ The references in tests/golden/*.npz were written by
 tests/golden/make_golden.py, which calls only the input generator and the
 FP64 CPU oracle.  The GPU runs the same networks, F and options:
 
-* FP64 engines: status agreement >= 90% and sigma relative error <= 1e-5 on
-  RVEs converged on both sides.
-* Mixed precision (tol_rel 1e-5, the FP32 residual floor): >= 90% of the
-  jointly converged RVEs within 1e-4 of the FP64 oracle.
+* FP64 engines: the oracle's status for every RVE (except RVEs within 2% of
+  the iteration cap, where rounding decides the side of n_max) and, on
+  every RVE converged on both sides, sigma within 1e-5 of the oracle or a
+  different equilibrium verified with the oracle's arithmetic (the GPU
+  state is an equilibrium of the same network and its stress is the GPU's
+  sigma; tests/gpu_common.grade_parity).
+* Mixed precision (tol_rel 1e-5, the FP32 residual floor): every RVE the
+  oracle converged converges (same exemption), and every jointly converged
+  RVE is within 1e-4 of the FP64 oracle or a verified different
+  equilibrium.
 
 Sizes: 64 RVEs of the 4096-RVE workload (200-400 seeds), 4 of the 512
 large RVEs (2000 seeds, streamed kernel), 16 of the 8192-RVE FE^2 workload
@@ -20,7 +26,8 @@ import numpy as np
 import pytest
 
 from paper_2306_09427_amd import synth
-from tests.gpu_common import log, rel_err, require_gpu
+import oracle
+from tests.gpu_common import grade_parity, log, rel_err, require_gpu
 
 pytestmark = pytest.mark.gpu
 HERE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
@@ -48,17 +55,20 @@ def test_fullshape_parity(name, precision):
     log(f"  groups {b.describe()}")
     sig, st, stats = b.solve(F, stats=True)
     ref_st = g["status"]
-    both = (st == 0) & (ref_st == 0)
-    err = rel_err(sig[both], g["sigma"][both])
+    near_cap = stats["iters"] >= 0.98 * o["n_max"]
+    miss = (st != ref_st) if precision == 0 else ((ref_st == 0) & (st != 0))
     log(f"  status gpu {np.bincount(st, minlength=4).tolist()} oracle {np.bincount(ref_st, minlength=4).tolist()} "
-        f"both {both.sum()} max err {err.max() if both.any() else 0:.2e}")
-    assert both.sum() >= max(1, int(0.5 * (ref_st == 0).sum()))
+        f"mismatches {int(miss.sum())} (near the cap {int((miss & near_cap).sum())})")
+    assert not np.any(miss & ~near_cap), np.where(miss & ~near_cap)[0]
+    oo = oracle.make_opts(law=oracle.EXP, mass=o["mass"], alpha=o["alpha"], tol_abs=0.0, tol_rel=o["tol_rel"],
+                          n_max=o["n_max"])
+    grade = grade_parity(b, batch, F, sig, st, g["sigma"], ref_st, 1e-5 if precision == 0 else 1e-4, oo,
+                         f"{name} precision {precision}", residual_rel=1e-7 if precision == 0 else 1e-4)
+    assert grade["both"] >= 1
     if precision == 0:
-        assert np.mean(st == ref_st) >= 0.9
-        assert np.mean(err <= 1e-5) >= 0.9, np.sort(err)[-5:]
         # converged FP64 RVEs take the oracle's iteration count up to rounding
+        both = (st == 0) & (ref_st == 0)
         it_diff = np.abs(stats["iters"][both] - g["iters"][both]) / np.maximum(g["iters"][both], 1)
+        log(f"  iteration count relative difference: median {np.median(it_diff):.1e} max {it_diff.max():.1e}")
         assert np.median(it_diff) <= 0.01
-    else:
-        assert np.mean(err <= 1e-4) >= 0.9, np.sort(err)[-5:]
     b.close()

@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 from paper_2306_09427_amd import synth
-from tests.gpu_common import log, rel_err, require_gpu
+from tests.gpu_common import grade_parity, log, rel_err, require_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -129,20 +129,32 @@ def cfg2_subset():
     return batch, F, ref
 
 
+def _status_agreement(st, ref, gpu_iters, n_max, label, superset=False):
+    """FP64: statuses equal; mixed (superset): every RVE the oracle converged
+    also converges on the GPU.  Exempt are RVEs within 2% of the iteration
+    cap on the GPU (rounding decides which side of n_max they stop on)."""
+    near_cap = np.asarray(gpu_iters) >= 0.98 * n_max
+    miss = (ref["status"] == 0) & (st != 0) if superset else (st != ref["status"])
+    log(f"  [{label}] status gpu {np.bincount(st, minlength=4).tolist()} oracle "
+        f"{np.bincount(ref['status'], minlength=4).tolist()}; mismatches {int(miss.sum())} "
+        f"(near the cap {int((miss & near_cap).sum())})")
+    assert not np.any(miss & ~near_cap), np.where(miss & ~near_cap)[0]
+
+
 @pytest.mark.parametrize("engine", ["resident", "streamed"])
 def test_config2_fp64_matches_oracle(rb, cfg2_subset, engine):
     batch, F, ref = cfg2_subset
     log(f"config2 fp64 engine={engine}")
     eng = rb.ENGINE_AUTO if engine == "resident" else rb.ENGINE_STREAMED
     b = rb.Batch(batch, precision=rb.FP64, law=rb.LAW_EXP, tol_abs=0.0, tol_rel=1e-8, engine=eng, **CFG2)
+    log(f"  groups {b.describe()}")
     sig, st, stats = b.solve(F, stats=True)
-    both = (st == 0) & (ref["status"] == 0)
-    log(f"  gpu statuses {np.bincount(st, minlength=4).tolist()} agree={np.mean(st == ref['status']):.2f}")
-    err = rel_err(sig[both], ref["sigma"][both])
-    log(f"  converged on both: {both.sum()}  max rel err {err.max() if both.any() else 0:.2e}")
-    assert both.sum() >= 8
-    assert np.mean(st == ref["status"]) >= 0.9
-    assert np.all(err <= 1e-5), err
+    _status_agreement(st, ref, stats["iters"], CFG2["n_max"], "fp64 " + engine)
+    o = _oracle_opts(oracle.EXP, alpha=CFG2["alpha"], tol_abs=0.0, tol_rel=1e-8, n_max=CFG2["n_max"])
+    xs = np.split(ref["x"], batch.node_off[1:-1])
+    g = grade_parity(b, batch, F, sig, st, ref["sigma"], ref["status"], 1e-5, o, "fp64 " + engine, ref_x=xs,
+                     residual_rel=1e-7)
+    assert g["both"] >= 8
     b.close()
 
 
@@ -152,12 +164,14 @@ def test_config2_mixed_matches_oracle(rb, cfg2_subset):
     # FP32 positions and forces put the residual floor near 1e-5 |f_bnd| on these
     # networks (short stiff fibers), so mixed precision stops at tol_rel = 1e-5
     b = rb.Batch(batch, precision=rb.MIXED, law=rb.LAW_EXP, tol_abs=0.0, tol_rel=1e-5, **CFG2)
+    log(f"  groups {b.describe()}")
     sig, st, stats = b.solve(F, stats=True)
-    both = (st == 0) & (ref["status"] == 0)
-    err = rel_err(sig[both], ref["sigma"][both])
-    log(f"  gpu statuses {np.bincount(st, minlength=4).tolist()}; both {both.sum()} errs {np.round(np.log10(err + 1e-300), 1).tolist()}")
-    assert both.sum() >= 8
-    assert np.mean(err <= 1e-4) >= 0.9
+    _status_agreement(st, ref, stats["iters"], CFG2["n_max"], "mixed", superset=True)
+    o = _oracle_opts(oracle.EXP, alpha=CFG2["alpha"], tol_abs=0.0, tol_rel=1e-8, n_max=CFG2["n_max"])
+    xs = np.split(ref["x"], batch.node_off[1:-1])
+    g = grade_parity(b, batch, F, sig, st, ref["sigma"], ref["status"], 1e-4, o, "mixed", ref_x=xs,
+                     residual_rel=1e-4)
+    assert g["both"] >= 8
     b.close()
 
 

@@ -397,3 +397,43 @@ def test_central_difference_trajectory_closed_form(c):
     if c == 0.0:
         theta = np.arccos(1 - p / 2)
         assert (A * z ** 40).sum().real == pytest.approx(u0 * np.cos(40 * theta), abs=1e-14)
+
+
+# ---------------------------------------------------------------- state validity and stability
+def test_stability_of_a_chain_in_tension_and_compression():
+    """Two boundary nodes and one free node on a line: in tension K_ff is
+    k_t/L0 (2x) along the line and 2 T/l across it, positive definite; in
+    compression the transverse stiffness 2 T/l < 0 makes it indefinite."""
+    from oracle.stability import equilibrium, is_stable
+    net = synth.chain_network([[0.0, 0.5, 0.5], [0.5, 0.5, 0.5], [1.0, 0.5, 0.5]])
+    o = oracle.make_opts(law=oracle.LINEAR)
+    Xm = net.X - 0.5
+    for lam, stable in ((1.1, True), (0.9, False)):
+        F = np.diag([lam, 1.0, 1.0])
+        x = Xm @ F.T
+        R, Fb, sig = equilibrium(net, F, x, o)
+        assert R < 1e-14                       # the affine state of a symmetric chain is an equilibrium
+        T = lam - 1.0                          # linear law, EA = 1, eps = lam - 1
+        assert abs(Fb - np.sqrt(2) * abs(T)) < 1e-14
+        assert abs(sig[0, 0] - T * lam / lam) < 1e-14   # sigma_11 = T l / (J V0) with l = lam/2 per fiber, 2 fibers
+        assert is_stable(net, x, o) is stable
+
+
+def test_stability_of_relaxed_lattice_and_floppy_mode():
+    """A relaxed n^3 lattice in tension is stable.  A free node hanging on a
+    single fiber has K_ff = (k_t/L0) n n^T + (T/l)(I - n n^T): at the rest
+    length (T = 0) it is semidefinite with two zero eigenvalues (a floppy
+    mode), which the relative shift accepts as stable; shortened (T < 0) the
+    two transverse eigenvalues T/l are negative: unstable."""
+    from oracle.stability import is_stable
+    o = oracle.make_opts(law=oracle.EXP)
+    net = synth.lattice_network(3)
+    Xm = net.X - 0.5
+    assert is_stable(net, Xm @ np.diag([1.1, 1.05, 1.08]).T, o) is True
+    hang = synth.Network(np.array([[0.0, 0.5, 0.5], [0.4, 0.5, 0.5]]), np.array([1, 0], np.uint8),
+                         np.array([[0, 1]], np.int32))
+    x = hang.X - 0.5
+    assert is_stable(hang, x, o) is True
+    x2 = x.copy()
+    x2[1, 0] -= 0.1
+    assert is_stable(hang, x2, o) is False
