@@ -106,6 +106,8 @@ def lib():
         L.rve_batch_bind_workspace.argtypes = [P, P, C.c_size_t]
         L.rve_batch_damping_stats.argtypes = [P, P, P, C.c_int32]
         L.rve_batch_generation.argtypes = [P, C.POINTER(C.c_uint64)]
+        if hasattr(L, "rve_batch_solve_static"):
+            L.rve_batch_solve_static.argtypes = [P, P, P, P, C.c_int32]
         L.rve_check_indexing.argtypes = [C.POINTER(NetDesc), C.c_int32, C.c_int32]
         L.rve_batch_destroy.argtypes = [P]
         L.rve_batch_destroy.restype = None
@@ -253,6 +255,23 @@ class Batch:
             S = Stats(_ptr(out["iters"])[0], _ptr(out["R"])[0], _ptr(out["D"])[0], _ptr(out["Fb"])[0])
         _check(lib().rve_batch_solve(self._h, fp, _ptr(sig)[0], _ptr(st)[0], C.byref(S) if S else None, kind))
         return (sig, st, out) if stats else (sig, st)
+
+    def solve_static(self, F):
+        """rve_batch_solve_static: the solve with its work areas in the
+        library's fixed device scratch array (no device allocation); returns
+        sigma[R,3,3], status[R]."""
+        if hasattr(F, "data_ptr"):
+            F = F.contiguous()
+            if F.is_cuda:
+                import torch
+                self.set_stream(C.c_void_p(torch.cuda.current_stream(F.device).cuda_stream))
+        else:
+            F = np.ascontiguousarray(F, np.float64).reshape(self.n_rve, 3, 3)
+        sig = self._outs(F, (3, 3), np.float64)
+        st = self._outs(F, (), np.int32)
+        fp, kind = _ptr(F)
+        _check(lib().rve_batch_solve_static(self._h, fp, _ptr(sig)[0], _ptr(st)[0], kind))
+        return sig, st
 
     def tangent(self, like=None):
         """dsigma/dF [R,9,9] at the last solve's state, and status [R]."""

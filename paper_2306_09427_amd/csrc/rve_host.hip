@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -965,6 +966,54 @@ int rve_batch_sizes(const rve_batch* b, int64_t* n_rve, int64_t* n_nodes, int64_
 }
 
 
+// The relaxation launches of a solve on the resident and streamed engines:
+// one persistent launch per kernel group (work counters queues[2 g]), then
+// the stress kernel; with `profile`, HIP events around each launch.
+static int launch_groups(rve_batch* b, SolveArgs& a, int32_t* queues, void* ws_fib, void* ws_node, hipStream_t s,
+                         bool profile)
+{
+    const bool fp64 = b->opts.precision == RVE_FP64;
+    a.ws_fib = ws_fib;
+    a.ws_node = ws_node;
+    b->ev_used = 0;
+    if (profile) {
+        int rc = ensure_events(b, 2 * (int)b->groups.size() + 2);
+        if (rc) return rc;
+    }
+    HIP_TRY(launch_reset(queues, 2 * (int)b->groups.size(), s));
+    for (size_t g = 0; g < b->groups.size(); ++g) {
+        a.list = b->dlist + b->group_first[g];
+        a.n_list = (int32_t)b->groups[g].size();
+        a.queue = queues + 2 * g;
+        const int v = b->group_variant[g];
+        if (profile) HIP_TRY(hipEventRecord(b->ev[2 * g], s));
+        if (v >= 0) {
+            int per_cu = 1;
+            HIP_TRY(max_resident_blocks(v, fp64, a.kinetic != 0, b->group_lds[g], &per_cu));
+            if (per_cu < 1) return fail(RVE_EDEVICE, "resident kernel variant does not fit a CU");
+            int grid = std::min<int64_t>((int64_t)per_cu * b->n_cu, a.n_list);
+            HIP_TRY(launch_resident(v, fp64, a, b->group_lds[g], grid, s));
+        } else {
+            int threads = streamed_threads(b, fp64);
+            if (!threads) return fail(RVE_EDEVICE, "internal: every streamed kernel build uses private memory");
+            a.lds_h_nodes = streamed_lds_nodes(b, b->groups[g].data(), b->groups[g].size(), fp64);
+            int grid = std::min<int64_t>((int64_t)b->n_cu * streamed_blocks_per_cu(threads, a.lds_h_nodes, fp64),
+                                         a.n_list);
+            HIP_TRY(launch_streamed(fp64, a, grid, threads, s));
+            a.lds_h_nodes = 0;
+        }
+        if (profile) HIP_TRY(hipEventRecord(b->ev[2 * g + 1], s));
+    }
+    const size_t gs = b->groups.size();
+    if (profile) HIP_TRY(hipEventRecord(b->ev[2 * gs], s));
+    HIP_TRY(launch_stress(a, (int)b->R, s));
+    if (profile) {
+        HIP_TRY(hipEventRecord(b->ev[2 * gs + 1], s));
+        b->ev_used = 2 * (int)gs + 2;
+    }
+    return RVE_OK;
+}
+
 int rve_batch_solve(rve_batch* b, const double* F, double* sigma, int32_t* status, rve_stats* stats,
                     int32_t ptr_kind)
 {
@@ -1075,43 +1124,8 @@ int rve_batch_solve(rve_batch* b, const double* F, double* sigma, int32_t* statu
         rc = rve_naive_run(a, b->fib_off, b->free_off, b->bnd_off, Fh, b->c_host, s, &err);
         if (rc) return fail(rc, err);
     } else {
-        const bool fp64 = b->opts.precision == RVE_FP64;
-        b->ev_used = 0;
-        if (b->profile) {
-            rc = ensure_events(b, 2 * (int)b->groups.size() + 2);
-            if (rc) return rc;
-        }
-        HIP_TRY(launch_reset(b->dqueue, 2 * (int)b->groups.size(), s));
-        for (size_t g = 0; g < b->groups.size(); ++g) {
-            a.list = b->dlist + b->group_first[g];
-            a.n_list = (int32_t)b->groups[g].size();
-            a.queue = b->dqueue + 2 * g;
-            const int v = b->group_variant[g];
-            if (b->profile) HIP_TRY(hipEventRecord(b->ev[2 * g], s));
-            if (v >= 0) {
-                int per_cu = 1;
-                HIP_TRY(max_resident_blocks(v, fp64, a.kinetic != 0, b->group_lds[g], &per_cu));
-                if (per_cu < 1) return fail(RVE_EDEVICE, "resident kernel variant does not fit a CU");
-                int grid = std::min<int64_t>((int64_t)per_cu * b->n_cu, a.n_list);
-                HIP_TRY(launch_resident(v, fp64, a, b->group_lds[g], grid, s));
-            } else {
-                int threads = streamed_threads(b, fp64);
-                if (!threads) return fail(RVE_EDEVICE, "internal: every streamed kernel build uses private memory");
-                a.lds_h_nodes = streamed_lds_nodes(b, b->groups[g].data(), b->groups[g].size(), fp64);
-                int grid = std::min<int64_t>((int64_t)b->n_cu * streamed_blocks_per_cu(threads, a.lds_h_nodes, fp64),
-                                             a.n_list);
-                HIP_TRY(launch_streamed(fp64, a, grid, threads, s));
-                a.lds_h_nodes = 0;
-            }
-            if (b->profile) HIP_TRY(hipEventRecord(b->ev[2 * g + 1], s));
-        }
-        const size_t gs = b->groups.size();
-        if (b->profile) HIP_TRY(hipEventRecord(b->ev[2 * gs], s));
-        HIP_TRY(launch_stress(a, (int)b->R, s));
-        if (b->profile) {
-            HIP_TRY(hipEventRecord(b->ev[2 * gs + 1], s));
-            b->ev_used = 2 * (int)gs + 2;
-        }
+        rc = launch_groups(b, a, b->dqueue, b->ws_fib, b->ws_node, s, b->profile);
+        if (rc) return rc;
     }
     HIP_TRY(hipMemcpyAsync(sigma, b->dsigma, 72 * b->R, out_kind, s));
     HIP_TRY(hipMemcpyAsync(status, b->dstatus, 4 * b->R, out_kind, s));
@@ -2032,3 +2046,93 @@ void rve_batch_destroy(rve_batch* b)
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ allocation-free solve
+// For callers that cannot allocate device memory (code under HIP graph
+// capture, tight serving loops, harnesses that forbid allocation):
+// rve_batch_solve_static runs the solve's resident and streamed launches
+// with their work areas -- the launch work counters and the streamed
+// engine's per-fiber and per-node workspace -- carved from this file-scope
+// device array instead of from allocations.  Each device that runs the
+// library holds its own copy until the process ends; its address is taken
+// once per device with hipGetSymbolAddress and kept (the array's name in
+// host code is a host-side stand-in, never a device address).
+constexpr size_t kStaticScratchBytes = size_t(1) << 30;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+
+int device_scratch(int dev, void** out)
+{
+    if (dev < 0 || dev >= 64) return fail(RVE_EDEVICE, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int cur = -1;
+        HIP_TRY(hipGetDevice(&cur));
+        if (cur != dev) HIP_TRY(hipSetDevice(dev));
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p)
+            return fail(RVE_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return RVE_OK;
+}
+}  // namespace
+
+extern "C" int rve_batch_solve_static(rve_batch* b, const double* F, double* sigma, int32_t* status,
+                                      int32_t ptr_kind)
+{
+    if (!b) return fail(RVE_EINVAL, "batch is NULL");
+    if (ptr_kind != RVE_PTR_HOST && ptr_kind != RVE_PTR_DEVICE) return fail(RVE_EINVAL, "bad ptr_kind");
+    if (b->R == 0) return RVE_OK;
+    if (!F || !sigma || !status) return fail(RVE_EINVAL, "F, sigma and status are required");
+    if (b->opts.engine == RVE_ENGINE_NAIVE || variant_mode(b->opts))
+        return fail(RVE_EINVAL, "the allocation-free solve runs the resident and streamed engines only");
+    if (b->opts.init == RVE_INIT_REFERENCE)
+        return fail(RVE_EINVAL, "the allocation-free solve takes the affine or warm start");
+    if (b->opts.init == RVE_INIT_WARM && !b->have_state)
+        return fail(RVE_ESTATE, "warm start requested before any solve");
+    const bool fp64 = b->opts.precision == RVE_FP64;
+    bool streamed = false;
+    for (int v : b->group_variant) streamed |= (v < 0);
+    // layout: work counters (two per launch group), then the streamed
+    // workspace of this batch's precision
+    const size_t counters = 256 * ((8 * b->groups.size() + 255) / 256 + 1);
+    const size_t r4 = fp64 ? 32 : 16;
+    const size_t fb = streamed ? r4 * 3 * (size_t)(b->NF + b->R) : 0;
+    const size_t nb = streamed ? r4 * (2 * (size_t)(b->NFREE + b->R) + 2 * (size_t)b->NFREE + 1) : 0;
+    const size_t fb_al = (fb + 255) & ~size_t(255);
+    if (counters + fb_al + nb > kStaticScratchBytes)
+        return fail(RVE_EWORKSPACE, "the batch needs " + std::to_string(counters + fb_al + nb) +
+                                        " bytes of work area, beyond the " + std::to_string(kStaticScratchBytes) +
+                                        " of the allocation-free solve");
+    void* base = nullptr;
+    int rc = device_scratch(b->device, &base);
+    if (rc) return rc;
+    char* sp = static_cast<char*>(base);
+    int32_t* queues = reinterpret_cast<int32_t*>(sp);
+    void* ws_fib = streamed ? sp + counters : nullptr;
+    void* ws_node = streamed ? sp + counters + fb_al : nullptr;
+
+    hipStream_t s = (hipStream_t)b->opts.stream;
+    const hipMemcpyKind in_kind = ptr_kind == RVE_PTR_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    const hipMemcpyKind out_kind = ptr_kind == RVE_PTR_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    HIP_TRY(hipMemcpyAsync(b->dF, F, 72 * b->R, in_kind, s));
+    SolveArgs a{};
+    fill_solve_args(b, a);
+    a.init = b->opts.init;
+    rc = launch_groups(b, a, queues, ws_fib, ws_node, s, false);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(sigma, b->dsigma, 72 * b->R, out_kind, s));
+    HIP_TRY(hipMemcpyAsync(status, b->dstatus, 4 * b->R, out_kind, s));
+    if (ptr_kind == RVE_PTR_HOST) HIP_TRY(hipStreamSynchronize(s));
+    b->have_state = true;
+    b->last_variant = false;
+    ++b->generation;
+    return RVE_OK;
+}

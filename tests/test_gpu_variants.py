@@ -24,8 +24,10 @@ def rb():
 
 
 @pytest.mark.parametrize("prec", [0, pytest.param(1, marks=pytest.mark.skip(
-    reason="a run of this mixed-precision case faulted the GPU (illegal memory access) and the cause is not "
-           "known; the (512,8,4) and (256,16,8) builds it used are switched off and the case stays off the GPU"))])
+    reason="a run of this mixed-precision case (forced 256- and 512-thread workgroups) faulted the GPU "
+           "(illegal memory access) with the former (512,8,4) and (256,16,8) builds; those builds are removed "
+           "and no build that uses private memory is launched, but the cause of the fault was not shown, so this "
+           "case stays off the GPU"))])
 def test_variants_agree(rb, prec):
     batch, F = synth.make_config_batch(2, idx=np.arange(64))
     common = dict(law=rb.LAW_EXP, mass=1, alpha=0.5, c=0.1, tol_abs=0.0, tol_rel=1e-8 if prec == 0 else 1e-5,
@@ -51,3 +53,32 @@ def test_variants_agree(rb, prec):
         else:
             assert both.sum() >= 0.9 * (st0 == 0).sum()
             assert err.max() <= 1e-4
+
+
+def test_mixed_builds_agree(rb):
+    """Mixed precision: the automatic choice (512-, 768- and 1024-thread
+    builds by size), the 768- and 1024-thread builds alone and the streamed
+    engine give stresses within 1e-4 of each other on RVEs converged in
+    both runs (the FP32 trajectories differ in rounding order where the work
+    distribution differs), and the same statuses except near the cap."""
+    batch, F = synth.make_config_batch(2, idx=np.arange(64))
+    common = dict(law=rb.LAW_EXP, mass=1, alpha=0.5, c=0.1, tol_abs=0.0, tol_rel=1e-5, n_max=100000, check_every=8)
+    runs = {}
+    for name, kw in (("streamed", dict(engine=rb.ENGINE_STREAMED)), ("auto", {}), ("t768", dict(threads_per_rve=768)),
+                     ("t1024", dict(threads_per_rve=1024))):
+        b = rb.Batch(batch, precision=1, **common, **kw)
+        sig, st, stats = b.solve(F, stats=True)
+        runs[name] = (sig, st, stats["iters"])
+        log(f"  mixed {name}: {b.describe()} status {np.bincount(st, minlength=4).tolist()}")
+        b.close()
+    s0, st0, it0 = runs["streamed"]
+    assert (st0 == 0).sum() >= 32
+    for name in ("auto", "t768", "t1024"):
+        s, st, it = runs[name]
+        both = (st == 0) & (st0 == 0)
+        near = (it >= 98000) | (it0 >= 98000)
+        err = rel_err(s[both], s0[both])
+        log(f"  mixed {name} vs streamed: {int(both.sum())} both converged, sigma max rel diff {err.max():.2e}, "
+            f"status mismatches {int((st != st0).sum())} (near the cap {int(((st != st0) & near).sum())})")
+        assert np.all((st == st0) | near)
+        assert err.max() <= 1e-4
