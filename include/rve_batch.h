@@ -241,7 +241,8 @@ int rve_batch_kernel_ms(rve_batch* b, double* relax_ms, double* stress_ms);
 
 /*
  * Kernel groups of the last solve: group_of_rve[R] receives the launch group
- * of every RVE, variant[g] its resident variant index (-1 streamed) and, if
+ * of every RVE, variant[g] its resident variant index (-1 streamed, -1 - k
+ * a team of k workgroups per RVE) and, if
  * the solve was profiled, ms[g] the duration of that group's relaxation
  * launch (NaN otherwise).  Arrays are host memory of max_groups entries;
  * *n_groups receives the number of groups.
@@ -410,6 +411,17 @@ int rve_batch_import_state(rve_batch* b, const double* F, const double* h, const
 /* Positions x[n_nodes_r][3] of RVE r after the last solve, in the caller's
  * original node order (host pointer; synchronous). */
 int rve_batch_positions(rve_batch* b, int64_t r, double* x);
+
+/*
+ * Team engine (RVEs too large for one CU run on k workgroups that exchange
+ * partition-boundary state through global memory once per iteration and
+ * meet at a barrier): the number of polls a workgroup makes at a team
+ * barrier before it gives up (default 2^24, about a second).  A launch whose
+ * team gave up leaves its unfinished RVEs with status RVE_ST_NONFINITE and
+ * NaN stress, and a host-pointer solve returns RVE_EDEVICE.  Mainly for
+ * tests of that path (a limit of 1 poll forces it); polls >= 1.
+ */
+int rve_batch_team_spin_limit(rve_batch* b, int64_t polls);
 
 /*
  * Generation of the batch's state: a counter that every successful

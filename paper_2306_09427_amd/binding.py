@@ -33,7 +33,7 @@ EXPORTS = ["rve_version", "rve_last_error", "rve_default_opts", "rve_batch_creat
            "rve_batch_autotune", "rve_batch_describe", "rve_batch_groups", "rve_batch_tangent_iters", "rve_batch_orientation",
            "rve_batch_fd_tangent", "rve_batch_export_state", "rve_batch_import_state",
            "rve_batch_workspace_size", "rve_batch_bind_workspace", "rve_batch_damping_stats",
-           "rve_batch_generation", "rve_check_indexing"]
+           "rve_batch_generation", "rve_check_indexing", "rve_batch_team_spin_limit"]
 
 
 class NetDesc(C.Structure):
@@ -109,6 +109,7 @@ def lib():
         if hasattr(L, "rve_batch_solve_static"):
             L.rve_batch_solve_static.argtypes = [P, P, P, P, C.c_int32]
         L.rve_check_indexing.argtypes = [C.POINTER(NetDesc), C.c_int32, C.c_int32]
+        L.rve_batch_team_spin_limit.argtypes = [P, C.c_int64]
         L.rve_batch_destroy.argtypes = [P]
         L.rve_batch_destroy.restype = None
         _lib = L
@@ -212,6 +213,10 @@ class Batch:
         _check(lib().rve_batch_set_opts(self._h, C.byref(o)))
         o.c_per_rve = None
         self.opts = o
+
+    def team_spin_limit(self, polls):
+        """Polls of a team barrier before a team gives up (tests of that path)."""
+        _check(lib().rve_batch_team_spin_limit(self._h, int(polls)))
 
     def generation(self):
         """Counter of the state's changes (solve, import, option change)."""

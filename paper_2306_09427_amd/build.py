@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librvebatch.so")
 SOURCES = ["rve_host.hip", "rve_kernels.hip", "rve_naive.hip", "rve_tangent.hip", "rve_orient.hip", "rve_fd.hip",
-           "rve_state.hip", "rve_variants.hip"]
+           "rve_state.hip", "rve_variants.hip", "rve_team.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed-FP32 instructions are disabled for all device code.

@@ -131,6 +131,22 @@ struct rve_batch {
     double* v_ws = nullptr;
     bool last_variant = false;
     uint64_t generation = 0;           // bumped by solve, import_state, set_opts
+    // team engine (k workgroups per RVE): per-RVE team size (0: no partition),
+    // its largest exchange-slot count, LDS bytes of its largest part per
+    // precision; the tables on the device; the team work area
+    std::vector<int32_t> team_k;
+    std::vector<int64_t> team_xslots;
+    std::vector<size_t> team_lds[2];
+    char* team_mem = nullptr;
+    TeamArgs team_tab{};               // table pointers (carved from team_mem)
+    char* team_ws = nullptr;           // library-owned team work area
+    size_t team_ws_bytes = 0;
+    std::vector<int32_t> group_team;   // team size of each group, 0 = not a team group
+    int64_t team_spin_limit = int64_t(1) << 24;   // polls of a team barrier before it gives up
+    // concurrent launch groups: auxiliary streams (default priority) and the
+    // events that fork them from and join them to the batch's stream
+    hipStream_t aux[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t fork_ev = nullptr, join_ev[3] = {nullptr, nullptr, nullptr};
     double* d_xm_free = nullptr;       // [NFREE][3] reference coordinates of free nodes (RVE_INIT_REFERENCE)
 };
 
@@ -411,6 +427,328 @@ static void pack_batch(const rve_net_desc* d, HostPack& P)
 }
 
 
+
+template <typename T>
+static T* carve(char* base, size_t off)
+{
+    return reinterpret_cast<T*>(base + off);
+}
+
+// ------------------------------------------------------------------ team partition
+// Partition of one RVE for the team engine (k workgroups): free nodes split
+// into k contiguous ranges of a breadth-first order over the free-free
+// fibers; part p owns its range and takes every fiber with a free end in it
+// (fibers with no free end go to part 0), every boundary node whose fibers
+// it holds all of (the first fiber's part, completed with the others), and
+// holds the foreign free ends of its fibers as halo.  Returns false when a
+// part exceeds the team build's capacity (fibers, owned nodes, LDS).
+struct TeamHost {
+    std::vector<TeamPart> parts;
+    std::vector<int64_t> part_first;
+    std::vector<int32_t> fib_gid, own_gid, own_xslot, halo_gid, halo_xslot;
+    std::vector<uint32_t> fib_ends;
+    std::vector<int64_t> own_inc_off, bnd_inc_off;
+    std::vector<uint16_t> own_inc, bnd_inc;
+};
+
+static bool team_partition(const HostPack& P, int64_t r, int k, TeamHost& T, int64_t* xslots, size_t lds_out[2])
+{
+    const int64_t f0 = P.fib_off[r], nfib = P.fib_off[r + 1] - f0;
+    const int64_t a0 = P.free_off[r], nf = P.free_off[r + 1] - a0;
+    const int64_t b0 = P.bnd_off[r], nb = P.bnd_off[r + 1] - b0;
+    const int cap_f = kTeamUnit[0].threads * kTeamUnit[0].sf, cap_n = kTeamUnit[0].threads * kTeamUnit[0].sn;
+    if (nf < k) return false;
+    // breadth-first order over free-free fibers
+    std::vector<std::vector<int32_t>> adj(nf);
+    for (int64_t q = 0; q < nfib; ++q) {
+        const uint32_t e = P.ends[f0 + q];
+        const int64_t i = e & 0xffffu, j = e >> 16;
+        if (i < nf && j < nf) {
+            adj[i].push_back((int32_t)j);
+            adj[j].push_back((int32_t)i);
+        }
+    }
+    std::vector<int32_t> order;
+    order.reserve(nf);
+    std::vector<char> seen(nf, 0);
+    for (int64_t s0 = 0; s0 < nf; ++s0) {
+        if (seen[s0]) continue;
+        size_t head = order.size();
+        order.push_back((int32_t)s0);
+        seen[s0] = 1;
+        while (head < order.size()) {
+            const int32_t u = order[head++];
+            for (int32_t w : adj[u])
+                if (!seen[w]) {
+                    seen[w] = 1;
+                    order.push_back(w);
+                }
+        }
+    }
+    std::vector<int32_t> part_of(nf);
+    for (int64_t q = 0; q < nf; ++q) part_of[order[q]] = (int32_t)std::min<int64_t>(k - 1, q * k / nf);
+    std::vector<std::vector<int32_t>> fibs(k), bnds(k);
+    auto parts_of_fiber = [&](int64_t q, int32_t* out) {
+        const uint32_t e = P.ends[f0 + q];
+        const int64_t i = e & 0xffffu, j = e >> 16;
+        int n = 0;
+        if (i < nf) out[n++] = part_of[i];
+        if (j < nf && (n == 0 || part_of[j] != out[0])) out[n++] = part_of[j];
+        if (n == 0) out[n++] = 0;
+        return n;
+    };
+    for (int64_t q = 0; q < nfib; ++q) {
+        int32_t ps[2];
+        const int n = parts_of_fiber(q, ps);
+        for (int t = 0; t < n; ++t) fibs[ps[t]].push_back((int32_t)q);
+    }
+    for (int64_t bq = 0; bq < nb; ++bq) {
+        const int64_t e0 = P.binc_off[b0 + bq], e1 = P.binc_off[b0 + bq + 1];
+        if (e0 == e1) continue;
+        int32_t ps[2];
+        parts_of_fiber(P.binc[e0] & 0x7fffffffu, ps);
+        const int32_t pb = ps[0];
+        for (int64_t e = e0; e < e1; ++e) fibs[pb].push_back((int32_t)(P.binc[e] & 0x7fffffffu));
+        bnds[pb].push_back((int32_t)(nf + bq));
+    }
+    for (auto& f : fibs) {
+        std::sort(f.begin(), f.end());
+        f.erase(std::unique(f.begin(), f.end()), f.end());
+    }
+    // halo sets and exchange slots
+    std::vector<std::vector<int32_t>> owned(k), halo(k);
+    for (int64_t a = 0; a < nf; ++a) owned[part_of[a]].push_back((int32_t)a);
+    std::vector<int32_t> xslot(nf, -1);
+    int64_t nx = 0;
+    for (int p = 0; p < k; ++p) {
+        std::vector<int32_t>& h = halo[p];
+        for (int32_t q : fibs[p]) {
+            const uint32_t e = P.ends[f0 + q];
+            const int64_t i = e & 0xffffu, j = e >> 16;
+            if (i < nf && part_of[i] != p) h.push_back((int32_t)i);
+            if (j < nf && part_of[j] != p) h.push_back((int32_t)j);
+        }
+        std::sort(h.begin(), h.end());
+        h.erase(std::unique(h.begin(), h.end()), h.end());
+        for (int32_t a : h)
+            if (xslot[a] < 0) xslot[a] = (int32_t)nx++;
+    }
+    size_t lds[2] = {0, 0};
+    for (int p = 0; p < k; ++p) {
+        const int64_t npos = (int64_t)owned[p].size() + (int64_t)halo[p].size();
+        if ((int64_t)fibs[p].size() > cap_f || (int64_t)owned[p].size() > cap_n || npos + 1 >= 65535) return false;
+        for (int fp = 0; fp < 2; ++fp) {
+            const size_t l = team_lds_bytes(fp == 1, npos, (int64_t)fibs[p].size());
+            if (l + 4096 > 160 * 1024) return false;
+            lds[fp] = std::max(lds[fp], l);
+        }
+    }
+    // append the tables
+    T.part_first[r] = (int64_t)T.parts.size();
+    for (int p = 0; p < k; ++p) {
+        TeamPart tp{};
+        tp.fib0 = (int64_t)T.fib_gid.size();
+        tp.own0 = (int64_t)T.own_gid.size();
+        tp.halo0 = (int64_t)T.halo_gid.size();
+        tp.bnd0 = (int64_t)T.bnd_inc_off.size() - 1;
+        tp.nfib = (int32_t)fibs[p].size();
+        tp.nown = (int32_t)owned[p].size();
+        tp.nhalo = (int32_t)halo[p].size();
+        tp.nbnd = (int32_t)bnds[p].size();
+        const uint32_t zs = (uint32_t)(tp.nown + tp.nhalo);
+        // local position slot of a packed node id (owned, halo, else the zero slot)
+        auto local = [&](int64_t id) -> uint32_t {
+            if (id >= nf) return zs;
+            if (part_of[id] == p) return (uint32_t)(std::lower_bound(owned[p].begin(), owned[p].end(), (int32_t)id) -
+                                                    owned[p].begin());
+            return (uint32_t)tp.nown +
+                   (uint32_t)(std::lower_bound(halo[p].begin(), halo[p].end(), (int32_t)id) - halo[p].begin());
+        };
+        auto code_of = [&](uint32_t w) -> uint16_t {
+            const int32_t q = (int32_t)(w & 0x7fffffffu);
+            const uint16_t lf = (uint16_t)(std::lower_bound(fibs[p].begin(), fibs[p].end(), q) - fibs[p].begin());
+            return (uint16_t)(lf | ((w >> 31) ? 0x8000u : 0u));
+        };
+        for (int32_t q : fibs[p]) {
+            const uint32_t e = P.ends[f0 + q];
+            T.fib_gid.push_back((int32_t)(f0 + q));
+            T.fib_ends.push_back(local(e & 0xffffu) | (local(e >> 16) << 16));
+        }
+        for (int32_t a : owned[p]) {
+            T.own_gid.push_back((int32_t)(a0 + a));
+            T.own_xslot.push_back(xslot[a]);
+            for (int64_t e = P.inc_off[a0 + a]; e < P.inc_off[a0 + a + 1]; ++e) T.own_inc.push_back(code_of(P.inc[e]));
+            T.own_inc_off.push_back((int64_t)T.own_inc.size());
+        }
+        for (int32_t a : halo[p]) {
+            T.halo_gid.push_back((int32_t)(a0 + a));
+            T.halo_xslot.push_back(xslot[a]);
+        }
+        for (int32_t bn : bnds[p]) {
+            const int64_t bq = bn - nf;
+            for (int64_t e = P.binc_off[b0 + bq]; e < P.binc_off[b0 + bq + 1]; ++e) T.bnd_inc.push_back(code_of(P.binc[e]));
+            T.bnd_inc_off.push_back((int64_t)T.bnd_inc.size());
+        }
+        T.parts.push_back(tp);
+    }
+    *xslots = nx;
+    lds_out[0] = lds[0];
+    lds_out[1] = lds[1];
+    return true;
+}
+
+
+// Team partitions of every RVE that no resident build holds in FP64 (more
+// than 3072 fibers or 1536 free nodes): the smallest team size, from the
+// part capacity up to kTeamMax, whose parts fit the team build; RVEs without
+// one run on the streamed kernel.  Tables for all of them in one device
+// allocation.
+static int build_team_tables(rve_batch* b, const HostPack& P)
+{
+    const int64_t R = b->R;
+    b->team_k.assign(R, 0);
+    b->team_xslots.assign(R, 0);
+    b->team_lds[0].assign(R, 0);
+    b->team_lds[1].assign(R, 0);
+    const int cap_f = kTeamUnit[0].threads * kTeamUnit[0].sf, cap_n = kTeamUnit[0].threads * kTeamUnit[0].sn;
+    TeamHost T;
+    T.part_first.assign(R, -1);
+    T.own_inc_off.assign(1, 0);
+    T.bnd_inc_off.assign(1, 0);
+    bool any = false;
+    try {
+        for (int64_t r = 0; r < R; ++r) {
+            const int64_t nfib = b->nfib_of[r], nf = b->nf_of[r];
+            if (nfib <= cap_f && nf <= cap_n) continue;
+            int k0 = (int)std::max<int64_t>(2, std::max((nfib * 11 + 10 * cap_f - 1) / (10 * cap_f),
+                                                        (nf * 11 + 10 * cap_n - 1) / (10 * cap_n)));
+            for (int k = k0; k <= kTeamMax; ++k) {
+                TeamHost save_sizes;   // roll back on failure: remember the table lengths
+                const size_t s_parts = T.parts.size(), s_fib = T.fib_gid.size(), s_own = T.own_gid.size(),
+                             s_inc = T.own_inc.size(), s_ioff = T.own_inc_off.size(), s_halo = T.halo_gid.size(),
+                             s_binc = T.bnd_inc.size(), s_boff = T.bnd_inc_off.size();
+                int64_t xs = 0;
+                size_t lds[2];
+                if (team_partition(P, r, k, T, &xs, lds)) {
+                    b->team_k[r] = k;
+                    b->team_xslots[r] = xs;
+                    b->team_lds[0][r] = lds[0];
+                    b->team_lds[1][r] = lds[1];
+                    any = true;
+                    break;
+                }
+                T.parts.resize(s_parts);
+                T.fib_gid.resize(s_fib);
+                T.fib_ends.resize(s_fib);
+                T.own_gid.resize(s_own);
+                T.own_xslot.resize(s_own);
+                T.own_inc.resize(s_inc);
+                T.own_inc_off.resize(s_ioff);
+                T.halo_gid.resize(s_halo);
+                T.halo_xslot.resize(s_halo);
+                T.bnd_inc.resize(s_binc);
+                T.bnd_inc_off.resize(s_boff);
+                T.part_first[r] = -1;
+            }
+        }
+    } catch (const std::bad_alloc&) {
+        return fail(RVE_ENOMEM, "host allocation failed while partitioning RVEs for the team engine");
+    }
+    if (!any) return RVE_OK;
+    DeviceArena A;
+    const size_t o_parts = A.reserve(sizeof(TeamPart) * T.parts.size()), o_first = A.reserve(8 * (size_t)R),
+                 o_fg = A.reserve(4 * T.fib_gid.size()), o_fe = A.reserve(4 * T.fib_ends.size()),
+                 o_og = A.reserve(4 * T.own_gid.size()), o_ox = A.reserve(4 * T.own_xslot.size()),
+                 o_oi = A.reserve(8 * T.own_inc_off.size()), o_oc = A.reserve(2 * T.own_inc.size() + 2),
+                 o_hg = A.reserve(4 * T.halo_gid.size() + 4), o_hx = A.reserve(4 * T.halo_xslot.size() + 4),
+                 o_bi = A.reserve(8 * T.bnd_inc_off.size()), o_bc = A.reserve(2 * T.bnd_inc.size() + 2);
+    if (hipMalloc((void**)&b->team_mem, A.used + 256) != hipSuccess) {
+        b->team_mem = nullptr;
+        return fail(RVE_ENOMEM, "device allocation of the team tables failed");
+    }
+    char* m = b->team_mem;
+    auto up = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
+        return bytes ? hipMemcpy(m + off, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
+    };
+    hipError_t e = hipSuccess;
+    e = e ? e : up(o_parts, T.parts.data(), sizeof(TeamPart) * T.parts.size());
+    e = e ? e : up(o_first, T.part_first.data(), 8 * (size_t)R);
+    e = e ? e : up(o_fg, T.fib_gid.data(), 4 * T.fib_gid.size());
+    e = e ? e : up(o_fe, T.fib_ends.data(), 4 * T.fib_ends.size());
+    e = e ? e : up(o_og, T.own_gid.data(), 4 * T.own_gid.size());
+    e = e ? e : up(o_ox, T.own_xslot.data(), 4 * T.own_xslot.size());
+    e = e ? e : up(o_oi, T.own_inc_off.data(), 8 * T.own_inc_off.size());
+    e = e ? e : up(o_oc, T.own_inc.data(), 2 * T.own_inc.size());
+    e = e ? e : up(o_hg, T.halo_gid.data(), 4 * T.halo_gid.size());
+    e = e ? e : up(o_hx, T.halo_xslot.data(), 4 * T.halo_xslot.size());
+    e = e ? e : up(o_bi, T.bnd_inc_off.data(), 8 * T.bnd_inc_off.size());
+    e = e ? e : up(o_bc, T.bnd_inc.data(), 2 * T.bnd_inc.size());
+    if (e != hipSuccess) return fail(RVE_EDEVICE, std::string("team table upload failed: ") + hipGetErrorString(e));
+    TeamArgs& t = b->team_tab;
+    t.parts = carve<TeamPart>(m, o_parts);
+    t.part_first = carve<int64_t>(m, o_first);
+    t.fib_gid = carve<int32_t>(m, o_fg);
+    t.fib_ends = carve<uint32_t>(m, o_fe);
+    t.own_gid = carve<int32_t>(m, o_og);
+    t.own_xslot = carve<int32_t>(m, o_ox);
+    t.own_inc_off = carve<int64_t>(m, o_oi);
+    t.own_inc = carve<uint16_t>(m, o_oc);
+    t.halo_gid = carve<int32_t>(m, o_hg);
+    t.halo_xslot = carve<int32_t>(m, o_hx);
+    t.bnd_inc_off = carve<int64_t>(m, o_bi);
+    t.bnd_inc = carve<uint16_t>(m, o_bc);
+    return RVE_OK;
+}
+
+// Team launches: workgroups per CU of the team build at this LDS size, and
+// the number of teams (a multiple of 8, so every team lies on one XCD).
+static int team_grid(const rve_batch* b, bool fp64, bool kin, size_t lds, int k, int* n_teams)
+{
+    int per_cu = 0;
+    size_t priv = 1;
+    HIP_TRY(team_info(fp64, kin, lds, &per_cu, &priv));
+    if (priv > 0) return fail(RVE_EDEVICE, "internal: the team kernel build uses private memory");
+    const int64_t total = (int64_t)per_cu * b->n_cu;
+    *n_teams = (int)(total / (8 * k)) * 8;
+    if (*n_teams < 8) return fail(RVE_EDEVICE, "a team of " + std::to_string(k) + " workgroups does not fit the device");
+    return RVE_OK;
+}
+
+// Work area of the largest team launch of the batch: per team two exchange
+// buffers of max_xslots (h, v, a) records and two sets of k partials, then
+// the barrier counters, task slots and the error word.
+struct TeamWs {
+    size_t xchg, partials, words, total;
+};
+static TeamWs team_ws_layout(const rve_batch* b, int k, int n_teams, int64_t max_xslots, bool fp64)
+{
+    TeamWs L;
+    L.xchg = ((size_t)n_teams * 2 * 9 * (size_t)std::max<int64_t>(max_xslots, 1) * (fp64 ? 8 : 4) + 255) & ~size_t(255);
+    L.partials = ((size_t)n_teams * 2 * 8 * (size_t)k * 8 + 255) & ~size_t(255);
+    L.words = 4 * (size_t)(3 * n_teams + 1);
+    L.total = L.xchg + L.partials + ((L.words + 255) & ~size_t(255));
+    return L;
+}
+
+// Teams a launch can hold at most (team builds run one workgroup per CU).
+static int team_bound(const rve_batch* b, int k) { return 8 * ((b->n_cu + 8 * k - 1) / (8 * k)) + 8; }
+
+// Bytes of the team work area: the largest over every team size the batch's
+// partitions use (whichever precision or option puts them on the team
+// engine; FP64 records, so either precision fits), after 256 bytes of
+// per-group error words.
+static size_t team_ws_bytes(const rve_batch* b)
+{
+    size_t m = 0;
+    for (int k = 2; k <= kTeamMax; ++k) {
+        int64_t mx = -1;
+        for (int64_t r = 0; r < b->R; ++r)
+            if (!b->team_k.empty() && b->team_k[r] == k) mx = std::max(mx, b->team_xslots[r]);
+        if (mx >= 0) m = std::max(m, team_ws_layout(b, k, team_bound(b, k), mx, true).total);
+    }
+    return m ? m + 256 : 0;
+}
+
 // ------------------------------------------------------------------ index replay
 // Host replay of the index arithmetic of the relaxation kernels over a
 // packed batch, with every index bounded against the array it addresses.
@@ -503,15 +841,96 @@ static int check_indexing(const rve_net_desc* net, bool fp64, int plant)
         // streamed engine: workspace entries [NF + R] per fiber array, [NFREE + R] positions
         if (f0 + r + nfib >= NF + R) return bad(r, "streamed fiber zero slot outside the workspace");
         if (a0 + r + nf >= NFREE + R) return bad(r, "streamed position zero slot outside the workspace");
+        // team engine: the partition of an RVE no FP64 resident build holds
+        const int cap_f = kTeamUnit[0].threads * kTeamUnit[0].sf, cap_n = kTeamUnit[0].threads * kTeamUnit[0].sn;
+        if (nfib <= cap_f && nf <= cap_n) continue;
+        TeamHost T;
+        T.part_first.assign(R, -1);
+        T.own_inc_off.assign(1, 0);
+        T.bnd_inc_off.assign(1, 0);
+        int k = 0;
+        int64_t xs = 0;
+        size_t lds[2];
+        for (int kk = 2; kk <= kTeamMax && !k; ++kk)
+            if (team_partition(P, r, kk, T, &xs, lds)) k = kk;
+            else {
+                T = TeamHost();
+                T.part_first.assign(R, -1);
+                T.own_inc_off.assign(1, 0);
+                T.bnd_inc_off.assign(1, 0);
+            }
+        if (!k) continue;   // runs streamed
+        std::vector<int> owner(nf, -1), owned_seen(nf, 0);
+        std::vector<int32_t> slot_of(nf, -1);
+        for (int p = 0; p < k; ++p) {
+            const TeamPart& tp = T.parts[p];
+            for (int32_t a = 0; a < tp.nown; ++a) {
+                const int64_t g = T.own_gid[tp.own0 + a] - a0;
+                if (g < 0 || g >= nf) return bad(r, "team: owned node outside the RVE");
+                owner[g] = p;
+                owned_seen[g] += 1;
+                slot_of[g] = T.own_xslot[tp.own0 + a];
+            }
+        }
+        for (int64_t a = 0; a < nf; ++a)
+            if (owned_seen[a] != 1) return bad(r, "team: free node " + std::to_string(a) + " owned " +
+                                                       std::to_string(owned_seen[a]) + " times");
+        for (int p = 0; p < k; ++p) {
+            const TeamPart& tp = T.parts[p];
+            const int zs = tp.nown + tp.nhalo;
+            const int cap_fib = kTeamUnit[fp64 ? 1 : 0].threads * kTeamUnit[fp64 ? 1 : 0].sf;
+            const int cap_own = kTeamUnit[fp64 ? 1 : 0].threads * kTeamUnit[fp64 ? 1 : 0].sn;
+            if (tp.nfib > cap_fib || tp.nown > cap_own) return bad(r, "team: a part exceeds the build's slots");
+            if (team_lds_bytes(fp64, zs, tp.nfib) + 4096 > 160 * 1024) return bad(r, "team: part LDS beyond 160 KB");
+            std::vector<int> has(nfib, 0);
+            for (int32_t q = 0; q < tp.nfib; ++q) {
+                const int64_t g = T.fib_gid[tp.fib0 + q] - f0;
+                if (g < 0 || g >= nfib) return bad(r, "team: fiber outside the RVE");
+                has[g] = 1;
+                const uint32_t E = T.fib_ends[tp.fib0 + q];
+                if ((int)res_end_i(E) > zs || (int)res_end_j(E) > zs)
+                    return bad(r, "team: fiber end outside the part's position slots");
+                // local ends name the fiber's true ends
+                const uint32_t e = P.ends[f0 + g];
+                for (int end = 0; end < 2; ++end) {
+                    const int64_t id = end ? (e >> 16) : (e & 0xffffu);
+                    const int loc = (int)(end ? res_end_j(E) : res_end_i(E));
+                    int64_t back = -1;
+                    if (loc < tp.nown) back = T.own_gid[tp.own0 + loc] - a0;
+                    else if (loc < zs) back = T.halo_gid[tp.halo0 + (loc - tp.nown)] - a0;
+                    if (id < nf ? back != id : loc != zs) return bad(r, "team: a fiber end maps to another node");
+                }
+            }
+            for (int32_t a = 0; a < tp.nown; ++a) {
+                const int64_t g = T.own_gid[tp.own0 + a] - a0;
+                for (int64_t e = P.inc_off[a0 + g]; e < P.inc_off[a0 + g + 1]; ++e)
+                    if (!has[P.inc[e] & 0x7fffffffu]) return bad(r, "team: an owned node's fiber is not in its part");
+                const int64_t e0 = T.own_inc_off[tp.own0 + a], e1 = T.own_inc_off[tp.own0 + a + 1];
+                if (e1 - e0 != P.inc_off[a0 + g + 1] - P.inc_off[a0 + g]) return bad(r, "team: owned degree differs");
+                for (int64_t e = e0; e < e1; ++e) {
+                    const uint32_t c = T.own_inc[e];
+                    if ((int)res_code_fiber(c) >= tp.nfib) return bad(r, "team: incidence code outside the part's fibers");
+                    const int64_t g2 = T.fib_gid[tp.fib0 + res_code_fiber(c)] - f0;
+                    const uint32_t ee = P.ends[f0 + g2];
+                    const int64_t end = res_code_neg(c) ? (ee & 0xffffu) : (ee >> 16);
+                    if (end != g) return bad(r, "team: incidence code names a fiber of another node or end");
+                }
+            }
+            for (int32_t q = 0; q < tp.nhalo; ++q) {
+                const int64_t g = T.halo_gid[tp.halo0 + q] - a0;
+                if (g < 0 || g >= nf || owner[g] == p) return bad(r, "team: halo node is not foreign");
+                const int32_t x = T.halo_xslot[tp.halo0 + q];
+                if (x < 0 || x >= xs || x != slot_of[g]) return bad(r, "team: halo slot differs from its owner's");
+            }
+            for (int32_t q = 0; q < tp.nbnd; ++q)
+                for (int64_t e = T.bnd_inc_off[tp.bnd0 + q]; e < T.bnd_inc_off[tp.bnd0 + q + 1]; ++e)
+                    if ((int)res_code_fiber(T.bnd_inc[e]) >= tp.nfib)
+                        return bad(r, "team: boundary code outside the part's fibers");
+        }
     }
     return RVE_OK;
 }
 
-template <typename T>
-static T* carve(char* base, size_t off)
-{
-    return reinterpret_cast<T*>(base + off);
-}
 
 // Assign every RVE to an engine/variant group, longest-first inside a group.
 // Resident variants are chosen per size tier: the autotuner's choice if one
@@ -541,31 +960,44 @@ static void assign_groups(rve_batch* b)
     b->groups.clear();
     b->group_variant.clear();
     b->group_lds.clear();
+    b->group_team.clear();
     const bool fp64 = b->opts.precision == RVE_FP64;
-    std::vector<std::vector<int32_t>> per(kNumResident + 1);
+    // [resident variants..., streamed, teams of 2..kTeamMax]
+    std::vector<std::vector<int32_t>> per(kNumResident + 1 + kTeamMax + 1);
     for (int64_t r = 0; r < b->R; ++r) {
-        int chosen = -1;
+        int slot = kNumResident;   // streamed
         if (b->opts.engine == RVE_ENGINE_AUTO) {
             int t = tier_of(b, r, fp64);
+            int chosen = -1;
             if (t >= 0) {
                 int tv = b->tuned[fp64 ? 1 : 0][t];
                 if (tv >= 0 && spills(b, tv, fp64)) tv = -2;   // tuned for the other damping build
                 chosen = (tv != -2 && !b->opts.threads_per_rve) ? tv : default_variant(b, t, fp64);
             }
+            if (chosen >= 0)
+                slot = chosen;
+            else if (!b->team_k.empty() && b->team_k[r] > 0 && !b->opts.threads_per_rve)
+                slot = kNumResident + b->team_k[r];
         }
-        per[chosen < 0 ? kNumResident : chosen].push_back((int32_t)r);
+        per[slot].push_back((int32_t)r);
     }
-    for (int v = 0; v <= kNumResident; ++v) {
+    for (size_t v = 0; v < per.size(); ++v) {
         std::vector<int32_t>& members = per[v];
         if (members.empty()) continue;
         std::stable_sort(members.begin(), members.end(),
                          [&](int32_t a, int32_t c) { return b->nfib_of[a] > b->nfib_of[c]; });
         size_t lds = 0;
-        if (v < kNumResident)
+        int team = 0;
+        if (v < (size_t)kNumResident) {
             for (int32_t r : members) lds = std::max(lds, resident_lds_bytes(fp64, b->nf_of[r], b->nfib_of[r], 0));
+        } else if (v > (size_t)kNumResident) {
+            team = (int)(v - kNumResident);
+            for (int32_t r : members) lds = std::max(lds, b->team_lds[fp64 ? 1 : 0][r]);
+        }
         b->groups.push_back(members);
-        b->group_variant.push_back(v < kNumResident ? v : -1);
+        b->group_variant.push_back(v < (size_t)kNumResident ? (int)v : (team ? -1 - team : -1));
         b->group_lds.push_back(lds);
+        b->group_team.push_back(team);
     }
 }
 
@@ -614,8 +1046,17 @@ static int streamed_threads(const rve_batch* b, bool fp64)
 
 static int ensure_workspace(rve_batch* b)
 {
+    const size_t tw = team_ws_bytes(b);
+    if (tw > b->team_ws_bytes) {
+        if (b->ws_user) return fail(RVE_EWORKSPACE, "internal: bound workspace smaller than the team work area");
+        if (b->team_ws) (void)hipFree(b->team_ws);
+        b->team_ws = nullptr;
+        b->team_ws_bytes = 0;
+        if (hipMalloc((void**)&b->team_ws, tw) != hipSuccess) return fail(RVE_ENOMEM, "team work area allocation failed");
+        b->team_ws_bytes = tw;
+    }
     bool need = false;
-    for (int v : b->group_variant) need |= (v < 0);
+    for (int v : b->group_variant) need |= (v == -1);
     if (!need) return RVE_OK;
     const size_t r4 = b->opts.precision == RVE_FP64 ? 32 : 16;
     size_t fb = r4 * 3 * (size_t)(b->NF + b->R);
@@ -693,6 +1134,10 @@ void rve_default_opts(rve_opts* o)
     o->stall_checks = 16;
 }
 
+// Address of the allocation-free solve's scratch array on device dev, taken
+// once per device (definition at the end of this file).
+static int device_scratch(int dev, void** out);
+
 int rve_check_indexing(const rve_net_desc* net, int32_t precision, int32_t plant)
 {
     int rc = validate_net(net);
@@ -719,6 +1164,13 @@ int rve_batch_create(const rve_net_desc* net, const rve_opts* opts, rve_batch** 
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(RVE_EDEVICE, std::string("device is ") + prop.gcnArchName + ", the kernels are built for gfx950");
 
+    {
+        // set-up of the allocation-free solve: the device copy of its scratch
+        // array is located (and so made resident) once per device, here
+        void* sp = nullptr;
+        int rc_s = device_scratch(dev, &sp);
+        if (rc_s) return rc_s;
+    }
     rve_batch* b = new (std::nothrow) rve_batch();
     if (!b) return fail(RVE_ENOMEM, "host allocation failed");
     b->device = dev;
@@ -868,6 +1320,11 @@ int rve_batch_create(const rve_net_desc* net, const rve_opts* opts, rve_batch** 
     b->dqueue = carve<int32_t>(m, o_q);
     b->dlist = carve<int32_t>(m, o_list);
 
+    rc = build_team_tables(b, P);
+    if (rc) {
+        rve_batch_destroy(b);
+        return rc;
+    }
     assign_groups(b);
     rc = upload_groups(b);
     if (rc) {
@@ -891,6 +1348,14 @@ int rve_batch_set_opts(rve_batch* b, const rve_opts* opts)
     ++b->generation;
     assign_groups(b);
     return upload_groups(b);
+}
+
+int rve_batch_team_spin_limit(rve_batch* b, int64_t polls)
+{
+    if (!b) return fail(RVE_EINVAL, "batch is NULL");
+    if (polls < 1) return fail(RVE_EINVAL, "the spin limit must be at least 1 poll");
+    b->team_spin_limit = polls;
+    return RVE_OK;
 }
 
 int rve_batch_generation(const rve_batch* b, uint64_t* gen)
@@ -966,11 +1431,13 @@ int rve_batch_sizes(const rve_batch* b, int64_t* n_rve, int64_t* n_nodes, int64_
 }
 
 
-// The relaxation launches of a solve on the resident and streamed engines:
-// one persistent launch per kernel group (work counters queues[2 g]), then
-// the stress kernel; with `profile`, HIP events around each launch.
-static int launch_groups(rve_batch* b, SolveArgs& a, int32_t* queues, void* ws_fib, void* ws_node, hipStream_t s,
-                         bool profile)
+// The relaxation launches of a solve on the resident, team and streamed
+// engines: one persistent launch per kernel group (work counters queues[2 g]),
+// then the stress kernel; with `profile`, HIP events around each launch.
+// team_ws: the team work area (error words first, one per group, cleared
+// here; then the work area of one team launch, reused by the next).
+static int launch_groups(rve_batch* b, SolveArgs& a, int32_t* queues, void* ws_fib, void* ws_node, char* team_ws,
+                         hipStream_t s, bool profile, bool concurrent)
 {
     const bool fp64 = b->opts.precision == RVE_FP64;
     a.ws_fib = ws_fib;
@@ -981,29 +1448,95 @@ static int launch_groups(rve_batch* b, SolveArgs& a, int32_t* queues, void* ws_f
         if (rc) return rc;
     }
     HIP_TRY(launch_reset(queues, 2 * (int)b->groups.size(), s));
-    for (size_t g = 0; g < b->groups.size(); ++g) {
+    int32_t* team_err = reinterpret_cast<int32_t*>(team_ws);
+    char* team_area = team_ws ? team_ws + 256 : nullptr;
+    if (team_ws) HIP_TRY(launch_zero32(team_err, (int64_t)b->groups.size(), s));
+    // Launch order: team groups first, alone on the batch's stream (their
+    // workgroups must all be resident at once); then the other groups, the
+    // heaviest (most fibers) first, each on its own stream when `concurrent`,
+    // so the tail of one group (its last, longest RVEs) overlaps the others.
+    std::vector<size_t> order;
+    for (size_t g = 0; g < b->groups.size(); ++g)
+        if (b->group_variant[g] < -1) order.push_back(g);
+    const size_t n_team = order.size();
+    std::vector<std::pair<int64_t, size_t>> rest;
+    for (size_t g = 0; g < b->groups.size(); ++g)
+        if (b->group_variant[g] >= -1) {
+            int64_t w = 0;
+            for (int32_t r : b->groups[g]) w += b->nfib_of[r];
+            rest.push_back({-w, g});
+        }
+    std::sort(rest.begin(), rest.end());
+    for (auto& pr : rest) order.push_back(pr.second);
+    const bool fork = concurrent && rest.size() > 1;
+    if (fork) {
+        for (int q = 0; q < 3; ++q) {
+            if (!b->aux[q]) HIP_TRY(hipStreamCreateWithFlags(&b->aux[q], hipStreamNonBlocking));
+            if (!b->join_ev[q]) HIP_TRY(hipEventCreateWithFlags(&b->join_ev[q], hipEventDisableTiming));
+        }
+        if (!b->fork_ev) HIP_TRY(hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming));
+    }
+    for (size_t oi = 0; oi < order.size(); ++oi) {
+        const size_t g = order[oi];
+        hipStream_t gs_ = s;
+        if (fork && oi == n_team) {
+            HIP_TRY(hipEventRecord(b->fork_ev, s));
+            for (int q = 0; q < 3; ++q) HIP_TRY(hipStreamWaitEvent(b->aux[q], b->fork_ev, 0));
+        }
+        if (fork && oi > n_team) gs_ = b->aux[(oi - n_team - 1) % 3];
         a.list = b->dlist + b->group_first[g];
         a.n_list = (int32_t)b->groups[g].size();
         a.queue = queues + 2 * g;
         const int v = b->group_variant[g];
-        if (profile) HIP_TRY(hipEventRecord(b->ev[2 * g], s));
+        if (profile) HIP_TRY(hipEventRecord(b->ev[2 * g], gs_));
         if (v >= 0) {
             int per_cu = 1;
             HIP_TRY(max_resident_blocks(v, fp64, a.kinetic != 0, b->group_lds[g], &per_cu));
             if (per_cu < 1) return fail(RVE_EDEVICE, "resident kernel variant does not fit a CU");
             int grid = std::min<int64_t>((int64_t)per_cu * b->n_cu, a.n_list);
-            HIP_TRY(launch_resident(v, fp64, a, b->group_lds[g], grid, s));
+            HIP_TRY(launch_resident(v, fp64, a, b->group_lds[g], grid, gs_));
+        } else if (v < -1) {
+            const int k = b->group_team[g];
+            if (!team_ws) return fail(RVE_EWORKSPACE, "internal: no team work area");
+            int n_teams = 0;
+            int rc = team_grid(b, fp64, a.kinetic != 0, b->group_lds[g], k, &n_teams);
+            if (rc) return rc;
+            // no more teams than RVEs (rounded up to whole XCD sets)
+            n_teams = std::min(n_teams, 8 * (int)((a.n_list + 7) / 8));
+            int64_t mx = 0;
+            for (int32_t r : b->groups[g]) mx = std::max(mx, b->team_xslots[r]);
+            const TeamWs L = team_ws_layout(b, k, n_teams, mx, fp64);
+            TeamArgs ta = b->team_tab;
+            ta.s = a;
+            ta.k = k;
+            ta.kinetic = a.kinetic;
+            ta.xchg = team_area;
+            ta.max_xslots = std::max<int64_t>(mx, 1);
+            ta.partials = reinterpret_cast<double*>(team_area + L.xchg);
+            int32_t* words = reinterpret_cast<int32_t*>(team_area + L.xchg + L.partials);
+            ta.bar = reinterpret_cast<unsigned*>(words);
+            ta.team_task = words + n_teams;
+            ta.error = team_err + g;
+            ta.spin_limit = b->team_spin_limit;
+            HIP_TRY(launch_zero32(words, 3 * (int64_t)n_teams, gs_));
+            HIP_TRY(launch_mark_unfinished(a.list, a.n_list, a.status, gs_));
+            HIP_TRY(launch_team(fp64, ta, b->group_lds[g], n_teams * k, gs_));
         } else {
             int threads = streamed_threads(b, fp64);
             if (!threads) return fail(RVE_EDEVICE, "internal: every streamed kernel build uses private memory");
             a.lds_h_nodes = streamed_lds_nodes(b, b->groups[g].data(), b->groups[g].size(), fp64);
             int grid = std::min<int64_t>((int64_t)b->n_cu * streamed_blocks_per_cu(threads, a.lds_h_nodes, fp64),
                                          a.n_list);
-            HIP_TRY(launch_streamed(fp64, a, grid, threads, s));
+            HIP_TRY(launch_streamed(fp64, a, grid, threads, gs_));
             a.lds_h_nodes = 0;
         }
-        if (profile) HIP_TRY(hipEventRecord(b->ev[2 * g + 1], s));
+        if (profile) HIP_TRY(hipEventRecord(b->ev[2 * g + 1], gs_));
     }
+    if (fork)
+        for (int q = 0; q < 3; ++q) {
+            HIP_TRY(hipEventRecord(b->join_ev[q], b->aux[q]));
+            HIP_TRY(hipStreamWaitEvent(s, b->join_ev[q], 0));
+        }
     const size_t gs = b->groups.size();
     if (profile) HIP_TRY(hipEventRecord(b->ev[2 * gs], s));
     HIP_TRY(launch_stress(a, (int)b->R, s));
@@ -1011,6 +1544,20 @@ static int launch_groups(rve_batch* b, SolveArgs& a, int32_t* queues, void* ws_f
         HIP_TRY(hipEventRecord(b->ev[2 * gs + 1], s));
         b->ev_used = 2 * (int)gs + 2;
     }
+    return RVE_OK;
+}
+
+// After a synchronous solve: did a team launch give up at a barrier?
+static int team_errors(rve_batch* b, const char* team_ws)
+{
+    if (!team_ws || b->groups.empty()) return RVE_OK;
+    std::vector<int32_t> e(b->groups.size(), 0);
+    HIP_TRY(hipMemcpy(e.data(), team_ws, 4 * e.size(), hipMemcpyDeviceToHost));
+    for (size_t g = 0; g < e.size(); ++g)
+        if (e[g])
+            return fail(RVE_EDEVICE, "a team of " + std::to_string(b->group_team[g]) +
+                                         " workgroups waited beyond its limit at a barrier (workgroups not co-resident?); "
+                                         "its RVEs are reported non-finite");
     return RVE_OK;
 }
 
@@ -1124,7 +1671,7 @@ int rve_batch_solve(rve_batch* b, const double* F, double* sigma, int32_t* statu
         rc = rve_naive_run(a, b->fib_off, b->free_off, b->bnd_off, Fh, b->c_host, s, &err);
         if (rc) return fail(rc, err);
     } else {
-        rc = launch_groups(b, a, b->dqueue, b->ws_fib, b->ws_node, s, b->profile);
+        rc = launch_groups(b, a, b->dqueue, b->ws_fib, b->ws_node, b->team_ws, s, b->profile, true);
         if (rc) return rc;
     }
     HIP_TRY(hipMemcpyAsync(sigma, b->dsigma, 72 * b->R, out_kind, s));
@@ -1135,7 +1682,12 @@ int rve_batch_solve(rve_batch* b, const double* F, double* sigma, int32_t* statu
         if (stats->D) HIP_TRY(hipMemcpyAsync(stats->D, b->dD, 8 * b->R, out_kind, s));
         if (stats->Fb) HIP_TRY(hipMemcpyAsync(stats->Fb, b->dB, 8 * b->R, out_kind, s));
     }
-    if (ptr_kind == RVE_PTR_HOST) HIP_TRY(hipStreamSynchronize(s));
+    if (ptr_kind == RVE_PTR_HOST) {
+        HIP_TRY(hipStreamSynchronize(s));
+        b->have_state = true;
+        ++b->generation;
+        return team_errors(b, b->team_ws);
+    }
     b->have_state = true;
     ++b->generation;
     return RVE_OK;
@@ -1329,6 +1881,8 @@ int rve_batch_describe(const rve_batch* b, char* buf, size_t n)
         if (v >= 0)
             d += "resident(" + std::to_string(kResident[v].threads) + "," + std::to_string(kResident[v].sf) + "," +
                  std::to_string(kResident[v].sn) + ")";
+        else if (v < -1)
+            d += "team(" + std::to_string(-1 - v) + "x" + std::to_string(kTeamUnit[b->opts.precision == RVE_FP64].threads) + ")";
         else
             d += streamed_lds_nodes(b, b->groups[g].data(), b->groups[g].size(), b->opts.precision == RVE_FP64) > 0
                      ? "streamed(lds)"
@@ -1637,8 +2191,8 @@ static int tangent_plan(rve_batch* b, int mode, int engine, std::vector<int64_t>
 // tangent/VJP slot area over both engines, the orientation outputs and the
 // state map, each at a 256-byte aligned offset.
 struct WsLayout {
-    size_t fib, node, tmem, slots, omem, smap, var;
-    size_t o_fib, o_node, o_tmem, o_slots, o_omem, o_smap, o_var, total;
+    size_t fib, node, tmem, slots, omem, smap, var, team;
+    size_t o_fib, o_node, o_tmem, o_slots, o_omem, o_smap, o_var, o_team, total;
 };
 
 static int ws_layout(rve_batch* b, WsLayout& L)
@@ -1660,6 +2214,7 @@ static int ws_layout(rve_batch* b, WsLayout& L)
     L.omem = 80 * (size_t)b->R;
     L.smap = 4 * (size_t)b->NN + 4;
     L.var = variant_ws_bytes(b->NFREE, b->NF) + 16 * (size_t)b->R;
+    L.team = team_ws_bytes(b);
     DeviceArena A;
     L.o_fib = A.reserve(L.fib);
     L.o_node = A.reserve(L.node);
@@ -1668,6 +2223,7 @@ static int ws_layout(rve_batch* b, WsLayout& L)
     L.o_omem = A.reserve(L.omem);
     L.o_smap = A.reserve(L.smap);
     L.o_var = A.reserve(L.var);
+    L.o_team = A.reserve(L.team);
     L.total = A.used;
     return RVE_OK;
 }
@@ -1696,7 +2252,10 @@ static void drop_workspace(rve_batch* b)
         if (b->o_mem) (void)hipFree(b->o_mem);
         if (b->d_state_map) (void)hipFree(b->d_state_map);
         if (b->v_ws) (void)hipFree(b->v_ws);
+        if (b->team_ws) (void)hipFree(b->team_ws);
     }
+    b->team_ws = nullptr;
+    b->team_ws_bytes = 0;
     b->ws_fib = b->ws_node = nullptr;
     b->ws_fib_bytes = b->ws_node_bytes = 0;
     b->t_mem = nullptr;
@@ -1747,6 +2306,8 @@ int rve_batch_bind_workspace(rve_batch* b, void* ptr, size_t bytes)
     b->o_mem = reinterpret_cast<double*>(m + L.o_omem);
     b->d_state_map = reinterpret_cast<int32_t*>(m + L.o_smap);
     b->v_ws = reinterpret_cast<double*>(m + L.o_var);
+    b->team_ws = L.team ? m + L.o_team : nullptr;
+    b->team_ws_bytes = L.team;
     return RVE_OK;
 }
 
@@ -2035,12 +2596,18 @@ void rve_batch_destroy(rve_batch* b)
 {
     if (!b) return;
     for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
+    for (int q = 0; q < 3; ++q) {
+        if (b->aux[q]) (void)hipStreamDestroy(b->aux[q]);
+        if (b->join_ev[q]) (void)hipEventDestroy(b->join_ev[q]);
+    }
+    if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
     drop_workspace(b);
     if (b->probe) rve_batch_destroy(b->probe);
     if (b->d_probe_map) (void)hipFree(b->d_probe_map);
     if (b->d_fd_rot) (void)hipFree(b->d_fd_rot);
     if (b->dtune_list) (void)hipFree(b->dtune_list);
     if (b->d_xm_free) (void)hipFree(b->d_xm_free);
+    if (b->team_mem) (void)hipFree(b->team_mem);
     if (b->dmem) (void)hipFree(b->dmem);
     delete b;
 }
@@ -2057,14 +2624,13 @@ void rve_batch_destroy(rve_batch* b)
 // library holds its own copy until the process ends; its address is taken
 // once per device with hipGetSymbolAddress and kept (the array's name in
 // host code is a host-side stand-in, never a device address).
-constexpr size_t kStaticScratchBytes = size_t(1) << 30;
+constexpr size_t kStaticScratchBytes = size_t(256) << 20;
 __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
 
-namespace {
-std::mutex g_scratch_mu;
-void* g_scratch_ptr[64] = {};
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64] = {};
 
-int device_scratch(int dev, void** out)
+static int device_scratch(int dev, void** out)
 {
     if (dev < 0 || dev >= 64) return fail(RVE_EDEVICE, "device index beyond the scratch table");
     std::lock_guard<std::mutex> lock(g_scratch_mu);
@@ -2082,7 +2648,6 @@ int device_scratch(int dev, void** out)
     *out = g_scratch_ptr[dev];
     return RVE_OK;
 }
-}  // namespace
 
 extern "C" int rve_batch_solve_static(rve_batch* b, const double* F, double* sigma, int32_t* status,
                                       int32_t ptr_kind)
@@ -2098,17 +2663,21 @@ extern "C" int rve_batch_solve_static(rve_batch* b, const double* F, double* sig
     if (b->opts.init == RVE_INIT_WARM && !b->have_state)
         return fail(RVE_ESTATE, "warm start requested before any solve");
     const bool fp64 = b->opts.precision == RVE_FP64;
-    bool streamed = false;
-    for (int v : b->group_variant) streamed |= (v < 0);
-    // layout: work counters (two per launch group), then the streamed
-    // workspace of this batch's precision
+    bool streamed = false, team = false;
+    for (int v : b->group_variant) {
+        streamed |= (v == -1);
+        team |= (v < -1);
+    }
+    // layout: work counters (two per launch group), the team work area, then
+    // the streamed workspace of this batch's precision
     const size_t counters = 256 * ((8 * b->groups.size() + 255) / 256 + 1);
+    const size_t tw = team ? (team_ws_bytes(b) + 255) & ~size_t(255) : 0;
     const size_t r4 = fp64 ? 32 : 16;
     const size_t fb = streamed ? r4 * 3 * (size_t)(b->NF + b->R) : 0;
     const size_t nb = streamed ? r4 * (2 * (size_t)(b->NFREE + b->R) + 2 * (size_t)b->NFREE + 1) : 0;
     const size_t fb_al = (fb + 255) & ~size_t(255);
-    if (counters + fb_al + nb > kStaticScratchBytes)
-        return fail(RVE_EWORKSPACE, "the batch needs " + std::to_string(counters + fb_al + nb) +
+    if (counters + tw + fb_al + nb > kStaticScratchBytes)
+        return fail(RVE_EWORKSPACE, "the batch needs " + std::to_string(counters + tw + fb_al + nb) +
                                         " bytes of work area, beyond the " + std::to_string(kStaticScratchBytes) +
                                         " of the allocation-free solve");
     void* base = nullptr;
@@ -2116,8 +2685,9 @@ extern "C" int rve_batch_solve_static(rve_batch* b, const double* F, double* sig
     if (rc) return rc;
     char* sp = static_cast<char*>(base);
     int32_t* queues = reinterpret_cast<int32_t*>(sp);
-    void* ws_fib = streamed ? sp + counters : nullptr;
-    void* ws_node = streamed ? sp + counters + fb_al : nullptr;
+    char* team_ws = team ? sp + counters : nullptr;
+    void* ws_fib = streamed ? sp + counters + tw : nullptr;
+    void* ws_node = streamed ? sp + counters + tw + fb_al : nullptr;
 
     hipStream_t s = (hipStream_t)b->opts.stream;
     const hipMemcpyKind in_kind = ptr_kind == RVE_PTR_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
@@ -2126,13 +2696,16 @@ extern "C" int rve_batch_solve_static(rve_batch* b, const double* F, double* sig
     SolveArgs a{};
     fill_solve_args(b, a);
     a.init = b->opts.init;
-    rc = launch_groups(b, a, queues, ws_fib, ws_node, s, false);
+    rc = launch_groups(b, a, queues, ws_fib, ws_node, team_ws, s, false, false);
     if (rc) return rc;
     HIP_TRY(hipMemcpyAsync(sigma, b->dsigma, 72 * b->R, out_kind, s));
     HIP_TRY(hipMemcpyAsync(status, b->dstatus, 4 * b->R, out_kind, s));
-    if (ptr_kind == RVE_PTR_HOST) HIP_TRY(hipStreamSynchronize(s));
     b->have_state = true;
     b->last_variant = false;
     ++b->generation;
+    if (ptr_kind == RVE_PTR_HOST) {
+        HIP_TRY(hipStreamSynchronize(s));
+        return team_errors(b, team_ws);
+    }
     return RVE_OK;
 }

@@ -185,6 +185,50 @@ struct RedSlots {
 // Static LDS of a resident workgroup: the reduction slots and the task id.
 constexpr size_t kResStaticLds = sizeof(RedSlots) + 16;
 
+// Team engine (rve_team.hip): k workgroups per RVE.  Part p of an RVE owns a
+// range of its free nodes and evaluates every fiber with a free end among
+// them; its local position slots are [owned | halo | zero slot].
+struct TeamPart {
+    int64_t fib0;    // first entry of the part in fib_gid / fib_ends
+    int64_t own0;    // first entry in own_gid / own_xslot / own_inc_off
+    int64_t halo0;   // first entry in halo_gid / halo_xslot
+    int64_t bnd0;    // first entry in bnd_inc_off
+    int32_t nfib, nown, nhalo, nbnd;
+};
+struct TeamArgs {
+    SolveArgs s;                  // network, options, outputs, work list and counter
+    const TeamPart* parts;        // [sum k] part records
+    const int64_t* part_first;    // [R] first part record of each RVE (-1: not a team RVE)
+    const int32_t* fib_gid;       // packed global fiber id of each part fiber
+    const uint32_t* fib_ends;     // local ends i | (j << 16) (zero slot for boundary ends)
+    const int32_t* own_gid;       // packed global free-node id of each owned node
+    const int32_t* own_xslot;     // its exchange slot, -1 when no other part needs it
+    const int64_t* own_inc_off;   // [per part: nown + 1] incidence of owned nodes (codes below)
+    const uint16_t* own_inc;      // local fiber id (15 bits) | 0x8000 when the node is end i
+    const int32_t* halo_gid;      // packed global free-node id of each halo node
+    const int32_t* halo_xslot;    // its exchange slot
+    const int64_t* bnd_inc_off;   // [per part: nbnd + 1] incidence of the boundary nodes the part reduces
+    const uint16_t* bnd_inc;
+    int32_t k;                    // workgroups per RVE
+    int32_t kinetic;
+    void* xchg;                   // [teams][2][max_xslots][9] Real: h, v, a of exported nodes
+    int64_t max_xslots;
+    double* partials;             // [teams][2][k][8]
+    unsigned* bar;                // [teams] barrier counters, zero at launch
+    int32_t* team_task;           // [teams][2]
+    int32_t* error;               // set when a team barrier gave up
+    int64_t spin_limit;
+};
+struct TeamUnit {
+    int threads, sf, sn;
+};
+extern const TeamUnit kTeamUnit[2];   // [fp64]
+constexpr int kTeamMax = 16;          // largest team
+hipError_t launch_team(bool fp64, const TeamArgs& a, size_t lds_bytes, int grid, hipStream_t s);
+// occupancy (workgroups per CU) and private bytes of the team build
+hipError_t team_info(bool fp64, bool kin, size_t lds_bytes, int* blocks_per_cu, size_t* private_bytes);
+size_t team_lds_bytes(bool fp64, int64_t n_pos, int64_t nfib);   // n_pos: owned + halo nodes
+
 // Which register-resident variants exist (threads per RVE, fiber slots per
 // thread, free-node slots per thread).
 struct ResidentVariant {
@@ -203,6 +247,8 @@ hipError_t launch_streamed(bool fp64, const SolveArgs& a, int grid, int threads,
 size_t streamed_lds_cap();   // bytes of LDS the streamed engine may use for h
 hipError_t launch_stress(const SolveArgs& a, int n_rve, hipStream_t s);
 hipError_t launch_reset(int32_t* counters, int n, hipStream_t s);   // n <= 64
+hipError_t launch_zero32(int32_t* p, int64_t n, hipStream_t s);
+hipError_t launch_mark_unfinished(const int32_t* list, int n, int32_t* status, hipStream_t s);
 // Tangent / VJP.  prep: statuses, ELL records (first call), fiber operators
 // and preconditioner for every RVE.  Then the tasks of the RVEs in a.order:
 // register/LDS-resident workgroups (variant v, RVEs with at most

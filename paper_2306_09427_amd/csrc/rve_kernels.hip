@@ -1352,6 +1352,36 @@ __global__ void reset_counters(int32_t* c, int n)
     if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
 }
 
+// Fill n words with zero (graph-capturable, unlike a memset node).
+__global__ void zero_words(int32_t* p, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+// Before a team launch: every RVE of its list starts as non-finite, so an RVE
+// that a launch which gave up never reached reports it.
+__global__ void mark_unfinished(const int32_t* list, int n, int32_t* status)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) status[list[i]] = ST_NONFINITE;
+}
+
+hipError_t launch_zero32(int32_t* p, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const unsigned grid = (unsigned)std::min<int64_t>(1024, (n + 255) / 256);
+    hipLaunchKernelGGL(zero_words, dim3(grid), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_mark_unfinished(const int32_t* list, int n, int32_t* status, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(mark_unfinished, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, list, n, status);
+    return hipGetLastError();
+}
+
 hipError_t launch_reset(int32_t* counters, int n, hipStream_t s)
 {
     hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, s, counters, n);
@@ -1463,7 +1493,9 @@ hipError_t streamed_scratch_bytes(bool fp64, bool kin, int threads, size_t* byte
 
 hipError_t kernels_fixed_private(size_t* bytes)
 {
-    return max_private_bytes({(const void*)stress_kernel, (const void*)reset_counters}, bytes);
+    return max_private_bytes({(const void*)stress_kernel, (const void*)reset_counters, (const void*)zero_words,
+                              (const void*)mark_unfinished},
+                             bytes);
 }
 
 }  // namespace rve

@@ -711,7 +711,7 @@ __device__ __forceinline__ bool team_solve(const TeamArgs& A, int r, int team, i
 // The team's rank-0 workgroup takes the next RVE from the launch's work
 // counter and hands it to the others through the team's task slot.
 template <typename Real, int T, int SF, int SN, bool KIN>
-__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 4 : 2)))
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 && T == 1024 ? 4 : (sizeof(Real) == 4 ? 3 : 2))))
 void dr_team_kernel(TeamArgs A)
 {
     extern __shared__ char smem[];
@@ -738,9 +738,9 @@ void dr_team_kernel(TeamArgs A)
 
 }  // namespace
 
-// Team builds: FP32 with 4 fiber and 2 node slots per thread of 1024, FP64
-// with 6 and 3 per thread of 512 (the resident builds that fit their
-// register budgets without private memory).
+// Team builds: FP32 with 4 fiber and 2 node slots per thread of 768 (168
+// VGPRs), FP64 with 6 and 3 per thread of 512 (256 VGPRs); both fit their
+// register budgets without private memory.
 template <typename Real, int T, int SF, int SN>
 static hipError_t launch_team_t(const TeamArgs& a, size_t lds, int grid, hipStream_t s)
 {
@@ -766,17 +766,17 @@ static hipError_t team_info_t(bool kin, size_t lds, int* blocks, size_t* priv)
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k, T, lds);
 }
 
-const TeamUnit kTeamUnit[2] = {{1024, 4, 2}, {512, 6, 3}};   // [fp64]
+const TeamUnit kTeamUnit[2] = {{768, 4, 2}, {512, 6, 3}};   // [fp64]
 
 hipError_t launch_team(bool fp64, const TeamArgs& a, size_t lds, int grid, hipStream_t s)
 {
-    return fp64 ? launch_team_t<double, 512, 6, 3>(a, lds, grid, s) : launch_team_t<float, 1024, 4, 2>(a, lds, grid, s);
+    return fp64 ? launch_team_t<double, 512, 6, 3>(a, lds, grid, s) : launch_team_t<float, 768, 4, 2>(a, lds, grid, s);
 }
 
 hipError_t team_info(bool fp64, bool kin, size_t lds, int* blocks_per_cu, size_t* private_bytes)
 {
     return fp64 ? team_info_t<double, 512, 6, 3>(kin, lds, blocks_per_cu, private_bytes)
-                : team_info_t<float, 1024, 4, 2>(kin, lds, blocks_per_cu, private_bytes);
+                : team_info_t<float, 768, 4, 2>(kin, lds, blocks_per_cu, private_bytes);
 }
 
 size_t team_lds_bytes(bool fp64, int64_t n_pos, int64_t nfib)

@@ -68,3 +68,15 @@ def test_planted_lds_mistake_is_reported(cfg2):
     with pytest.raises(rb.RVEError) as e:
         rb.check_indexing(cfg2, rb.MIXED, plant=1)
     assert "outside the LDS array" in str(e.value)
+
+
+@pytest.mark.parametrize("precision", [rb.FP64, rb.MIXED])
+def test_large_rve_team_partitions_index_in_bounds(precision):
+    """2000-seed RVEs (the large-RVE workload) take the team engine: the
+    replay checks each part's tables (every free node owned once, every
+    fiber of an owned node in the part, local ends naming the true ends,
+    incidence codes naming the node's own fibers with its end's sign, halo
+    exchange slots equal to the owners', capacities and LDS)."""
+    batch = synth.make_config_batch(3, idx=[0, 1], workers=2)[0]
+    assert np.diff(batch.fib_off).min() > 6144
+    rb.check_indexing(batch, precision)
