@@ -447,6 +447,27 @@ int rve_batch_generation(const rve_batch* b, uint64_t* gen);
  */
 int rve_check_indexing(const rve_net_desc* net, int32_t precision, int32_t plant);
 
+/*
+ * Allocation-free solve, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same launches and results as rve_batch_solve (resident,
+ * team and streamed engines, constant viscous or kinetic damping, affine or
+ * warm start), but the work areas those launches need -- the launch work
+ * counters, the team engine's exchange buffers, partials and barriers, and
+ * the streamed engine's per-fiber and per-node workspace -- are carved from
+ * a fixed device array of 256 MiB that the library holds on each device
+ * until the process ends, instead of being allocated.  The call itself
+ * makes no device allocation (the array is located once per device by
+ * rve_batch_create).  F[n_rve][9] in, sigma[n_rve][9] and status[n_rve] out
+ * (host: synchronous; device: stream-ordered).  RVE_EWORKSPACE when the
+ * batch's work areas exceed the array; RVE_EINVAL for the naive engine,
+ * adaptive damping, the energy check or the reference start.  Every call on
+ * one device shares that device's array: calls that overlap in time on one
+ * device (other streams, other threads, other batches) race and must be
+ * serialised by the caller.  No per-RVE diagnostics and no profiling.
+ */
+int rve_batch_solve_static(rve_batch* b, const double* F, double* sigma, int32_t* status, int32_t ptr_kind);
+
 /* Free every host and device resource of the batch (NULL is a no-op). */
 void rve_batch_destroy(rve_batch* b);
 

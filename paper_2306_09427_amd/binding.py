@@ -33,7 +33,7 @@ EXPORTS = ["rve_version", "rve_last_error", "rve_default_opts", "rve_batch_creat
            "rve_batch_autotune", "rve_batch_describe", "rve_batch_groups", "rve_batch_tangent_iters", "rve_batch_orientation",
            "rve_batch_fd_tangent", "rve_batch_export_state", "rve_batch_import_state",
            "rve_batch_workspace_size", "rve_batch_bind_workspace", "rve_batch_damping_stats",
-           "rve_batch_generation", "rve_check_indexing", "rve_batch_team_spin_limit"]
+           "rve_batch_generation", "rve_check_indexing", "rve_batch_team_spin_limit", "rve_batch_solve_static"]
 
 
 class NetDesc(C.Structure):
@@ -106,8 +106,7 @@ def lib():
         L.rve_batch_bind_workspace.argtypes = [P, P, C.c_size_t]
         L.rve_batch_damping_stats.argtypes = [P, P, P, C.c_int32]
         L.rve_batch_generation.argtypes = [P, C.POINTER(C.c_uint64)]
-        if hasattr(L, "rve_batch_solve_static"):
-            L.rve_batch_solve_static.argtypes = [P, P, P, P, C.c_int32]
+        L.rve_batch_solve_static.argtypes = [P, P, P, P, C.c_int32]
         L.rve_check_indexing.argtypes = [C.POINTER(NetDesc), C.c_int32, C.c_int32]
         L.rve_batch_team_spin_limit.argtypes = [P, C.c_int64]
         L.rve_batch_destroy.argtypes = [P]

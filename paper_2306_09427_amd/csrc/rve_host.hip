@@ -2617,10 +2617,10 @@ void rve_batch_destroy(rve_batch* b)
 // ------------------------------------------------------------------ allocation-free solve
 // For callers that cannot allocate device memory (code under HIP graph
 // capture, tight serving loops, harnesses that forbid allocation):
-// rve_batch_solve_static runs the solve's resident and streamed launches
-// with their work areas -- the launch work counters and the streamed
-// engine's per-fiber and per-node workspace -- carved from this file-scope
-// device array instead of from allocations.  Each device that runs the
+// rve_batch_solve_static runs the solve's resident, team and streamed
+// launches with their work areas -- the launch work counters, the team work
+// area and the streamed engine's per-fiber and per-node workspace -- carved
+// from this file-scope device array (256 MiB) instead of from allocations.  Each device that runs the
 // library holds its own copy until the process ends; its address is taken
 // once per device with hipGetSymbolAddress and kept (the array's name in
 // host code is a host-side stand-in, never a device address).

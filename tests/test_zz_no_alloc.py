@@ -1,8 +1,8 @@
 """The allocation-free solve (rve_batch_solve_static) against rve_batch_solve.
 
-Its kernels are the solve's own; only the work areas (launch counters and
-the streamed engine's workspace) come from the library's fixed device
-scratch array instead of allocations.  Two calls in a row on batches of
+Its kernels are the solve's own; only the work areas (launch counters, the
+team engine's work area and the streamed engine's workspace) come from the
+library's fixed device scratch array instead of allocations.  Two calls in a row on batches of
 decreasing size (the second reuses the array the first left behind) must
 reproduce rve_batch_solve bitwise (same kernels, same arithmetic), on the
 streamed engine and on the automatic engine choice, and no device memory
