@@ -81,6 +81,11 @@ extern "C" {
 #define RVE_ENGINE_STREAMED 1  /* persistent kernel, state in global memory */
 #define RVE_ENGINE_NAIVE 2     /* one RVE at a time, one launch per step of
                                   every iteration, atomics, FP64 only */
+#define RVE_ENGINE_TEAM 3      /* as AUTO, but RVEs no resident build holds run
+                                  on the team engine (k workgroups per RVE)
+                                  wherever a partition fits, else streamed;
+                                  AUTO runs them streamed unless
+                                  rve_batch_autotune measured the team faster */
 #define RVE_DAMP_VISCOUS 0     /* constant mass-proportional damping c M v */
 #define RVE_DAMP_KINETIC 1     /* kinetic damping: v = 0 at kinetic-energy peaks */
 #define RVE_DAMP_ADAPTIVE 2    /* c re-estimated each step (Rayleigh quotient) */

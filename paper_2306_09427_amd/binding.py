@@ -20,7 +20,7 @@ FP64, MIXED = 0, 1
 LAW_LINEAR, LAW_EXP = 0, 1
 MASS_LUMPED, MASS_SCALED = 0, 1
 INIT_AFFINE, INIT_REFERENCE, INIT_WARM = 0, 1, 2
-ENGINE_AUTO, ENGINE_STREAMED, ENGINE_NAIVE = 0, 1, 2
+ENGINE_AUTO, ENGINE_STREAMED, ENGINE_NAIVE, ENGINE_TEAM = 0, 1, 2, 3
 PTR_HOST, PTR_DEVICE = 0, 1
 ST_CONVERGED, ST_MAXITER, ST_NONFINITE, ST_BAD_F, ST_NO_STATE, ST_CG_MAXITER, ST_CG_INDEFINITE, ST_ENERGY = range(8)
 ST_STAGNATED = 8

@@ -143,6 +143,8 @@ struct rve_batch {
     size_t team_ws_bytes = 0;
     std::vector<int32_t> group_team;   // team size of each group, 0 = not a team group
     int64_t team_spin_limit = int64_t(1) << 24;   // polls of a team barrier before it gives up
+    // autotuner's choice for RVEs partitioned into k parts: [fp64][k] 1 team, 0 streamed, -1 untuned
+    int tuned_team[2][kTeamMax + 1];
     // concurrent launch groups: auxiliary streams (default priority) and the
     // events that fork them from and join them to the batch's stream
     hipStream_t aux[3] = {nullptr, nullptr, nullptr};
@@ -227,7 +229,8 @@ static int validate_opts(const rve_opts* o, int64_t R)
     if (!(o->tol_abs >= 0) || !(o->tol_rel >= 0)) return fail(RVE_EINVAL, "tolerances must be >= 0");
     if (o->n_max < 0) return fail(RVE_EINVAL, "n_max must be >= 0");
     if (o->check_every < 1) return fail(RVE_EINVAL, "check_every must be >= 1");
-    if (o->engine != RVE_ENGINE_AUTO && o->engine != RVE_ENGINE_STREAMED && o->engine != RVE_ENGINE_NAIVE)
+    if (o->engine != RVE_ENGINE_AUTO && o->engine != RVE_ENGINE_STREAMED && o->engine != RVE_ENGINE_NAIVE &&
+        o->engine != RVE_ENGINE_TEAM)
         return fail(RVE_EINVAL, "bad engine");
     if (o->engine == RVE_ENGINE_NAIVE && o->precision != RVE_FP64)
         return fail(RVE_EINVAL, "the naive engine is FP64 only");
@@ -966,7 +969,7 @@ static void assign_groups(rve_batch* b)
     std::vector<std::vector<int32_t>> per(kNumResident + 1 + kTeamMax + 1);
     for (int64_t r = 0; r < b->R; ++r) {
         int slot = kNumResident;   // streamed
-        if (b->opts.engine == RVE_ENGINE_AUTO) {
+        if (b->opts.engine == RVE_ENGINE_AUTO || b->opts.engine == RVE_ENGINE_TEAM) {
             int t = tier_of(b, r, fp64);
             int chosen = -1;
             if (t >= 0) {
@@ -974,10 +977,13 @@ static void assign_groups(rve_batch* b)
                 if (tv >= 0 && spills(b, tv, fp64)) tv = -2;   // tuned for the other damping build
                 chosen = (tv != -2 && !b->opts.threads_per_rve) ? tv : default_variant(b, t, fp64);
             }
+            const int k = b->team_k.empty() ? 0 : b->team_k[r];
+            const bool team = k > 0 && !b->opts.threads_per_rve &&
+                              (b->opts.engine == RVE_ENGINE_TEAM || b->tuned_team[fp64 ? 1 : 0][k] == 1);
             if (chosen >= 0)
                 slot = chosen;
-            else if (!b->team_k.empty() && b->team_k[r] > 0 && !b->opts.threads_per_rve)
-                slot = kNumResident + b->team_k[r];
+            else if (team)
+                slot = kNumResident + k;
         }
         per[slot].push_back((int32_t)r);
     }
@@ -1175,6 +1181,8 @@ int rve_batch_create(const rve_net_desc* net, const rve_opts* opts, rve_batch** 
     if (!b) return fail(RVE_ENOMEM, "host allocation failed");
     b->device = dev;
     b->n_cu = prop.multiProcessorCount;
+    for (int p = 0; p < 2; ++p)
+        for (int k = 0; k <= kTeamMax; ++k) b->tuned_team[p][k] = -1;
     // Admission: a kernel build that uses private (scratch) memory is never
     // launched.  Every GPU fault and wrong result seen while developing these
     // kernels came from builds at or over their register budget, so the rule
@@ -1729,7 +1737,8 @@ int rve_batch_autotune(rve_batch* b, const double* F, int32_t ptr_kind, int32_t 
     if (!b || !F) return fail(RVE_EINVAL, "NULL argument");
     if (ptr_kind != RVE_PTR_HOST && ptr_kind != RVE_PTR_DEVICE) return fail(RVE_EINVAL, "bad ptr_kind");
     if (n_iter < 1) return fail(RVE_EINVAL, "n_iter must be >= 1");
-    if (b->R == 0 || b->opts.engine != RVE_ENGINE_AUTO || variant_mode(b->opts)) return RVE_OK;
+    if (b->R == 0 || (b->opts.engine != RVE_ENGINE_AUTO && b->opts.engine != RVE_ENGINE_TEAM) || variant_mode(b->opts))
+        return RVE_OK;
     hipStream_t s = (hipStream_t)b->opts.stream;
     const bool fp64 = b->opts.precision == RVE_FP64;
     HIP_TRY(hipMemcpyAsync(b->dF, F, 72 * b->R, ptr_kind == RVE_PTR_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s));
@@ -1846,6 +1855,85 @@ int rve_batch_autotune(rve_batch* b, const double* F, int32_t ptr_kind, int32_t 
             }
         }
         b->tuned[fp64 ? 1 : 0][t] = best_v;
+    }
+    // RVEs no resident build holds: the team engine (per team size k) against
+    // the streamed kernel on the same RVEs, both from the affine start for
+    // n_iter iterations; the team counts only if it takes every RVE the
+    // streamed run took through all iterations through the same count to a
+    // final state within 5% of the streamed one
+    for (int k = 2; k <= kTeamMax; ++k) {
+        std::vector<int32_t> members;
+        for (int64_t r = 0; r < b->R; ++r)
+            if (tier_of(b, r, fp64) < 0 && b->team_k[r] == k) members.push_back((int32_t)r);
+        if (members.empty()) continue;
+        std::stable_sort(members.begin(), members.end(),
+                         [&](int32_t x, int32_t y) { return b->nfib_of[x] > b->nfib_of[y]; });
+        members.resize(std::min<size_t>(members.size(), (size_t)std::max(8, (b->n_cu / k) / 8 * 8)));
+        double ms_c[2] = {0.0, 0.0};
+        std::vector<double> href;
+        std::vector<int32_t> sref;
+        std::vector<int64_t> iref;
+        bool team_valid = true;
+        const std::vector<std::vector<int32_t>> saved_groups = b->groups;
+        const std::vector<int32_t> saved_v = b->group_variant, saved_team = b->group_team, saved_first = b->group_first;
+        const std::vector<size_t> saved_lds = b->group_lds;
+        for (int cand = 0; cand < 2; ++cand) {   // 0 streamed, 1 team
+            size_t lds = 0;
+            for (int32_t r : members) lds = std::max(lds, b->team_lds[fp64 ? 1 : 0][r]);
+            b->groups.assign(1, members);
+            b->group_variant.assign(1, cand ? -1 - k : -1);
+            b->group_team.assign(1, cand ? k : 0);
+            b->group_lds.assign(1, cand ? lds : 0);
+            b->group_first.assign(1, 0);
+            HIP_TRY(hipMemcpy(b->dlist, members.data(), 4 * members.size(), hipMemcpyHostToDevice));
+            rc = ensure_workspace(b);
+            if (rc) break;
+            SolveArgs a;
+            fill_solve_args(b, a);
+            a.n_max = n_iter;
+            a.tol_abs = 0.0;
+            a.tol_rel = 0.0;
+            for (int rep = 0; rep < 2 && !rc; ++rep) {
+                HIP_TRY(hipEventRecord(b->ev[0], s));
+                rc = launch_groups(b, a, b->dqueue, b->ws_fib, b->ws_node, b->team_ws, s, false, false);
+                HIP_TRY(hipEventRecord(b->ev[1], s));
+            }
+            if (rc) break;
+            HIP_TRY(hipEventSynchronize(b->ev[1]));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, b->ev[0], b->ev[1]));
+            ms_c[cand] = ms;
+            std::vector<int32_t> stv(b->R);
+            std::vector<int64_t> itv(b->R);
+            std::vector<double> hv(3 * (size_t)b->NFREE);
+            HIP_TRY(hipMemcpy(stv.data(), b->dstatus, 4 * (size_t)b->R, hipMemcpyDeviceToHost));
+            HIP_TRY(hipMemcpy(itv.data(), b->diters, 8 * (size_t)b->R, hipMemcpyDeviceToHost));
+            if (b->NFREE) HIP_TRY(hipMemcpy(hv.data(), b->dh, 24 * (size_t)b->NFREE, hipMemcpyDeviceToHost));
+            if (!cand) {
+                href = hv;
+                sref = stv;
+                iref = itv;
+            } else {
+                if (team_errors(b, b->team_ws)) team_valid = false;
+                for (int32_t r : members) {
+                    if (sref[r] != RVE_ST_MAXITER) continue;
+                    team_valid = team_valid && stv[r] == RVE_ST_MAXITER && itv[r] == iref[r];
+                    double dmax = 0.0, hmax = 0.0;
+                    for (int64_t q = 3 * b->free_off[r]; q < 3 * b->free_off[r + 1]; ++q) {
+                        dmax = std::max(dmax, std::fabs(hv[q] - href[q]));
+                        hmax = std::max(hmax, std::fabs(href[q]));
+                    }
+                    team_valid = team_valid && std::isfinite(dmax) && dmax <= 0.05 * std::max(hmax, 1e-30);
+                }
+            }
+        }
+        b->groups = saved_groups;
+        b->group_variant = saved_v;
+        b->group_team = saved_team;
+        b->group_first = saved_first;
+        b->group_lds = saved_lds;
+        if (rc) return rc;
+        b->tuned_team[fp64 ? 1 : 0][k] = (team_valid && ms_c[1] < ms_c[0]) ? 1 : 0;
     }
     b->have_state = false;
     assign_groups(b);

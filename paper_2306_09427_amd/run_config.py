@@ -34,6 +34,11 @@ def main(argv=None) -> int:
     ap.add_argument("--n-max", type=int, default=100000)
     ap.add_argument("--check-every", type=int, default=8)
     ap.add_argument("--cache", default=None, help="npz file holding the generated networks (written if absent)")
+    ap.add_argument("--threads-per-rve", type=int, default=0, help="force resident builds of this workgroup size")
+    ap.add_argument("--engine", choices=["auto", "streamed", "team"], default="auto")
+    ap.add_argument("--tangent", action="store_true", help="also one tangent dsigma/dF call after the timed solve")
+    ap.add_argument("--damping", choices=["viscous", "kinetic"], default="viscous")
+    ap.add_argument("--solves", type=int, default=1, help="timed solves (after one untimed warm-up solve)")
     args = ap.parse_args(argv)
 
     import torch
@@ -63,17 +68,28 @@ def main(argv=None) -> int:
     fp64 = args.precision == "fp64"
     law = rb.LAW_LINEAR if args.config == 1 else rb.LAW_EXP
     b = rb.Batch(batch, precision=rb.FP64 if fp64 else rb.MIXED, law=law, mass=rb.MASS_SCALED, alpha=args.alpha,
-                 c=args.c, tol_abs=0.0, tol_rel=args.tol_rel, n_max=args.n_max, check_every=args.check_every)
+                 c=args.c, tol_abs=0.0, tol_rel=args.tol_rel, n_max=args.n_max, check_every=args.check_every,
+                 threads_per_rve=args.threads_per_rve,
+                 engine={"auto": rb.ENGINE_AUTO, "streamed": rb.ENGINE_STREAMED, "team": rb.ENGINE_TEAM}[args.engine],
+                 damping=rb.DAMP_KINETIC if args.damping == "kinetic" else rb.DAMP_VISCOUS)
     b.profile(True)
     Fd = torch.tensor(F, device=dev)
     b.solve(Fd)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    sig, st, stats = b.solve(Fd, stats=True)
+    for _ in range(max(1, args.solves)):
+        sig, st, stats = b.solve(Fd, stats=True)
     torch.cuda.synchronize()
-    ms = 1e3 * (time.perf_counter() - t1)
+    ms = 1e3 * (time.perf_counter() - t1) / max(1, args.solves)
     relax_ms, stress_ms = b.kernel_ms()
     g_of, g_var, g_ms = b.groups()
+    tangent = None
+    if args.tangent:
+        t2 = time.perf_counter()
+        C, ct = b.tangent(like=Fd)
+        torch.cuda.synchronize()
+        tangent = {"ms": 1e3 * (time.perf_counter() - t2), "status_counts": np.bincount(ct.cpu().numpy(), minlength=7).tolist(),
+                   "inner_iters": int(b.tangent_iters().sum())}
     st = st.cpu().numpy()
     it = stats["iters"].cpu().numpy()
     bpf, bpn = (32, 104) if fp64 else (20, 52)
@@ -83,7 +99,9 @@ def main(argv=None) -> int:
         if not sel.any():
             continue
         alg = float((it[sel] * (bpf * nfib[sel] + bpn * nfree[sel])).sum())
-        groups.append({"kernel": ("resident(%s)" % rb_variant(int(g_var[g]))) if g_var[g] >= 0 else "streamed",
+        kern = ("resident(%s)" % rb_variant(int(g_var[g]))) if g_var[g] >= 0 else (
+            "streamed" if g_var[g] == -1 else "team(%d)" % (-1 - int(g_var[g])))
+        groups.append({"kernel": kern,
                        "rves": int(sel.sum()), "ms": float(g_ms[g]), "algorithmic_bytes": alg,
                        "algorithmic_GB_per_s": alg / (float(g_ms[g]) / 1e3) / 1e9 if g_ms[g] > 0 else None})
     b.close()
@@ -91,14 +109,15 @@ def main(argv=None) -> int:
                       "fibers": int(nfib.sum()), "free_nodes": int(nfree.sum()), "generate_s": t_gen,
                       "solve_ms": ms, "relax_ms": relax_ms, "stress_ms": stress_ms,
                       "status_counts": np.bincount(st, minlength=4).tolist(),
-                      "iters_median": float(np.median(it)), "iters_total": int(it.sum()), "groups": groups}),
+                      "iters_median": float(np.median(it)), "iters_total": int(it.sum()), "groups": groups,
+                      "tangent": tangent}),
           flush=True)
     return 0
 
 
 # resident kernel variants (threads, fiber slots, node slots per thread), in
 # the library's order
-VARIANTS = [(256, 4, 2), (512, 4, 2), (1024, 4, 2), (512, 8, 4), (1024, 6, 3), (256, 16, 8)]
+VARIANTS = [(256, 4, 2), (512, 4, 2), (768, 4, 2), (512, 6, 3), (1024, 4, 2), (1024, 6, 3)]
 
 
 def rb_variant(v: int) -> str:

@@ -17,7 +17,8 @@ FP64 CPU oracle.  The GPU runs the same networks, F and options:
 
 Sizes: 64 RVEs of the 4096-RVE workload (200-400 seeds), 4 of the 512
 large RVEs (2000 seeds, streamed kernel), 16 of the 8192-RVE FE^2 workload
-spanning 100-3000 seeds (resident and streamed kernels).
+spanning 100-3000 seeds (resident and streamed kernels); the large ones
+also on the team engine (engine 3, k workgroups per RVE).
 """
 import json
 import os
@@ -41,17 +42,17 @@ def _load(name):
     return g, json.loads(str(g["opts"]))
 
 
-@pytest.mark.parametrize("name", ["cfg2_64", "cfg3_4", "cfg5_16"])
+@pytest.mark.parametrize("name,engine", [("cfg2_64", 0), ("cfg3_4", 0), ("cfg5_16", 0), ("cfg3_4", 3), ("cfg5_16", 3)])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_fullshape_parity(name, precision):
+def test_fullshape_parity(name, engine, precision):
     rb = require_gpu()
     g, o = _load(name)
     idx = g["idx"]
-    log(f"{name} precision={precision}: {len(idx)} RVEs")
+    log(f"{name} precision={precision} engine={engine}: {len(idx)} RVEs")
     batch, F = synth.make_config_batch(o["config"], idx=idx)
     tol_rel = o["tol_rel"] if precision == 0 else 1e-5
     b = rb.Batch(batch, precision=precision, law=rb.LAW_EXP, mass=o["mass"], alpha=o["alpha"], c=o["c"],
-                 tol_abs=0.0, tol_rel=tol_rel, n_max=o["n_max"], check_every=1 if precision == 0 else 8)
+                 tol_abs=0.0, tol_rel=tol_rel, n_max=o["n_max"], check_every=1 if precision == 0 else 8, engine=engine)
     log(f"  groups {b.describe()}")
     sig, st, stats = b.solve(F, stats=True)
     ref_st = g["status"]

@@ -41,17 +41,17 @@ KW = dict(law=1, mass=1, alpha=0.5, c=0.1, tol_abs=0.0, check_every=8)
 def test_team_matches_streamed(rb, large, prec, tol_rel, n_max, sig_tol, damping):
     batch, F = large
     runs = {}
-    for name, eng in (("auto", rb.ENGINE_AUTO), ("streamed", rb.ENGINE_STREAMED)):
+    for name, eng in (("team", rb.ENGINE_TEAM), ("streamed", rb.ENGINE_STREAMED)):
         b = rb.Batch(batch, precision=prec, engine=eng, tol_rel=tol_rel, n_max=n_max, damping=damping, **KW)
         d = b.describe()
         sig, st, stats = b.solve(F, stats=True)
         runs[name] = (sig, st, stats["iters"])
         log(f"  precision {prec} damping {damping} {name}: {d} status {np.bincount(st, minlength=4).tolist()} "
             f"iters {stats['iters'].tolist()}")
-        if name == "auto":
+        if name == "team":
             assert "team(" in d
         b.close()
-    (s1, t1, i1), (s0, t0, i0) = runs["auto"], runs["streamed"]
+    (s1, t1, i1), (s0, t0, i0) = runs["team"], runs["streamed"]
     near = (i1 >= 0.98 * n_max) | (i0 >= 0.98 * n_max)
     assert np.all((t1 == t0) | near), (t1, t0)
     both = (t1 == 0) & (t0 == 0)
@@ -66,11 +66,12 @@ def test_team_matches_streamed(rb, large, prec, tol_rel, n_max, sig_tol, damping
 
 def test_team_warm_start_and_repeatable(rb, large):
     batch, F = large
-    b = rb.Batch(batch, precision=1, tol_rel=1e-5, n_max=30000, **KW)
+    b = rb.Batch(batch, precision=1, engine=rb.ENGINE_TEAM, tol_rel=1e-5, n_max=30000, **KW)
+    assert "team(" in b.describe()
     s1, t1 = b.solve(F)
     s2, t2 = b.solve(F)
     assert np.array_equal(s1, s2, equal_nan=True) and np.array_equal(t1, t2)
-    b.set_opts(precision=1, init=rb.INIT_WARM, tol_rel=1e-5, n_max=30000, **KW)
+    b.set_opts(precision=1, engine=rb.ENGINE_TEAM, init=rb.INIT_WARM, tol_rel=1e-5, n_max=30000, **KW)
     s3, t3, st3 = b.solve(F * (1 + 1e-4), stats=True)
     log(f"  warm increment: iterations {st3['iters'].tolist()}, status {t3.tolist()}")
     assert np.all(t3[t1 == 0] == 0)
@@ -83,12 +84,28 @@ def test_team_gives_up_cleanly_at_a_one_poll_limit(rb, large):
     team RVEs it did not finish are non-finite with NaN stress; with the
     default limit the same batch solves again."""
     batch, F = large
-    b = rb.Batch(batch, precision=1, tol_rel=1e-5, n_max=30000, **KW)
+    b = rb.Batch(batch, precision=1, engine=rb.ENGINE_TEAM, tol_rel=1e-5, n_max=30000, **KW)
     b.team_spin_limit(1)
     with pytest.raises(rb.RVEError) as e:
         b.solve(F)
     assert e.value.code == rb.EDEVICE and "team" in str(e.value)
     b.team_spin_limit(1 << 24)
+    sig, st = b.solve(F)
+    assert np.all(np.isin(st, (0, 1)))
+    b.close()
+
+
+def test_autotune_chooses_team_or_streamed_by_measurement(rb, large):
+    """The autotuner times the team engine against the streamed kernel on
+    the RVEs no resident build holds and keeps the faster (validated: same
+    iterations and final states within 5% of the streamed run)."""
+    batch, F = large
+    b = rb.Batch(batch, precision=1, tol_rel=1e-5, n_max=30000, **KW)
+    before = b.describe()
+    b.autotune(F, 200)
+    after = b.describe()
+    log(f"  before autotune: {before}; after: {after}")
+    assert "team(" not in before
     sig, st = b.solve(F)
     assert np.all(np.isin(st, (0, 1)))
     b.close()
