@@ -151,6 +151,8 @@ def main():
     ap.add_argument("--no-kinetic", action="store_true", help="skip the kinetic-damping line")
     ap.add_argument("--no-floor", action="store_true", help="skip the stagnation-stop line")
     ap.add_argument("--tangent-steps", type=int, default=2)
+    ap.add_argument("--cap-lines", type=int, nargs="*", default=[40000, 20000],
+                    help="extra timed solves at these iteration caps (yield against time)")
     ap.add_argument("--autotune", action="store_true", help="autotune the mixed-precision kernel variants")
     ap.add_argument("--cache", default="/tmp/rve_bench_cfg2.npz",
                     help="network cache: loaded when present (no worker processes), else written")
@@ -226,14 +228,22 @@ def main():
     value = int(acc.sum()) / (ms_per_step / 1e3)
 
     # dominant launch group and its roofline
-    dom = int(np.argmax(g_ms))
-    in_dom = g_of == dom
-    dom_ms = float(g_ms[dom])
-    alg_bytes = float((iters[in_dom] * (20 * nfib[in_dom] + 52 * nfree[in_dom])).sum())
-    alg_flops = float((iters[in_dom] * (53 * nfib[in_dom] + 40 * nfree[in_dom])).sum())
+    # the relaxation of one step: every launch group (concurrent streams),
+    # from the first group's start to the join, HIP events on those streams
+    def gname(g):
+        return (f"dr_resident_kernel<float,{rb_variant_name(int(g_var[g]))}>" if g_var[g] >= 0
+                else "dr_streamed_kernel<float,1024>" if g_var[g] == -1 else f"dr_team_kernel<float> x{-1 - int(g_var[g])}")
+    dom_ms = float(relax_ms)
+    alg_bytes = float((iters * (20 * nfib + 52 * nfree)).sum())
+    alg_flops = float((iters * (53 * nfib + 40 * nfree)).sum())
     flop_rate = alg_flops / (dom_ms / 1e3)
-    dom_name = (f"dr_resident_kernel<float,{rb_variant_name(int(g_var[dom]))}>" if g_var[dom] >= 0
-                else "dr_streamed_kernel<float,1024>")
+    dom_name = " + ".join(gname(g) for g in range(len(g_ms))) + " (one launch each, concurrent streams)"
+    group_lines = []
+    for g in range(len(g_ms)):
+        m = g_of == g
+        fl = float((iters[m] * (53 * nfib[m] + 40 * nfree[m])).sum())
+        group_lines.append({"kernel": gname(g), "rves": int(m.sum()), "ms": float(g_ms[g]),
+                            "algorithmic_flops": fl, "tflops_over_own_span": fl / (float(g_ms[g]) / 1e3) / 1e12})
 
     out = {
         "metric": "RVE solves/sec (sigma rel-err <= 1e-4) mixed vs FP64 plain; fraction of HBM peak",
@@ -313,21 +323,47 @@ def main():
     b.close()
 
     # ---------------- side lines on the same batch: kinetic damping, stagnation stop
-    def side_line(name, bb, note, ok_status=(0,)):
+    def side_line(name, bb, note, ok_status=(0,), ref=None):
         bb.profile(True)
         ms, s, stt, itt, _ = timed_solves(bb, Fd, args.steps, args.warmup)
         a, bo, _ = accurate(s, stt, ok_status)
         bb.close()
-        log(f"{name}: {ms:.1f} ms/step, status {np.bincount(stt, minlength=9).tolist()}, counted {int(a.sum())}")
-        return {"workload": note, "ms_per_step": ms, "solves_per_s": int(a.sum()) / (ms / 1e3),
-                "counted": int(a.sum()), "status_counts": np.bincount(stt, minlength=9).tolist(),
+        line = {"workload": note, "ms_per_step": ms, "solves_per_s": int(a.sum()) / (ms / 1e3),
+                "counted": int(a.sum()), "converged": int((stt == 0).sum()),
+                "converged_per_s": int((stt == 0).sum()) / (ms / 1e3),
+                "status_counts": np.bincount(stt, minlength=9).tolist(),
                 "iters_median": float(np.median(itt)),
                 "iters_share_on_n_max_rves": float(itt[stt == 1].sum() / max(itt.sum(), 1))}
+        if ref is not None:
+            # the same count against an FP64 reference of the same scheme
+            rs, rst = ref
+            a2 = np.isin(stt, ok_status) & (rst == 0) & (rel_err(s, rs) <= 1e-4)
+            line["counted_vs_same_scheme_fp64"] = int(a2.sum())
+            line["solves_per_s_vs_same_scheme_fp64"] = int(a2.sum()) / (ms / 1e3)
+        log(f"{name}: {ms:.1f} ms/step, status {np.bincount(stt, minlength=9).tolist()}, counted {int(a.sum())}"
+            + (f" ({line['counted_vs_same_scheme_fp64']} against the same scheme in FP64)" if ref is not None else ""))
+        return line
 
     if not args.no_kinetic:
+        bkr = rb.Batch(batch, precision=rb.FP64, damping=rb.DAMP_KINETIC, **dict(common, tol_rel=args.ref_tol_rel))
+        ks, kst = bkr.solve(Fd)
+        torch.cuda.synchronize()
+        kref = (ks.cpu().numpy(), kst.cpu().numpy())
+        bkr.close()
         bk = rb.Batch(batch, precision=rb.MIXED, damping=rb.DAMP_KINETIC, **common)
         out["kinetic_damping"] = side_line("kinetic", bk, "same batch and tolerance, kinetic damping (velocities "
-                                           "zeroed at kinetic-energy peaks); same accuracy count")
+                                           "zeroed at kinetic-energy peaks); counted against the viscous FP64 "
+                                           "reference, and against a kinetic FP64 solve at the same tol_rel",
+                                           ref=kref)
+    # iteration cap: the same viscous solve stopped at a lower n_max (the yield
+    # of converged RVEs against the time spent on RVEs that never converge)
+    out["n_max_tradeoff"] = []
+    for cap in args.cap_lines:
+        if cap >= args.n_max:
+            continue
+        bc = rb.Batch(batch, precision=rb.MIXED, **dict(common, n_max=cap))
+        out["n_max_tradeoff"].append(dict(side_line(f"n_max {cap}", bc, f"same batch and options, n_max {cap}"),
+                                          n_max=cap))
     if not args.no_floor:
         bf = rb.Batch(batch, precision=rb.MIXED, floor_tol_rel=3e-5, stall_checks=32, **dict(common, tol_rel=1e-8))
         out["floor_stop"] = side_line("floor stop", bf, "same batch, tol_rel 1e-8 with the stagnation stop "
@@ -382,7 +418,9 @@ def main():
         "traffic": measured_traffic("relax_cfg2"),
         "kernel": dom_name,
         "kernel_ms": dom_ms,
-        "rves_in_kernel": int(in_dom.sum()),
+        "span": "relaxation of the whole batch (all launch groups, first start to join)",
+        "rves_in_kernel": int(batch.n_rve),
+        "groups": group_lines,
         "algorithmic_flops_per_launch": alg_flops,
         "flops_per_unit": "53 per fiber-iteration + 40 per free-node-iteration",
         "peak_note": "published FP32 vector peak (packed FMA); attainable_* is against the 78.6 TFLOP/s of "

@@ -198,6 +198,9 @@ typedef struct {
     double energy_tol;      /* relative energy-balance tolerance (> 0) */
     double floor_tol_rel;   /* stagnation stop (0: off) */
     int32_t stall_checks;   /* tests without R halving before the stop (>= 1) */
+    int32_t tangent_rhs;    /* right-hand sides per tangent task: 0 library choice (one per task,
+                               the faster on MI355X), 1 one per task, 3 three per task where a
+                               blocked build holds the RVE (at most 2048 free nodes) */
 } rve_opts;
 
 /* Optional per-RVE diagnostics of a solve (each pointer may be NULL; same
@@ -327,7 +330,11 @@ int rve_batch_solve(rve_batch* b, const double* F, double* sigma, int32_t* statu
  * - sigma (F^-1)_lk.  K_ff is applied matrix-free (per-fiber Hessian
  * blocks); each right-hand side is an independent block-Jacobi
  * preconditioned CG with FP32 products inside FP64 iterative refinement,
- * stopped at |r| <= cg_tol |b| (FP64 residual).
+ * stopped at |r| <= cg_tol |b| (FP64 residual).  With opts.tangent_rhs 3
+ * the three right-hand sides of one k (columns 3k, 3k+1, 3k+2) of an RVE of
+ * at most 2048 free nodes share one workgroup, each record read and each
+ * reduction; every column still follows its own CG, and the results agree
+ * with one task per right-hand side to rounding.
  * dsdF[n_rve][9][9] (row 3i+j = sigma_ij, column 3k+l = F_kl); status per
  * RVE: 0, RVE_ST_NO_STATE if the solve did not converge (outputs NaN),
  * RVE_ST_CG_MAXITER, RVE_ST_CG_INDEFINITE (p.Kp <= 0 met: K_ff not

@@ -48,7 +48,8 @@ class Opts(C.Structure):
                 ("n_max", C.c_int64), ("check_every", C.c_int32), ("engine", C.c_int32),
                 ("threads_per_rve", C.c_int32), ("cg_tol", C.c_double), ("cg_max_iter", C.c_int64),
                 ("stream", C.c_void_p), ("damping", C.c_int32), ("energy_check", C.c_int32),
-                ("energy_tol", C.c_double), ("floor_tol_rel", C.c_double), ("stall_checks", C.c_int32)]
+                ("energy_tol", C.c_double), ("floor_tol_rel", C.c_double), ("stall_checks", C.c_int32),
+                ("tangent_rhs", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -127,7 +128,7 @@ def _check(rc):
 def make_opts(precision=FP64, law=LAW_EXP, mass=MASS_LUMPED, init=INIT_AFFINE, EA=1.0, B=10.0, rhoA=1.0,
               alpha=0.9, c=2.0, tol_abs=1e-10, tol_rel=0.0, n_max=1_000_000, check_every=1,
               engine=ENGINE_AUTO, threads_per_rve=0, cg_tol=1e-6, cg_max_iter=0, damping=DAMP_VISCOUS,
-              energy_check=False, energy_tol=0.05, floor_tol_rel=0.0, stall_checks=16) -> Opts:
+              energy_check=False, energy_tol=0.05, floor_tol_rel=0.0, stall_checks=16, tangent_rhs=0) -> Opts:
     o = Opts()
     lib().rve_default_opts(C.byref(o))
     o.precision, o.law, o.mass, o.init = int(precision), int(law), int(mass), int(init)
@@ -137,6 +138,7 @@ def make_opts(precision=FP64, law=LAW_EXP, mass=MASS_LUMPED, init=INIT_AFFINE, E
     o.cg_tol, o.cg_max_iter = float(cg_tol), int(cg_max_iter)
     o.damping, o.energy_check, o.energy_tol = int(damping), int(bool(energy_check)), float(energy_tol)
     o.floor_tol_rel, o.stall_checks = float(floor_tol_rel), int(stall_checks)
+    o.tangent_rhs = int(tangent_rhs)
     return o
 
 

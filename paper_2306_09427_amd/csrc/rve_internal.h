@@ -270,6 +270,16 @@ hipError_t resident_scratch_bytes(int variant, bool fp64, bool kin, size_t* byte
 // Same for a streamed build (256 or 1024 threads) and a resident tangent build.
 hipError_t streamed_scratch_bytes(bool fp64, bool kin, int threads, size_t* bytes);
 hipError_t tangent_res_scratch_bytes(int variant, bool vjp, size_t* bytes);
+// Blocked tangent tasks (three right-hand sides of one RVE per workgroup) for
+// the RVEs of the per-column variants 0 .. kNumTanBlk-1 (same node capacity);
+// slot: FP64 x and b (3 slot_nodes each) and FP32 d and q (slot_nodes float4
+// each) per right-hand side, 240 slot_nodes bytes per workgroup.
+constexpr int kNumTanBlk = 3;
+constexpr int kTanBlkRhs = 3;
+extern const TangentVariant kTanBlk[kNumTanBlk];   // threads * sn = that of kTanRes[v]
+hipError_t tangent_blk_blocks(int variant, int* blocks_per_cu);
+hipError_t launch_tangent_blk(int variant, const TangentArgs& a, int grid, hipStream_t s);
+hipError_t tangent_blk_scratch_bytes(int variant, size_t* bytes);
 // Largest private segment over the kernels that have a single build (stress,
 // counters, naive engine, orientation, state, tangent preparation and
 // streamed tangent, variant engine, probe seeding): must be 0.

@@ -282,6 +282,12 @@ struct Lds<float> {
         float4 q = h[a];
         x = q.x; y = q.y; z = q.z;
     }
+    // position record with a per-node word in .w (the resident kernel keeps
+    // the inverse mass there instead of in a register)
+    __device__ void put_hw(int a, float x, float y, float z, float w) { h[a] = make_float4(x, y, z, w); }
+    __device__ float4 get_hw(int a) const { return h[a]; }
+    __device__ float get_w(int a) const { return h[a].w; }
+    __device__ void put_w(int a, float w) { h[a].w = w; }
     __device__ void put_fv(int k, const FiberOut<float>& o) { fv[k] = make_float4(o.fx, o.fy, o.fz, o.b); }
     __device__ void get_fv(int k, float& x, float& y, float& z, float& b) const
     {
@@ -597,19 +603,35 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
     }
     // ---- free nodes: velocity, acceleration, inverse mass and incidence in
     // registers; the positions live only in the LDS exchange array
-    Real vx[SN], vy[SN], vz[SN], iM[SN];
+    // FP32: the inverse mass of a free node lives in the .w word of its LDS
+    // position record (read once per iteration by the node's own thread),
+    // which frees one register per node slot; FP64 keeps it in registers.
+    constexpr bool IML = sizeof(Real) == 4;
+    Real vx[SN], vy[SN], vz[SN], iMr[IML ? 1 : SN];
+    auto iM_get = [&](int s, int a) __attribute__((always_inline)) -> Real {
+        if constexpr (IML)
+            return L.get_w(a);
+        else
+            return iMr[s];
+    };
+    auto iM_set = [&](int s, int a, Real v) __attribute__((always_inline)) {
+        if constexpr (IML)
+            L.put_w(a, v);
+        else
+            iMr[s] = v;
+    };
     uint32_t inc[SN][kResIncRegs / 2];
     int degw[SN];   // largest degree in this wave's node slot (scalar)
 #pragma unroll
     for (int s = 0; s < SN; ++s) {
         const int a = s * T + tid;
         vx[s] = vy[s] = vz[s] = Real(0);
-        iM[s] = Real(0);
+        if constexpr (!IML) iMr[s] = Real(0);
         int deg = 0;
 #pragma unroll
         for (int q = 0; q < kResIncRegs / 2; ++q) inc[s][q] = (uint32_t)nfib | ((uint32_t)nfib << 16);
         if (a < nf) {
-            iM[s] = (Real)(1.0 / (massb[a] * A.rhoA));
+            const Real im0 = (Real)(1.0 / (massb[a] * A.rhoA));
             const int64_t e0 = incoffb[a];
             deg = (int)(incoffb[a + 1] - e0);
 #pragma unroll
@@ -627,7 +649,12 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
                 const double* h = hsb + 3 * a;
                 hx = (Real)h[0]; hy = (Real)h[1]; hz = (Real)h[2];
             }
-            L.put_h(a, hx, hy, hz);
+            if constexpr (IML) {
+                L.put_hw(a, hx, hy, hz, im0);
+            } else {
+                iMr[s] = im0;
+                L.put_h(a, hx, hy, hz);
+            }
         }
         degw[s] = (int)__builtin_amdgcn_readfirstlane(
             __float_as_uint(wave_max_nonneg(__uint_as_float((unsigned)deg))));
@@ -710,11 +737,15 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
         if (a < nf) {
             Real fx, fy, fz, G;
             gather(tid, s, fx, fy, fz, G);
-            if (A.mass_mode == kMassScaled) iM[s] = G > Real(0) ? Real(4) / G : Real(1);
-            ax[s] = -fx * iM[s];
-            ay[s] = -fy * iM[s];
-            az[s] = -fz * iM[s];
-            gpart = fmax(gpart, G * iM[s]);
+            Real im = iM_get(s, a);
+            if (A.mass_mode == kMassScaled) {
+                im = G > Real(0) ? Real(4) / G : Real(1);
+                iM_set(s, a, im);
+            }
+            ax[s] = -fx * im;
+            ay[s] = -fy * im;
+            az[s] = -fz * im;
+            gpart = fmax(gpart, G * im);
             r2p += (double)fx * fx + (double)fy * fy + (double)fz * fz;
         }
     }
@@ -771,10 +802,16 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
             const int a = s * T + t;
             if (a < nf) {
                 vx[s] += hdt * ax[s]; vy[s] += hdt * ay[s]; vz[s] += hdt * az[s];
-                Real hx, hy, hz;
-                L.get_h(a, hx, hy, hz);
-                hx += rdt * vx[s]; hy += rdt * vy[s]; hz += rdt * vz[s];
-                L.put_h(a, hx, hy, hz);
+                if constexpr (IML) {
+                    float4 q = L.get_hw(a);
+                    q.x += rdt * vx[s]; q.y += rdt * vy[s]; q.z += rdt * vz[s];
+                    L.put_hw(a, q.x, q.y, q.z, q.w);
+                } else {
+                    Real hx, hy, hz;
+                    L.get_h(a, hx, hy, hz);
+                    hx += rdt * vx[s]; hy += rdt * vy[s]; hz += rdt * vz[s];
+                    L.put_h(a, hx, hy, hz);
+                }
             }
         }
         __syncthreads();
@@ -791,20 +828,21 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
             const int a = s * T + t;
             if (a < nf) {
                 Real fx, fy, fz, G;
+                const Real im = iM_get(s, a);
                 gather(t, s, fx, fy, fz, G);
                 // damped acceleration with the half-step velocity, then second half step
-                ax[s] = -fx * iM[s] - c * vx[s];
-                ay[s] = -fy * iM[s] - c * vy[s];
-                az[s] = -fz * iM[s] - c * vz[s];
+                ax[s] = -fx * im - c * vx[s];
+                ay[s] = -fy * im - c * vy[s];
+                az[s] = -fz * im - c * vz[s];
                 vx[s] += hdt * ax[s]; vy[s] += hdt * ay[s]; vz[s] += hdt * az[s];
-                gpart = fmax(gpart, G * iM[s]);
+                gpart = fmax(gpart, G * im);
                 if constexpr (KIN)
-                    kep += 0.5 * (double)((vx[s] * vx[s] + vy[s] * vy[s] + vz[s] * vz[s]) * dev_rcp(iM[s]));
+                    kep += 0.5 * (double)((vx[s] * vx[s] + vy[s] * vy[s] + vz[s] * vz[s]) * dev_rcp(im));
                 if (check) {
                     r2p += (double)fx * fx + (double)fy * fy + (double)fz * fz;
                     // damping-force norm c |M v| of this node (kinetic damping
                     // applies no viscous force but keeps c as the test's scale)
-                    const Real cm = cg * dev_rcp(iM[s]);
+                    const Real cm = cg * dev_rcp(im);
                     const double px = (double)(cm * vx[s]), py = (double)(cm * vy[s]), pz = (double)(cm * vz[s]);
                     d2p += px * px + py * py + pz * pz;
                 }
@@ -886,7 +924,7 @@ __device__ __forceinline__ void resident_solve(const SolveArgs& A, int r, char* 
 template <typename Real, int T, int SF, int SN>
 constexpr int resident_waves_per_eu()
 {
-    return sizeof(Real) == 8 ? 2 : ((T == 768 || SF > 4) ? 3 : 4);
+    return sizeof(Real) == 8 ? 2 : (T == 768 ? 3 : 4);
 }
 
 template <typename Real, int T, int SF, int SN, bool KIN>

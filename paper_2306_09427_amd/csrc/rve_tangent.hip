@@ -991,6 +991,406 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) void cg_
     }
 }
 
+// ------------------------------------------------------------------ blocked tangent tasks
+// Tangent only: one workgroup solves the three right-hand sides F_k0, F_k1,
+// F_k2 of one column group k together.  Every ELL record is read once per
+// iteration for the three products, and every workgroup reduction carries
+// the three columns' sums, so one record read and one barrier serve three
+// solves.  Per column the arithmetic is that of cg_res_task, in the same
+// order and with the same workgroup sums, so each column's result equals
+// the per-column kernel's bitwise.  A column whose inner solve has met its
+// criterion (or has ended) makes no further update while the others finish
+// theirs; then the columns of the round take the refinement step x += d
+// together.  p of each column lives in LDS, its correction d in the
+// workgroup's global slot, z = P r is recomputed where needed.
+constexpr int kBlk = kTanBlkRhs;
+
+struct BlkRed {
+    double s[2][2 * kBlk][16];   // per-wavefront partial sums, alternating buffers
+};
+
+// Workgroup sums of N values; each value is summed exactly as block_sum3
+// sums it (wavefront sum, then the wavefronts in order).
+template <int NW, int N>
+__device__ __forceinline__ void block_sum_n(BlkRed& red, int parity, double (&v)[N])
+{
+    static_assert(N <= 2 * kBlk, "too many values");
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const double w = wsum(v[i]);
+        if (lane == 0) red.s[parity][i][wave] = w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        double x = 0.0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) x += red.s[parity][i][q];
+        v[i] = uniformd(x);
+    }
+}
+
+template <int T, int SN, int BLK_RB>
+__device__ void cg_blk_task(const TangentArgs& A, int r, int grp, float4* zl, BlkRed& red)
+{
+    constexpr int NW = T / 64;
+    constexpr int ZS = T * SN + 1;   // LDS entries of one column's p
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    if (__builtin_amdgcn_readfirstlane(A.solve_status[r]) != 0) {
+        // as no_state, with the opaque thread id (nothing kept live across tasks)
+        if (tid == 0) atomicMax(&A.status[r], ST_NO_STATE);
+        if (tid < 9) {
+            // one double per store (a vector store would keep a NaN tuple live)
+#pragma unroll 1
+            for (int j = 0; j < kBlk; ++j) {
+                double nanv = NAN;
+                asm volatile("" : "+v"(nanv));
+                A.out[(int64_t)r * 81 + 9 * tid + kBlk * grp + j] = nanv;
+            }
+        }
+        return;
+    }
+    const Ctx c = make_ctx(A, r);
+    const int64_t nf = c.nf;
+    const int kk = grp;
+    const float4* Pc = A.precond + 2 * c.a0;
+    const int64_t cf = uni64(A.chunk_first[r]);
+    const int64_t S = A.slot_nodes;
+    // slot: x, b (FP64, 3 S each), then d and q = K p (FP32 float4, S each)
+    // per column
+    double* ws = A.slot_ws64 + (int64_t)blockIdx.x * 10 * kBlk * S;
+    auto x64 = [&](int j) __attribute__((always_inline)) { return ws + 6 * S * j; };
+    auto b64 = [&](int j) __attribute__((always_inline)) { return ws + 6 * S * j + 3 * S; };
+    float4* d32 = reinterpret_cast<float4*>(ws + 6 * S * kBlk);
+    float4* q32 = d32 + S * kBlk;
+    const int64_t rec0 = uni64(A.chunk_rec[cf]);
+    const float4* recA = A.recA + rec0;
+    const int2* recB = A.recB + rec0;
+    int rb[SN];
+    int wd[SN];
+#pragma unroll
+    for (int k = 0; k < SN; ++k) {
+        const int64_t ch = wave + NW * k;
+        rb[k] = 0;
+        wd[k] = 0;
+        if (64 * ch < nf) {
+            const int64_t c0 = uni64(A.chunk_rec[cf + ch]);
+            wd[k] = (int)((uni64(A.chunk_rec[cf + ch + 1]) - c0) >> 6);
+            rb[k] = (int)(c0 - rec0) + lane;
+        }
+    }
+    int parity = 0;
+
+    // right-hand sides (FP64)
+    double bb[kBlk];
+    {
+        double F[9], G[9];
+        for (int k = 0; k < 9; ++k) F[k] = A.F[9 * r + k];
+#pragma unroll
+        for (int j = 0; j < kBlk; ++j) bb[j] = 0.0;
+#pragma unroll 1
+        for (int k = 0; k < SN; ++k) {
+            const int64_t a = tid + T * k;
+            if (a < nf) {
+#pragma unroll 1
+                for (int j = 0; j < kBlk; ++j) {
+                    double b[3];
+                    rhs_node<true>(A, c, a, kk, j, F, G, b);
+                    for (int p = 0; p < 3; ++p) {
+                        b64(j)[3 * a + p] = b[p];
+                        x64(j)[3 * a + p] = 0.0;
+                    }
+                    bb[j] += b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+                }
+            }
+        }
+        if (tid < 3)
+            for (int j = 0; j < kBlk; ++j) x64(j)[3 * nf + tid] = 0.0;
+    }
+    block_sum_n<NW>(red, parity, bb);
+    parity ^= 1;
+
+    float R[kBlk][SN][3];
+    auto own_p = [&](int j, int k) __attribute__((always_inline)) -> float4 { return zl[ZS * j + tid + T * k]; };
+    // inverse block of slot k (reloaded where needed, as in cg_res_task)
+    auto pblock = [&](int k, float4& p0, float4& p1) __attribute__((always_inline)) {
+        const int64_t a = tid + T * k;
+        p0 = make_float4(0.f, 0.f, 0.f, 0.f);
+        p1 = p0;
+        if (a < nf) {
+            const float4* pp = Pc + 2 * a;
+            asm volatile("" : "+v"(pp));
+            p0 = pp[0];
+            p1 = pp[1];
+        }
+    };
+    auto papply = [&](const float4& p0, const float4& p1, const float* v) __attribute__((always_inline)) -> float4 {
+        return make_float4(p0.x * v[0] + p0.y * v[1] + p0.z * v[2], p0.y * v[0] + p0.w * v[1] + p1.x * v[2],
+                           p0.z * v[0] + p1.x * v[1] + p1.y * v[2], 0.f);
+    };
+    int status[kBlk];
+    int it_total[kBlk];
+    // bit j: column j's solve has ended (converged, cap, indefinite) / is in
+    // this round's inner solve / took part in this round
+    unsigned fin = 0u, act = 0u, in_round = 0u;
+    // per-task copy: a kernel-lifetime value would be kept live across tasks
+    double cgt = A.cg_tol;
+    asm volatile("" : "+v"(cgt));
+    const double tol2 = uniformd(cgt * cgt);
+    const int64_t maxit = A.cg_max > 0 ? A.cg_max : 6 * nf + 100;
+#pragma unroll
+    for (int j = 0; j < kBlk; ++j) {
+        status[j] = ST_CONVERGED;
+        it_total[j] = 0;
+        if (!(bb[j] > 0.0)) fin |= 1u << j;
+    }
+    for (int outer = 0; outer < 8; ++outer) {
+        // thread id opaque per phase: no per-thread address of any column is
+        // hoisted out of the loops and kept live
+        asm volatile("" : "+v"(tid));
+        if (fin == (1u << kBlk) - 1u) break;
+        // FP64 residuals of the columns still running; d = 0, p = z = P r
+        double sums[2 * kBlk];
+#pragma unroll
+        for (int i = 0; i < 2 * kBlk; ++i) sums[i] = 0.0;
+#pragma unroll
+        for (int k = 0; k < SN; ++k) {
+            const int64_t a = tid + T * k;
+            float4 p0, p1;
+            pblock(k, p0, p1);
+#pragma unroll
+            for (int j = 0; j < kBlk; ++j) {
+                if (fin & (1u << j)) continue;
+                double ra[3] = {0.0, 0.0, 0.0};
+                if (a < nf) residual_node(A, c, a, x64(j), b64(j), outer == 0, ra);
+                for (int p = 0; p < 3; ++p) R[j][k][p] = (float)ra[p];
+                sums[j] += ra[0] * ra[0] + ra[1] * ra[1] + ra[2] * ra[2];
+                const float4 z = papply(p0, p1, R[j][k]);
+                sums[kBlk + j] += (double)R[j][k][0] * z.x + (double)R[j][k][1] * z.y + (double)R[j][k][2] * z.z;
+                zl[ZS * j + tid + T * k] = z;
+                if (a < nf) d32[S * j + a] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        }
+        block_sum_n<NW>(red, parity, sums);
+        parity ^= 1;
+        double rz[kBlk], rr0[kBlk];
+        act = 0u;
+#pragma unroll
+        for (int j = 0; j < kBlk; ++j) {
+            rz[j] = sums[kBlk + j];
+            rr0[j] = sums[j];
+            if (fin & (1u << j)) continue;
+            if (sums[j] <= tol2 * bb[j]) {
+                fin |= 1u << j;   // converged
+                continue;
+            }
+            if (it_total[j] >= maxit) {
+                status[j] = ST_CG_MAXITER;
+                fin |= 1u << j;
+                continue;
+            }
+            act |= 1u << j;
+        }
+        in_round = act;
+        for (;;) {
+#pragma unroll
+            for (int j = 0; j < kBlk; ++j) {
+                if ((act & (1u << j)) && it_total[j] >= maxit) act &= ~(1u << j);
+                if (act & (1u << j)) ++it_total[j];
+            }
+            if (!act) break;
+            asm volatile("" : "+v"(tid));
+            __syncthreads();
+            // q = K p for the active columns: each record read once
+            double pq[kBlk];
+#pragma unroll
+            for (int i = 0; i < kBlk; ++i) pq[i] = 0.0;
+#pragma unroll
+            for (int k = 0; k < SN; ++k) {
+                float sx[kBlk], sy[kBlk], sz[kBlk];
+                float px[kBlk], py[kBlk], pz[kBlk];
+#pragma unroll
+                for (int j = 0; j < kBlk; ++j) {
+                    sx[j] = sy[j] = sz[j] = 0.f;
+                    const float4 q = (act & (1u << j)) ? own_p(j, k) : make_float4(0.f, 0.f, 0.f, 0.f);
+                    px[j] = q.x;
+                    py[j] = q.y;
+                    pz[j] = q.z;
+                }
+                constexpr int RB = BLK_RB;
+#pragma unroll 1
+                for (int s0 = 0; s0 < wd[k]; s0 += RB) {
+                    float4 nA[RB];
+                    int2 ob[RB];
+#pragma unroll
+                    for (int u = 0; u < RB; ++u) {
+                        nA[u] = recA[rb[k] + 64 * (s0 + u)];
+                        ob[u] = recB[rb[k] + 64 * (s0 + u)];
+                    }
+#pragma unroll
+                    for (int j = 0; j < kBlk; ++j) {
+                        if (!(act & (1u << j))) continue;
+#pragma unroll
+                        for (int u = 0; u < RB; ++u) {
+                            const float4 po = zl[ZS * j + ob[u].x];
+                            const float g = __int_as_float(ob[u].y);
+                            const float dx = px[j] - po.x, dy = py[j] - po.y, dz = pz[j] - po.z;
+                            const float cn = (nA[u].w - g) * (nA[u].x * dx + nA[u].y * dy + nA[u].z * dz);
+                            sx[j] += fmaf(g, dx, cn * nA[u].x);
+                            sy[j] += fmaf(g, dy, cn * nA[u].y);
+                            sz[j] += fmaf(g, dz, cn * nA[u].z);
+                        }
+                    }
+                }
+                const int64_t a = tid + T * k;
+#pragma unroll
+                for (int j = 0; j < kBlk; ++j) {
+                    if (!(act & (1u << j))) continue;
+                    if (a < nf) q32[S * j + a] = make_float4(sx[j], sy[j], sz[j], 0.f);
+                    pq[j] += (double)px[j] * sx[j] + (double)py[j] * sy[j] + (double)pz[j] * sz[j];
+                }
+            }
+            block_sum_n<NW>(red, parity, pq);
+            parity ^= 1;
+            float af[kBlk];
+#pragma unroll
+            for (int j = 0; j < kBlk; ++j) {
+                af[j] = 0.f;
+                if (!(act & (1u << j))) continue;
+                if (!(pq[j] > 0.0)) {
+                    status[j] = ST_CG_INDEFINITE;
+                    fin |= 1u << j;
+                    act &= ~(1u << j);
+                    continue;
+                }
+                af[j] = (float)(rz[j] / pq[j]);
+            }
+            double rs[2 * kBlk];
+#pragma unroll
+            for (int i = 0; i < 2 * kBlk; ++i) rs[i] = 0.0;
+#pragma unroll
+            for (int k = 0; k < SN; ++k) {
+                const int64_t a = tid + T * k;
+                float4 p0, p1;
+                pblock(k, p0, p1);
+#pragma unroll
+                for (int j = 0; j < kBlk; ++j) {
+                    if (!(act & (1u << j))) continue;
+                    const float4 pk = own_p(j, k);
+                    if (a < nf) {
+                        float4 d = d32[S * j + a];
+                        d.x = fmaf(af[j], pk.x, d.x);
+                        d.y = fmaf(af[j], pk.y, d.y);
+                        d.z = fmaf(af[j], pk.z, d.z);
+                        d32[S * j + a] = d;
+                    }
+                    const float4 qa = a < nf ? q32[S * j + a] : make_float4(0.f, 0.f, 0.f, 0.f);
+                    R[j][k][0] = fmaf(-af[j], qa.x, R[j][k][0]);
+                    R[j][k][1] = fmaf(-af[j], qa.y, R[j][k][1]);
+                    R[j][k][2] = fmaf(-af[j], qa.z, R[j][k][2]);
+                    const float4 z = papply(p0, p1, R[j][k]);
+                    rs[j] += (double)R[j][k][0] * R[j][k][0] + (double)R[j][k][1] * R[j][k][1] +
+                             (double)R[j][k][2] * R[j][k][2];
+                    rs[kBlk + j] += (double)R[j][k][0] * z.x + (double)R[j][k][1] * z.y + (double)R[j][k][2] * z.z;
+                }
+            }
+            block_sum_n<NW>(red, parity, rs);
+            parity ^= 1;
+            float bf[kBlk];
+#pragma unroll
+            for (int j = 0; j < kBlk; ++j) {
+                bf[j] = 0.f;
+                if (!(act & (1u << j))) continue;
+                if (rs[j] <= 1e-6 * rr0[j] || rs[j] <= 0.25 * tol2 * bb[j]) {
+                    act &= ~(1u << j);   // inner solve of this round done
+                    continue;
+                }
+                bf[j] = (float)(rs[kBlk + j] / rz[j]);
+                rz[j] = rs[kBlk + j];
+            }
+#pragma unroll
+            for (int k = 0; k < SN; ++k) {
+                float4 p0, p1;
+                if (!act) break;
+                pblock(k, p0, p1);
+#pragma unroll
+                for (int j = 0; j < kBlk; ++j) {
+                    if (!(act & (1u << j))) continue;
+                    const float4 z = papply(p0, p1, R[j][k]);
+                    const float4 pk = own_p(j, k);
+                    zl[ZS * j + tid + T * k] =
+                        make_float4(fmaf(bf[j], pk.x, z.x), fmaf(bf[j], pk.y, z.y), fmaf(bf[j], pk.z, z.z), 0.f);
+                }
+            }
+        }
+        // x += d for the columns of this round
+        asm volatile("" : "+v"(tid));
+#pragma unroll
+        for (int k = 0; k < SN; ++k) {
+            const int64_t a = tid + T * k;
+            if (a < nf) {
+#pragma unroll
+                for (int j = 0; j < kBlk; ++j) {
+                    if (!(in_round & (1u << j))) continue;
+                    const float4 d = d32[S * j + a];
+                    x64(j)[3 * a] += (double)d.x;
+                    x64(j)[3 * a + 1] += (double)d.y;
+                    x64(j)[3 * a + 2] += (double)d.z;
+                }
+            }
+        }
+        __syncthreads();
+        if (outer == 7)
+#pragma unroll
+            for (int j = 0; j < kBlk; ++j)
+                if (!(fin & (1u << j)) && status[j] == ST_CONVERGED) status[j] = ST_CG_MAXITER;
+    }
+
+    // assembly of each column
+#pragma unroll 1
+    for (int j = 0; j < kBlk; ++j) {
+        asm volatile("" : "+v"(tid));
+        double acc[9];
+        assembly_partial<true>(A, c, r, kk, j, x64(j), tid, T, acc);
+        double tot[9];
+#pragma unroll
+        for (int p = 0; p < 9; p += 3) {
+            double v3[3] = {acc[p], acc[p + 1], acc[p + 2]};
+            block_sum_n<NW>(red, parity, v3);
+            parity ^= 1;
+            tot[p] = v3[0];
+            tot[p + 1] = v3[1];
+            tot[p + 2] = v3[2];
+        }
+        if (tid == 0) assembly_write<true>(A, r, kBlk * grp + j, tot, status[j], it_total[j]);
+    }
+    __syncthreads();
+}
+
+// Waves per SIMD WPE (registers 512 / WPE): the three columns' residuals
+// stay in registers.
+template <int T, int SN, int WPE>
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(WPE))) void cg_blk_kernel(TangentArgs A)
+{
+    extern __shared__ float4 zl[];   // [kBlk][T * SN + 1]; entries past an RVE's nodes stay zero
+    __shared__ BlkRed red;
+    __shared__ int task;
+    constexpr int ZS = T * SN + 1;
+    if (threadIdx.x < kBlk) zl[ZS * threadIdx.x + T * SN] = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int64_t n_tasks = A.n_order * kBlk;
+    for (;;) {
+        if (threadIdx.x == 0) task = atomicAdd(A.queue, 1);
+        __syncthreads();
+        const int t = __builtin_amdgcn_readfirstlane(task);
+        __syncthreads();
+        if (t >= n_tasks) break;
+        cg_blk_task<T, SN, WPE >= 4 ? 1 : 2>(A, __builtin_amdgcn_readfirstlane(A.order[t / kBlk]), t % kBlk, zl, red);
+    }
+}
+
 __global__ void zero_status(int32_t* st, unsigned long long* it, int64_t n)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -1078,6 +1478,50 @@ hipError_t tangent_res_scratch_bytes(int v, bool vjp, size_t* bytes)
 {
     if (v < 0 || v >= kNumTanRes) return hipErrorInvalidValue;
     return max_private_bytes({res_kernel(v, vjp)}, bytes);
+}
+
+// Blocked tangent tasks (three right-hand sides per workgroup) with the
+// node capacity of the per-column variants 0-2 (512, 1024, 2048 free nodes).
+const TangentVariant kTanBlk[kNumTanBlk] = {{256, 2}, {512, 2}, {1024, 2}};
+
+static const void* blk_kernel(int v)
+{
+    switch (v) {
+    case 0: return (const void*)cg_blk_kernel<256, 2, 4>;
+    case 1: return (const void*)cg_blk_kernel<512, 2, 4>;
+    default: return (const void*)cg_blk_kernel<1024, 2, 4>;
+    }
+}
+
+static size_t blk_lds(int v)
+{
+    return 16 * (size_t)kBlk * ((size_t)kTanBlk[v].threads * kTanBlk[v].sn + 1);
+}
+
+hipError_t tangent_blk_blocks(int v, int* blocks_per_cu)
+{
+    if (v < 0 || v >= kNumTanBlk) return hipErrorInvalidValue;
+    const void* k = blk_kernel(v);
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)blk_lds(v));
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, kTanBlk[v].threads, blk_lds(v));
+}
+
+hipError_t launch_tangent_blk(int v, const TangentArgs& a, int grid, hipStream_t s)
+{
+    if (v < 0 || v >= kNumTanBlk) return hipErrorInvalidValue;
+    if (a.n_order <= 0) return hipSuccess;
+    const void* k = blk_kernel(v);
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)blk_lds(v));
+    if (e != hipSuccess) return e;
+    void* args[] = {const_cast<TangentArgs*>(&a)};
+    return hipLaunchKernel(k, dim3(grid), dim3(kTanBlk[v].threads), args, blk_lds(v), s);
+}
+
+hipError_t tangent_blk_scratch_bytes(int v, size_t* bytes)
+{
+    if (v < 0 || v >= kNumTanBlk) return hipErrorInvalidValue;
+    return max_private_bytes({blk_kernel(v)}, bytes);
 }
 
 hipError_t tangent_fixed_private(size_t* bytes)
