@@ -239,10 +239,13 @@ int rve_batch_set_stream(rve_batch* b, void* stream);
 
 /*
  * Kernel timing: after rve_batch_profile(b, 1), every solve records HIP
- * events around each relaxation launch and the stress launch on the batch's
- * stream.  rve_batch_kernel_ms then returns, for the last solve, the summed
- * duration of the relaxation kernels (*relax_ms) and of the stress kernel
- * (*stress_ms) in milliseconds (it synchronises the stream).
+ * events around each relaxation launch (on the stream that launch runs on:
+ * the batch's stream or, for concurrent launch groups, an auxiliary stream
+ * joined back to it) and around the stress launch.  rve_batch_kernel_ms then
+ * returns, for the last solve, the span of the relaxation from the earliest
+ * launch's start to the join of all launches (*relax_ms) and the duration of
+ * the stress kernel (*stress_ms) in milliseconds (it synchronises the
+ * stream); rve_batch_groups gives each launch's own duration.
  */
 int rve_batch_profile(rve_batch* b, int enable);
 int rve_batch_kernel_ms(rve_batch* b, double* relax_ms, double* stress_ms);

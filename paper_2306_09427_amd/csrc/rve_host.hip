@@ -76,6 +76,7 @@ struct rve_batch {
     double *dh = nullptr, *dV0 = nullptr;
     int32_t *dstatus = nullptr, *dqueue = nullptr, *dlist = nullptr;
     int64_t* diters = nullptr;
+    bool cost_order = false;   // diters holds a previous solve's iterations: order the work lists by cost
     void *ws_fib = nullptr, *ws_node = nullptr;
     size_t ws_fib_bytes = 0, ws_node_bytes = 0;
     // engine assignment: RVE ids per launch group, in longest-first order
@@ -1412,11 +1413,13 @@ int rve_batch_kernel_ms(rve_batch* b, double* relax_ms, double* stress_ms)
     if (!b || !relax_ms || !stress_ms) return fail(RVE_EINVAL, "NULL argument");
     if (b->ev_used < 2) return fail(RVE_ESTATE, "no profiled solve");
     HIP_TRY(hipEventSynchronize(b->ev[b->ev_used - 1]));
+    // relaxation span: from the earliest group start to the join of all
+    // groups (the groups may run concurrently on several streams)
     double relax = 0.0;
     for (int g = 0; g + 2 < b->ev_used; g += 2) {
         float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, b->ev[g], b->ev[g + 1]));
-        relax += ms;
+        HIP_TRY(hipEventElapsedTime(&ms, b->ev[g], b->ev[b->ev_used - 2]));
+        relax = std::max(relax, (double)ms);
     }
     float st = 0.f;
     HIP_TRY(hipEventElapsedTime(&st, b->ev[b->ev_used - 2], b->ev[b->ev_used - 1]));
@@ -1474,6 +1477,22 @@ static int launch_groups(rve_batch* b, SolveArgs& a, int32_t* queues, void* ws_f
     if (profile) {
         int rc = ensure_events(b, 2 * (int)b->groups.size() + 2);
         if (rc) return rc;
+    }
+    // After a first solve, each resident or streamed group takes its RVEs in
+    // longest-processing-time order of the previous solve's cost (iterations
+    // x fibers), so the RVEs that ran longest start first and the launch's
+    // tail (its last, long RVEs on few CUs) shrinks; before it, the host's
+    // order (most fibers first).  Team groups keep theirs.
+    if (b->cost_order && (int)b->groups.size() <= kOrderGroups) {
+        OrderArgs o{};
+        o.list = b->dlist;
+        o.iters = b->diters;
+        o.fib_off = b->net.fib_off;
+        for (size_t g = 0; g < b->groups.size(); ++g) {
+            o.first[g] = b->group_first[g];
+            o.count[g] = b->group_variant[g] >= -1 ? (int32_t)b->groups[g].size() : 0;
+        }
+        HIP_TRY(launch_order_by_cost(o, (int)b->groups.size(), s));
     }
     HIP_TRY(launch_reset(queues, 2 * (int)b->groups.size(), s));
     int32_t* team_err = reinterpret_cast<int32_t*>(team_ws);
@@ -1701,6 +1720,7 @@ int rve_batch_solve(rve_batch* b, const double* F, double* sigma, int32_t* statu
     } else {
         rc = launch_groups(b, a, b->dqueue, b->ws_fib, b->ws_node, b->team_ws, s, b->profile, true);
         if (rc) return rc;
+        b->cost_order = true;
     }
     HIP_TRY(hipMemcpyAsync(sigma, b->dsigma, 72 * b->R, out_kind, s));
     HIP_TRY(hipMemcpyAsync(status, b->dstatus, 4 * b->R, out_kind, s));
@@ -1956,6 +1976,7 @@ int rve_batch_autotune(rve_batch* b, const double* F, int32_t ptr_kind, int32_t 
         b->tuned_team[fp64 ? 1 : 0][k] = (team_valid && ms_c[1] < ms_c[0]) ? 1 : 0;
     }
     b->have_state = false;
+    b->cost_order = false;   // the iterations of the timing runs are no cost estimate
     assign_groups(b);
     return upload_groups(b);
 }
@@ -2831,6 +2852,7 @@ extern "C" int rve_batch_solve_static(rve_batch* b, const double* F, double* sig
     a.init = b->opts.init;
     rc = launch_groups(b, a, queues, ws_fib, ws_node, team_ws, s, false, false);
     if (rc) return rc;
+    b->cost_order = true;
     HIP_TRY(hipMemcpyAsync(sigma, b->dsigma, 72 * b->R, out_kind, s));
     HIP_TRY(hipMemcpyAsync(status, b->dstatus, 4 * b->R, out_kind, s));
     b->have_state = true;

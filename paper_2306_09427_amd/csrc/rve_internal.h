@@ -247,6 +247,19 @@ hipError_t launch_streamed(bool fp64, const SolveArgs& a, int grid, int threads,
 size_t streamed_lds_cap();   // bytes of LDS the streamed engine may use for h
 hipError_t launch_stress(const SolveArgs& a, int n_rve, hipStream_t s);
 hipError_t launch_reset(int32_t* counters, int n, hipStream_t s);   // n <= 64
+
+// Work-list order by the previous solve's cost (iterations x fibers), one
+// sort per launch group; groups of more than kOrderMax RVEs keep their order.
+constexpr int kOrderMax = 8192;     // positions fit the key's 14 low bits
+constexpr int kOrderGroups = 32;
+struct OrderArgs {
+    int32_t* list;                  // device work lists of all groups
+    const int64_t* iters;           // [R] iterations of the previous solve
+    const int64_t* fib_off;         // [R+1]
+    int32_t first[kOrderGroups];    // offset of group g's ids in list
+    int32_t count[kOrderGroups];    // RVEs of group g (0: leave alone)
+};
+hipError_t launch_order_by_cost(const OrderArgs& o, int n_groups, hipStream_t s);
 hipError_t launch_zero32(int32_t* p, int64_t n, hipStream_t s);
 hipError_t launch_mark_unfinished(const int32_t* list, int n, int32_t* status, hipStream_t s);
 // Tangent / VJP.  prep: statuses, ELL records (first call), fiber operators

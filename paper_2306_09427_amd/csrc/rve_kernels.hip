@@ -1420,6 +1420,67 @@ hipError_t launch_mark_unfinished(const int32_t* list, int n, int32_t* status, h
     return hipGetLastError();
 }
 
+// Longest-processing-time order of the work lists: one workgroup per launch
+// group sorts the group's RVE ids by the estimated cost iters[r] * fibers(r)
+// of the previous solve, largest first, ties in the present order (a stable
+// sort: the key carries the position), with a bitonic sort of packed 64-bit
+// keys (cost << 14 | (16383 - position)) in LDS.  Groups of more than
+// kOrderMax RVEs keep their order.  Only the order in which the persistent
+// workgroups take RVEs changes; every RVE's arithmetic is the same.
+constexpr int kOrderThreads = 1024;
+
+__global__ __launch_bounds__(kOrderThreads) void order_by_cost_kernel(OrderArgs o)
+{
+    __shared__ unsigned long long key[kOrderMax];
+    __shared__ int32_t id[kOrderMax];
+    const int g = blockIdx.x;
+    const int n = o.count[g];
+    if (n < 2 || n > kOrderMax) return;
+    int32_t* list = o.list + o.first[g];
+    int m = 2;
+    while (m < n) m <<= 1;
+    for (int i = threadIdx.x; i < m; i += kOrderThreads) {
+        unsigned long long k = 0ull;   // padding sorts last
+        if (i < n) {
+            const int32_t r = list[i];
+            id[i] = r;
+            const int64_t it = o.iters[r] > 0 ? o.iters[r] : 0;
+            const int64_t nf = o.fib_off[r + 1] - o.fib_off[r];
+            unsigned long long cost = (unsigned long long)it * (unsigned long long)(nf > 0 ? nf : 0);
+            cost = cost < (1ull << 48) ? cost : (1ull << 48) - 1ull;
+            k = ((cost + 1ull) << 14) | (unsigned long long)(kOrderMax - 1 - i);
+        }
+        key[i] = k;
+    }
+    __syncthreads();
+    // bitonic sort, descending
+    for (int size = 2; size <= m; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = threadIdx.x; t < (m >> 1); t += kOrderThreads) {
+                const int lo = 2 * t - (t & (stride - 1));
+                const int hi = lo + stride;
+                const bool desc = (lo & size) == 0;
+                const unsigned long long a = key[lo], b = key[hi];
+                if ((a < b) == desc) {
+                    key[lo] = b;
+                    key[hi] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < n; i += kOrderThreads)
+        list[i] = id[kOrderMax - 1 - (int)(key[i] & (unsigned long long)(kOrderMax - 1))];
+}
+
+hipError_t launch_order_by_cost(const OrderArgs& o, int n_groups, hipStream_t s)
+{
+    if (n_groups <= 0) return hipSuccess;
+    if (n_groups > kOrderGroups) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(order_by_cost_kernel, dim3((unsigned)n_groups), dim3(kOrderThreads), 0, s, o);
+    return hipGetLastError();
+}
+
 hipError_t launch_reset(int32_t* counters, int n, hipStream_t s)
 {
     hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, s, counters, n);
@@ -1532,7 +1593,7 @@ hipError_t streamed_scratch_bytes(bool fp64, bool kin, int threads, size_t* byte
 hipError_t kernels_fixed_private(size_t* bytes)
 {
     return max_private_bytes({(const void*)stress_kernel, (const void*)reset_counters, (const void*)zero_words,
-                              (const void*)mark_unfinished},
+                              (const void*)mark_unfinished, (const void*)order_by_cost_kernel},
                              bytes);
 }
 

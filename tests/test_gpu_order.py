@@ -1,0 +1,41 @@
+"""Work-list order by the previous solve's cost, GPU.
+
+After a first solve, every resident or streamed launch group takes its RVEs
+in longest-processing-time order of the previous solve (iterations x
+fibers, a bitonic sort on the device).  The order only decides which
+persistent workgroup takes which RVE when, so every result must be bitwise
+the one of a batch that solves in the host's order; a wrong permutation
+(an RVE taken twice, another never) would leave that RVE's outputs from the
+previous call, which the second F exposes.
+"""
+import numpy as np
+import pytest
+
+from paper_2306_09427_amd import synth
+from tests.gpu_common import log, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_cost_order_gives_the_same_results(precision):
+    rb = require_gpu()
+    idx = np.arange(96)
+    batch, F1 = synth.make_config_batch(2, idx=idx)
+    F2 = np.eye(3)[None] + 0.8 * (F1 - np.eye(3)[None])
+    kw = dict(precision=precision, law=rb.LAW_EXP, mass=1, alpha=0.5, c=0.1, tol_abs=0.0,
+              tol_rel=1e-5 if precision == 1 else 1e-8, n_max=20000, check_every=8)
+    b = rb.Batch(batch, **kw)
+    s1, t1, x1 = b.solve(F1, stats=True)       # host order (most fibers first)
+    s1b, t1b, x1b = b.solve(F1, stats=True)    # order by the first solve's cost
+    s2, t2, x2 = b.solve(F2, stats=True)       # order by F1's cost, new F
+    log(f"groups {b.describe()}; statuses {np.bincount(t2, minlength=4).tolist()}")
+    fresh = rb.Batch(batch, **kw)
+    r2, u2, y2 = fresh.solve(F2, stats=True)
+    assert np.array_equal(s1, s1b, equal_nan=True) and np.array_equal(t1, t1b)
+    assert np.array_equal(x1["iters"], x1b["iters"])
+    assert np.array_equal(s2, r2, equal_nan=True) and np.array_equal(t2, u2)
+    assert np.array_equal(x2["iters"], y2["iters"])
+    assert not np.array_equal(s2, s1, equal_nan=True)
+    b.close()
+    fresh.close()
