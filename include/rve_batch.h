@@ -320,6 +320,10 @@ int rve_batch_sizes(const rve_batch* b, int64_t* n_rve, int64_t* n_nodes, int64_
  *   boundary node b (its reaction), x_b = F Xm_b.
  * The converged fluctuation state stays on the device for rve_batch_tangent,
  * rve_batch_vjp, rve_batch_positions and warm starts.
+ * Scheduling: the RVEs of a launch group are taken most-fibers-first on the
+ * batch's first solve and, after it, in decreasing order of the previous
+ * solve's iterations times fibers (a device-side sort on the batch's
+ * stream); every RVE's arithmetic and results are independent of the order.
  */
 int rve_batch_solve(rve_batch* b, const double* F, double* sigma, int32_t* status,
                     rve_stats* stats, int32_t ptr_kind);
@@ -454,8 +458,10 @@ int rve_batch_generation(const rve_batch* b, uint64_t* gen);
  * register-resident kernel build whose slots hold it, bounds every index the
  * build forms (packed fiber ends against the LDS position array, incidence
  * codes and overflow reads against the LDS force array, the code's end sign,
- * LDS bytes against 160 KB), the streamed engine's workspace offsets, and the
- * packing's incidence lists.  precision: RVE_FP64 or RVE_MIXED (LDS layout).
+ * LDS bytes against 160 KB), the streamed engine's workspace offsets, the
+ * team engine's partition and halo tables for the RVEs it would take, and
+ * the packing's incidence lists.  precision: RVE_FP64 or RVE_MIXED (LDS
+ * layout).
  * plant: 0; 1 makes the replay assume one LDS position entry fewer (a
  * deliberate mistake that the replay must report; tests only).
  * RVE_OK, or RVE_EINVAL with the first violation in rve_last_error().

@@ -82,18 +82,20 @@ __device__ inline double dev_sqrt(double x) { return sqrt(x); }
 // exp(x) - 1 for the exponential fiber law in FP32: degree-8 Taylor series
 // below 0.5 (relative truncation error < 2e-8 there), the hardware 2^x
 // above (relative error < 2e-7 of e^x - 1 at the switch, falling with x).
+// e^x - 1 for x >= 0 (the law's argument B max(eps, 0)): below 1/4 the
+// Taylor series to x^6 (truncation x^6/5040 relative, under half an FP32
+// ulp); above, the hardware exp2 minus one (cancellation at most a factor
+// e^x / (e^x - 1) <= 4.6 on its error).
 __device__ inline float dev_expm1(float x)
 {
-    float t = x * (1.f / 40320.f) + (1.f / 5040.f);
-    t = t * x + (1.f / 720.f);
-    t = t * x + (1.f / 120.f);
+    float t = x * (1.f / 720.f) + (1.f / 120.f);
     t = t * x + (1.f / 24.f);
     t = t * x + (1.f / 6.f);
     t = t * x + 0.5f;
     t = t * x + 1.f;
     float taylor = t * x;
     float big = __builtin_amdgcn_exp2f(x * 1.44269504088896341f) - 1.f;
-    return fabsf(x) < 0.5f ? taylor : big;
+    return x < 0.25f ? taylor : big;
 }
 __device__ inline double dev_expm1(double x) { return expm1(x); }
 
@@ -503,15 +505,17 @@ __device__ __forceinline__ FiberOut<Real> fiber_eval_scaled(bool linear, Real EA
         s = sqrt(m);
     const Real eps = qn * dev_rcp(s + Real(1));
     Real T, kt;
+    const Real Tl = EA * eps;   // linear law (and the exponential law in compression)
     if (linear) {
-        T = EA * eps;
+        T = Tl;
         kt = EA;
     } else {
-        // both branches of the exponential law without divergence
+        // both branches of the exponential law without divergence; in
+        // tension k_t = EA e^{B eps} = EA + B T
         const bool pos = eps >= Real(0);
-        const Real em1 = dev_expm1(B * (pos ? eps : Real(0)));
-        T = pos ? EAoB * em1 : EA * eps;
-        kt = pos ? EA * (em1 + Real(1)) : EA;
+        const Real Te = EAoB * dev_expm1(B * fmax(eps, Real(0)));
+        T = pos ? Te : Tl;
+        kt = pos ? fma(B, Te, EA) : EA;
     }
     const Real g = T * rs;
     FiberOut<Real> o;

@@ -62,20 +62,18 @@ __device__ inline float t_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ inline double t_rsqrt(double x) { return 1.0 / sqrt(x); }
 __device__ inline double t_rcp(double x) { return 1.0 / x; }
 
-// exp(x) - 1 in FP32: degree-8 Taylor series below 0.5, the hardware 2^x above
-// (the resident kernel's formula)
+// e^x - 1 in FP32 for x >= 0: the Taylor series to x^6 below 1/4, the
+// hardware 2^x minus one above (the resident kernel's formula)
 __device__ inline float t_expm1(float x)
 {
-    float t = x * (1.f / 40320.f) + (1.f / 5040.f);
-    t = t * x + (1.f / 720.f);
-    t = t * x + (1.f / 120.f);
+    float t = x * (1.f / 720.f) + (1.f / 120.f);
     t = t * x + (1.f / 24.f);
     t = t * x + (1.f / 6.f);
     t = t * x + 0.5f;
     t = t * x + 1.f;
     const float taylor = t * x;
     const float big = __builtin_amdgcn_exp2f(x * 1.44269504088896341f) - 1.f;
-    return fabsf(x) < 0.5f ? taylor : big;
+    return x < 0.25f ? taylor : big;
 }
 __device__ inline double t_expm1(double x) { return expm1(x); }
 
@@ -101,14 +99,15 @@ __device__ __forceinline__ Fv<Real> fiber_scaled(bool linear, Real EA, Real B, R
         s = sqrt(m);
     const Real eps = qn * t_rcp(s + Real(1));
     Real T, kt;
+    const Real Tl = EA * eps;
     if (linear) {
-        T = EA * eps;
+        T = Tl;
         kt = EA;
     } else {
         const bool pos = eps >= Real(0);
-        const Real em1 = t_expm1(B * (pos ? eps : Real(0)));
-        T = pos ? EAoB * em1 : EA * eps;
-        kt = pos ? EA * (em1 + Real(1)) : EA;
+        const Real Te = EAoB * t_expm1(B * fmax(eps, Real(0)));
+        T = pos ? Te : Tl;
+        kt = pos ? fma(B, Te, EA) : EA;
     }
     const Real g = T * rs;
     Fv<Real> o;
