@@ -253,16 +253,20 @@ __device__ __forceinline__ Ctx make_ctx(const TangentArgs& A, int r)
     return c;
 }
 
-// Outputs of a task whose RVE has no converged state.
+// Outputs of a task whose RVE has no converged state.  tid: the caller's
+// thread id (opaque in the persistent kernels); the NaN is produced at the
+// store so that no constant is kept live across tasks.
 template <bool TAN>
-__device__ void no_state(const TangentArgs& A, int r, int col)
+__device__ void no_state(const TangentArgs& A, int r, int col, int tid)
 {
-    if (threadIdx.x == 0) atomicMax(&A.status[r], ST_NO_STATE);
-    if (threadIdx.x < 9) {
+    if (tid == 0) atomicMax(&A.status[r], ST_NO_STATE);
+    if (tid < 9) {
+        double nanv = NAN;
+        asm volatile("" : "+v"(nanv));
         if (TAN)
-            A.out[(int64_t)r * 81 + 9 * threadIdx.x + col] = NAN;
+            A.out[(int64_t)r * 81 + 9 * tid + col] = nanv;
         else
-            A.out[(int64_t)r * 9 + threadIdx.x] = NAN;
+            A.out[(int64_t)r * 9 + tid] = nanv;
     }
 }
 
@@ -475,7 +479,7 @@ __device__ void cg_stream_task(const TangentArgs& A, int r, int col, CgRed& red)
         }
     };
     if (__builtin_amdgcn_readfirstlane(A.solve_status[r]) != 0) {
-        no_state<TAN>(A, r, col);
+        no_state<TAN>(A, r, col, tid);
         return;
     }
     const Ctx c = make_ctx(A, r);
@@ -706,7 +710,7 @@ __device__ void cg_res_task(const TangentArgs& A, int r, int col, float4* zl, Cg
     asm volatile("" : "+v"(tid));
     const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     if (__builtin_amdgcn_readfirstlane(A.solve_status[r]) != 0) {
-        no_state<TAN>(A, r, col);
+        no_state<TAN>(A, r, col, tid);
         return;
     }
     const Ctx c = make_ctx(A, r);
@@ -791,11 +795,17 @@ __device__ void cg_res_task(const TangentArgs& A, int r, int col, float4* zl, Cg
                            p0.z * R[k][0] + p1.x * R[k][1] + p1.y * R[k][2], 0.f);
     };
     int status = ST_CONVERGED;
-    const double tol2 = A.cg_tol * A.cg_tol;
+    // per-task copy: a kernel-lifetime value would be kept live across tasks
+    double cgt = A.cg_tol;
+    asm volatile("" : "+v"(cgt));
+    const double tol2 = uniformd(cgt * cgt);
     const int64_t maxit = A.cg_max > 0 ? A.cg_max : 6 * nf + 100;
     int64_t it_total = 0;
     bool done = !(bb > 0.0);
     for (int outer = 0; outer < 8 && !done; ++outer) {
+        // thread id opaque per phase: no per-thread address is hoisted out of
+        // the loops and kept live across them
+        asm volatile("" : "+v"(tid));
         // FP64 residual of the FP64 solution (x64 complete: barrier above);
         // d = 0, p = z = P r
         double rr = 0.0, rz = 0.0;
@@ -841,6 +851,7 @@ __device__ void cg_res_task(const TangentArgs& A, int r, int col, float4* zl, Cg
         for (;;) {
             if (it_total >= maxit) break;
             ++it_total;
+            asm volatile("" : "+v"(tid));
             if (!PL) {
 #pragma unroll
                 for (int k = 0; k < SN; ++k) zl[tid + T * k] = make_float4(P[k][0], P[k][1], P[k][2], 0.f);
@@ -937,6 +948,7 @@ __device__ void cg_res_task(const TangentArgs& A, int r, int col, float4* zl, Cg
             }
         }
         // x += d
+        asm volatile("" : "+v"(tid));
 #pragma unroll
         for (int k = 0; k < SN; ++k) {
             const int64_t a = tid + T * k;

@@ -23,15 +23,14 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-featu
 
 # builds with a private segment, each excluded at run time by the host
 # (FP64 state of 4+2 slots per thread does not fit 168 or 128 VGPRs; the
-# FP64 streamed kernel in 128; the lean 1024-thread tangent tasks with 4 or 8
-# node slots).  The FP32 6+3 slot builds fit 128 VGPRs with the inverse mass
+# FP64 streamed kernel in 128; the lean 1024-thread tangent task with 8 node
+# slots).  The FP32 6+3 slot builds fit 128 VGPRs with the inverse mass
 # held in the LDS position record.
 EXPECTED_PRIVATE = {
     "dr_resident_kernel<double, 768, 4, 2, false>", "dr_resident_kernel<double, 768, 4, 2, true>",
     "dr_resident_kernel<double, 1024, 4, 2, false>", "dr_resident_kernel<double, 1024, 4, 2, true>",
     "dr_resident_kernel<double, 1024, 6, 3, false>", "dr_resident_kernel<double, 1024, 6, 3, true>",
     "dr_streamed_kernel<double, 1024, false>", "dr_streamed_kernel<double, 1024, true>",
-    "cg_res_kernel<false, 1024, 4, true>", "cg_res_kernel<true, 1024, 4, true>",
     "cg_res_kernel<false, 1024, 8, true>", "cg_res_kernel<true, 1024, 8, true>",
 }
 
