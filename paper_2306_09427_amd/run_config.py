@@ -37,6 +37,8 @@ def main(argv=None) -> int:
     ap.add_argument("--threads-per-rve", type=int, default=0, help="force resident builds of this workgroup size")
     ap.add_argument("--engine", choices=["auto", "streamed", "team"], default="auto")
     ap.add_argument("--tangent", action="store_true", help="also one tangent dsigma/dF call after the timed solve")
+    ap.add_argument("--tangent-rhs", type=int, default=0, choices=[0, 1, 3],
+                    help="right-hand sides per tangent task (0: library choice, 3: blocked)")
     ap.add_argument("--damping", choices=["viscous", "kinetic"], default="viscous")
     ap.add_argument("--solves", type=int, default=1, help="timed solves (after one untimed warm-up solve)")
     args = ap.parse_args(argv)
@@ -71,7 +73,8 @@ def main(argv=None) -> int:
                  c=args.c, tol_abs=0.0, tol_rel=args.tol_rel, n_max=args.n_max, check_every=args.check_every,
                  threads_per_rve=args.threads_per_rve,
                  engine={"auto": rb.ENGINE_AUTO, "streamed": rb.ENGINE_STREAMED, "team": rb.ENGINE_TEAM}[args.engine],
-                 damping=rb.DAMP_KINETIC if args.damping == "kinetic" else rb.DAMP_VISCOUS)
+                 damping=rb.DAMP_KINETIC if args.damping == "kinetic" else rb.DAMP_VISCOUS,
+                 tangent_rhs=args.tangent_rhs)
     b.profile(True)
     Fd = torch.tensor(F, device=dev)
     b.solve(Fd)
@@ -85,6 +88,8 @@ def main(argv=None) -> int:
     g_of, g_var, g_ms = b.groups()
     tangent = None
     if args.tangent:
+        C, ct = b.tangent(like=Fd)   # builds the tangent's records
+        torch.cuda.synchronize()
         t2 = time.perf_counter()
         C, ct = b.tangent(like=Fd)
         torch.cuda.synchronize()
