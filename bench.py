@@ -150,6 +150,7 @@ def main():
     ap.add_argument("--naive-sample", type=int, default=4)
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--cfg3-rves", type=int, default=512, help="RVEs of the large-RVE (2000 seeds) leg; 0 skips it")
+    ap.add_argument("--cfg3-streamed", type=int, default=1, help="also time the large-RVE leg on the streamed kernel (0: skip)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-naive", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -239,7 +240,9 @@ def main():
     # from the first group's start to the join, HIP events on those streams
     def gname(g):
         return (f"dr_resident_kernel<float,{rb_variant_name(int(g_var[g]))}>" if g_var[g] >= 0
-                else "dr_streamed_kernel<float,1024>" if g_var[g] == -1 else f"dr_team_kernel<float> x{-1 - int(g_var[g])}")
+                else "dr_streamed_kernel<float,1024>" if g_var[g] == rb.GROUP_STREAMED
+                else "dr_incidence_kernel" if g_var[g] == rb.GROUP_INCIDENCE
+                else f"dr_team_kernel<float> x{-1 - int(g_var[g])}")
     dom_ms = float(relax_ms)
     alg_bytes = float((iters * (20 * nfib + 52 * nfree)).sum())
     alg_flops = float((iters * (53 * nfib + 40 * nfree)).sum())
@@ -468,6 +471,20 @@ def main():
         log(f"large RVEs: {ms3:.0f} ms, groups {b3.describe()}, status {np.bincount(st3, minlength=4).tolist()}, "
             f"{rate3 / 1e9:.0f} GB/s algorithmic ({rate3 / PEAK_HBM:.2f} of peak)")
         b3.close()
+        if args.cfg3_streamed:
+            # the same workload on the streamed kernel (every array in global
+            # memory, fiber forces written and gathered): one timed solve
+            b3s = rb.Batch(b3net, precision=rb.MIXED, **dict(common, engine=rb.ENGINE_STREAMED))
+            b3s.profile(True)
+            ms3s, s3s, st3s, it3s, _ = timed_solves(b3s, F3d, 1, 0)
+            both3 = (st3 == 0) & (st3s == 0)
+            out["large_rves"]["streamed_kernel"] = {
+                "ms_per_solve": ms3s, "groups": b3s.describe(),
+                "status_counts": np.bincount(st3s, minlength=4).tolist(),
+                "speedup_of_default": ms3s / ms3,
+                "sigma_max_rel_diff_both_converged": float(rel_err(s3, s3s)[both3].max()) if both3.any() else None}
+            log(f"large RVEs on the streamed kernel: {ms3s:.0f} ms ({ms3s / ms3:.2f}x the default engine)")
+            b3s.close()
 
     # ---------------- CPU oracle on a bounded sample
     if not args.no_cpu and args.cpu_sample > 0:

@@ -77,18 +77,33 @@ extern "C" {
 #define RVE_INIT_WARM 2        /* free nodes start at F Xm + h, h = fluctuation
                                   left by the previous solve of this batch */
 #define RVE_ENGINE_AUTO 0      /* register-resident persistent kernel where an
-                                  RVE fits, streamed persistent kernel otherwise */
+                                  RVE fits; beyond it the incidence kernel
+                                  (RVE_MIXED, free nodes within its limits),
+                                  else the streamed persistent kernel */
 #define RVE_ENGINE_STREAMED 1  /* persistent kernel, state in global memory */
 #define RVE_ENGINE_NAIVE 2     /* one RVE at a time, one launch per step of
                                   every iteration, atomics, FP64 only */
 #define RVE_ENGINE_TEAM 3      /* as AUTO, but RVEs no resident build holds run
                                   on the team engine (k workgroups per RVE)
-                                  wherever a partition fits, else streamed;
-                                  AUTO runs them streamed unless
-                                  rve_batch_autotune measured the team faster */
+                                  wherever a partition fits, else as AUTO;
+                                  AUTO runs them on the team engine only where
+                                  rve_batch_autotune measured it faster than
+                                  the streamed kernel */
+#define RVE_ENGINE_INCIDENCE 4 /* every RVE within the incidence kernel's
+                                  limits runs on it (RVE_MIXED only: node
+                                  state in registers, positions in LDS, one
+                                  record per node-fiber incidence read from
+                                  global memory each iteration; at most 12288
+                                  free nodes of degree <= 16), the rest as
+                                  AUTO */
 #define RVE_DAMP_VISCOUS 0     /* constant mass-proportional damping c M v */
 #define RVE_DAMP_KINETIC 1     /* kinetic damping: v = 0 at kinetic-energy peaks */
 #define RVE_DAMP_ADAPTIVE 2    /* c re-estimated each step (Rayleigh quotient) */
+
+/* opts.work_order: the order in which a persistent launch takes its RVEs */
+#define RVE_ORDER_AUTO 0       /* library choice per engine (below) */
+#define RVE_ORDER_HOST 1       /* most fibers first, every solve */
+#define RVE_ORDER_COST 2       /* after a first solve: longest previous solve first */
 #define RVE_PTR_HOST 0
 #define RVE_PTR_DEVICE 1
 
@@ -175,6 +190,13 @@ typedef struct {
  *     Constant viscous damping on the resident and streamed engines only
  *     (RVE_EINVAL with kinetic or adaptive damping, the energy check or
  *     RVE_ENGINE_NAIVE).
+ *   work_order: the order in which the workgroups of a persistent resident
+ *     or streamed launch take its RVEs.  RVE_ORDER_HOST: most fibers first.
+ *     RVE_ORDER_COST: from the second solve of the batch on, descending
+ *     cost of the previous solve (iterations x fibers, longest processing
+ *     time first; ties and the first solve in host order).  RVE_ORDER_AUTO:
+ *     cost order for resident launches, host order for streamed ones.  Team
+ *     launches keep host order.  Results do not depend on the order.
  */
 typedef struct {
     int32_t precision;
@@ -201,6 +223,7 @@ typedef struct {
     int32_t tangent_rhs;    /* right-hand sides per tangent task: 0 library choice (one per task,
                                the faster on MI355X), 1 one per task, 3 three per task where a
                                blocked build holds the RVE (at most 2048 free nodes) */
+    int32_t work_order;     /* RVE_ORDER_*: order of the RVEs in a resident or streamed launch */
 } rve_opts;
 
 /* Optional per-RVE diagnostics of a solve (each pointer may be NULL; same
@@ -253,7 +276,7 @@ int rve_batch_kernel_ms(rve_batch* b, double* relax_ms, double* stress_ms);
 /*
  * Kernel groups of the last solve: group_of_rve[R] receives the launch group
  * of every RVE, variant[g] its resident variant index (-1 streamed, -1 - k
- * a team of k workgroups per RVE) and, if
+ * a team of k workgroups per RVE, -100 the incidence kernel) and, if
  * the solve was profiled, ms[g] the duration of that group's relaxation
  * launch (NaN otherwise).  Arrays are host memory of max_groups entries;
  * *n_groups receives the number of groups.
@@ -459,11 +482,13 @@ int rve_batch_generation(const rve_batch* b, uint64_t* gen);
  * build forms (packed fiber ends against the LDS position array, incidence
  * codes and overflow reads against the LDS force array, the code's end sign,
  * LDS bytes against 160 KB), the streamed engine's workspace offsets, the
- * team engine's partition and halo tables for the RVEs it would take, and
- * the packing's incidence lists.  precision: RVE_FP64 or RVE_MIXED (LDS
- * layout).
- * plant: 0; 1 makes the replay assume one LDS position entry fewer (a
- * deliberate mistake that the replay must report; tests only).
+ * team engine's partition and halo tables for the RVEs it would take, the
+ * incidence engine's rank permutation, rounds and records (each record's
+ * fiber, orientation and other end), and the packing's incidence lists.
+ * precision: RVE_FP64 or RVE_MIXED (LDS layout).
+ * plant: 0; 1 makes the replay assume one LDS position entry fewer, 2
+ * corrupts the other end of one incidence record (deliberate mistakes that
+ * the replay must report; tests only).
  * RVE_OK, or RVE_EINVAL with the first violation in rve_last_error().
  */
 int rve_check_indexing(const rve_net_desc* net, int32_t precision, int32_t plant);

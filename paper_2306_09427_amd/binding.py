@@ -20,11 +20,13 @@ FP64, MIXED = 0, 1
 LAW_LINEAR, LAW_EXP = 0, 1
 MASS_LUMPED, MASS_SCALED = 0, 1
 INIT_AFFINE, INIT_REFERENCE, INIT_WARM = 0, 1, 2
-ENGINE_AUTO, ENGINE_STREAMED, ENGINE_NAIVE, ENGINE_TEAM = 0, 1, 2, 3
+ENGINE_AUTO, ENGINE_STREAMED, ENGINE_NAIVE, ENGINE_TEAM, ENGINE_INCIDENCE = 0, 1, 2, 3, 4
+GROUP_STREAMED, GROUP_INCIDENCE = -1, -100
 PTR_HOST, PTR_DEVICE = 0, 1
 ST_CONVERGED, ST_MAXITER, ST_NONFINITE, ST_BAD_F, ST_NO_STATE, ST_CG_MAXITER, ST_CG_INDEFINITE, ST_ENERGY = range(8)
 ST_STAGNATED = 8
 DAMP_VISCOUS, DAMP_KINETIC, DAMP_ADAPTIVE = 0, 1, 2
+ORDER_AUTO, ORDER_HOST, ORDER_COST = 0, 1, 2
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EWORKSPACE = 0, -22, -12, -5, -3, -28
 
 EXPORTS = ["rve_version", "rve_last_error", "rve_default_opts", "rve_batch_create", "rve_batch_set_opts",
@@ -49,7 +51,7 @@ class Opts(C.Structure):
                 ("threads_per_rve", C.c_int32), ("cg_tol", C.c_double), ("cg_max_iter", C.c_int64),
                 ("stream", C.c_void_p), ("damping", C.c_int32), ("energy_check", C.c_int32),
                 ("energy_tol", C.c_double), ("floor_tol_rel", C.c_double), ("stall_checks", C.c_int32),
-                ("tangent_rhs", C.c_int32)]
+                ("tangent_rhs", C.c_int32), ("work_order", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -128,7 +130,8 @@ def _check(rc):
 def make_opts(precision=FP64, law=LAW_EXP, mass=MASS_LUMPED, init=INIT_AFFINE, EA=1.0, B=10.0, rhoA=1.0,
               alpha=0.9, c=2.0, tol_abs=1e-10, tol_rel=0.0, n_max=1_000_000, check_every=1,
               engine=ENGINE_AUTO, threads_per_rve=0, cg_tol=1e-6, cg_max_iter=0, damping=DAMP_VISCOUS,
-              energy_check=False, energy_tol=0.05, floor_tol_rel=0.0, stall_checks=16, tangent_rhs=0) -> Opts:
+              energy_check=False, energy_tol=0.05, floor_tol_rel=0.0, stall_checks=16, tangent_rhs=0,
+              work_order=0) -> Opts:
     o = Opts()
     lib().rve_default_opts(C.byref(o))
     o.precision, o.law, o.mass, o.init = int(precision), int(law), int(mass), int(init)
@@ -139,6 +142,7 @@ def make_opts(precision=FP64, law=LAW_EXP, mass=MASS_LUMPED, init=INIT_AFFINE, E
     o.damping, o.energy_check, o.energy_tol = int(damping), int(bool(energy_check)), float(energy_tol)
     o.floor_tol_rel, o.stall_checks = float(floor_tol_rel), int(stall_checks)
     o.tangent_rhs = int(tangent_rhs)
+    o.work_order = int(work_order)
     return o
 
 
@@ -400,7 +404,8 @@ class Batch:
         return buf.value.decode()
 
     def groups(self):
-        """(group index per RVE, resident variant per group (-1 streamed), ms per group of the last profiled solve)."""
+        """(group index per RVE, code per group (resident variant >= 0, -1 streamed, -1 - k team of k,
+        -100 incidence), ms per group of the last profiled solve)."""
         g = np.empty(self.n_rve, np.int32)
         var = np.empty(16, np.int32)
         ms = np.empty(16)

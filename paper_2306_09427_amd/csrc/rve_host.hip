@@ -152,7 +152,20 @@ struct rve_batch {
     hipStream_t aux[3] = {nullptr, nullptr, nullptr};
     hipEvent_t fork_ev = nullptr, join_ev[3] = {nullptr, nullptr, nullptr};
     double* d_xm_free = nullptr;       // [NFREE][3] reference coordinates of free nodes (RVE_INIT_REFERENCE)
+    // incidence engine: per-RVE first record (-1: no tables), the tables on
+    // the device, and which builds use private memory ([kinetic][variant])
+    std::vector<int64_t> inc_first;
+    char* inc_mem = nullptr;
+    IncArgs inc_tab{};
+    bool inc_private[2][kNumInc] = {};
 };
+
+// Launch-group codes beside the resident variants (>= 0): the streamed
+// kernel, teams of k workgroups per RVE (-1 - k, k >= 2) and the incidence
+// kernel.
+constexpr int kStreamedGroup = -1;
+constexpr int kIncGroup = -100;
+static bool team_group(int v) { return v <= -3 && v >= -1 - kTeamMax; }
 
 // Adaptive damping and the energy check run on the FP64 variant engine;
 // kinetic damping alone runs on the ordinary engines (their kinetic builds).
@@ -232,10 +245,12 @@ static int validate_opts(const rve_opts* o, int64_t R)
     if (o->n_max < 0) return fail(RVE_EINVAL, "n_max must be >= 0");
     if (o->check_every < 1) return fail(RVE_EINVAL, "check_every must be >= 1");
     if (o->engine != RVE_ENGINE_AUTO && o->engine != RVE_ENGINE_STREAMED && o->engine != RVE_ENGINE_NAIVE &&
-        o->engine != RVE_ENGINE_TEAM)
+        o->engine != RVE_ENGINE_TEAM && o->engine != RVE_ENGINE_INCIDENCE)
         return fail(RVE_EINVAL, "bad engine");
     if (o->engine == RVE_ENGINE_NAIVE && o->precision != RVE_FP64)
         return fail(RVE_EINVAL, "the naive engine is FP64 only");
+    if (o->engine == RVE_ENGINE_INCIDENCE && o->precision != RVE_MIXED)
+        return fail(RVE_EINVAL, "the incidence engine is RVE_MIXED only");
     if (!(o->cg_tol > 0) || o->cg_max_iter < 0) return fail(RVE_EINVAL, "cg_tol must be > 0, cg_max_iter >= 0");
     if (o->threads_per_rve != 0 && o->threads_per_rve != 256 && o->threads_per_rve != 512 &&
         o->threads_per_rve != 768 && o->threads_per_rve != 1024)
@@ -251,6 +266,8 @@ static int validate_opts(const rve_opts* o, int64_t R)
     }
     if (o->tangent_rhs != 0 && o->tangent_rhs != 1 && o->tangent_rhs != 3)
         return fail(RVE_EINVAL, "tangent_rhs must be 0, 1 or 3");
+    if (o->work_order != RVE_ORDER_AUTO && o->work_order != RVE_ORDER_HOST && o->work_order != RVE_ORDER_COST)
+        return fail(RVE_EINVAL, "work_order must be RVE_ORDER_AUTO, RVE_ORDER_HOST or RVE_ORDER_COST");
     if (!(o->floor_tol_rel >= 0) || !std::isfinite(o->floor_tol_rel))
         return fail(RVE_EINVAL, "floor_tol_rel must be >= 0 and finite");
     if (o->floor_tol_rel > 0) {
@@ -707,6 +724,131 @@ static int build_team_tables(rve_batch* b, const HostPack& P)
     return RVE_OK;
 }
 
+// ------------------------------------------------------------------ incidence tables
+// Host tables of the incidence engine (layout in rve_internal.h).  An RVE
+// gets tables when its free nodes fit every incidence build (at most
+// kIncMaxNodes, their positions within the LDS budget) and no free node has
+// more than kIncMaxDeg fibers.
+struct IncHost {
+    std::vector<int64_t> rec_first;     // [R]
+    std::vector<int32_t> round_first;   // [R][kIncMaxDeg + 1]
+    std::vector<int32_t> perm;          // [NFREE]
+    std::vector<uint32_t> rec_fib;
+    std::vector<uint2> rec_st;
+    std::vector<uint2> brec_st;         // [NBINC]
+};
+
+static size_t inc_lds_cap() { return 160 * 1024 - kResStaticLds; }
+
+static bool inc_fits(const HostPack& P, int64_t r)
+{
+    const int64_t nf = P.free_off[r + 1] - P.free_off[r];
+    return nf >= 1 && nf <= kIncMaxNodes && P.maxdeg[r] <= kIncMaxDeg && incidence_lds_bytes(nf) <= inc_lds_cap();
+}
+
+static uint32_t f32_bits(float x)
+{
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    return u;
+}
+
+// Tables of RVE r: ranks by descending degree (ties in the packed order),
+// then round q lists the q-th incidence of ranks 0 .. P_q - 1.  Each record
+// keeps the incidence word (fiber and which end the node is), 1/L0 in FP32
+// and the rank of the fiber's other end (nf, the zero slot, for a boundary
+// end).  Boundary incidences get the same static part in DevNet::binc order.
+static void inc_build(const HostPack& P, int64_t r, IncHost& H)
+{
+    const int64_t f0 = P.fib_off[r], a0 = P.free_off[r], b0 = P.bnd_off[r];
+    const int64_t nf = P.free_off[r + 1] - a0, nb = P.bnd_off[r + 1] - b0;
+    auto deg = [&](int64_t a) { return P.inc_off[a0 + a + 1] - P.inc_off[a0 + a]; };
+    std::vector<int32_t> order(nf), rank(nf);
+    for (int64_t a = 0; a < nf; ++a) order[a] = (int32_t)a;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return deg(x) > deg(y); });
+    for (int64_t p = 0; p < nf; ++p) {
+        rank[order[p]] = (int32_t)p;
+        H.perm[a0 + p] = order[p];
+    }
+    auto other_rank = [&](uint32_t w) -> uint32_t {
+        const uint32_t e = P.ends[f0 + (w & 0x7fffffffu)];
+        const int64_t o = (w >> 31) ? (e >> 16) : (e & 0xffffu);   // the node is end i: the other is end j
+        return o < nf ? (uint32_t)rank[o] : (uint32_t)nf;
+    };
+    auto inv_len = [&](uint32_t w) { return f32_bits((float)(1.0 / P.L0[f0 + (w & 0x7fffffffu)])); };
+    H.rec_first[r] = (int64_t)H.rec_fib.size();
+    int32_t* rf = &H.round_first[(size_t)r * (kIncMaxDeg + 1)];
+    int32_t cur = 0;
+    for (int q = 0; q < kIncMaxDeg; ++q) {
+        rf[q] = cur;
+        for (int64_t p = 0; p < nf && deg(order[p]) > q; ++p) {
+            const uint32_t w = P.inc[P.inc_off[a0 + order[p]] + q];
+            H.rec_fib.push_back(w);
+            H.rec_st.push_back(make_uint2(inv_len(w), other_rank(w)));
+            ++cur;
+        }
+    }
+    rf[kIncMaxDeg] = cur;
+    for (int64_t e = P.binc_off[b0]; e < P.binc_off[b0 + nb]; ++e)
+        H.brec_st[e] = make_uint2(inv_len(P.binc[e]), other_rank(P.binc[e]));
+}
+
+static void inc_build_all(const HostPack& P, int64_t R, IncHost& H)
+{
+    H.rec_first.assign(R, -1);
+    H.round_first.assign((size_t)R * (kIncMaxDeg + 1), 0);
+    H.perm.assign(P.free_off[R], 0);
+    H.brec_st.assign(P.binc.size(), make_uint2(0u, 0u));
+    for (int64_t r = 0; r < R; ++r)
+        if (inc_fits(P, r)) inc_build(P, r, H);
+}
+
+static int build_inc_tables(rve_batch* b, const HostPack& P)
+{
+    IncHost H;
+    try {
+        inc_build_all(P, b->R, H);
+    } catch (const std::bad_alloc&) {
+        return fail(RVE_ENOMEM, "host allocation failed while building the incidence tables");
+    }
+    b->inc_first = H.rec_first;
+    if (H.rec_fib.empty()) return RVE_OK;
+    const size_t NREC = H.rec_fib.size(), NB = std::max<size_t>(H.brec_st.size(), 1);
+    DeviceArena A;
+    const size_t o_first = A.reserve(8 * (size_t)b->R), o_round = A.reserve(4 * H.round_first.size()),
+                 o_perm = A.reserve(4 * H.perm.size() + 4), o_fib = A.reserve(4 * NREC), o_st = A.reserve(8 * NREC),
+                 o_rec = A.reserve(16 * NREC), o_bst = A.reserve(8 * NB), o_brec = A.reserve(16 * NB),
+                 o_im = A.reserve(4 * H.perm.size() + 4);
+    if (hipMalloc((void**)&b->inc_mem, A.used + 256) != hipSuccess) {
+        b->inc_mem = nullptr;
+        b->inc_first.assign(b->R, -1);
+        return fail(RVE_ENOMEM, "device allocation of the incidence tables failed");
+    }
+    char* m = b->inc_mem;
+    auto up = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
+        return bytes ? hipMemcpy(m + off, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
+    };
+    hipError_t e = hipSuccess;
+    e = e ? e : up(o_first, H.rec_first.data(), 8 * (size_t)b->R);
+    e = e ? e : up(o_round, H.round_first.data(), 4 * H.round_first.size());
+    e = e ? e : up(o_perm, H.perm.data(), 4 * H.perm.size());
+    e = e ? e : up(o_fib, H.rec_fib.data(), 4 * NREC);
+    e = e ? e : up(o_st, H.rec_st.data(), 8 * NREC);
+    e = e ? e : up(o_bst, H.brec_st.data(), 8 * H.brec_st.size());
+    if (e != hipSuccess) return fail(RVE_EDEVICE, std::string("incidence table upload failed: ") + hipGetErrorString(e));
+    IncArgs& t = b->inc_tab;
+    t.rec_first = carve<int64_t>(m, o_first);
+    t.round_first = carve<int32_t>(m, o_round);
+    t.perm = carve<int32_t>(m, o_perm);
+    t.rec_fib = carve<uint32_t>(m, o_fib);
+    t.rec_st = carve<uint2>(m, o_st);
+    t.rec = carve<float4>(m, o_rec);
+    t.brec_st = carve<uint2>(m, o_bst);
+    t.brec = carve<float4>(m, o_brec);
+    t.imass = carve<float>(m, o_im);
+    return RVE_OK;
+}
+
 // Team launches: workgroups per CU of the team build at this LDS size, and
 // the number of teams (a multiple of 8, so every team lies on one XCD).
 static int team_grid(const rve_batch* b, bool fp64, bool kin, size_t lds, int k, int* n_teams)
@@ -767,8 +909,11 @@ static size_t team_ws_bytes(const rve_batch* b)
 // against a CU's 160 KB.  Streamed engine: the workspace offsets of every
 // fiber, node and zero slot against the workspace sizes.  The packing itself:
 // every fiber appears in the incidence of each of its ends with the sign of
-// that end.  `plant` (tests only) shrinks the LDS position array by one
-// entry, a mistake the replay must report.
+// that end.  Incidence engine: the rank permutation, the rounds and every
+// record (node, fiber, orientation, other end) of the tables the batch
+// builds.  `plant` (tests only) 1 shrinks the LDS position array by one
+// entry, 2 corrupts the other-end rank of one incidence record: mistakes the
+// replay must report.
 static int check_indexing(const rve_net_desc* net, bool fp64, int plant)
 {
     HostPack P;
@@ -782,6 +927,13 @@ static int check_indexing(const rve_net_desc* net, bool fp64, int plant)
     auto bad = [&](int64_t r, const std::string& what) {
         return fail(RVE_EINVAL, "index replay, RVE " + std::to_string(r) + ": " + what);
     };
+    IncHost H;
+    try {
+        inc_build_all(P, R, H);
+    } catch (const std::bad_alloc&) {
+        return fail(RVE_ENOMEM, "host allocation failed while building the incidence tables");
+    }
+    if (plant == 2 && !H.rec_st.empty()) H.rec_st[H.rec_st.size() / 2].y ^= 1u;
     for (int64_t r = 0; r < R; ++r) {
         const int64_t f0 = P.fib_off[r], a0 = P.free_off[r], b0 = P.bnd_off[r];
         const int64_t nfib = P.fib_off[r + 1] - f0, nf = P.free_off[r + 1] - a0, nb = P.bnd_off[r + 1] - b0;
@@ -848,6 +1000,55 @@ static int check_indexing(const rve_net_desc* net, bool fp64, int plant)
         // streamed engine: workspace entries [NF + R] per fiber array, [NFREE + R] positions
         if (f0 + r + nfib >= NF + R) return bad(r, "streamed fiber zero slot outside the workspace");
         if (a0 + r + nf >= NFREE + R) return bad(r, "streamed position zero slot outside the workspace");
+        // incidence engine: ranks, rounds and records against the node slots,
+        // the LDS positions (nf + 1) and the record arrays; each record names
+        // its node's fiber, the node as the end its sign says, and the rank of
+        // the other end (the zero slot nf for a boundary end)
+        if (H.rec_first[r] >= 0) {
+            const int64_t rb0 = H.rec_first[r];
+            const int32_t* rf = &H.round_first[(size_t)r * (kIncMaxDeg + 1)];
+            for (int v = 0; v < kNumInc; ++v)
+                if ((int64_t)kInc[v].threads * kInc[v].slots < nf) return bad(r, "incidence: node slots below nf");
+            if (incidence_lds_bytes(nf) + kResStaticLds > 160 * 1024) return bad(r, "incidence: LDS beyond 160 KB");
+            std::vector<int> hit(nf, 0);
+            for (int64_t p = 0; p < nf; ++p) {
+                const int32_t a = H.perm[a0 + p];
+                if (a < 0 || a >= nf || hit[a]++) return bad(r, "incidence: ranks are not a permutation");
+            }
+            if (rf[0] != 0) return bad(r, "incidence: round 0 does not start the records");
+            int64_t count = 0;
+            for (int q = 0; q < kIncMaxDeg; ++q) {
+                const int64_t Pq = rf[q + 1] - rf[q];
+                if (Pq < 0 || Pq > nf || (q > 0 && Pq > rf[q] - rf[q - 1]))
+                    return bad(r, "incidence: rounds are not shrinking prefixes of the ranks");
+                for (int64_t p = 0; p < Pq; ++p) {
+                    const int64_t j = rb0 + rf[q] + p;
+                    if (j < 0 || j >= (int64_t)H.rec_fib.size()) return bad(r, "incidence: record outside the arrays");
+                    const int32_t a = H.perm[a0 + p];
+                    const int64_t deg = P.inc_off[a0 + a + 1] - P.inc_off[a0 + a];
+                    if (deg <= q || H.rec_fib[j] != P.inc[P.inc_off[a0 + a] + q])
+                        return bad(r, "incidence: record is not the node's incidence of its round");
+                    const uint32_t w = H.rec_fib[j], e = P.ends[f0 + (w & 0x7fffffffu)];
+                    if ((int64_t)(w & 0x7fffffffu) >= nfib) return bad(r, "incidence: fiber outside the RVE");
+                    const int64_t self = (w >> 31) ? (e & 0xffffu) : (e >> 16);
+                    const int64_t other = (w >> 31) ? (e >> 16) : (e & 0xffffu);
+                    if (self != a) return bad(r, "incidence: record oriented from another node");
+                    const uint32_t o = H.rec_st[j].y;
+                    if (o > (uint32_t)nf || (other < nf ? (o == (uint32_t)nf || H.perm[a0 + o] != other) : o != (uint32_t)nf))
+                        return bad(r, "incidence: record names a wrong other end");
+                    ++count;
+                }
+            }
+            if (count != P.inc_off[a0 + nf] - P.inc_off[a0] || rf[kIncMaxDeg] != count)
+                return bad(r, "incidence: rounds do not hold every incidence once");
+            for (int64_t e = P.binc_off[b0]; e < P.binc_off[b0 + nb]; ++e) {
+                const uint32_t w = P.binc[e], ee = P.ends[f0 + (w & 0x7fffffffu)];
+                const int64_t other = (w >> 31) ? (ee >> 16) : (ee & 0xffffu);
+                const uint32_t o = H.brec_st[e].y;
+                if (o > (uint32_t)nf || (other < nf ? (o == (uint32_t)nf || H.perm[a0 + o] != other) : o != (uint32_t)nf))
+                    return bad(r, "incidence: boundary record names a wrong other end");
+            }
+        }
         // team engine: the partition of an RVE no FP64 resident build holds
         const int cap_f = kTeamUnit[0].threads * kTeamUnit[0].sf, cap_n = kTeamUnit[0].threads * kTeamUnit[0].sn;
         if (nfib <= cap_f && nf <= cap_n) continue;
@@ -973,6 +1174,21 @@ static int default_variant(const rve_batch* b, int tier, bool fp64)
     return chosen;
 }
 
+// Incidence build for the batch's options: the first of kInc without
+// private memory (of threads_per_rve threads when that is set), -1 when
+// none or the options rule the engine out.
+static int inc_variant(const rve_batch* b)
+{
+    if (b->opts.precision != RVE_MIXED || b->opts.damping == RVE_DAMP_ADAPTIVE || b->opts.energy_check ||
+        b->opts.engine == RVE_ENGINE_STREAMED || b->opts.engine == RVE_ENGINE_NAIVE || b->inc_first.empty())
+        return -1;
+    const int k = b->opts.damping == RVE_DAMP_KINETIC ? 1 : 0;
+    for (int v = 0; v < kNumInc; ++v)
+        if (!b->inc_private[k][v] && (!b->opts.threads_per_rve || b->opts.threads_per_rve == kInc[v].threads))
+            return v;
+    return -1;
+}
+
 static void assign_groups(rve_batch* b)
 {
     b->groups.clear();
@@ -980,11 +1196,17 @@ static void assign_groups(rve_batch* b)
     b->group_lds.clear();
     b->group_team.clear();
     const bool fp64 = b->opts.precision == RVE_FP64;
-    // [resident variants..., streamed, teams of 2..kTeamMax]
-    std::vector<std::vector<int32_t>> per(kNumResident + 1 + kTeamMax + 1);
+    // [resident variants..., streamed, teams of 2..kTeamMax, incidence]
+    const int inc_slot = kNumResident + kTeamMax + 1;
+    std::vector<std::vector<int32_t>> per(inc_slot + 1);
+    const int eng = b->opts.engine;
+    const bool inc_build = inc_variant(b) >= 0;
     for (int64_t r = 0; r < b->R; ++r) {
         int slot = kNumResident;   // streamed
-        if (b->opts.engine == RVE_ENGINE_AUTO || b->opts.engine == RVE_ENGINE_TEAM) {
+        const bool inc = inc_build && b->inc_first[r] >= 0;
+        if (eng == RVE_ENGINE_INCIDENCE && inc) {
+            slot = inc_slot;
+        } else if (eng == RVE_ENGINE_AUTO || eng == RVE_ENGINE_TEAM || eng == RVE_ENGINE_INCIDENCE) {
             int t = tier_of(b, r, fp64);
             int chosen = -1;
             if (t >= 0) {
@@ -994,11 +1216,13 @@ static void assign_groups(rve_batch* b)
             }
             const int k = b->team_k.empty() ? 0 : b->team_k[r];
             const bool team = k > 0 && !b->opts.threads_per_rve &&
-                              (b->opts.engine == RVE_ENGINE_TEAM || b->tuned_team[fp64 ? 1 : 0][k] == 1);
+                              (eng == RVE_ENGINE_TEAM || b->tuned_team[fp64 ? 1 : 0][k] == 1);
             if (chosen >= 0)
                 slot = chosen;
             else if (team)
                 slot = kNumResident + k;
+            else if (inc)
+                slot = inc_slot;
         }
         per[slot].push_back((int32_t)r);
     }
@@ -1008,15 +1232,20 @@ static void assign_groups(rve_batch* b)
         std::stable_sort(members.begin(), members.end(),
                          [&](int32_t a, int32_t c) { return b->nfib_of[a] > b->nfib_of[c]; });
         size_t lds = 0;
-        int team = 0;
+        int team = 0, code = kStreamedGroup;
         if (v < (size_t)kNumResident) {
             for (int32_t r : members) lds = std::max(lds, resident_lds_bytes(fp64, b->nf_of[r], b->nfib_of[r], 0));
+            code = (int)v;
+        } else if (v == (size_t)inc_slot) {
+            for (int32_t r : members) lds = std::max(lds, incidence_lds_bytes(b->nf_of[r]));
+            code = kIncGroup;
         } else if (v > (size_t)kNumResident) {
             team = (int)(v - kNumResident);
             for (int32_t r : members) lds = std::max(lds, b->team_lds[fp64 ? 1 : 0][r]);
+            code = -1 - team;
         }
         b->groups.push_back(members);
-        b->group_variant.push_back(v < (size_t)kNumResident ? (int)v : (team ? -1 - team : -1));
+        b->group_variant.push_back(code);
         b->group_lds.push_back(lds);
         b->group_team.push_back(team);
     }
@@ -1154,6 +1383,7 @@ void rve_default_opts(rve_opts* o)
     o->floor_tol_rel = 0.0;
     o->stall_checks = 16;
     o->tangent_rhs = 0;
+    o->work_order = RVE_ORDER_AUTO;
 }
 
 // Address of the allocation-free solve's scratch array on device dev, taken
@@ -1217,6 +1447,12 @@ int rve_batch_create(const rve_net_desc* net, const rve_opts* opts, rve_batch** 
                 if (streamed_scratch_bytes(p == 1, k == 1, w ? 1024 : 256, &sb) != hipSuccess) sb = 1;
                 b->streamed_private[k][p][w] = sb > 0;
             }
+        }
+    for (int k = 0; k < 2; ++k)
+        for (int v = 0; v < kNumInc; ++v) {
+            size_t sb = 1;
+            if (incidence_scratch_bytes(v, k == 1, &sb) != hipSuccess) sb = 1;
+            b->inc_private[k][v] = sb > 0;
         }
     for (int m = 0; m < 2; ++m)
         for (int v = 0; v < kNumTanRes; ++v) {
@@ -1350,6 +1586,7 @@ int rve_batch_create(const rve_net_desc* net, const rve_opts* opts, rve_batch** 
     b->dlist = carve<int32_t>(m, o_list);
 
     rc = build_team_tables(b, P);
+    if (!rc) rc = build_inc_tables(b, P);
     if (rc) {
         rve_batch_destroy(b);
         return rc;
@@ -1478,21 +1715,29 @@ static int launch_groups(rve_batch* b, SolveArgs& a, int32_t* queues, void* ws_f
         int rc = ensure_events(b, 2 * (int)b->groups.size() + 2);
         if (rc) return rc;
     }
-    // After a first solve, each resident or streamed group takes its RVEs in
+    // Work order (opts.work_order).  In cost order a group takes its RVEs in
     // longest-processing-time order of the previous solve's cost (iterations
     // x fibers), so the RVEs that ran longest start first and the launch's
-    // tail (its last, long RVEs on few CUs) shrinks; before it, the host's
-    // order (most fibers first).  Team groups keep theirs.
-    if (b->cost_order && (int)b->groups.size() <= kOrderGroups) {
+    // tail (its last, long RVEs on few CUs) shrinks; in host order, most
+    // fibers first.  The sort is in place and stable (ties keep host order);
+    // rve_batch_set_opts uploads the host order again, so a change of
+    // work_order starts from it.  Team groups keep host order.
+    if ((int)b->groups.size() <= kOrderGroups) {
         OrderArgs o{};
         o.list = b->dlist;
         o.iters = b->diters;
         o.fib_off = b->net.fib_off;
+        bool any = false;
         for (size_t g = 0; g < b->groups.size(); ++g) {
+            const int v = b->group_variant[g];
+            bool by_cost = b->cost_order && !team_group(v);
+            if (b->opts.work_order == RVE_ORDER_HOST) by_cost = false;
+            if (b->opts.work_order == RVE_ORDER_AUTO && v < 0) by_cost = false;
             o.first[g] = b->group_first[g];
-            o.count[g] = b->group_variant[g] >= -1 ? (int32_t)b->groups[g].size() : 0;
+            o.count[g] = by_cost ? (int32_t)b->groups[g].size() : 0;
+            any = any || by_cost;
         }
-        HIP_TRY(launch_order_by_cost(o, (int)b->groups.size(), s));
+        if (any) HIP_TRY(launch_order_by_cost(o, (int)b->groups.size(), s));
     }
     HIP_TRY(launch_reset(queues, 2 * (int)b->groups.size(), s));
     int32_t* team_err = reinterpret_cast<int32_t*>(team_ws);
@@ -1504,11 +1749,11 @@ static int launch_groups(rve_batch* b, SolveArgs& a, int32_t* queues, void* ws_f
     // so the tail of one group (its last, longest RVEs) overlaps the others.
     std::vector<size_t> order;
     for (size_t g = 0; g < b->groups.size(); ++g)
-        if (b->group_variant[g] < -1) order.push_back(g);
+        if (team_group(b->group_variant[g])) order.push_back(g);
     const size_t n_team = order.size();
     std::vector<std::pair<int64_t, size_t>> rest;
     for (size_t g = 0; g < b->groups.size(); ++g)
-        if (b->group_variant[g] >= -1) {
+        if (!team_group(b->group_variant[g])) {
             int64_t w = 0;
             for (int32_t r : b->groups[g]) w += b->nfib_of[r];
             rest.push_back({-w, g});
@@ -1542,7 +1787,15 @@ static int launch_groups(rve_batch* b, SolveArgs& a, int32_t* queues, void* ws_f
             if (per_cu < 1) return fail(RVE_EDEVICE, "resident kernel variant does not fit a CU");
             int grid = std::min<int64_t>((int64_t)per_cu * b->n_cu, a.n_list);
             HIP_TRY(launch_resident(v, fp64, a, b->group_lds[g], grid, gs_));
-        } else if (v < -1) {
+        } else if (v == kIncGroup) {
+            const int iv = inc_variant(b);
+            if (iv < 0) return fail(RVE_EDEVICE, "internal: no incidence build for these options");
+            int per_cu = 1;
+            HIP_TRY(incidence_blocks(iv, a.kinetic != 0, b->group_lds[g], &per_cu));
+            if (per_cu < 1) return fail(RVE_EDEVICE, "incidence kernel does not fit a CU");
+            int grid = std::min<int64_t>((int64_t)per_cu * b->n_cu, a.n_list);
+            HIP_TRY(launch_incidence(iv, a, b->inc_tab, b->group_lds[g], grid, gs_));
+        } else if (team_group(v)) {
             const int k = b->group_team[g];
             if (!team_ws) return fail(RVE_EWORKSPACE, "internal: no team work area");
             int n_teams = 0;
@@ -2010,7 +2263,11 @@ int rve_batch_describe(const rve_batch* b, char* buf, size_t n)
         if (v >= 0)
             d += "resident(" + std::to_string(kResident[v].threads) + "," + std::to_string(kResident[v].sf) + "," +
                  std::to_string(kResident[v].sn) + ")";
-        else if (v < -1)
+        else if (v == kIncGroup) {
+            const int iv = std::max(inc_variant(b), 0);
+            d += "incidence(" + std::to_string(kInc[iv].threads) + "," + std::to_string(kInc[iv].slots) + "," +
+                 std::to_string(kInc[iv].batch) + ")";
+        } else if (team_group(v))
             d += "team(" + std::to_string(-1 - v) + "x" + std::to_string(kTeamUnit[b->opts.precision == RVE_FP64].threads) + ")";
         else
             d += streamed_lds_nodes(b, b->groups[g].data(), b->groups[g].size(), b->opts.precision == RVE_FP64) > 0
@@ -2762,6 +3019,7 @@ void rve_batch_destroy(rve_batch* b)
     if (b->dtune_list) (void)hipFree(b->dtune_list);
     if (b->d_xm_free) (void)hipFree(b->d_xm_free);
     if (b->team_mem) (void)hipFree(b->team_mem);
+    if (b->inc_mem) (void)hipFree(b->inc_mem);
     if (b->dmem) (void)hipFree(b->dmem);
     delete b;
 }
@@ -2811,7 +3069,7 @@ extern "C" int rve_batch_solve_static(rve_batch* b, const double* F, double* sig
     if (b->R == 0) return RVE_OK;
     if (!F || !sigma || !status) return fail(RVE_EINVAL, "F, sigma and status are required");
     if (b->opts.engine == RVE_ENGINE_NAIVE || variant_mode(b->opts))
-        return fail(RVE_EINVAL, "the allocation-free solve runs the resident and streamed engines only");
+        return fail(RVE_EINVAL, "the allocation-free solve runs the resident, incidence, team and streamed engines only");
     if (b->opts.init == RVE_INIT_REFERENCE)
         return fail(RVE_EINVAL, "the allocation-free solve takes the affine or warm start");
     if (b->opts.init == RVE_INIT_WARM && !b->have_state)
@@ -2819,8 +3077,8 @@ extern "C" int rve_batch_solve_static(rve_batch* b, const double* F, double* sig
     const bool fp64 = b->opts.precision == RVE_FP64;
     bool streamed = false, team = false;
     for (int v : b->group_variant) {
-        streamed |= (v == -1);
-        team |= (v < -1);
+        streamed |= (v == kStreamedGroup);
+        team |= team_group(v);
     }
     // layout: work counters (two per launch group), the team work area, then
     // the streamed workspace of this batch's precision

@@ -229,6 +229,43 @@ hipError_t launch_team(bool fp64, const TeamArgs& a, size_t lds_bytes, int grid,
 hipError_t team_info(bool fp64, bool kin, size_t lds_bytes, int* blocks_per_cu, size_t* private_bytes);
 size_t team_lds_bytes(bool fp64, int64_t n_pos, int64_t nfib);   // n_pos: owned + halo nodes
 
+// Incidence engine (rve_kernels.hip): one workgroup per RVE; the velocity,
+// acceleration and inverse mass of the free nodes stay in registers (node
+// rank p in slot p / T of thread p % T), the positions in LDS (one float
+// array per component, the zero slot at nf), and every iteration reads one
+// record per (node, incident fiber) from global memory and evaluates the
+// fiber at that end, so no fiber force is written or gathered.  Ranks order
+// the free nodes by descending degree; round q holds the q-th incidence of
+// the ranks 0 .. P_q - 1 (the nodes of degree > q), rank p at record
+// rec_first + round_first[q] + p, so the lanes of a wave read consecutive
+// records.  Record orientation: the node plays the fiber's end j, i.e. (Dn,
+// Qn, 1/L0) of the scaled form with Dn = F (X_node - X_other) / L0 and the
+// position difference h_node - h_other; the force it yields is the
+// internal force at the node.
+constexpr int kIncMaxDeg = 16;    // free-node degree limit of the tables
+constexpr int kIncMaxNodes = 12288;
+struct IncArgs {
+    const int64_t* rec_first;     // [R] first record of the RVE, -1 when it has no tables
+    const int32_t* round_first;   // [R][kIncMaxDeg + 1] start of round q relative to rec_first ([kIncMaxDeg]: total)
+    const int32_t* perm;          // [NFREE] local free-node id of rank p, at free_off[r] + p
+    const uint32_t* rec_fib;      // [NREC] local fiber id | (1u << 31 when the node is the fiber's end i)
+    const uint2* rec_st;          // [NREC] (bits of FP32 1/L0, rank of the other end or nf for a boundary end)
+    float4* rec;                  // [NREC] (Dn, Qn) under the solve's F, written at the start of the solve
+    const uint2* brec_st;         // [NBINC] the same for each boundary incidence (DevNet::binc order)
+    float4* brec;                 // [NBINC]
+    float* imass;                 // [NFREE] inverse mass of rank p (builds that keep it out of registers)
+};
+struct IncVariant {
+    int threads, slots, batch;   // batch: records of rounds loaded together
+};
+constexpr int kNumInc = 2;
+extern const IncVariant kInc[kNumInc];
+inline size_t incidence_lds_bytes(int64_t nf) { return 12 * (size_t)(nf + 1); }
+hipError_t launch_incidence(int variant, const SolveArgs& a, const IncArgs& inc, size_t lds_bytes, int grid,
+                            hipStream_t s);
+hipError_t incidence_blocks(int variant, bool kin, size_t lds_bytes, int* blocks_per_cu);
+hipError_t incidence_scratch_bytes(int variant, bool kin, size_t* bytes);
+
 // Which register-resident variants exist (threads per RVE, fiber slots per
 // thread, free-node slots per thread).
 struct ResidentVariant {

@@ -1328,6 +1328,389 @@ __global__ __launch_bounds__(T) void dr_streamed_kernel(SolveArgs A)
     }
 }
 
+// ------------------------------------------------------------------ incidence kernel
+// RVEs beyond the register-resident capacity whose free nodes fit one
+// workgroup's registers and LDS (layout in rve_internal.h).  Per iteration
+// the network is read once from global memory as per-incidence records, the
+// node state never leaves the CU, and no fiber force goes through memory:
+// each fiber is evaluated at both of its ends (twice the fiber arithmetic of
+// the other engines, which this memory-bound regime has to spare).
+const IncVariant kInc[kNumInc] = {{768, 16, 2}, {512, 24, 4}};
+
+// Record of one incidence under F: the scaled form (Dn, Qn) of the fiber
+// oriented so that the node is its end j (rve_internal.h), formed in FP64.
+__device__ __forceinline__ float4 inc_record(const double* F, const DevNet& net, int64_t f0, uint32_t w)
+{
+    const int64_t k = f0 + (int64_t)(w & 0x7fffffffu);
+    const double* d0 = net.d0 + 3 * k;
+    const double L0 = net.L0[k], il = 1.0 / L0;
+    const double Dx = F[0] * d0[0] + F[1] * d0[1] + F[2] * d0[2];
+    const double Dy = F[3] * d0[0] + F[4] * d0[1] + F[5] * d0[2];
+    const double Dz = F[6] * d0[0] + F[7] * d0[1] + F[8] * d0[2];
+    const double sg = (w >> 31) ? -il : il;
+    return make_float4((float)(Dx * sg), (float)(Dy * sg), (float)(Dz * sg),
+                       (float)((((Dx * Dx + Dy * Dy + Dz * Dz) - L0 * L0) * il) * il));
+}
+
+// One RVE on one workgroup of T threads with S node slots per thread.  IMG:
+// the inverse masses live in a global array (rank order, 4 bytes per node
+// and iteration) instead of registers (the builds take it: with it in
+// registers they exceed their budget).  The first QU rounds are unrolled,
+// their records loaded QR at a time.
+template <int T, int S, int QR, bool IMG, bool KIN>
+__device__ __forceinline__ void incidence_solve(const SolveArgs& A, const IncArgs& I, int r, char* smem,
+                                                RedSlots& red)
+{
+    constexpr int NW = T / 64;
+    constexpr int QU = 4;
+    static_assert(QU % QR == 0, "record batches tile the unrolled rounds");
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const DevNet& net = A.net;
+    const int64_t f0 = uniform64(net.fib_off[r]), a0 = uniform64(net.free_off[r]), b0 = uniform64(net.bnd_off[r]);
+    const int nf = uniform32((int)(net.free_off[r + 1] - a0));
+    const int nb = uniform32((int)(net.bnd_off[r + 1] - b0));
+    const int64_t rb = uniform64(I.rec_first[r]);
+    const int32_t* rq = I.round_first + (int64_t)r * (kIncMaxDeg + 1);
+    int Rq[QU + 1];
+#pragma unroll
+    for (int q = 0; q <= QU; ++q) Rq[q] = uniform32(rq[q]);
+    const int nrec = uniform32(rq[kIncMaxDeg]);
+    const float4* recb = I.rec + rb;
+    const uint2* stb = I.rec_st + rb;
+    const int32_t* permb = I.perm + a0;
+    float* imb = I.imass + a0;
+    double* hsb = A.h_state + 3 * a0;
+
+    double F[9];
+    bool finite = true;
+    for (int k = 0; k < 9; ++k) {
+        F[k] = A.F[9 * r + k];
+        finite = finite && isfinite(F[k]);
+    }
+    const double J = det3(F);
+    if (!finite || !(J > 0.0)) {
+        if (tid == 0) {
+            A.status[r] = ST_BAD_F;
+            A.iters[r] = 0;
+            A.Rres[r] = NAN; A.Dres[r] = NAN; A.Bres[r] = NAN;
+            for (int k = 0; k < 9; ++k) A.sigma[9 * r + k] = NAN;
+        }
+        return;
+    }
+    const bool linear = A.law == kLawLinear;
+    // law constants from opaque per-RVE copies: nothing derived from them is
+    // held in vector registers across RVEs of the persistent loop
+    double EAd = A.EA, Bd = A.B;
+    asm volatile("" : "+s"(EAd), "+s"(Bd));
+    const float EA = uniform((float)EAd), Bc = uniform((float)Bd), EAoB = uniform((float)(EAd / Bd));
+    const double cr = uniform(A.c[r]);
+    const float c = KIN ? 0.f : uniform((float)cr);
+    const float cg = uniform((float)cr);   // scale of the damping-force test
+
+    float* lhx = reinterpret_cast<float*>(smem);
+    float* lhy = lhx + (nf + 1);
+    float* lhz = lhy + (nf + 1);
+
+    // ---- records of this F (free and boundary incidences)
+#pragma unroll 1
+    for (int j = tid; j < nrec; j += T) I.rec[rb + j] = inc_record(F, net, f0, I.rec_fib[rb + j]);
+    const int64_t be0 = uniform64(net.binc_off[b0]), be1 = uniform64(net.binc_off[b0 + nb]);
+#pragma unroll 1
+    for (int64_t e = be0 + tid; e < be1; e += T) I.brec[e] = inc_record(F, net, f0, net.binc[e]);
+
+    // ---- node state: velocity and acceleration in registers, positions in LDS
+    float vx[S], vy[S], vz[S], ax[S], ay[S], az[S], imr[IMG ? 1 : S];
+    auto im_get = [&](int s, int p) __attribute__((always_inline)) -> float {
+        if constexpr (IMG)
+            return imb[p];
+        else
+            return imr[s];
+    };
+    auto im_set = [&](int s, int p, float v) __attribute__((always_inline)) {
+        if constexpr (IMG)
+            imb[p] = v;
+        else
+            imr[s] = v;
+    };
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int p = s * T + tid;
+        vx[s] = vy[s] = vz[s] = ax[s] = ay[s] = az[s] = 0.f;
+        if constexpr (!IMG) imr[s] = 0.f;
+        if (p < nf) {
+            const int a = permb[p];
+            im_set(s, p, (float)(1.0 / (net.mass[a0 + a] * A.rhoA)));
+            float hx = 0.f, hy = 0.f, hz = 0.f;
+            if (A.init == kInitWarm) {
+                const double* h = hsb + 3 * a;
+                hx = (float)h[0]; hy = (float)h[1]; hz = (float)h[2];
+            }
+            lhx[p] = hx; lhy[p] = hy; lhz[p] = hz;
+        }
+    }
+    reset_gslots(red);
+    if (tid == 0) lhx[nf] = lhy[nf] = lhz[nf] = 0.f;
+    __syncthreads();
+
+    // internal force and Gershgorin sum at the node of slot s: the records of
+    // the first QR rounds are loaded together, further rounds (nodes of
+    // higher degree, the first ranks) one at a time; a lane past the round's
+    // nodes evaluates the zero slot and discards the result
+    auto node_force = [&](int t, int s, float& fx, float& fy, float& fz, float& G) __attribute__((always_inline)) {
+        const int p = s * T + t;
+        fx = fy = fz = G = 0.f;
+        float hxa = 0.f, hya = 0.f, hza = 0.f;
+        if (p < nf) {
+            hxa = lhx[p]; hya = lhy[p]; hza = lhz[p];
+        }
+#pragma unroll
+        for (int q0 = 0; q0 < QU; q0 += QR) {
+            float4 rc[QR];
+            uint2 st[QR];
+#pragma unroll
+            for (int u = 0; u < QR; ++u) {
+                const int q = q0 + u, Pq = Rq[q + 1] - Rq[q];
+                rc[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+                st[u] = make_uint2(0u, (uint32_t)nf);
+                if (s * T < Pq && p < Pq) {
+                    rc[u] = recb[Rq[q] + p];
+                    st[u] = stb[Rq[q] + p];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < QR; ++u) {
+                const int q = q0 + u, Pq = Rq[q + 1] - Rq[q];
+                if (s * T < Pq) {
+                    const int o = (int)st[u].y;
+                    const FiberOut<float> f = fiber_eval_scaled<float>(linear, EA, Bc, EAoB, rc[u].x, rc[u].y,
+                                                                       rc[u].z, rc[u].w, __uint_as_float(st[u].x),
+                                                                       hxa - lhx[o], hya - lhy[o], hza - lhz[o]);
+                    if (p < Pq) {
+                        fx += f.fx; fy += f.fy; fz += f.fz; G += f.b;
+                    }
+                }
+                // one fiber evaluation at a time (their temporaries do not overlap)
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+#pragma unroll 1
+        for (int q = QU; q < kIncMaxDeg; ++q) {
+            const int R0 = uniform32(rq[q]), Pq = uniform32(rq[q + 1]) - R0;
+            if (s * T >= Pq) break;
+            if (p < Pq) {
+                const float4 x = recb[R0 + p];
+                const uint2 y = stb[R0 + p];
+                const int o = (int)y.y;
+                const FiberOut<float> f = fiber_eval_scaled<float>(linear, EA, Bc, EAoB, x.x, x.y, x.z, x.w,
+                                                                   __uint_as_float(y.x), hxa - lhx[o], hya - lhy[o],
+                                                                   hza - lhz[o]);
+                fx += f.fx; fy += f.fy; fz += f.fz; G += f.b;
+            }
+        }
+        G *= 2.f;
+    };
+    // boundary reaction norm^2 partial of this thread (test iterations)
+    auto bnorm2 = [&](int t) __attribute__((always_inline)) -> double {
+        double acc = 0.0;
+#pragma unroll 1
+        for (int q = t; q < nb; q += T) {
+            double x = 0.0, y = 0.0, z = 0.0;
+            const int64_t e1 = net.binc_off[b0 + q + 1];
+#pragma unroll 1
+            for (int64_t e = net.binc_off[b0 + q]; e < e1; ++e) {
+                const float4 rc = I.brec[e];
+                const uint2 st = I.brec_st[e];
+                const int o = (int)st.y;
+                const FiberOut<float> f = fiber_eval_scaled<float>(linear, EA, Bc, EAoB, rc.x, rc.y, rc.z, rc.w,
+                                                                   __uint_as_float(st.x), 0.f - lhx[o], 0.f - lhy[o],
+                                                                   0.f - lhz[o]);
+                x += (double)f.fx; y += (double)f.fy; z += (double)f.fz;
+            }
+            acc += x * x + y * y + z * z;
+        }
+        return acc;
+    };
+
+    // ---- initial force, residual and (optionally) stiffness-scaled mass
+    float gpart = 0.f;
+    double r2p = 0.0, b2p = 0.0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        if (s * T < nf) {
+            const int p = s * T + tid;
+            float fx, fy, fz, G;
+            node_force(tid, s, fx, fy, fz, G);
+            if (p < nf) {
+                float im = im_get(s, p);
+                if (A.mass_mode == kMassScaled) {
+                    im = G > 0.f ? 4.f / G : 1.f;
+                    im_set(s, p, im);
+                }
+                ax[s] = -fx * im;
+                ay[s] = -fy * im;
+                az[s] = -fz * im;
+                gpart = fmax(gpart, G * im);
+                r2p += (double)fx * fx + (double)fy * fy + (double)fz * fz;
+            }
+        }
+    }
+    b2p = bnorm2(tid);
+    double gmax;
+    double R2 = 0.0, D2 = 0.0, B2 = 0.0;
+    int parity = 0;
+    block_reduce<float, NW>(red, tid, parity, gpart, r2p, 0.0, b2p, true, gmax, R2, D2, B2);
+
+    int64_t n = 0;
+    int status = ST_CONVERGED;
+    const int ce = A.check_every > 0 ? A.check_every : 1;
+    int countdown = ce;
+    bool done = sqrt(R2) <= fmax(A.tol_abs, A.tol_rel * sqrt(B2));   // v = 0: damping norm is 0
+    double Rref = uniform(sqrt(R2));
+    int stall = 0;
+    if (!isfinite(R2)) {
+        status = ST_NONFINITE;
+        done = true;
+    }
+    if (!done && n >= A.n_max) {
+        status = ST_MAXITER;
+        done = true;
+    }
+    auto time_step = [&](double g) __attribute__((always_inline)) -> double {
+        return uniform((double)(uniform((float)(2.0 * A.alpha)) * __builtin_amdgcn_rsqf((float)g)));
+    };
+    double dt = time_step(gmax);
+    double ke_prev = 0.0;
+
+    while (!done) {
+        const int t = opaque_tid();
+        // round starts opaque per iteration: the record addresses of every
+        // (slot, round) are formed where used, not hoisted and held in SGPRs
+#pragma unroll
+        for (int q = 0; q <= QU; ++q) asm volatile("" : "+s"(Rq[q]));
+        const float hdt = (float)(0.5 * dt), rdt = (float)dt;
+        // half-step velocity and position update
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int p = s * T + t;
+            if (s * T < nf && p < nf) {
+                vx[s] += hdt * ax[s]; vy[s] += hdt * ay[s]; vz[s] += hdt * az[s];
+                lhx[p] += rdt * vx[s]; lhy[p] += rdt * vy[s]; lhz[p] += rdt * vz[s];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        __syncthreads();
+        // a new opaque thread id for the force phase: the lane masks and LDS
+        // addresses of the update phase are not kept live across the barrier
+        const int tb = opaque_tid();
+        ++n;
+        const bool check = --countdown == 0;
+        if (check) countdown = ce;
+        gpart = 0.f;
+        r2p = 0.0;
+        double d2p = 0.0, kep = 0.0;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            if (s * T < nf) {
+                const int p = s * T + tb;
+                float fx, fy, fz, G;
+                node_force(tb, s, fx, fy, fz, G);
+                if (p < nf) {
+                    const float im = im_get(s, p);
+                    ax[s] = -fx * im - c * vx[s];
+                    ay[s] = -fy * im - c * vy[s];
+                    az[s] = -fz * im - c * vz[s];
+                    vx[s] += hdt * ax[s]; vy[s] += hdt * ay[s]; vz[s] += hdt * az[s];
+                    gpart = fmax(gpart, G * im);
+                    if constexpr (KIN)
+                        kep += 0.5 * (double)((vx[s] * vx[s] + vy[s] * vy[s] + vz[s] * vz[s]) * dev_rcp(im));
+                    if (check) {
+                        r2p += (double)fx * fx + (double)fy * fy + (double)fz * fz;
+                        const float cm = cg * dev_rcp(im);
+                        const double px = (double)(cm * vx[s]), py = (double)(cm * vy[s]), pz = (double)(cm * vz[s]);
+                        d2p += px * px + py * py + pz * pz;
+                    }
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (check) b2p = bnorm2(tb);
+        parity ^= 1;
+        double r2n = R2, d2n = D2, b2n = B2, ke = 0.0;
+        block_reduce<float, NW, KIN>(red, tb, parity, gpart, r2p, d2p, b2p, check, gmax, r2n, d2n, b2n, kep, &ke);
+        if constexpr (KIN) {
+            if (ke < ke_prev) {
+#pragma unroll
+                for (int s = 0; s < S; ++s) vx[s] = vy[s] = vz[s] = 0.f;
+                ke = 0.0;
+                if (check) d2n = 0.0;
+            }
+            ke_prev = ke;
+        }
+        if (check) {
+            R2 = r2n;
+            D2 = d2n;
+            B2 = b2n;
+            if (!isfinite(R2) || !isfinite(D2)) {
+                status = ST_NONFINITE;
+                break;
+            }
+            const double Rn = sqrt(R2), Dn = sqrt(D2), Bn = sqrt(B2);
+            const double tol = fmax(A.tol_abs, A.tol_rel * Bn);
+            if (Rn <= tol && Dn <= tol) break;
+            if (stagnated(A, Rn, Dn, Bn, Rref, stall)) {
+                status = ST_STAGNATED;
+                break;
+            }
+            Rref = uniform(Rref);
+        }
+        if (!(gmax > 0.0) || !isfinite(gmax)) {
+            status = ST_NONFINITE;
+            break;
+        }
+        if (n >= A.n_max) {
+            status = ST_MAXITER;
+            break;
+        }
+        dt = time_step(gmax);
+    }
+
+    // ---- fluctuation state in the packed order
+    const int te = opaque_tid();
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int p = s * T + te;
+        if (s * T < nf && p < nf) {
+            double* h = hsb + 3 * permb[p];
+            h[0] = (double)lhx[p]; h[1] = (double)lhy[p]; h[2] = (double)lhz[p];
+        }
+    }
+    if (te == 0) {
+        A.status[r] = status;
+        A.iters[r] = n;
+        A.Rres[r] = sqrt(R2);
+        A.Dres[r] = sqrt(D2);
+        A.Bres[r] = sqrt(B2);
+    }
+    __syncthreads();
+}
+
+template <int T, int S, int QR, bool KIN>
+__global__ __launch_bounds__(T) void dr_incidence_kernel(SolveArgs A, IncArgs I)
+{
+    extern __shared__ char smem_i[];
+    __shared__ RedSlots red;
+    __shared__ int task;
+    for (;;) {
+        if (threadIdx.x == 0) task = atomicAdd(A.queue, 1);
+        __syncthreads();
+        const int t = __builtin_amdgcn_readfirstlane(task);
+        __syncthreads();
+        if (t >= A.n_list) break;
+        incidence_solve<T, S, QR, true, KIN>(A, I, __builtin_amdgcn_readfirstlane(A.list[t]), smem_i, red);
+    }
+}
+
 // ------------------------------------------------------------------ stress kernel
 // Homogenized stress of every RVE from its final fluctuation state, one
 // workgroup per RVE: each fiber with a boundary end is re-evaluated in FP64
@@ -1592,6 +1975,54 @@ hipError_t streamed_scratch_bytes(bool fp64, bool kin, int threads, size_t* byte
     if (threads == 1024)
         return fp64 ? streamed_private_t<double, 1024>(kin, bytes) : streamed_private_t<float, 1024>(kin, bytes);
     return hipErrorInvalidValue;
+}
+
+template <int T, int S, int QR, bool KIN>
+static hipError_t launch_inc_t(const SolveArgs& a, const IncArgs& inc, size_t lds, int grid, hipStream_t s)
+{
+    auto k = dr_incidence_kernel<T, S, QR, KIN>;
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3(grid), dim3(T), lds, s, a, inc);
+    return hipGetLastError();
+}
+
+template <int T, int S, int QR, bool KIN>
+static hipError_t occ_inc_t(size_t lds, int* blocks)
+{
+    auto k = dr_incidence_kernel<T, S, QR, KIN>;
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, (const void*)k, T, lds);
+}
+
+template <int T, int S, int QR, bool KIN>
+static hipError_t spill_inc_t(size_t* bytes)
+{
+    return max_private_bytes({(const void*)dr_incidence_kernel<T, S, QR, KIN>}, bytes);
+}
+
+#define RVE_INC_DISPATCH(FN, ...)                                                                      \
+    switch (variant) {                                                                                \
+    case 0: return kin ? FN<768, 16, 2, true>(__VA_ARGS__) : FN<768, 16, 2, false>(__VA_ARGS__);       \
+    case 1: return kin ? FN<512, 24, 4, true>(__VA_ARGS__) : FN<512, 24, 4, false>(__VA_ARGS__);       \
+    default: return hipErrorInvalidValue;                                                             \
+    }
+
+hipError_t launch_incidence(int variant, const SolveArgs& a, const IncArgs& inc, size_t lds, int grid, hipStream_t s)
+{
+    const bool kin = a.kinetic != 0;
+    RVE_INC_DISPATCH(launch_inc_t, a, inc, lds, grid, s)
+}
+
+hipError_t incidence_blocks(int variant, bool kin, size_t lds, int* blocks)
+{
+    RVE_INC_DISPATCH(occ_inc_t, lds, blocks)
+}
+
+hipError_t incidence_scratch_bytes(int variant, bool kin, size_t* bytes)
+{
+    RVE_INC_DISPATCH(spill_inc_t, bytes)
 }
 
 hipError_t kernels_fixed_private(size_t* bytes)

@@ -4,7 +4,7 @@
 
 The workloads are those of synth.make_config_batch (config 1: one 100-seed
 RVE, linear fibers; 2-5: exponential fibers).  The line gives the kernel
-groups the batch chose, the wall time and the HIP-event time of every
+groups the batch chose (rve_batch_describe and per group), the wall time and the HIP-event time of every
 launch group of one solve (after one untimed warm-up solve), the statuses,
 and the algorithmic HBM bytes of every group (per iteration and RVE
 20 B per fiber + 52 B per free node in mixed precision, 32 B + 104 B in
@@ -35,12 +35,14 @@ def main(argv=None) -> int:
     ap.add_argument("--check-every", type=int, default=8)
     ap.add_argument("--cache", default=None, help="npz file holding the generated networks (written if absent)")
     ap.add_argument("--threads-per-rve", type=int, default=0, help="force resident builds of this workgroup size")
-    ap.add_argument("--engine", choices=["auto", "streamed", "team"], default="auto")
+    ap.add_argument("--engine", choices=["auto", "streamed", "team", "incidence"], default="auto")
     ap.add_argument("--tangent", action="store_true", help="also one tangent dsigma/dF call after the timed solve")
     ap.add_argument("--tangent-rhs", type=int, default=0, choices=[0, 1, 3],
                     help="right-hand sides per tangent task (0: library choice, 3: blocked)")
     ap.add_argument("--damping", choices=["viscous", "kinetic"], default="viscous")
     ap.add_argument("--solves", type=int, default=1, help="timed solves (after one untimed warm-up solve)")
+    ap.add_argument("--work-order", choices=["auto", "host", "cost"], default="auto",
+                    help="order of the RVEs in a launch (the warm-up solve is always in host order)")
     args = ap.parse_args(argv)
 
     import torch
@@ -72,13 +74,17 @@ def main(argv=None) -> int:
     b = rb.Batch(batch, precision=rb.FP64 if fp64 else rb.MIXED, law=law, mass=rb.MASS_SCALED, alpha=args.alpha,
                  c=args.c, tol_abs=0.0, tol_rel=args.tol_rel, n_max=args.n_max, check_every=args.check_every,
                  threads_per_rve=args.threads_per_rve,
-                 engine={"auto": rb.ENGINE_AUTO, "streamed": rb.ENGINE_STREAMED, "team": rb.ENGINE_TEAM}[args.engine],
+                 engine={"auto": rb.ENGINE_AUTO, "streamed": rb.ENGINE_STREAMED, "team": rb.ENGINE_TEAM,
+                         "incidence": rb.ENGINE_INCIDENCE}[args.engine],
                  damping=rb.DAMP_KINETIC if args.damping == "kinetic" else rb.DAMP_VISCOUS,
-                 tangent_rhs=args.tangent_rhs)
+                 tangent_rhs=args.tangent_rhs,
+                 work_order={"auto": rb.ORDER_AUTO, "host": rb.ORDER_HOST, "cost": rb.ORDER_COST}[args.work_order])
     b.profile(True)
     Fd = torch.tensor(F, device=dev)
     b.solve(Fd)
     torch.cuda.synchronize()
+    warm_relax_ms, _ = b.kernel_ms()
+    warm_group_ms = [float(x) for x in b.groups()[2]]
     t1 = time.perf_counter()
     for _ in range(max(1, args.solves)):
         sig, st, stats = b.solve(Fd, stats=True)
@@ -105,14 +111,16 @@ def main(argv=None) -> int:
             continue
         alg = float((it[sel] * (bpf * nfib[sel] + bpn * nfree[sel])).sum())
         kern = ("resident(%s)" % rb_variant(int(g_var[g]))) if g_var[g] >= 0 else (
-            "streamed" if g_var[g] == -1 else "team(%d)" % (-1 - int(g_var[g])))
+            "streamed" if g_var[g] == rb.GROUP_STREAMED else "incidence" if g_var[g] == rb.GROUP_INCIDENCE
+            else "team(%d)" % (-1 - int(g_var[g])))
         groups.append({"kernel": kern,
                        "rves": int(sel.sum()), "ms": float(g_ms[g]), "algorithmic_bytes": alg,
                        "algorithmic_GB_per_s": alg / (float(g_ms[g]) / 1e3) / 1e9 if g_ms[g] > 0 else None})
     b.close()
     print(json.dumps({"config": args.config, "precision": args.precision, "n_rve": int(batch.n_rve),
                       "fibers": int(nfib.sum()), "free_nodes": int(nfree.sum()), "generate_s": t_gen,
-                      "solve_ms": ms, "relax_ms": relax_ms, "stress_ms": stress_ms,
+                      "work_order": args.work_order, "solve_ms": ms, "relax_ms": relax_ms, "stress_ms": stress_ms,
+                      "warmup_relax_ms": warm_relax_ms, "warmup_group_ms": warm_group_ms,
                       "status_counts": np.bincount(st, minlength=4).tolist(),
                       "iters_median": float(np.median(it)), "iters_total": int(it.sum()), "groups": groups,
                       "tangent": tangent}),

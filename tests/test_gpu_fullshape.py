@@ -16,9 +16,12 @@ FP64 CPU oracle.  The GPU runs the same networks, F and options:
   equilibrium.
 
 Sizes: 64 RVEs of the 4096-RVE workload (200-400 seeds), 4 of the 512
-large RVEs (2000 seeds, streamed kernel), 16 of the 8192-RVE FE^2 workload
-spanning 100-3000 seeds (resident and streamed kernels); the large ones
-also on the team engine (engine 3, k workgroups per RVE).
+large RVEs (2000 seeds: the incidence kernel in mixed precision, the
+streamed kernel in FP64), 16 of the 8192-RVE FE^2 workload spanning
+100-3000 seeds (resident, incidence and streamed kernels); the large ones
+also on the team engine (engine 3, k workgroups per RVE), and the 4096-RVE
+and FE^2 samples with every RVE the incidence kernel holds on it (engine 4,
+mixed precision).
 """
 import json
 import os
@@ -42,9 +45,12 @@ def _load(name):
     return g, json.loads(str(g["opts"]))
 
 
-@pytest.mark.parametrize("name,engine", [("cfg2_64", 0), ("cfg3_4", 0), ("cfg5_16", 0), ("cfg3_4", 3), ("cfg5_16", 3)])
+@pytest.mark.parametrize("name,engine", [("cfg2_64", 0), ("cfg3_4", 0), ("cfg5_16", 0), ("cfg3_4", 3), ("cfg5_16", 3),
+                                         ("cfg2_64", 4), ("cfg5_16", 4)])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_fullshape_parity(name, engine, precision):
+    if engine == 4 and precision == 0:
+        pytest.skip("the incidence engine is mixed precision only")
     rb = require_gpu()
     g, o = _load(name)
     idx = g["idx"]

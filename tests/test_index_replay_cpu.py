@@ -70,6 +70,14 @@ def test_planted_lds_mistake_is_reported(cfg2):
     assert "outside the LDS array" in str(e.value)
 
 
+def test_planted_incidence_record_mistake_is_reported(cfg2):
+    """With one incidence record naming the wrong other end, the replay of
+    the incidence engine's tables must report it."""
+    with pytest.raises(rb.RVEError) as e:
+        rb.check_indexing(cfg2, rb.MIXED, plant=2)
+    assert "wrong other end" in str(e.value)
+
+
 @pytest.mark.parametrize("precision", [rb.FP64, rb.MIXED])
 def test_large_rve_team_partitions_index_in_bounds(precision):
     """2000-seed RVEs (the large-RVE workload) take the team engine: the
