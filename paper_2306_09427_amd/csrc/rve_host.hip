@@ -2265,8 +2265,7 @@ int rve_batch_describe(const rve_batch* b, char* buf, size_t n)
                  std::to_string(kResident[v].sn) + ")";
         else if (v == kIncGroup) {
             const int iv = std::max(inc_variant(b), 0);
-            d += "incidence(" + std::to_string(kInc[iv].threads) + "," + std::to_string(kInc[iv].slots) + "," +
-                 std::to_string(kInc[iv].batch) + ")";
+            d += "incidence(" + std::to_string(kInc[iv].threads) + "," + std::to_string(kInc[iv].slots) + ")";
         } else if (team_group(v))
             d += "team(" + std::to_string(-1 - v) + "x" + std::to_string(kTeamUnit[b->opts.precision == RVE_FP64].threads) + ")";
         else

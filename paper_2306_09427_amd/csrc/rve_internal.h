@@ -253,12 +253,12 @@ struct IncArgs {
     float4* rec;                  // [NREC] (Dn, Qn) under the solve's F, written at the start of the solve
     const uint2* brec_st;         // [NBINC] the same for each boundary incidence (DevNet::binc order)
     float4* brec;                 // [NBINC]
-    float* imass;                 // [NFREE] inverse mass of rank p (builds that keep it out of registers)
+    float* imass;                 // [NFREE] inverse mass of rank p
 };
 struct IncVariant {
-    int threads, slots, batch;   // batch: records of rounds loaded together
+    int threads, slots;
 };
-constexpr int kNumInc = 2;
+constexpr int kNumInc = 1;
 extern const IncVariant kInc[kNumInc];
 inline size_t incidence_lds_bytes(int64_t nf) { return 12 * (size_t)(nf + 1); }
 hipError_t launch_incidence(int variant, const SolveArgs& a, const IncArgs& inc, size_t lds_bytes, int grid,

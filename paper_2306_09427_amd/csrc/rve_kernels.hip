@@ -1335,7 +1335,7 @@ __global__ __launch_bounds__(T) void dr_streamed_kernel(SolveArgs A)
 // node state never leaves the CU, and no fiber force goes through memory:
 // each fiber is evaluated at both of its ends (twice the fiber arithmetic of
 // the other engines, which this memory-bound regime has to spare).
-const IncVariant kInc[kNumInc] = {{768, 16, 2}, {512, 24, 4}};
+const IncVariant kInc[kNumInc] = {{768, 16}};
 
 // Record of one incidence under F: the scaled form (Dn, Qn) of the fiber
 // oriented so that the node is its end j (rve_internal.h), formed in FP64.
@@ -1352,12 +1352,12 @@ __device__ __forceinline__ float4 inc_record(const double* F, const DevNet& net,
                        (float)((((Dx * Dx + Dy * Dy + Dz * Dz) - L0 * L0) * il) * il));
 }
 
-// One RVE on one workgroup of T threads with S node slots per thread.  IMG:
-// the inverse masses live in a global array (rank order, 4 bytes per node
-// and iteration) instead of registers (the builds take it: with it in
-// registers they exceed their budget).  The first QU rounds are unrolled,
-// their records loaded QR at a time.
-template <int T, int S, int QR, bool IMG, bool KIN>
+// One RVE on one workgroup of T threads with S node slots per thread: the
+// velocity and acceleration of every node slot stay in registers, the
+// inverse masses are read from a global float array (rank order; in
+// registers they would exceed the build's budget).  The first QU rounds of
+// a slot are unrolled and their records loaded QR rounds at a time.
+template <int T, int S, int QR, bool KIN>
 __device__ __forceinline__ void incidence_solve(const SolveArgs& A, const IncArgs& I, int r, char* smem,
                                                 RedSlots& red)
 {
@@ -1420,27 +1420,14 @@ __device__ __forceinline__ void incidence_solve(const SolveArgs& A, const IncArg
     for (int64_t e = be0 + tid; e < be1; e += T) I.brec[e] = inc_record(F, net, f0, net.binc[e]);
 
     // ---- node state: velocity and acceleration in registers, positions in LDS
-    float vx[S], vy[S], vz[S], ax[S], ay[S], az[S], imr[IMG ? 1 : S];
-    auto im_get = [&](int s, int p) __attribute__((always_inline)) -> float {
-        if constexpr (IMG)
-            return imb[p];
-        else
-            return imr[s];
-    };
-    auto im_set = [&](int s, int p, float v) __attribute__((always_inline)) {
-        if constexpr (IMG)
-            imb[p] = v;
-        else
-            imr[s] = v;
-    };
+    float vx[S], vy[S], vz[S], ax[S], ay[S], az[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const int p = s * T + tid;
         vx[s] = vy[s] = vz[s] = ax[s] = ay[s] = az[s] = 0.f;
-        if constexpr (!IMG) imr[s] = 0.f;
         if (p < nf) {
             const int a = permb[p];
-            im_set(s, p, (float)(1.0 / (net.mass[a0 + a] * A.rhoA)));
+            imb[p] = (float)(1.0 / (net.mass[a0 + a] * A.rhoA));
             float hx = 0.f, hy = 0.f, hz = 0.f;
             if (A.init == kInitWarm) {
                 const double* h = hsb + 3 * a;
@@ -1453,47 +1440,58 @@ __device__ __forceinline__ void incidence_solve(const SolveArgs& A, const IncArg
     if (tid == 0) lhx[nf] = lhy[nf] = lhz[nf] = 0.f;
     __syncthreads();
 
-    // internal force and Gershgorin sum at the node of slot s: the records of
-    // the first QR rounds are loaded together, further rounds (nodes of
-    // higher degree, the first ranks) one at a time; a lane past the round's
-    // nodes evaluates the zero slot and discards the result
-    auto node_force = [&](int t, int s, float& fx, float& fy, float& fz, float& G) __attribute__((always_inline)) {
+    // records of the first QU rounds of slot s (a lane past a round's nodes
+    // keeps a null record that reads the zero slot; its result is discarded)
+    struct Recs {
+        float4 rc[QU];
+        uint2 st[QU];
+    };
+    auto load_recs = [&](int t, int s, Recs& R, int qlo, int qhi) __attribute__((always_inline)) {
         const int p = s * T + t;
-        fx = fy = fz = G = 0.f;
-        float hxa = 0.f, hya = 0.f, hza = 0.f;
+#pragma unroll
+        for (int q = 0; q < QU; ++q) {
+            if (q < qlo || q >= qhi) continue;
+            const int Pq = Rq[q + 1] - Rq[q];
+            R.rc[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+            R.st[q] = make_uint2(0u, (uint32_t)nf);
+            if (s * T < Pq && p < Pq) {
+                R.rc[q] = recb[Rq[q] + p];
+                R.st[q] = stb[Rq[q] + p];
+            }
+        }
+    };
+    // internal force and Gershgorin sum at the node of slot s: rounds
+    // [qlo, qhi) from its loaded records; node_tail adds the rounds beyond
+    // QU (nodes of higher degree, the first ranks), read one at a time
+    auto own_h = [&](int p, float& x, float& y, float& z) __attribute__((always_inline)) {
+        x = y = z = 0.f;
         if (p < nf) {
-            hxa = lhx[p]; hya = lhy[p]; hza = lhz[p];
+            x = lhx[p]; y = lhy[p]; z = lhz[p];
         }
+    };
+    auto node_rounds = [&](int t, int s, const Recs& R, int qlo, int qhi, float hxa, float hya, float hza, float& fx,
+                           float& fy, float& fz, float& G) __attribute__((always_inline)) {
+        const int p = s * T + t;
 #pragma unroll
-        for (int q0 = 0; q0 < QU; q0 += QR) {
-            float4 rc[QR];
-            uint2 st[QR];
-#pragma unroll
-            for (int u = 0; u < QR; ++u) {
-                const int q = q0 + u, Pq = Rq[q + 1] - Rq[q];
-                rc[u] = make_float4(0.f, 0.f, 0.f, 0.f);
-                st[u] = make_uint2(0u, (uint32_t)nf);
-                if (s * T < Pq && p < Pq) {
-                    rc[u] = recb[Rq[q] + p];
-                    st[u] = stb[Rq[q] + p];
+        for (int q = 0; q < QU; ++q) {
+            if (q < qlo || q >= qhi) continue;
+            const int Pq = Rq[q + 1] - Rq[q];
+            if (s * T < Pq) {
+                const int o = (int)R.st[q].y;
+                const FiberOut<float> f = fiber_eval_scaled<float>(linear, EA, Bc, EAoB, R.rc[q].x, R.rc[q].y,
+                                                                   R.rc[q].z, R.rc[q].w, __uint_as_float(R.st[q].x),
+                                                                   hxa - lhx[o], hya - lhy[o], hza - lhz[o]);
+                if (p < Pq) {
+                    fx += f.fx; fy += f.fy; fz += f.fz; G += f.b;
                 }
             }
-#pragma unroll
-            for (int u = 0; u < QR; ++u) {
-                const int q = q0 + u, Pq = Rq[q + 1] - Rq[q];
-                if (s * T < Pq) {
-                    const int o = (int)st[u].y;
-                    const FiberOut<float> f = fiber_eval_scaled<float>(linear, EA, Bc, EAoB, rc[u].x, rc[u].y,
-                                                                       rc[u].z, rc[u].w, __uint_as_float(st[u].x),
-                                                                       hxa - lhx[o], hya - lhy[o], hza - lhz[o]);
-                    if (p < Pq) {
-                        fx += f.fx; fy += f.fy; fz += f.fz; G += f.b;
-                    }
-                }
-                // one fiber evaluation at a time (their temporaries do not overlap)
-                __builtin_amdgcn_sched_barrier(0);
-            }
+            // one fiber evaluation at a time (their temporaries do not overlap)
+            __builtin_amdgcn_sched_barrier(0);
         }
+    };
+    auto node_tail = [&](int t, int s, float hxa, float hya, float hza, float& fx, float& fy, float& fz, float& G)
+                         __attribute__((always_inline)) {
+        const int p = s * T + t;
 #pragma unroll 1
         for (int q = QU; q < kIncMaxDeg; ++q) {
             const int R0 = uniform32(rq[q]), Pq = uniform32(rq[q + 1]) - R0;
@@ -1531,30 +1529,44 @@ __device__ __forceinline__ void incidence_solve(const SolveArgs& A, const IncArg
         }
         return acc;
     };
+    // the force pass over every slot: slot_body(s, p, fx, fy, fz, G) runs on
+    // the lanes that hold a node
+    auto force_pass = [&](int t, auto&& slot_body) __attribute__((always_inline)) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            if (s * T < nf) {
+                const int p = s * T + t;
+                float hxa, hya, hza;
+                float fx = 0.f, fy = 0.f, fz = 0.f, G = 0.f;
+                own_h(p, hxa, hya, hza);
+#pragma unroll
+                for (int q0 = 0; q0 < QU; q0 += QR) {
+                    Recs R;
+                    load_recs(t, s, R, q0, q0 + QR);
+                    node_rounds(t, s, R, q0, q0 + QR, hxa, hya, hza, fx, fy, fz, G);
+                }
+                node_tail(t, s, hxa, hya, hza, fx, fy, fz, G);
+                if (p < nf) slot_body(s, p, fx, fy, fz, G);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
 
     // ---- initial force, residual and (optionally) stiffness-scaled mass
     float gpart = 0.f;
     double r2p = 0.0, b2p = 0.0;
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        if (s * T < nf) {
-            const int p = s * T + tid;
-            float fx, fy, fz, G;
-            node_force(tid, s, fx, fy, fz, G);
-            if (p < nf) {
-                float im = im_get(s, p);
-                if (A.mass_mode == kMassScaled) {
-                    im = G > 0.f ? 4.f / G : 1.f;
-                    im_set(s, p, im);
-                }
-                ax[s] = -fx * im;
-                ay[s] = -fy * im;
-                az[s] = -fz * im;
-                gpart = fmax(gpart, G * im);
-                r2p += (double)fx * fx + (double)fy * fy + (double)fz * fz;
-            }
+    force_pass(tid, [&](int s, int p, float fx, float fy, float fz, float G) __attribute__((always_inline)) {
+        float im = imb[p];
+        if (A.mass_mode == kMassScaled) {
+            im = G > 0.f ? 4.f / G : 1.f;
+            imb[p] = im;
         }
-    }
+        ax[s] = -fx * im;
+        ay[s] = -fy * im;
+        az[s] = -fz * im;
+        gpart = fmax(gpart, G * im);
+        r2p += (double)fx * fx + (double)fy * fy + (double)fz * fz;
+    });
     b2p = bnorm2(tid);
     double gmax;
     double R2 = 0.0, D2 = 0.0, B2 = 0.0;
@@ -1609,36 +1621,30 @@ __device__ __forceinline__ void incidence_solve(const SolveArgs& A, const IncArg
         gpart = 0.f;
         r2p = 0.0;
         double d2p = 0.0, kep = 0.0;
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            if (s * T < nf) {
-                const int p = s * T + tb;
-                float fx, fy, fz, G;
-                node_force(tb, s, fx, fy, fz, G);
-                if (p < nf) {
-                    const float im = im_get(s, p);
-                    ax[s] = -fx * im - c * vx[s];
-                    ay[s] = -fy * im - c * vy[s];
-                    az[s] = -fz * im - c * vz[s];
-                    vx[s] += hdt * ax[s]; vy[s] += hdt * ay[s]; vz[s] += hdt * az[s];
-                    gpart = fmax(gpart, G * im);
-                    if constexpr (KIN)
-                        kep += 0.5 * (double)((vx[s] * vx[s] + vy[s] * vy[s] + vz[s] * vz[s]) * dev_rcp(im));
-                    if (check) {
-                        r2p += (double)fx * fx + (double)fy * fy + (double)fz * fz;
-                        const float cm = cg * dev_rcp(im);
-                        const double px = (double)(cm * vx[s]), py = (double)(cm * vy[s]), pz = (double)(cm * vz[s]);
-                        d2p += px * px + py * py + pz * pz;
-                    }
-                }
+        force_pass(tb, [&](int s, int p, float fx, float fy, float fz, float G) __attribute__((always_inline)) {
+            const float im = imb[p];
+            // damped acceleration with the half-step velocity, then second half step
+            ax[s] = -fx * im - c * vx[s];
+            ay[s] = -fy * im - c * vy[s];
+            az[s] = -fz * im - c * vz[s];
+            vx[s] += hdt * ax[s]; vy[s] += hdt * ay[s]; vz[s] += hdt * az[s];
+            gpart = fmax(gpart, G * im);
+            if constexpr (KIN)
+                kep += 0.5 * (double)((vx[s] * vx[s] + vy[s] * vy[s] + vz[s] * vz[s]) * dev_rcp(im));
+            if (check) {
+                r2p += (double)fx * fx + (double)fy * fy + (double)fz * fz;
+                const float cm = cg * dev_rcp(im);
+                const double px = (double)(cm * vx[s]), py = (double)(cm * vy[s]), pz = (double)(cm * vz[s]);
+                d2p += px * px + py * py + pz * pz;
             }
-            __builtin_amdgcn_sched_barrier(0);
-        }
+        });
         if (check) b2p = bnorm2(tb);
         parity ^= 1;
         double r2n = R2, d2n = D2, b2n = B2, ke = 0.0;
         block_reduce<float, NW, KIN>(red, tb, parity, gpart, r2p, d2p, b2p, check, gmax, r2n, d2n, b2n, kep, &ke);
         if constexpr (KIN) {
+            // a kinetic-energy peak was passed: restart every node from rest
+            // (the acceleration is already -f/M)
             if (ke < ke_prev) {
 #pragma unroll
                 for (int s = 0; s < S; ++s) vx[s] = vy[s] = vz[s] = 0.f;
@@ -1707,7 +1713,7 @@ __global__ __launch_bounds__(T) void dr_incidence_kernel(SolveArgs A, IncArgs I)
         const int t = __builtin_amdgcn_readfirstlane(task);
         __syncthreads();
         if (t >= A.n_list) break;
-        incidence_solve<T, S, QR, true, KIN>(A, I, __builtin_amdgcn_readfirstlane(A.list[t]), smem_i, red);
+        incidence_solve<T, S, QR, KIN>(A, I, __builtin_amdgcn_readfirstlane(A.list[t]), smem_i, red);
     }
 }
 
@@ -2005,7 +2011,6 @@ static hipError_t spill_inc_t(size_t* bytes)
 #define RVE_INC_DISPATCH(FN, ...)                                                                      \
     switch (variant) {                                                                                \
     case 0: return kin ? FN<768, 16, 2, true>(__VA_ARGS__) : FN<768, 16, 2, false>(__VA_ARGS__);       \
-    case 1: return kin ? FN<512, 24, 4, true>(__VA_ARGS__) : FN<512, 24, 4, false>(__VA_ARGS__);       \
     default: return hipErrorInvalidValue;                                                             \
     }
 
