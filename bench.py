@@ -54,7 +54,7 @@ def rb_variant_name(v):
 # Committed rocprofv3 summaries: key -> (summary file, kernel source)
 TRAFFIC_PROFILES = {
     "relax_cfg2": ("dr_resident_kernel_4096rve_200-400seeds_mixed.md", "rve_kernels.hip"),
-    "relax_cfg3": ("dr_streamed_kernel_512rve_2000seeds_mixed.md", "rve_kernels.hip"),
+    "relax_cfg3": ("dr_incidence_kernel_512rve_2000seeds_mixed.md", "rve_kernels.hip"),
     "tangent": ("tangent_4096rve_200-400seeds_mixed.md", "rve_tangent.hip"),
 }
 
