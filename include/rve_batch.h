@@ -95,7 +95,11 @@ extern "C" {
                                   record per node-fiber incidence read from
                                   global memory each iteration; at most 12288
                                   free nodes of degree <= 16), the rest as
-                                  AUTO */
+                                  AUTO.  Its tables (about 56 bytes per
+                                  fiber) are built at rve_batch_create: for
+                                  every RVE that fits when the batch is
+                                  created with this engine, else only for
+                                  the RVEs no resident build holds */
 #define RVE_DAMP_VISCOUS 0     /* constant mass-proportional damping c M v */
 #define RVE_DAMP_KINETIC 1     /* kinetic damping: v = 0 at kinetic-energy peaks */
 #define RVE_DAMP_ADAPTIVE 2    /* c re-estimated each step (Rayleigh quotient) */
@@ -291,8 +295,11 @@ int rve_batch_groups(rve_batch* b, int32_t* group_of_rve, int32_t* variant, doub
  * kernel) on a sample of that tier's largest RVEs for n_iter relaxation
  * iterations under F (host or device pointer per ptr_kind), time it with HIP
  * events, and keep the fastest per fiber evaluation for the batch's current
- * precision.  Later solves use the choice.  The trial runs overwrite the
- * state of the last solve.
+ * precision; for the RVEs beyond every resident build that the incidence
+ * kernel does not take, the team engine of each team size against the
+ * streamed kernel.  Later solves use the choice (team launches run alone,
+ * before the other groups).  The trial runs overwrite the state of the
+ * last solve.
  */
 int rve_batch_autotune(rve_batch* b, const double* F, int32_t ptr_kind, int32_t n_iter);
 

@@ -793,21 +793,27 @@ static void inc_build(const HostPack& P, int64_t r, IncHost& H)
         H.brec_st[e] = make_uint2(inv_len(P.binc[e]), other_rank(P.binc[e]));
 }
 
-static void inc_build_all(const HostPack& P, int64_t R, IncHost& H)
+// want(r): whether RVE r gets tables (every RVE that fits when null).
+template <typename Want>
+static void inc_build_all(const HostPack& P, int64_t R, IncHost& H, Want want)
 {
     H.rec_first.assign(R, -1);
     H.round_first.assign((size_t)R * (kIncMaxDeg + 1), 0);
     H.perm.assign(P.free_off[R], 0);
     H.brec_st.assign(P.binc.size(), make_uint2(0u, 0u));
     for (int64_t r = 0; r < R; ++r)
-        if (inc_fits(P, r)) inc_build(P, r, H);
+        if (inc_fits(P, r) && want(r)) inc_build(P, r, H);
 }
 
+// Tables for the RVEs AUTO sends to the incidence kernel (those no FP32
+// resident build holds), or for every RVE that fits when the batch is
+// created with RVE_ENGINE_INCIDENCE: about 56 B per fiber of device memory.
 static int build_inc_tables(rve_batch* b, const HostPack& P)
 {
     IncHost H;
+    const bool all = b->opts.engine == RVE_ENGINE_INCIDENCE;
     try {
-        inc_build_all(P, b->R, H);
+        inc_build_all(P, b->R, H, [&](int64_t r) { return all || tier_of(b, r, false) < 0; });
     } catch (const std::bad_alloc&) {
         return fail(RVE_ENOMEM, "host allocation failed while building the incidence tables");
     }
@@ -929,7 +935,7 @@ static int check_indexing(const rve_net_desc* net, bool fp64, int plant)
     };
     IncHost H;
     try {
-        inc_build_all(P, R, H);
+        inc_build_all(P, R, H, [](int64_t) { return true; });
     } catch (const std::bad_alloc&) {
         return fail(RVE_ENOMEM, "host allocation failed while building the incidence tables");
     }
@@ -1214,9 +1220,11 @@ static void assign_groups(rve_batch* b)
                 if (tv >= 0 && spills(b, tv, fp64)) tv = -2;   // tuned for the other damping build
                 chosen = (tv != -2 && !b->opts.threads_per_rve) ? tv : default_variant(b, t, fp64);
             }
+            // the autotuner's team choice was measured against the streamed
+            // kernel: it applies to the RVEs the incidence kernel does not take
             const int k = b->team_k.empty() ? 0 : b->team_k[r];
             const bool team = k > 0 && !b->opts.threads_per_rve &&
-                              (eng == RVE_ENGINE_TEAM || b->tuned_team[fp64 ? 1 : 0][k] == 1);
+                              (eng == RVE_ENGINE_TEAM || (b->tuned_team[fp64 ? 1 : 0][k] == 1 && !inc));
             if (chosen >= 0)
                 slot = chosen;
             else if (team)
@@ -2149,15 +2157,18 @@ int rve_batch_autotune(rve_batch* b, const double* F, int32_t ptr_kind, int32_t 
         }
         b->tuned[fp64 ? 1 : 0][t] = best_v;
     }
-    // RVEs no resident build holds: the team engine (per team size k) against
-    // the streamed kernel on the same RVEs, both from the affine start for
-    // n_iter iterations; the team counts only if it takes every RVE the
-    // streamed run took through all iterations through the same count to a
-    // final state within 5% of the streamed one
+    // RVEs no resident build holds and the incidence kernel does not take:
+    // the team engine (per team size k) against the streamed kernel on the
+    // same RVEs, both from the affine start for n_iter iterations; the team
+    // counts only if it takes every RVE the streamed run took through all
+    // iterations through the same count to a final state within 5% of the
+    // streamed one
+    const bool inc_on = inc_variant(b) >= 0;
     for (int k = 2; k <= kTeamMax; ++k) {
         std::vector<int32_t> members;
         for (int64_t r = 0; r < b->R; ++r)
-            if (tier_of(b, r, fp64) < 0 && b->team_k[r] == k) members.push_back((int32_t)r);
+            if (tier_of(b, r, fp64) < 0 && b->team_k[r] == k && !(inc_on && b->inc_first[r] >= 0))
+                members.push_back((int32_t)r);
         if (members.empty()) continue;
         std::stable_sort(members.begin(), members.end(),
                          [&](int32_t x, int32_t y) { return b->nfib_of[x] > b->nfib_of[y]; });

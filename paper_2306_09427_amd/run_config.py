@@ -41,6 +41,8 @@ def main(argv=None) -> int:
                     help="right-hand sides per tangent task (0: library choice, 3: blocked)")
     ap.add_argument("--damping", choices=["viscous", "kinetic"], default="viscous")
     ap.add_argument("--solves", type=int, default=1, help="timed solves (after one untimed warm-up solve)")
+    ap.add_argument("--autotune", type=int, default=0, metavar="N_ITER",
+                    help="run rve_batch_autotune with this many iterations under F before the solves (0: no)")
     ap.add_argument("--work-order", choices=["auto", "host", "cost"], default="auto",
                     help="order of the RVEs in a launch (the warm-up solve is always in host order)")
     args = ap.parse_args(argv)
@@ -81,6 +83,12 @@ def main(argv=None) -> int:
                  work_order={"auto": rb.ORDER_AUTO, "host": rb.ORDER_HOST, "cost": rb.ORDER_COST}[args.work_order])
     b.profile(True)
     Fd = torch.tensor(F, device=dev)
+    tune_s = None
+    if args.autotune > 0:
+        t_tune = time.perf_counter()
+        b.autotune(Fd, n_iter=args.autotune)
+        torch.cuda.synchronize()
+        tune_s = time.perf_counter() - t_tune
     b.solve(Fd)
     torch.cuda.synchronize()
     warm_relax_ms, _ = b.kernel_ms()
@@ -92,6 +100,7 @@ def main(argv=None) -> int:
     ms = 1e3 * (time.perf_counter() - t1) / max(1, args.solves)
     relax_ms, stress_ms = b.kernel_ms()
     g_of, g_var, g_ms = b.groups()
+    b_desc = b.describe()
     tangent = None
     if args.tangent:
         C, ct = b.tangent(like=Fd)   # builds the tangent's records
@@ -119,7 +128,7 @@ def main(argv=None) -> int:
     b.close()
     print(json.dumps({"config": args.config, "precision": args.precision, "n_rve": int(batch.n_rve),
                       "fibers": int(nfib.sum()), "free_nodes": int(nfree.sum()), "generate_s": t_gen,
-                      "work_order": args.work_order, "solve_ms": ms, "relax_ms": relax_ms, "stress_ms": stress_ms,
+                      "work_order": args.work_order, "autotune_s": tune_s, "describe": b_desc, "solve_ms": ms, "relax_ms": relax_ms, "stress_ms": stress_ms,
                       "warmup_relax_ms": warm_relax_ms, "warmup_group_ms": warm_group_ms,
                       "status_counts": np.bincount(st, minlength=4).tolist(),
                       "iters_median": float(np.median(it)), "iters_total": int(it.sum()), "groups": groups,

@@ -95,17 +95,22 @@ def test_team_gives_up_cleanly_at_a_one_poll_limit(rb, large):
     b.close()
 
 
-def test_autotune_chooses_team_or_streamed_by_measurement(rb, large):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_autotune_chooses_team_or_streamed_by_measurement(rb, large, precision):
     """The autotuner times the team engine against the streamed kernel on
-    the RVEs no resident build holds and keeps the faster (validated: same
-    iterations and final states within 5% of the streamed run)."""
+    the RVEs no resident build holds and the incidence kernel does not take
+    (FP64 here), and keeps the faster (validated: same iterations and final
+    states within 5% of the streamed run); in mixed precision the incidence
+    kernel takes these RVEs and the choice leaves them there."""
     batch, F = large
-    b = rb.Batch(batch, precision=1, tol_rel=1e-5, n_max=30000, **KW)
+    b = rb.Batch(batch, precision=precision, tol_rel=1e-5 if precision else 1e-8, n_max=30000, **KW)
     before = b.describe()
     b.autotune(F, 200)
     after = b.describe()
     log(f"  before autotune: {before}; after: {after}")
     assert "team(" not in before
+    if precision == 1:
+        assert after == before and after.startswith("incidence(")
     sig, st = b.solve(F)
     assert np.all(np.isin(st, (0, 1)))
     b.close()
