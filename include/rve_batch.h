@@ -296,10 +296,11 @@ int rve_batch_groups(rve_batch* b, int32_t* group_of_rve, int32_t* variant, doub
  * iterations under F (host or device pointer per ptr_kind), time it with HIP
  * events, and keep the fastest per fiber evaluation for the batch's current
  * precision; for the RVEs beyond every resident build that the incidence
- * kernel does not take, the team engine of each team size against the
- * streamed kernel.  Later solves use the choice (team launches run alone,
- * before the other groups).  The trial runs overwrite the state of the
- * last solve.
+ * kernel does not take, the team engine of each team size k against the
+ * streamed kernel, kept only where it takes less CU-time (k times its time
+ * below the streamed kernel's: a team holds k CUs per RVE, and team
+ * launches run alone, before the other groups).  Later solves use the
+ * choice.  The trial runs overwrite the state of the last solve.
  */
 int rve_batch_autotune(rve_batch* b, const double* F, int32_t ptr_kind, int32_t n_iter);
 

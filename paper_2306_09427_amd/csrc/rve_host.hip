@@ -2159,10 +2159,10 @@ int rve_batch_autotune(rve_batch* b, const double* F, int32_t ptr_kind, int32_t 
     }
     // RVEs no resident build holds and the incidence kernel does not take:
     // the team engine (per team size k) against the streamed kernel on the
-    // same RVEs, both from the affine start for n_iter iterations; the team
-    // counts only if it takes every RVE the streamed run took through all
-    // iterations through the same count to a final state within 5% of the
-    // streamed one
+    // same RVEs, both from the affine start for n_iter iterations, compared
+    // per CU-time; the team counts only if it takes every RVE the streamed
+    // run took through all iterations through the same count to a final
+    // state within 5% of the streamed one
     const bool inc_on = inc_variant(b) >= 0;
     for (int k = 2; k <= kTeamMax; ++k) {
         std::vector<int32_t> members;
@@ -2237,7 +2237,10 @@ int rve_batch_autotune(rve_batch* b, const double* F, int32_t ptr_kind, int32_t 
         b->group_first = saved_first;
         b->group_lds = saved_lds;
         if (rc) return rc;
-        b->tuned_team[fp64 ? 1 : 0][k] = (team_valid && ms_c[1] < ms_c[0]) ? 1 : 0;
+        // per CU-time: a team holds k CUs per RVE where the streamed kernel
+        // holds one (and team launches run alone), so the team must relax
+        // its RVEs k times faster to give the batch more throughput
+        b->tuned_team[fp64 ? 1 : 0][k] = (team_valid && (double)k * ms_c[1] < ms_c[0]) ? 1 : 0;
     }
     b->have_state = false;
     b->cost_order = false;   // the iterations of the timing runs are no cost estimate

@@ -99,9 +99,10 @@ def test_team_gives_up_cleanly_at_a_one_poll_limit(rb, large):
 def test_autotune_chooses_team_or_streamed_by_measurement(rb, large, precision):
     """The autotuner times the team engine against the streamed kernel on
     the RVEs no resident build holds and the incidence kernel does not take
-    (FP64 here), and keeps the faster (validated: same iterations and final
-    states within 5% of the streamed run); in mixed precision the incidence
-    kernel takes these RVEs and the choice leaves them there."""
+    (all eight in FP64, the six largest in mixed precision), and keeps the
+    team where it takes less CU-time (validated: same iterations and final
+    states within 5% of the streamed run); the RVEs the incidence kernel
+    takes stay on it."""
     batch, F = large
     b = rb.Batch(batch, precision=precision, tol_rel=1e-5 if precision else 1e-8, n_max=30000, **KW)
     before = b.describe()
@@ -110,7 +111,10 @@ def test_autotune_chooses_team_or_streamed_by_measurement(rb, large, precision):
     log(f"  before autotune: {before}; after: {after}")
     assert "team(" not in before
     if precision == 1:
-        assert after == before and after.startswith("incidence(")
+        # the two 2000-seed RVEs stay on the incidence kernel; the six
+        # largest (beyond its limits) may move from the streamed kernel to a team
+        inc = [g for g in before.split(";") if g.startswith("incidence(")]
+        assert inc == [g for g in after.split(";") if g.startswith("incidence(")] and inc[0].endswith(":2")
     sig, st = b.solve(F)
     assert np.all(np.isin(st, (0, 1)))
     b.close()
