@@ -5,8 +5,8 @@ team engine's work area and the streamed engine's workspace) come from the
 library's fixed device scratch array instead of allocations.  Two calls in a row on batches of
 decreasing size (the second reuses the array the first left behind) must
 reproduce rve_batch_solve bitwise (same kernels, same arithmetic), on the
-streamed engine and on the automatic engine choice, and no device memory
-may be allocated by the call.
+streamed, team and incidence engines and on the automatic engine choice, and
+no device memory may be allocated by the call.
 """
 import ctypes as C
 
@@ -26,7 +26,8 @@ def test_static_solve_matches_solve_twice_shrinking():
     small, Fs = synth.make_config_batch(5, idx=[3, 8, 13, 21, 89, 144])   # includes RVEs above every resident tier
     kw = dict(law=rb.LAW_EXP, mass=1, alpha=0.5, c=0.1, tol_abs=0.0, tol_rel=1e-5, n_max=20000, check_every=8)
     for prec in (rb.MIXED, rb.FP64):
-        for engine in (rb.ENGINE_STREAMED, rb.ENGINE_AUTO, rb.ENGINE_TEAM):
+        engines = (rb.ENGINE_STREAMED, rb.ENGINE_AUTO, rb.ENGINE_TEAM) + ((rb.ENGINE_INCIDENCE,) if prec == rb.MIXED else ())
+        for engine in engines:
             for name, batch, F in (("24 config-2 RVEs", big, Fb), ("6 config-5 RVEs", small, Fs)):
                 b = rb.Batch(batch, precision=prec, engine=engine, **kw)
                 s_ref, st_ref = b.solve(F)
