@@ -412,7 +412,7 @@ __device__ __forceinline__ void block_reduce(RedSlots& red, int tid, int parity,
         gmax_o = uniform(__longlong_as_double((long long)red.g64[parity]));
     if (tid == 0) {
         red.g32[parity ^ 1] = 0u;
-        red.g64[parity ^ 1] = 0ull;
+        if constexpr (sizeof(Real) == 8) red.g64[parity ^ 1] = 0ull;   // FP32 builds use the 32-bit slots only
     }
     if (full || KE) {
         const int p = lane >> 4, w = lane & 15;
@@ -1356,7 +1356,9 @@ __device__ __forceinline__ float4 inc_record(const double* F, const DevNet& net,
 // velocity and acceleration of every node slot stay in registers, the
 // inverse masses are read from a global float array (rank order; in
 // registers they would exceed the build's budget).  The first QU rounds of
-// a slot are unrolled and their records loaded QR rounds at a time.
+// a slot are unrolled and their records loaded QR rounds at a time: all
+// four in the viscous build (one memory round trip per node slot), two in
+// the kinetic build, whose kinetic-energy sum leaves fewer registers.
 template <int T, int S, int QR, bool KIN>
 __device__ __forceinline__ void incidence_solve(const SolveArgs& A, const IncArgs& I, int r, char* smem,
                                                 RedSlots& red)
@@ -1392,7 +1394,10 @@ __device__ __forceinline__ void incidence_solve(const SolveArgs& A, const IncArg
     if (!finite || !(J > 0.0)) {
         if (tid == 0) {
             A.status[r] = ST_BAD_F;
-            A.iters[r] = 0;
+            // an opaque zero: no 64-bit zero register pair is held across RVEs for it
+            int64_t zero = 0;
+            asm volatile("" : "+s"(zero));
+            A.iters[r] = zero;
             A.Rres[r] = NAN; A.Dres[r] = NAN; A.Bres[r] = NAN;
             for (int k = 0; k < 9; ++k) A.sigma[9 * r + k] = NAN;
         }
@@ -1436,7 +1441,7 @@ __device__ __forceinline__ void incidence_solve(const SolveArgs& A, const IncArg
             lhx[p] = hx; lhy[p] = hy; lhz[p] = hz;
         }
     }
-    reset_gslots(red);
+    if (tid < 2) red.g32[tid] = 0u;   // FP32: only the 32-bit time-step slots are used
     if (tid == 0) lhx[nf] = lhy[nf] = lhz[nf] = 0.f;
     __syncthreads();
 
@@ -1462,16 +1467,13 @@ __device__ __forceinline__ void incidence_solve(const SolveArgs& A, const IncArg
     };
     // internal force and Gershgorin sum at the node of slot s: rounds
     // [qlo, qhi) from its loaded records; node_tail adds the rounds beyond
-    // QU (nodes of higher degree, the first ranks), read one at a time
-    auto own_h = [&](int p, float& x, float& y, float& z) __attribute__((always_inline)) {
-        x = y = z = 0.f;
-        if (p < nf) {
-            x = lhx[p]; y = lhy[p]; z = lhz[p];
-        }
-    };
-    auto node_rounds = [&](int t, int s, const Recs& R, int qlo, int qhi, float hxa, float hya, float hza, float& fx,
-                           float& fy, float& fz, float& G) __attribute__((always_inline)) {
-        const int p = s * T + t;
+    // QU (nodes of higher degree, the first ranks), read one at a time.  The
+    // node's own position is read from LDS in every round rather than held
+    // (three registers fewer across the rounds; lanes past nf read the zero
+    // slot)
+    auto node_rounds = [&](int t, int s, const Recs& R, int qlo, int qhi, float& fx, float& fy, float& fz, float& G)
+                           __attribute__((always_inline)) {
+        const int p = s * T + t, pp = p < nf ? p : nf;
 #pragma unroll
         for (int q = 0; q < QU; ++q) {
             if (q < qlo || q >= qhi) continue;
@@ -1480,7 +1482,7 @@ __device__ __forceinline__ void incidence_solve(const SolveArgs& A, const IncArg
                 const int o = (int)R.st[q].y;
                 const FiberOut<float> f = fiber_eval_scaled<float>(linear, EA, Bc, EAoB, R.rc[q].x, R.rc[q].y,
                                                                    R.rc[q].z, R.rc[q].w, __uint_as_float(R.st[q].x),
-                                                                   hxa - lhx[o], hya - lhy[o], hza - lhz[o]);
+                                                                   lhx[pp] - lhx[o], lhy[pp] - lhy[o], lhz[pp] - lhz[o]);
                 if (p < Pq) {
                     fx += f.fx; fy += f.fy; fz += f.fz; G += f.b;
                 }
@@ -1489,9 +1491,8 @@ __device__ __forceinline__ void incidence_solve(const SolveArgs& A, const IncArg
             __builtin_amdgcn_sched_barrier(0);
         }
     };
-    auto node_tail = [&](int t, int s, float hxa, float hya, float hza, float& fx, float& fy, float& fz, float& G)
-                         __attribute__((always_inline)) {
-        const int p = s * T + t;
+    auto node_tail = [&](int t, int s, float& fx, float& fy, float& fz, float& G) __attribute__((always_inline)) {
+        const int p = s * T + t, pp = p < nf ? p : nf;
 #pragma unroll 1
         for (int q = QU; q < kIncMaxDeg; ++q) {
             const int R0 = uniform32(rq[q]), Pq = uniform32(rq[q + 1]) - R0;
@@ -1501,8 +1502,8 @@ __device__ __forceinline__ void incidence_solve(const SolveArgs& A, const IncArg
                 const uint2 y = stb[R0 + p];
                 const int o = (int)y.y;
                 const FiberOut<float> f = fiber_eval_scaled<float>(linear, EA, Bc, EAoB, x.x, x.y, x.z, x.w,
-                                                                   __uint_as_float(y.x), hxa - lhx[o], hya - lhy[o],
-                                                                   hza - lhz[o]);
+                                                                   __uint_as_float(y.x), lhx[pp] - lhx[o],
+                                                                   lhy[pp] - lhy[o], lhz[pp] - lhz[o]);
                 fx += f.fx; fy += f.fy; fz += f.fz; G += f.b;
             }
         }
@@ -1536,16 +1537,14 @@ __device__ __forceinline__ void incidence_solve(const SolveArgs& A, const IncArg
         for (int s = 0; s < S; ++s) {
             if (s * T < nf) {
                 const int p = s * T + t;
-                float hxa, hya, hza;
                 float fx = 0.f, fy = 0.f, fz = 0.f, G = 0.f;
-                own_h(p, hxa, hya, hza);
 #pragma unroll
                 for (int q0 = 0; q0 < QU; q0 += QR) {
                     Recs R;
                     load_recs(t, s, R, q0, q0 + QR);
-                    node_rounds(t, s, R, q0, q0 + QR, hxa, hya, hza, fx, fy, fz, G);
+                    node_rounds(t, s, R, q0, q0 + QR, fx, fy, fz, G);
                 }
-                node_tail(t, s, hxa, hya, hza, fx, fy, fz, G);
+                node_tail(t, s, fx, fy, fz, G);
                 if (p < nf) slot_body(s, p, fx, fy, fz, G);
             }
             __builtin_amdgcn_sched_barrier(0);
@@ -2010,7 +2009,7 @@ static hipError_t spill_inc_t(size_t* bytes)
 
 #define RVE_INC_DISPATCH(FN, ...)                                                                      \
     switch (variant) {                                                                                \
-    case 0: return kin ? FN<768, 16, 2, true>(__VA_ARGS__) : FN<768, 16, 2, false>(__VA_ARGS__);       \
+    case 0: return kin ? FN<768, 16, 2, true>(__VA_ARGS__) : FN<768, 16, 4, false>(__VA_ARGS__);       \
     default: return hipErrorInvalidValue;                                                             \
     }
 
