@@ -199,8 +199,9 @@ typedef struct {
  *     RVE_ORDER_COST: from the second solve of the batch on, descending
  *     cost of the previous solve (iterations x fibers, longest processing
  *     time first; ties and the first solve in host order).  RVE_ORDER_AUTO:
- *     cost order for resident launches, host order for streamed ones.  Team
- *     launches keep host order.  Results do not depend on the order.
+ *     cost order for resident and incidence launches, host order for
+ *     streamed ones.  Team launches keep host order.  Results do not depend
+ *     on the order.
  */
 typedef struct {
     int32_t precision;

@@ -1740,7 +1740,7 @@ static int launch_groups(rve_batch* b, SolveArgs& a, int32_t* queues, void* ws_f
             const int v = b->group_variant[g];
             bool by_cost = b->cost_order && !team_group(v);
             if (b->opts.work_order == RVE_ORDER_HOST) by_cost = false;
-            if (b->opts.work_order == RVE_ORDER_AUTO && v < 0) by_cost = false;
+            if (b->opts.work_order == RVE_ORDER_AUTO && v == kStreamedGroup) by_cost = false;
             o.first[g] = b->group_first[g];
             o.count[g] = by_cost ? (int32_t)b->groups[g].size() : 0;
             any = any || by_cost;

@@ -1,7 +1,7 @@
 """Work-list order by the previous solve's cost, GPU.
 
-After a first solve, a resident launch group (and a streamed one under
-work_order RVE_ORDER_COST) takes its RVEs in longest-processing-time order
+After a first solve, a resident or incidence launch group (and a streamed
+one under work_order RVE_ORDER_COST) takes its RVEs in longest-processing-time order
 of the previous solve (iterations x fibers, a bitonic sort on the device).  The order only decides which
 persistent workgroup takes which RVE when, so every result must be bitwise
 the one of a batch that solves in the host's order; a wrong permutation
