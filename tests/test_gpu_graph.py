@@ -13,13 +13,17 @@ from tests.gpu_common import log, require_gpu
 pytestmark = pytest.mark.gpu
 
 
-def test_graph_replay_matches_eager():
+@pytest.mark.parametrize("engine", [0, 4])
+def test_graph_replay_matches_eager(engine):
+    """engine 0: resident kernels; 4: the incidence kernel (its per-solve
+    records are written by the kernel itself, no memset node)."""
     rb = require_gpu()
     import torch
-    log("graph capture of solve + tangent")
+    log(f"graph capture of solve + tangent, engine {engine}")
     batch, F = synth.make_config_batch(4, idx=np.arange(6))
     b = rb.Batch(batch, precision=rb.MIXED, law=rb.LAW_EXP, mass=1, alpha=0.5, c=0.1, tol_abs=0.0, tol_rel=1e-5,
-                 n_max=20000, check_every=8, cg_tol=1e-6)
+                 n_max=20000, check_every=8, cg_tol=1e-6, engine=engine)
+    log(f"  groups {b.describe()}")
     s = torch.cuda.Stream()
     Fd = torch.tensor(F, device="cuda")
     with torch.cuda.stream(s):
