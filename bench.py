@@ -242,6 +242,7 @@ def main():
         return (f"dr_resident_kernel<float,{rb_variant_name(int(g_var[g]))}>" if g_var[g] >= 0
                 else "dr_streamed_kernel<float,1024>" if g_var[g] == rb.GROUP_STREAMED
                 else "dr_incidence_kernel" if g_var[g] == rb.GROUP_INCIDENCE
+                else "dr_incidence_global_kernel" if g_var[g] == rb.GROUP_INCIDENCE_GLOBAL
                 else f"dr_team_kernel<float> x{-1 - int(g_var[g])}")
     dom_ms = float(relax_ms)
     alg_bytes = float((iters * (20 * nfib + 52 * nfree)).sum())

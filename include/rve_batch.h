@@ -78,7 +78,7 @@ extern "C" {
                                   left by the previous solve of this batch */
 #define RVE_ENGINE_AUTO 0      /* register-resident persistent kernel where an
                                   RVE fits; beyond it the incidence kernel
-                                  (RVE_MIXED, free nodes within its limits),
+                                  (RVE_MIXED, free nodes of degree <= 16),
                                   else the streamed persistent kernel */
 #define RVE_ENGINE_STREAMED 1  /* persistent kernel, state in global memory */
 #define RVE_ENGINE_NAIVE 2     /* one RVE at a time, one launch per step of
@@ -90,16 +90,18 @@ extern "C" {
                                   rve_batch_autotune measured it faster than
                                   the streamed kernel */
 #define RVE_ENGINE_INCIDENCE 4 /* every RVE within the incidence kernel's
-                                  limits runs on it (RVE_MIXED only: node
-                                  state in registers, positions in LDS, one
-                                  record per node-fiber incidence read from
-                                  global memory each iteration; at most 12288
-                                  free nodes of degree <= 16), the rest as
-                                  AUTO.  Its tables (about 56 bytes per
-                                  fiber) are built at rve_batch_create: for
-                                  every RVE that fits when the batch is
-                                  created with this engine, else only for
-                                  the RVEs no resident build holds */
+                                  limits runs on it (RVE_MIXED only; free
+                                  nodes of degree <= 16): one record per
+                                  node-fiber incidence read from global
+                                  memory each iteration, node state in
+                                  registers and positions in LDS up to 12288
+                                  free nodes, node state in global arrays
+                                  above (global mode); the rest as AUTO.  Its
+                                  tables (about 56 bytes per fiber) are built
+                                  at rve_batch_create: for every RVE that
+                                  fits when the batch is created with this
+                                  engine, else only for the RVEs no resident
+                                  build holds */
 #define RVE_DAMP_VISCOUS 0     /* constant mass-proportional damping c M v */
 #define RVE_DAMP_KINETIC 1     /* kinetic damping: v = 0 at kinetic-energy peaks */
 #define RVE_DAMP_ADAPTIVE 2    /* c re-estimated each step (Rayleigh quotient) */
@@ -200,8 +202,8 @@ typedef struct {
  *     cost of the previous solve (iterations x fibers, longest processing
  *     time first; ties and the first solve in host order).  RVE_ORDER_AUTO:
  *     cost order for resident and incidence launches, host order for
- *     streamed ones.  Team launches keep host order.  Results do not depend
- *     on the order.
+ *     streamed and global-mode incidence ones.  Team launches keep host
+ *     order.  Results do not depend on the order.
  */
 typedef struct {
     int32_t precision;
@@ -281,7 +283,8 @@ int rve_batch_kernel_ms(rve_batch* b, double* relax_ms, double* stress_ms);
 /*
  * Kernel groups of the last solve: group_of_rve[R] receives the launch group
  * of every RVE, variant[g] its resident variant index (-1 streamed, -1 - k
- * a team of k workgroups per RVE, -100 the incidence kernel) and, if
+ * a team of k workgroups per RVE, -100 the incidence kernel, -101 its
+ * global mode) and, if
  * the solve was profiled, ms[g] the duration of that group's relaxation
  * launch (NaN otherwise).  Arrays are host memory of max_groups entries;
  * *n_groups receives the number of groups.

@@ -21,7 +21,7 @@ LAW_LINEAR, LAW_EXP = 0, 1
 MASS_LUMPED, MASS_SCALED = 0, 1
 INIT_AFFINE, INIT_REFERENCE, INIT_WARM = 0, 1, 2
 ENGINE_AUTO, ENGINE_STREAMED, ENGINE_NAIVE, ENGINE_TEAM, ENGINE_INCIDENCE = 0, 1, 2, 3, 4
-GROUP_STREAMED, GROUP_INCIDENCE = -1, -100
+GROUP_STREAMED, GROUP_INCIDENCE, GROUP_INCIDENCE_GLOBAL = -1, -100, -101
 PTR_HOST, PTR_DEVICE = 0, 1
 ST_CONVERGED, ST_MAXITER, ST_NONFINITE, ST_BAD_F, ST_NO_STATE, ST_CG_MAXITER, ST_CG_INDEFINITE, ST_ENERGY = range(8)
 ST_STAGNATED = 8
@@ -405,7 +405,7 @@ class Batch:
 
     def groups(self):
         """(group index per RVE, code per group (resident variant >= 0, -1 streamed, -1 - k team of k,
-        -100 incidence), ms per group of the last profiled solve)."""
+        -100 incidence, -101 incidence in global mode), ms per group of the last profiled solve)."""
         g = np.empty(self.n_rve, np.int32)
         var = np.empty(16, np.int32)
         ms = np.empty(16)

@@ -158,6 +158,7 @@ struct rve_batch {
     char* inc_mem = nullptr;
     IncArgs inc_tab{};
     bool inc_private[2][kNumInc] = {};
+    bool incg_private[2] = {};         // [kinetic]: the global-mode build uses private memory
 };
 
 // Launch-group codes beside the resident variants (>= 0): the streamed
@@ -165,6 +166,7 @@ struct rve_batch {
 // kernel.
 constexpr int kStreamedGroup = -1;
 constexpr int kIncGroup = -100;
+constexpr int kIncGlobalGroup = -101;
 static bool team_group(int v) { return v <= -3 && v >= -1 - kTeamMax; }
 
 // Adaptive damping and the energy check run on the FP64 variant engine;
@@ -726,9 +728,8 @@ static int build_team_tables(rve_batch* b, const HostPack& P)
 
 // ------------------------------------------------------------------ incidence tables
 // Host tables of the incidence engine (layout in rve_internal.h).  An RVE
-// gets tables when its free nodes fit every incidence build (at most
-// kIncMaxNodes, their positions within the LDS budget) and no free node has
-// more than kIncMaxDeg fibers.
+// gets tables when no free node has more than kIncMaxDeg fibers; it runs the
+// LDS form up to kIncMaxNodes free nodes, the global mode above.
 struct IncHost {
     std::vector<int64_t> rec_first;     // [R]
     std::vector<int32_t> round_first;   // [R][kIncMaxDeg + 1]
@@ -743,7 +744,7 @@ static size_t inc_lds_cap() { return 160 * 1024 - kResStaticLds; }
 static bool inc_fits(const HostPack& P, int64_t r)
 {
     const int64_t nf = P.free_off[r + 1] - P.free_off[r];
-    return nf >= 1 && nf <= kIncMaxNodes && P.maxdeg[r] <= kIncMaxDeg && incidence_lds_bytes(nf) <= inc_lds_cap();
+    return nf >= 1 && P.maxdeg[r] <= kIncMaxDeg && (!incidence_lds_mode(nf) || incidence_lds_bytes(nf) <= inc_lds_cap());
 }
 
 static uint32_t f32_bits(float x)
@@ -820,11 +821,15 @@ static int build_inc_tables(rve_batch* b, const HostPack& P)
     b->inc_first = H.rec_first;
     if (H.rec_fib.empty()) return RVE_OK;
     const size_t NREC = H.rec_fib.size(), NB = std::max<size_t>(H.brec_st.size(), 1);
+    bool global = false;   // an RVE runs the global mode: node-state arrays [NFREE + R]
+    for (int64_t r = 0; r < b->R; ++r) global = global || (H.rec_first[r] >= 0 && !incidence_lds_mode(b->nf_of[r]));
+    const size_t NG = global ? (size_t)(b->NFREE + b->R) : 1;
     DeviceArena A;
     const size_t o_first = A.reserve(8 * (size_t)b->R), o_round = A.reserve(4 * H.round_first.size()),
                  o_perm = A.reserve(4 * H.perm.size() + 4), o_fib = A.reserve(4 * NREC), o_st = A.reserve(8 * NREC),
                  o_rec = A.reserve(16 * NREC), o_bst = A.reserve(8 * NB), o_brec = A.reserve(16 * NB),
-                 o_im = A.reserve(4 * H.perm.size() + 4);
+                 o_im = A.reserve(4 * H.perm.size() + 4), o_hg = A.reserve(16 * NG), o_vg = A.reserve(16 * NG),
+                 o_ag = A.reserve(16 * NG);
     if (hipMalloc((void**)&b->inc_mem, A.used + 256) != hipSuccess) {
         b->inc_mem = nullptr;
         b->inc_first.assign(b->R, -1);
@@ -852,6 +857,9 @@ static int build_inc_tables(rve_batch* b, const HostPack& P)
     t.brec_st = carve<uint2>(m, o_bst);
     t.brec = carve<float4>(m, o_brec);
     t.imass = carve<float>(m, o_im);
+    t.hg = carve<float4>(m, o_hg);
+    t.vg = carve<float4>(m, o_vg);
+    t.ag = carve<float4>(m, o_ag);
     return RVE_OK;
 }
 
@@ -1013,9 +1021,13 @@ static int check_indexing(const rve_net_desc* net, bool fp64, int plant)
         if (H.rec_first[r] >= 0) {
             const int64_t rb0 = H.rec_first[r];
             const int32_t* rf = &H.round_first[(size_t)r * (kIncMaxDeg + 1)];
-            for (int v = 0; v < kNumInc; ++v)
-                if ((int64_t)kInc[v].threads * kInc[v].slots < nf) return bad(r, "incidence: node slots below nf");
-            if (incidence_lds_bytes(nf) + kResStaticLds > 160 * 1024) return bad(r, "incidence: LDS beyond 160 KB");
+            if (incidence_lds_mode(nf)) {
+                for (int v = 0; v < kNumInc; ++v)
+                    if ((int64_t)kInc[v].threads * kInc[v].slots < nf) return bad(r, "incidence: node slots below nf");
+                if (incidence_lds_bytes(nf) + kResStaticLds > 160 * 1024) return bad(r, "incidence: LDS beyond 160 KB");
+            } else if (a0 + r + nf >= NFREE + R) {
+                return bad(r, "incidence (global mode): zero slot outside the node-state arrays");
+            }
             std::vector<int> hit(nf, 0);
             for (int64_t p = 0; p < nf; ++p) {
                 const int32_t a = H.perm[a0 + p];
@@ -1183,16 +1195,35 @@ static int default_variant(const rve_batch* b, int tier, bool fp64)
 // Incidence build for the batch's options: the first of kInc without
 // private memory (of threads_per_rve threads when that is set), -1 when
 // none or the options rule the engine out.
+static bool inc_options(const rve_batch* b)
+{
+    return b->opts.precision == RVE_MIXED && b->opts.damping != RVE_DAMP_ADAPTIVE && !b->opts.energy_check &&
+           b->opts.engine != RVE_ENGINE_STREAMED && b->opts.engine != RVE_ENGINE_NAIVE && !b->inc_first.empty();
+}
+
 static int inc_variant(const rve_batch* b)
 {
-    if (b->opts.precision != RVE_MIXED || b->opts.damping == RVE_DAMP_ADAPTIVE || b->opts.energy_check ||
-        b->opts.engine == RVE_ENGINE_STREAMED || b->opts.engine == RVE_ENGINE_NAIVE || b->inc_first.empty())
-        return -1;
+    if (!inc_options(b)) return -1;
     const int k = b->opts.damping == RVE_DAMP_KINETIC ? 1 : 0;
     for (int v = 0; v < kNumInc; ++v)
         if (!b->inc_private[k][v] && (!b->opts.threads_per_rve || b->opts.threads_per_rve == kInc[v].threads))
             return v;
     return -1;
+}
+
+// whether the global-mode build may run for the batch's options
+static bool incg_ok(const rve_batch* b)
+{
+    return inc_options(b) && !b->incg_private[b->opts.damping == RVE_DAMP_KINETIC ? 1 : 0] &&
+           (!b->opts.threads_per_rve || b->opts.threads_per_rve == kIncGlobalThreads);
+}
+
+// whether RVE r can take the incidence engine (its tables exist and the
+// build of its form may run)
+static bool inc_rve(const rve_batch* b, int64_t r)
+{
+    if (b->inc_first.empty() || b->inc_first[r] < 0) return false;
+    return incidence_lds_mode(b->nf_of[r]) ? inc_variant(b) >= 0 : incg_ok(b);
 }
 
 static void assign_groups(rve_batch* b)
@@ -1203,15 +1234,15 @@ static void assign_groups(rve_batch* b)
     b->group_team.clear();
     const bool fp64 = b->opts.precision == RVE_FP64;
     // [resident variants..., streamed, teams of 2..kTeamMax, incidence]
-    const int inc_slot = kNumResident + kTeamMax + 1;
-    std::vector<std::vector<int32_t>> per(inc_slot + 1);
+    const int inc_slot = kNumResident + kTeamMax + 1, incg_slot = inc_slot + 1;
+    std::vector<std::vector<int32_t>> per(incg_slot + 1);
     const int eng = b->opts.engine;
-    const bool inc_build = inc_variant(b) >= 0;
     for (int64_t r = 0; r < b->R; ++r) {
         int slot = kNumResident;   // streamed
-        const bool inc = inc_build && b->inc_first[r] >= 0;
+        const bool inc = inc_rve(b, r);
+        const int islot = incidence_lds_mode(b->nf_of[r]) ? inc_slot : incg_slot;
         if (eng == RVE_ENGINE_INCIDENCE && inc) {
-            slot = inc_slot;
+            slot = islot;
         } else if (eng == RVE_ENGINE_AUTO || eng == RVE_ENGINE_TEAM || eng == RVE_ENGINE_INCIDENCE) {
             int t = tier_of(b, r, fp64);
             int chosen = -1;
@@ -1230,7 +1261,7 @@ static void assign_groups(rve_batch* b)
             else if (team)
                 slot = kNumResident + k;
             else if (inc)
-                slot = inc_slot;
+                slot = islot;
         }
         per[slot].push_back((int32_t)r);
     }
@@ -1247,6 +1278,8 @@ static void assign_groups(rve_batch* b)
         } else if (v == (size_t)inc_slot) {
             for (int32_t r : members) lds = std::max(lds, incidence_lds_bytes(b->nf_of[r]));
             code = kIncGroup;
+        } else if (v == (size_t)incg_slot) {
+            code = kIncGlobalGroup;
         } else if (v > (size_t)kNumResident) {
             team = (int)(v - kNumResident);
             for (int32_t r : members) lds = std::max(lds, b->team_lds[fp64 ? 1 : 0][r]);
@@ -1456,12 +1489,16 @@ int rve_batch_create(const rve_net_desc* net, const rve_opts* opts, rve_batch** 
                 b->streamed_private[k][p][w] = sb > 0;
             }
         }
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < 2; ++k) {
         for (int v = 0; v < kNumInc; ++v) {
             size_t sb = 1;
             if (incidence_scratch_bytes(v, k == 1, &sb) != hipSuccess) sb = 1;
             b->inc_private[k][v] = sb > 0;
         }
+        size_t sb = 1;
+        if (incidence_global_scratch_bytes(k == 1, &sb) != hipSuccess) sb = 1;
+        b->incg_private[k] = sb > 0;
+    }
     for (int m = 0; m < 2; ++m)
         for (int v = 0; v < kNumTanRes; ++v) {
             size_t sb = 1;
@@ -1740,7 +1777,7 @@ static int launch_groups(rve_batch* b, SolveArgs& a, int32_t* queues, void* ws_f
             const int v = b->group_variant[g];
             bool by_cost = b->cost_order && !team_group(v);
             if (b->opts.work_order == RVE_ORDER_HOST) by_cost = false;
-            if (b->opts.work_order == RVE_ORDER_AUTO && v == kStreamedGroup) by_cost = false;
+            if (b->opts.work_order == RVE_ORDER_AUTO && (v == kStreamedGroup || v == kIncGlobalGroup)) by_cost = false;
             o.first[g] = b->group_first[g];
             o.count[g] = by_cost ? (int32_t)b->groups[g].size() : 0;
             any = any || by_cost;
@@ -1803,6 +1840,13 @@ static int launch_groups(rve_batch* b, SolveArgs& a, int32_t* queues, void* ws_f
             if (per_cu < 1) return fail(RVE_EDEVICE, "incidence kernel does not fit a CU");
             int grid = std::min<int64_t>((int64_t)per_cu * b->n_cu, a.n_list);
             HIP_TRY(launch_incidence(iv, a, b->inc_tab, b->group_lds[g], grid, gs_));
+        } else if (v == kIncGlobalGroup) {
+            if (!incg_ok(b)) return fail(RVE_EDEVICE, "internal: no global-mode incidence build for these options");
+            int per_cu = 1;
+            HIP_TRY(incidence_global_blocks(a.kinetic != 0, &per_cu));
+            if (per_cu < 1) return fail(RVE_EDEVICE, "incidence kernel (global mode) does not fit a CU");
+            int grid = std::min<int64_t>((int64_t)per_cu * b->n_cu, a.n_list);
+            HIP_TRY(launch_incidence_global(a, b->inc_tab, grid, gs_));
         } else if (team_group(v)) {
             const int k = b->group_team[g];
             if (!team_ws) return fail(RVE_EWORKSPACE, "internal: no team work area");
@@ -2163,12 +2207,10 @@ int rve_batch_autotune(rve_batch* b, const double* F, int32_t ptr_kind, int32_t 
     // per CU-time; the team counts only if it takes every RVE the streamed
     // run took through all iterations through the same count to a final
     // state within 5% of the streamed one
-    const bool inc_on = inc_variant(b) >= 0;
     for (int k = 2; k <= kTeamMax; ++k) {
         std::vector<int32_t> members;
         for (int64_t r = 0; r < b->R; ++r)
-            if (tier_of(b, r, fp64) < 0 && b->team_k[r] == k && !(inc_on && b->inc_first[r] >= 0))
-                members.push_back((int32_t)r);
+            if (tier_of(b, r, fp64) < 0 && b->team_k[r] == k && !inc_rve(b, r)) members.push_back((int32_t)r);
         if (members.empty()) continue;
         std::stable_sort(members.begin(), members.end(),
                          [&](int32_t x, int32_t y) { return b->nfib_of[x] > b->nfib_of[y]; });
@@ -2280,6 +2322,8 @@ int rve_batch_describe(const rve_batch* b, char* buf, size_t n)
         else if (v == kIncGroup) {
             const int iv = std::max(inc_variant(b), 0);
             d += "incidence(" + std::to_string(kInc[iv].threads) + "," + std::to_string(kInc[iv].slots) + ")";
+        } else if (v == kIncGlobalGroup) {
+            d += "incidence(global," + std::to_string(kIncGlobalThreads) + ")";
         } else if (team_group(v))
             d += "team(" + std::to_string(-1 - v) + "x" + std::to_string(kTeamUnit[b->opts.precision == RVE_FP64].threads) + ")";
         else

@@ -254,6 +254,11 @@ struct IncArgs {
     const uint2* brec_st;         // [NBINC] the same for each boundary incidence (DevNet::binc order)
     float4* brec;                 // [NBINC]
     float* imass;                 // [NFREE] inverse mass of rank p
+    // global mode (RVEs whose positions do not fit LDS): node state of rank p
+    // at free_off[r] + r + p, the zero slot at free_off[r] + r + nf
+    float4* hg;                   // [NFREE + R] (h, 1/M)
+    float4* vg;                   // [NFREE + R] velocity
+    float4* ag;                   // [NFREE + R] acceleration
 };
 struct IncVariant {
     int threads, slots;
@@ -265,6 +270,14 @@ hipError_t launch_incidence(int variant, const SolveArgs& a, const IncArgs& inc,
                             hipStream_t s);
 hipError_t incidence_blocks(int variant, bool kin, size_t lds_bytes, int* blocks_per_cu);
 hipError_t incidence_scratch_bytes(int variant, bool kin, size_t* bytes);
+// Global mode of the incidence engine: the same records, the node state in
+// the global arrays above (one 1024-thread workgroup per RVE, any size).
+constexpr int kIncGlobalThreads = 1024;
+hipError_t launch_incidence_global(const SolveArgs& a, const IncArgs& inc, int grid, hipStream_t s);
+hipError_t incidence_global_blocks(bool kin, int* blocks_per_cu);
+hipError_t incidence_global_scratch_bytes(bool kin, size_t* bytes);
+// whether an RVE of nf free nodes runs the LDS form (else the global mode)
+inline bool incidence_lds_mode(int64_t nf) { return nf <= kIncMaxNodes; }
 
 // Which register-resident variants exist (threads per RVE, fiber slots per
 // thread, free-node slots per thread).

@@ -1716,6 +1716,336 @@ __global__ __launch_bounds__(T) void dr_incidence_kernel(SolveArgs A, IncArgs I)
     }
 }
 
+// Global mode of the incidence engine, for RVEs whose positions do not fit
+// LDS (more than kIncMaxNodes free nodes): the same records and rounds, the
+// node state (h with 1/M, v, a) in global arrays in rank order, each thread
+// taking ranks tid, tid + T, ...  Per iteration every record is read once,
+// the other end's position is gathered from global memory (the RVE's
+// positions, 16 B per node, stay in L2), and no fiber force is written.
+// The force pass takes NP nodes of a thread at once and loads the records
+// of QU rounds of all of them before the gathers and the arithmetic, so
+// each thread has NP x QU record loads, then gathers, in flight: the pass
+// is a chain of dependent loads, and their number per iteration sets its
+// time.
+template <int T, int NP, int QU, bool KIN>
+__device__ __forceinline__ void incidence_global_solve(const SolveArgs& A, const IncArgs& I, int r, RedSlots& red)
+{
+    constexpr int NW = T / 64;
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const DevNet& net = A.net;
+    const int64_t f0 = uniform64(net.fib_off[r]), a0 = uniform64(net.free_off[r]), b0 = uniform64(net.bnd_off[r]);
+    const int nf = uniform32((int)(net.free_off[r + 1] - a0));
+    const int nb = uniform32((int)(net.bnd_off[r + 1] - b0));
+    const int64_t rb = uniform64(I.rec_first[r]);
+    const int32_t* rq = I.round_first + (int64_t)r * (kIncMaxDeg + 1);
+    const int nrec = uniform32(rq[kIncMaxDeg]);
+    const float4* recb = I.rec + rb;
+    const uint2* stb = I.rec_st + rb;
+    const int32_t* permb = I.perm + a0;
+    float4* hg = I.hg + a0 + r;
+    float4* vg = I.vg + a0 + r;
+    float4* ag = I.ag + a0 + r;
+    double* hsb = A.h_state + 3 * a0;
+
+    double F[9];
+    bool finite = true;
+    for (int k = 0; k < 9; ++k) {
+        F[k] = A.F[9 * r + k];
+        finite = finite && isfinite(F[k]);
+    }
+    const double J = det3(F);
+    if (!finite || !(J > 0.0)) {
+        if (tid == 0) {
+            A.status[r] = ST_BAD_F;
+            A.iters[r] = 0;
+            A.Rres[r] = NAN; A.Dres[r] = NAN; A.Bres[r] = NAN;
+            for (int k = 0; k < 9; ++k) A.sigma[9 * r + k] = NAN;
+        }
+        return;
+    }
+    const bool linear = A.law == kLawLinear;
+    double EAd = A.EA, Bd = A.B;
+    asm volatile("" : "+s"(EAd), "+s"(Bd));
+    const float EA = uniform((float)EAd), Bc = uniform((float)Bd), EAoB = uniform((float)(EAd / Bd));
+    const double cr = uniform(A.c[r]);
+    const float c = KIN ? 0.f : uniform((float)cr);
+    const float cg = uniform((float)cr);
+
+    // ---- records of this F, node state
+#pragma unroll 1
+    for (int j = tid; j < nrec; j += T) I.rec[rb + j] = inc_record(F, net, f0, I.rec_fib[rb + j]);
+    const int64_t be0 = uniform64(net.binc_off[b0]), be1 = uniform64(net.binc_off[b0 + nb]);
+#pragma unroll 1
+    for (int64_t e = be0 + tid; e < be1; e += T) I.brec[e] = inc_record(F, net, f0, net.binc[e]);
+#pragma unroll 1
+    for (int p = tid; p < nf; p += T) {
+        const int a = permb[p];
+        float hx = 0.f, hy = 0.f, hz = 0.f;
+        if (A.init == kInitWarm) {
+            const double* h = hsb + 3 * a;
+            hx = (float)h[0]; hy = (float)h[1]; hz = (float)h[2];
+        }
+        hg[p] = make_float4(hx, hy, hz, (float)(1.0 / (net.mass[a0 + a] * A.rhoA)));
+        vg[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    if (tid < 2) red.g32[tid] = 0u;   // FP32: only the 32-bit time-step slots are used
+    if (tid == 0) hg[nf] = make_float4(0.f, 0.f, 0.f, 0.f);
+    __syncthreads();
+
+    // internal force and Gershgorin sum at ranks pp[0 .. NP) (pp ascending,
+    // own positions ho; act: the rank is a node)
+    auto node_force = [&](const int (&pp)[NP], const bool (&act)[NP], const float4 (&ho)[NP], float (&fx)[NP],
+                          float (&fy)[NP], float (&fz)[NP], float (&G)[NP]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int i = 0; i < NP; ++i) fx[i] = fy[i] = fz[i] = G[i] = 0.f;
+        // a wave's ranks are consecutive, its first lane's node 0 the
+        // smallest: the wave stops at the first batch of rounds none of its
+        // nodes has
+        const int pw = __builtin_amdgcn_readfirstlane(pp[0]);
+#pragma unroll 1
+        for (int q0 = 0; q0 < kIncMaxDeg; q0 += QU) {
+            if (pw >= uniform32(rq[q0 + 1]) - uniform32(rq[q0])) break;
+            float4 rc[NP][QU], oh[NP][QU];
+            uint2 st[NP][QU];
+            bool on[NP][QU];
+#pragma unroll
+            for (int u = 0; u < QU; ++u) {
+                const int R0 = uniform32(rq[q0 + u]), Pq = uniform32(rq[q0 + u + 1]) - R0;
+#pragma unroll
+                for (int i = 0; i < NP; ++i) {
+                    on[i][u] = act[i] && pp[i] < Pq;
+                    rc[i][u] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    st[i][u] = make_uint2(0u, (uint32_t)nf);
+                    if (on[i][u]) {
+                        rc[i][u] = recb[R0 + pp[i]];
+                        st[i][u] = stb[R0 + pp[i]];
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < NP; ++i)
+#pragma unroll
+                for (int u = 0; u < QU; ++u) oh[i][u] = hg[st[i][u].y];
+#pragma unroll
+            for (int i = 0; i < NP; ++i)
+#pragma unroll
+                for (int u = 0; u < QU; ++u) {
+                    const FiberOut<float> f = fiber_eval_scaled<float>(
+                        linear, EA, Bc, EAoB, rc[i][u].x, rc[i][u].y, rc[i][u].z, rc[i][u].w,
+                        __uint_as_float(st[i][u].x), ho[i].x - oh[i][u].x, ho[i].y - oh[i][u].y,
+                        ho[i].z - oh[i][u].z);
+                    if (on[i][u]) {
+                        fx[i] += f.fx; fy[i] += f.fy; fz[i] += f.fz; G[i] += f.b;
+                    }
+                }
+        }
+#pragma unroll
+        for (int i = 0; i < NP; ++i) G[i] *= 2.f;
+    };
+    auto bnorm2 = [&](int t) __attribute__((always_inline)) -> double {
+        double acc = 0.0;
+#pragma unroll 1
+        for (int q = t; q < nb; q += T) {
+            double x = 0.0, y = 0.0, z = 0.0;
+            const int64_t e1 = net.binc_off[b0 + q + 1];
+#pragma unroll 1
+            for (int64_t e = net.binc_off[b0 + q]; e < e1; ++e) {
+                const float4 rc = I.brec[e];
+                const uint2 st = I.brec_st[e];
+                const float4 oh = hg[st.y];
+                const FiberOut<float> f = fiber_eval_scaled<float>(linear, EA, Bc, EAoB, rc.x, rc.y, rc.z, rc.w,
+                                                                   __uint_as_float(st.x), 0.f - oh.x, 0.f - oh.y,
+                                                                   0.f - oh.z);
+                x += (double)f.fx; y += (double)f.fy; z += (double)f.fz;
+            }
+            acc += x * x + y * y + z * z;
+        }
+        return acc;
+    };
+
+    // the force pass over the thread's nodes, NP at a time: body(p, ho, v,
+    // fx, fy, fz, G) for each node (its position record ho and velocity v)
+    auto force_pass = [&](int t, auto&& body) __attribute__((always_inline)) {
+#pragma unroll 1
+        for (int p0 = t; p0 < nf; p0 += NP * T) {
+            int pp[NP];
+            bool act[NP];
+            float4 ho[NP], v[NP];
+#pragma unroll
+            for (int i = 0; i < NP; ++i) {
+                pp[i] = p0 + i * T;
+                act[i] = pp[i] < nf;
+                ho[i] = act[i] ? hg[pp[i]] : make_float4(0.f, 0.f, 0.f, 1.f);
+                v[i] = act[i] ? vg[pp[i]] : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+            float fx[NP], fy[NP], fz[NP], G[NP];
+            node_force(pp, act, ho, fx, fy, fz, G);
+#pragma unroll
+            for (int i = 0; i < NP; ++i)
+                if (act[i]) body(pp[i], ho[i], v[i], fx[i], fy[i], fz[i], G[i]);
+        }
+    };
+
+    // ---- initial force, residual and (optionally) stiffness-scaled mass
+    float gpart = 0.f;
+    double r2p = 0.0, b2p = 0.0;
+    force_pass(tid, [&](int p, float4 ho, float4, float fx, float fy, float fz, float G) __attribute__((always_inline)) {
+        float im = ho.w;
+        if (A.mass_mode == kMassScaled) {
+            im = G > 0.f ? 4.f / G : 1.f;
+            ho.w = im;
+            hg[p] = ho;
+        }
+        ag[p] = make_float4(-fx * im, -fy * im, -fz * im, 0.f);
+        gpart = fmax(gpart, G * im);
+        r2p += (double)fx * fx + (double)fy * fy + (double)fz * fz;
+    });
+    b2p = bnorm2(tid);
+    double gmax;
+    double R2 = 0.0, D2 = 0.0, B2 = 0.0;
+    int parity = 0;
+    block_reduce<float, NW>(red, tid, parity, gpart, r2p, 0.0, b2p, true, gmax, R2, D2, B2);
+
+    int64_t n = 0;
+    int status = ST_CONVERGED;
+    const int ce = A.check_every > 0 ? A.check_every : 1;
+    int countdown = ce;
+    bool done = sqrt(R2) <= fmax(A.tol_abs, A.tol_rel * sqrt(B2));   // v = 0: damping norm is 0
+    double Rref = uniform(sqrt(R2));
+    int stall = 0;
+    if (!isfinite(R2)) {
+        status = ST_NONFINITE;
+        done = true;
+    }
+    if (!done && n >= A.n_max) {
+        status = ST_MAXITER;
+        done = true;
+    }
+    auto time_step = [&](double g) __attribute__((always_inline)) -> double {
+        return uniform((double)(uniform((float)(2.0 * A.alpha)) * __builtin_amdgcn_rsqf((float)g)));
+    };
+    double dt = time_step(gmax);
+    double ke_prev = 0.0;
+
+    while (!done) {
+        const int t = opaque_tid();
+        const float hdt = (float)(0.5 * dt), rdt = (float)dt;
+        // half-step velocity and position update
+#pragma unroll 1
+        for (int p = t; p < nf; p += T) {
+            float4 v = vg[p], h = hg[p];
+            const float4 a = ag[p];
+            v.x += hdt * a.x; v.y += hdt * a.y; v.z += hdt * a.z;
+            h.x += rdt * v.x; h.y += rdt * v.y; h.z += rdt * v.z;
+            vg[p] = v;
+            hg[p] = h;
+        }
+        __syncthreads();
+        const int tb = opaque_tid();
+        ++n;
+        const bool check = --countdown == 0;
+        if (check) countdown = ce;
+        gpart = 0.f;
+        r2p = 0.0;
+        double d2p = 0.0, kep = 0.0;
+        force_pass(tb, [&](int p, float4 ho, float4 v, float fx, float fy, float fz, float G) __attribute__((always_inline)) {
+            const float im = ho.w;
+            float4 a;
+            a.x = -fx * im - c * v.x;
+            a.y = -fy * im - c * v.y;
+            a.z = -fz * im - c * v.z;
+            a.w = 0.f;
+            v.x += hdt * a.x; v.y += hdt * a.y; v.z += hdt * a.z;
+            ag[p] = a;
+            vg[p] = v;
+            gpart = fmax(gpart, G * im);
+            if constexpr (KIN) kep += 0.5 * (double)((v.x * v.x + v.y * v.y + v.z * v.z) * dev_rcp(im));
+            if (check) {
+                r2p += (double)fx * fx + (double)fy * fy + (double)fz * fz;
+                const float cm = cg * dev_rcp(im);
+                const double px = (double)(cm * v.x), py = (double)(cm * v.y), pz = (double)(cm * v.z);
+                d2p += px * px + py * py + pz * pz;
+            }
+        });
+        if (check) b2p = bnorm2(tb);
+        parity ^= 1;
+        double r2n = R2, d2n = D2, b2n = B2, ke = 0.0;
+        block_reduce<float, NW, KIN>(red, tb, parity, gpart, r2p, d2p, b2p, check, gmax, r2n, d2n, b2n, kep, &ke);
+        if constexpr (KIN) {
+            // a kinetic-energy peak was passed: restart every node from rest
+            // (the stored acceleration is already -f/M); the velocities are
+            // read by their own threads only, so no barrier is needed
+            if (ke < ke_prev) {
+#pragma unroll 1
+                for (int p = tb; p < nf; p += T) vg[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+                ke = 0.0;
+                if (check) d2n = 0.0;
+            }
+            ke_prev = ke;
+        }
+        if (check) {
+            R2 = r2n;
+            D2 = d2n;
+            B2 = b2n;
+            if (!isfinite(R2) || !isfinite(D2)) {
+                status = ST_NONFINITE;
+                break;
+            }
+            const double Rn = sqrt(R2), Dn = sqrt(D2), Bn = sqrt(B2);
+            const double tol = fmax(A.tol_abs, A.tol_rel * Bn);
+            if (Rn <= tol && Dn <= tol) break;
+            if (stagnated(A, Rn, Dn, Bn, Rref, stall)) {
+                status = ST_STAGNATED;
+                break;
+            }
+            Rref = uniform(Rref);
+        }
+        if (!(gmax > 0.0) || !isfinite(gmax)) {
+            status = ST_NONFINITE;
+            break;
+        }
+        if (n >= A.n_max) {
+            status = ST_MAXITER;
+            break;
+        }
+        dt = time_step(gmax);
+    }
+
+    // ---- fluctuation state in the packed order
+    const int te = opaque_tid();
+    __syncthreads();
+#pragma unroll 1
+    for (int p = te; p < nf; p += T) {
+        const float4 h = hg[p];
+        double* hs = hsb + 3 * permb[p];
+        hs[0] = (double)h.x; hs[1] = (double)h.y; hs[2] = (double)h.z;
+    }
+    if (te == 0) {
+        A.status[r] = status;
+        A.iters[r] = n;
+        A.Rres[r] = sqrt(R2);
+        A.Dres[r] = sqrt(D2);
+        A.Bres[r] = sqrt(B2);
+    }
+    __syncthreads();
+}
+
+template <int T, int NP, int QU, bool KIN>
+__global__ __launch_bounds__(T) void dr_incidence_global_kernel(SolveArgs A, IncArgs I)
+{
+    __shared__ RedSlots red;
+    __shared__ int task;
+    for (;;) {
+        if (threadIdx.x == 0) task = atomicAdd(A.queue, 1);
+        __syncthreads();
+        const int t = __builtin_amdgcn_readfirstlane(task);
+        __syncthreads();
+        if (t >= A.n_list) break;
+        incidence_global_solve<T, NP, QU, KIN>(A, I, __builtin_amdgcn_readfirstlane(A.list[t]), red);
+    }
+}
+
 // ------------------------------------------------------------------ stress kernel
 // Homogenized stress of every RVE from its final fluctuation state, one
 // workgroup per RVE: each fiber with a boundary end is re-evaluated in FP64
@@ -2027,6 +2357,32 @@ hipError_t incidence_blocks(int variant, bool kin, size_t lds, int* blocks)
 hipError_t incidence_scratch_bytes(int variant, bool kin, size_t* bytes)
 {
     RVE_INC_DISPATCH(spill_inc_t, bytes)
+}
+
+// global-mode build: nodes per thread taken together and rounds per load batch
+constexpr int kIncGNP = 2, kIncGQU = 2;
+
+static const void* incg_kernel(bool kin)
+{
+    constexpr int T = kIncGlobalThreads;
+    return kin ? (const void*)dr_incidence_global_kernel<T, kIncGNP, kIncGQU, true>
+               : (const void*)dr_incidence_global_kernel<T, kIncGNP, kIncGQU, false>;
+}
+
+hipError_t launch_incidence_global(const SolveArgs& a, const IncArgs& inc, int grid, hipStream_t s)
+{
+    void* args[] = {const_cast<SolveArgs*>(&a), const_cast<IncArgs*>(&inc)};
+    return hipLaunchKernel(incg_kernel(a.kinetic != 0), dim3(grid), dim3(kIncGlobalThreads), args, 0, s);
+}
+
+hipError_t incidence_global_blocks(bool kin, int* blocks)
+{
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, incg_kernel(kin), kIncGlobalThreads, 0);
+}
+
+hipError_t incidence_global_scratch_bytes(bool kin, size_t* bytes)
+{
+    return max_private_bytes({incg_kernel(kin)}, bytes);
 }
 
 hipError_t kernels_fixed_private(size_t* bytes)

@@ -121,7 +121,7 @@ def main(argv=None) -> int:
         alg = float((it[sel] * (bpf * nfib[sel] + bpn * nfree[sel])).sum())
         kern = ("resident(%s)" % rb_variant(int(g_var[g]))) if g_var[g] >= 0 else (
             "streamed" if g_var[g] == rb.GROUP_STREAMED else "incidence" if g_var[g] == rb.GROUP_INCIDENCE
-            else "team(%d)" % (-1 - int(g_var[g])))
+            else "incidence(global)" if g_var[g] == rb.GROUP_INCIDENCE_GLOBAL else "team(%d)" % (-1 - int(g_var[g])))
         groups.append({"kernel": kern,
                        "rves": int(sel.sum()), "ms": float(g_ms[g]), "algorithmic_bytes": alg,
                        "algorithmic_GB_per_s": alg / (float(g_ms[g]) / 1e3) / 1e9 if g_ms[g] > 0 else None})

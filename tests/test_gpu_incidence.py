@@ -1,9 +1,10 @@
 """Incidence engine (node state in registers, one fiber record per
 node-fiber incidence read from global memory each iteration), GPU.
 
-RVE_ENGINE_INCIDENCE puts every RVE within the engine's limits (at most
-12288 free nodes of degree <= 16) on it, so small networks exercise it
-quickly; AUTO gives it the RVEs beyond the register-resident capacity.
+RVE_ENGINE_INCIDENCE puts every RVE within the engine's limits (free nodes
+of degree <= 16; positions in LDS up to 12288 free nodes, the global mode
+above) on it, so small networks exercise it quickly; AUTO gives it the RVEs
+beyond the register-resident capacity.
 
 * config 2 RVEs: statuses as on the resident engine (except within 2% of
   the cap) and every jointly converged RVE within 1e-4 of the resident
@@ -14,7 +15,8 @@ quickly; AUTO gives it the RVEs beyond the register-resident capacity.
   written in the packed order and read back through the rank permutation);
 * kinetic damping: the kinetic build converges like the resident one;
 * 2000-seed RVEs: AUTO takes them on the incidence kernel, statuses and
-  stresses as on the streamed kernel (same grading);
+  stresses as on the streamed kernel (same grading); the largest RVEs of
+  the FE^2 workload (above 12288 free nodes) on its global mode likewise;
 * RVE_ENGINE_INCIDENCE with RVE_FP64 is rejected.
 Parity with the FP64 oracle's stored results at the full workload shapes is
 in test_gpu_fullshape.py (engine 4).
@@ -129,6 +131,34 @@ def test_large_rves_take_the_incidence_kernel():
     _compare(b, batch, F, sig, st, x["iters"], rsig, rst, rx["iters"], kw, "large RVEs incidence vs streamed")
     b.close()
     ref.close()
+
+
+def test_global_mode_on_the_largest_rves():
+    """RVEs above 12288 free nodes (the largest of the FE^2 workload) run the
+    incidence engine's global mode (node state in global arrays); statuses
+    and stresses as on the streamed kernel (same grading), in both
+    dampings."""
+    rb = require_gpu()
+    seeds = np.array([synth.seed_count(5, r) for r in range(8192)])
+    idx = np.sort(np.argsort(seeds)[-6:])
+    batch, F = synth.make_config_batch(5, idx=idx)
+    nfree = [int((batch.is_bnd[batch.node_off[r]:batch.node_off[r + 1]] == 0).sum()) for r in range(batch.n_rve)]
+    log(f"free nodes {nfree}")
+    for damping in (rb.DAMP_VISCOUS, rb.DAMP_KINETIC):
+        kw = _kw(rb, rb.ENGINE_AUTO, n_max=100000, damping=damping)
+        b = rb.Batch(batch, **kw)
+        d = b.describe()
+        log(f"groups {d}")
+        assert "incidence(global," in d and "streamed" not in d
+        sig, st, x = b.solve(F, stats=True)
+        ref = rb.Batch(batch, **_kw(rb, rb.ENGINE_STREAMED, n_max=100000, damping=damping))
+        rsig, rst, rx = ref.solve(F, stats=True)
+        _compare(b, batch, F, sig, st, x["iters"], rsig, rst, rx["iters"], kw, f"global mode vs streamed, damping {damping}")
+        b2 = rb.Batch(batch, **kw)
+        s2, t2 = b2.solve(F)
+        assert np.array_equal(sig, s2, equal_nan=True) and np.array_equal(st, t2)   # repeatable
+        for h in (b, ref, b2):
+            h.close()
 
 
 def test_incidence_engine_rejects_fp64():

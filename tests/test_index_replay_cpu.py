@@ -70,6 +70,17 @@ def test_planted_lds_mistake_is_reported(cfg2):
     assert "outside the LDS array" in str(e.value)
 
 
+@pytest.mark.parametrize("precision", [rb.FP64, rb.MIXED])
+def test_largest_rves_index_in_bounds(precision):
+    """The largest RVEs of the FE2 workload (above 12288 free nodes: the
+    incidence engine's global mode, node state in [NFREE + R] arrays)."""
+    seeds = np.array([synth.seed_count(5, r) for r in range(8192)])
+    batch = synth.make_config_batch(5, idx=np.sort(np.argsort(seeds)[-2:]), workers=2)[0]
+    nfree = [int((batch.is_bnd[batch.node_off[r]:batch.node_off[r + 1]] == 0).sum()) for r in range(batch.n_rve)]
+    assert max(nfree) > 12288
+    rb.check_indexing(batch, precision)
+
+
 def test_planted_incidence_record_mistake_is_reported(cfg2):
     """With one incidence record naming the wrong other end, the replay of
     the incidence engine's tables must report it."""
