@@ -821,15 +821,21 @@ static int build_inc_tables(rve_batch* b, const HostPack& P)
     b->inc_first = H.rec_first;
     if (H.rec_fib.empty()) return RVE_OK;
     const size_t NREC = H.rec_fib.size(), NB = std::max<size_t>(H.brec_st.size(), 1);
-    bool global = false;   // an RVE runs the global mode: node-state arrays [NFREE + R]
-    for (int64_t r = 0; r < b->R; ++r) global = global || (H.rec_first[r] >= 0 && !incidence_lds_mode(b->nf_of[r]));
-    const size_t NG = global ? (size_t)(b->NFREE + b->R) : 1;
+    // node-state entries of the global-mode RVEs (nf + 1 each)
+    std::vector<int64_t> g_first(b->R, -1);
+    size_t NG = 0;
+    for (int64_t r = 0; r < b->R; ++r)
+        if (H.rec_first[r] >= 0 && !incidence_lds_mode(b->nf_of[r])) {
+            g_first[r] = (int64_t)NG;
+            NG += (size_t)b->nf_of[r] + 1;
+        }
+    NG = std::max<size_t>(NG, 1);
     DeviceArena A;
     const size_t o_first = A.reserve(8 * (size_t)b->R), o_round = A.reserve(4 * H.round_first.size()),
                  o_perm = A.reserve(4 * H.perm.size() + 4), o_fib = A.reserve(4 * NREC), o_st = A.reserve(8 * NREC),
                  o_rec = A.reserve(16 * NREC), o_bst = A.reserve(8 * NB), o_brec = A.reserve(16 * NB),
-                 o_im = A.reserve(4 * H.perm.size() + 4), o_hg = A.reserve(16 * NG), o_vg = A.reserve(16 * NG),
-                 o_ag = A.reserve(16 * NG);
+                 o_im = A.reserve(4 * H.perm.size() + 4), o_gf = A.reserve(8 * (size_t)b->R),
+                 o_hg = A.reserve(16 * NG), o_vg = A.reserve(16 * NG), o_ag = A.reserve(16 * NG);
     if (hipMalloc((void**)&b->inc_mem, A.used + 256) != hipSuccess) {
         b->inc_mem = nullptr;
         b->inc_first.assign(b->R, -1);
@@ -846,6 +852,7 @@ static int build_inc_tables(rve_batch* b, const HostPack& P)
     e = e ? e : up(o_fib, H.rec_fib.data(), 4 * NREC);
     e = e ? e : up(o_st, H.rec_st.data(), 8 * NREC);
     e = e ? e : up(o_bst, H.brec_st.data(), 8 * H.brec_st.size());
+    e = e ? e : up(o_gf, g_first.data(), 8 * (size_t)b->R);
     if (e != hipSuccess) return fail(RVE_EDEVICE, std::string("incidence table upload failed: ") + hipGetErrorString(e));
     IncArgs& t = b->inc_tab;
     t.rec_first = carve<int64_t>(m, o_first);
@@ -857,6 +864,7 @@ static int build_inc_tables(rve_batch* b, const HostPack& P)
     t.brec_st = carve<uint2>(m, o_bst);
     t.brec = carve<float4>(m, o_brec);
     t.imass = carve<float>(m, o_im);
+    t.g_first = carve<int64_t>(m, o_gf);
     t.hg = carve<float4>(m, o_hg);
     t.vg = carve<float4>(m, o_vg);
     t.ag = carve<float4>(m, o_ag);
@@ -948,6 +956,14 @@ static int check_indexing(const rve_net_desc* net, bool fp64, int plant)
         return fail(RVE_ENOMEM, "host allocation failed while building the incidence tables");
     }
     if (plant == 2 && !H.rec_st.empty()) H.rec_st[H.rec_st.size() / 2].y ^= 1u;
+    // node-state entries of the global-mode RVEs, as build_inc_tables lays them out
+    std::vector<int64_t> gfirst(R, -1);
+    int64_t gtotal = 0;
+    for (int64_t r = 0; r < R; ++r)
+        if (H.rec_first[r] >= 0 && !incidence_lds_mode(P.free_off[r + 1] - P.free_off[r])) {
+            gfirst[r] = gtotal;
+            gtotal += P.free_off[r + 1] - P.free_off[r] + 1;
+        }
     for (int64_t r = 0; r < R; ++r) {
         const int64_t f0 = P.fib_off[r], a0 = P.free_off[r], b0 = P.bnd_off[r];
         const int64_t nfib = P.fib_off[r + 1] - f0, nf = P.free_off[r + 1] - a0, nb = P.bnd_off[r + 1] - b0;
@@ -1025,7 +1041,7 @@ static int check_indexing(const rve_net_desc* net, bool fp64, int plant)
                 for (int v = 0; v < kNumInc; ++v)
                     if ((int64_t)kInc[v].threads * kInc[v].slots < nf) return bad(r, "incidence: node slots below nf");
                 if (incidence_lds_bytes(nf) + kResStaticLds > 160 * 1024) return bad(r, "incidence: LDS beyond 160 KB");
-            } else if (a0 + r + nf >= NFREE + R) {
+            } else if (gfirst[r] < 0 || gfirst[r] + nf >= gtotal) {
                 return bad(r, "incidence (global mode): zero slot outside the node-state arrays");
             }
             std::vector<int> hit(nf, 0);

@@ -255,10 +255,12 @@ struct IncArgs {
     float4* brec;                 // [NBINC]
     float* imass;                 // [NFREE] inverse mass of rank p
     // global mode (RVEs whose positions do not fit LDS): node state of rank p
-    // at free_off[r] + r + p, the zero slot at free_off[r] + r + nf
-    float4* hg;                   // [NFREE + R] (h, 1/M)
-    float4* vg;                   // [NFREE + R] velocity
-    float4* ag;                   // [NFREE + R] acceleration
+    // at g_first[r] + p, the zero slot at g_first[r] + nf (nf + 1 entries per
+    // global-mode RVE)
+    const int64_t* g_first;       // [R] first entry of the RVE's node state, -1 when it has none
+    float4* hg;                   // (h, 1/M)
+    float4* vg;                   // velocity
+    float4* ag;                   // acceleration
 };
 struct IncVariant {
     int threads, slots;

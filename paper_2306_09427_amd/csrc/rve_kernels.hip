@@ -1743,9 +1743,10 @@ __device__ __forceinline__ void incidence_global_solve(const SolveArgs& A, const
     const float4* recb = I.rec + rb;
     const uint2* stb = I.rec_st + rb;
     const int32_t* permb = I.perm + a0;
-    float4* hg = I.hg + a0 + r;
-    float4* vg = I.vg + a0 + r;
-    float4* ag = I.ag + a0 + r;
+    const int64_t gb = uniform64(I.g_first[r]);
+    float4* hg = I.hg + gb;
+    float4* vg = I.vg + gb;
+    float4* ag = I.ag + gb;
     double* hsb = A.h_state + 3 * a0;
 
     double F[9];
